@@ -1,0 +1,120 @@
+"""Pins of the oracle's Strang composition (algorithm "Strang split MHD step") and the
+nodal variable exchange: exact round trip, global mass conservation, free stream,
+divergence control, and second-order temporal self-convergence on the advected vortex
+(section "Temporal convergence")."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2609_10849_amd import workloads as W
+from tests._poly import Fields, div_max
+
+G = 5.0 / 3.0
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def mesh_of(L):
+    return O.Mesh(L.nx, L.ny, L.p, L.m, L.x0, L.x1, L.y0, L.y1, L.gamma)
+
+
+def test_exchange_round_trip():
+    L, U, *_ = W.random_state(5, 4, 3, 2, seed=1, amp=0.5)
+    M = mesh_of(L)
+    rho, e, u = O.to_primitive(M, U)
+    U2 = O.to_conservative(M, rho, e, u)
+    np.testing.assert_allclose(U2, U, rtol=4e-16, atol=4e-16 * np.abs(U).max())
+    p = (G - 1) * (U[4] - (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / (2 * U[0]))
+    np.testing.assert_allclose(e, p / ((G - 1) * rho), rtol=1e-14)
+
+
+def test_strang_mass_and_divergence():
+    L, U, Bx, By, Bz = W.orszag_tang_scaled(12, 12, 2, 2)
+    M = mesh_of(L)
+    x, w = O.gll(2)
+    Mw = M.hx * M.hy / 4 * np.outer(w, w)
+    mass0 = (Mw * U[0]).sum()
+    F = Fields(M.nx, M.ny, 2, 2, M.hx, M.hy)
+    d0 = div_max(F, Bx, By)
+    assert d0 < 1e-12
+    o = O.Options.full()
+    for _ in range(3):
+        U, Bx, By, Bz, rep, flags, st = O.strang_step(M, o, U, Bx, By, Bz, 0.01)
+        assert st == 0 and rep["accepted"] == rep["attempted"] == 2
+    assert abs((Mw * U[0]).sum() - mass0) <= 1e-13 * mass0
+    assert div_max(F, Bx, By) < 1e-11
+    assert O.divB_L2(M, Bx, By) < 1e-11
+
+
+def test_strang_free_stream():
+    M = O.Mesh(4, 3, 3, 2, 0, 1, 0, 1)
+    sh = (M.K, 4, 4)
+    U = W.conservative(np.full(sh, 1.1), np.full(sh, .4), np.full(sh, -.2), np.full(sh, .3), np.full(sh, .9), G)
+    Bx, By, Bz = [np.full(M.gshape(), v) for v in (0.3, -0.5, 0.2)]
+    U1, Bx1, By1, Bz1, rep, flags, st = O.strang_step(M, O.Options.full(), U, Bx, By, Bz, 0.01)
+    np.testing.assert_allclose(U1, U, rtol=1e-13)
+    for a, b in ((Bx1, Bx), (By1, By), (Bz1, Bz)):
+        np.testing.assert_allclose(a, b, rtol=1e-13)
+    assert rep["eta_max"] == 0.0 and (flags == 0).all()
+
+
+def central_l2(L, U, Bx, By, F, box=5.0):
+    """Per-field nodal arrays restricted to elements inside [-box, box]^2 (for Cauchy norms)."""
+    X, Y = L.u_nodes()
+    inside = (np.abs(X).max(axis=(1, 2)) <= box) & (np.abs(Y).max(axis=(1, 2)) <= box)
+    return inside
+
+
+def cauchy(L, M, sols):
+    x, w = O.gll(L.p)
+    Mw = L.hx * L.hy / 4 * np.outer(w, w)
+    X, Y = L.u_nodes()
+    inside = (np.abs(X).max(axis=(1, 2)) <= 5.0 + 1e-12) & (np.abs(Y).max(axis=(1, 2)) <= 5.0 + 1e-12)
+    out = []
+    for a, b in zip(sols[:-1], sols[1:]):
+        d = {}
+        d["rho"] = math.sqrt((Mw * (a[0][0] - b[0][0]) ** 2)[inside].sum())
+        ua = a[0][1:4] / a[0][0]; ub = b[0][1:4] / b[0][0]
+        d["u"] = math.sqrt((Mw * ((ua - ub) ** 2).sum(0))[inside].sum())
+        out.append(d)
+    return out
+
+
+def run_vortex(n, p, m, dt, tf):
+    L, U, Bx, By, Bz = W.balsara_vortex(n, n, p, m)
+    M = mesh_of(L)
+    o = O.Options()
+    for _ in range(int(round(tf / dt))):
+        U, Bx, By, Bz, rep, flags, st = O.strang_step(M, o, U, Bx, By, Bz, dt)
+        assert st == 0
+    return L, M, (U, Bx, By, Bz)
+
+
+def test_strang_second_order_reduced():
+    """Second-order self-convergence of the Strang composition on the advected vortex,
+    (p, m) = (2, 2), 24 x 24, t_f = 0.4."""
+    sols = []
+    for dt in (0.04, 0.02, 0.01, 0.005):
+        L, M, s = run_vortex(24, 2, 2, dt, 0.4)
+        sols.append(s)
+    d = cauchy(L, M, sols)
+    for f in ("rho", "u"):
+        r = [math.log2(d[i][f] / d[i + 1][f]) for i in range(len(d) - 1)]
+        assert abs(r[-1] - 2.0) < 0.15, (f, d, r)
+
+
+@pytest.mark.slow
+def test_strang_table3_slow():
+    gold = json.load(open(os.path.join(HERE, "golden", "vortex_table3.json")))
+    sols = []
+    for dt in gold["dt"][:3] + [gold["dt"][2] / 2]:
+        L, M, s = run_vortex(64, 2, 2, dt, 1.0)
+        sols.append(s)
+    d = cauchy(L, M, sols)
+    for i in range(3):
+        assert 0.75 * gold["d_rho"][i] < d[i]["rho"] < 1.25 * gold["d_rho"][i], (i, d[i], gold["d_rho"][i])
+    r = math.log2(d[1]["rho"] / d[2]["rho"])
+    assert abs(r - 2.0) < 0.05
