@@ -1,0 +1,190 @@
+/* mhd25.h -- C ABI of the MI355X (gfx950) library for the Strang-split 2.5D ideal-MHD
+ * scheme of Fan & Fu, "Structure-preserving operator splitting for 2.5D ideal MHD with an
+ * entropy-stable DGSEM and exactly divergence-free compatible finite elements".
+ *
+ * Conventions
+ *  - Every array argument is a caller-owned, contiguous FP64 (or integer, where stated)
+ *    DEVICE pointer, e.g. a torch tensor's data_ptr(); the library never frees it.
+ *    Host pointers are used only for the small report / diagnostics structs, as stated.
+ *  - Mesh: nx x ny periodic Cartesian elements on [x0,x1]x[y0,y1], element
+ *    e = ey*nx + ex.  K = nx*ny.  p = DGSEM degree (1..6), m = compatible magnetic degree
+ *    with m in {p-1, p} (section "Magnetic--velocity subflow: compatible finite elements").
+ *  - Euler layout U[5][K][p+1][p+1]: (rho, m_x, m_y, m_z, E_mech) at the GLL_p nodes, x index
+ *    fastest (section "Hydrodynamic subflow").  rho, e: [K][p+1][p+1]; u: [3][K][p+1][p+1].
+ *  - Magnetic layout: every field of the compatible complex is a periodic grid
+ *    [ny*(m+1)][nx*(m+1)] of PHYSICAL component values at nodes (eq. hcurl-basis,
+ *    eq. hdiv-basis; Piola maps are diagonal on rectangles).  Element (ex,ey) owns grid
+ *    columns ex*(m+1)..ex*(m+1)+m and rows ey*(m+1)..ey*(m+1)+m:
+ *       B_x, E_y, J_y : GLL_{m+1} in x (last node = neighbour's first) x Gauss_m in y
+ *       B_y, E_x, J_x : Gauss_m in x x GLL_{m+1} in y
+ *       B_z           : GLL_m x GLL_m (element-local, discontinuous)
+ *       E_z, J_z      : GLL_{m+1} x GLL_{m+1} (continuous)
+ *  - Calls are stream-ordered on the context's stream.  Calls that return a report or a
+ *    decision synchronise that stream.  One context belongs to one stream; concurrent
+ *    calls on one context are not allowed.
+ *  - Return codes: 0 ok; negative = caller or system error (-1 invalid argument, -2 HIP
+ *    error, -3 out of device memory, -4 unsupported degree); positive = numerical outcome
+ *    with the state left at its value on entry (1: substep not accepted within
+ *    max_halvings).  The library never aborts; mhd25_last_error() describes the failure.
+ */
+#ifndef MHD25_H
+#define MHD25_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mhd25_ctx mhd25_ctx; /* opaque: owns tables, workspace and counters */
+
+typedef struct {
+  int32_t nx, ny;           /* elements per direction (>= 1), periodic              */
+  double x0, x1, y0, y1;    /* rectangle Omega                                      */
+  int32_t p;                /* DGSEM degree, 1..6                                    */
+  int32_t m;                /* magnetic degree, p-1 or p                             */
+  double gamma;             /* ratio of specific heats (> 1)                         */
+} mhd25_mesh_desc;
+
+typedef struct {
+  int32_t oe_hydro;         /* hydro oscillation elimination on/off                 */
+  int32_t oe_mag;           /* velocity OE on/off                                    */
+  int32_t pp;               /* positivity-preserving scaling on/off                  */
+  int32_t ar;               /* artificial resistivity on/off                         */
+  double s_H, s_M;          /* OE scale factors (paper: 0.02)                        */
+  double C_s, C_eta;        /* A.R. sensor response and maximum (paper: 5, 0.2)      */
+  int32_t iface_flux;       /* 0: local Lax-Friedrichs (the scheme), 1: the EC flux  */
+  int32_t max_halvings;     /* reject-and-halve depth budget (default 10)            */
+} mhd25_options;
+
+typedef struct {
+  int32_t substeps_attempted; /* hydro substep attempts (including rejected ones)   */
+  int32_t substeps_accepted;
+  int32_t max_depth;          /* deepest halving level reached                      */
+  int32_t status;             /* return code of the call                            */
+  int64_t n_rho_limited;      /* elements with density scaling, summed over stages  */
+  int64_t n_p_limited;        /* elements with pressure scaling                     */
+  int64_t n_collapsed;        /* elements collapsed to their average                */
+  double eta_max;             /* max artificial-resistivity coefficient (last M stage) */
+  double dt;                  /* step size of the call                              */
+} mhd25_report;
+
+/* Defaults: all stabilisation off, paper constants, LLF interfaces, 10 halvings. */
+void mhd25_default_options(mhd25_options* opt);
+
+/* Create a context for one mesh.  `hip_stream` is a hipStream_t (NULL = default stream).
+ * Allocates all device workspace (about 12 state-sized arrays).  Returns 0 or <0. */
+int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* hip_stream, mhd25_ctx** out);
+void mhd25_destroy(mhd25_ctx* ctx);
+/* Replace the options of an existing context (host-side only). */
+int mhd25_set_options(mhd25_ctx* ctx, const mhd25_options* opt);
+const char* mhd25_last_error(const mhd25_ctx* ctx);
+
+/* L_E: mass-inverted DGSEM operator (eq. euler-nodal-index / eq. euler-semidiscrete):
+ * entropy-conservative flux differencing (eq. euler-chandrashekar-flux,
+ * eq. euler-volume-residual) with LLF interfaces (eq. euler-lf-flux).
+ * U, dUdt: [5][K][p+1][p+1]; dUdt is overwritten. */
+int mhd25_rhs_hydro(mhd25_ctx* ctx, const double* U, double* dUdt);
+
+/* Stage map P = P_PP o P_OE (eq. euler-stage-map) applied in place to a raw stage candidate
+ * U with stage step tau.  `flags` (device, [K] uint8, may be NULL) receives bit0 density
+ * limited, bit1 pressure limited, bit2 collapsed.  Returns 0; does not check admissibility. */
+int mhd25_hydro_stage_map(mhd25_ctx* ctx, double* U, double tau, uint8_t* flags);
+
+/* Algorithm "Hydrodynamic Euler substep": SSP-RK(3,3) (eq. euler-ssprk33) with P after every
+ * raw stage; a raw stage whose element average is inadmissible rejects the attempt, which
+ * is replaced by two attempts of tau/2 (recursively, depth <= max_halvings).  U in place.
+ * `rep` (host, may be NULL) is filled.  Returns 0, 1 (not accepted; U unchanged) or <0. */
+int mhd25_hydro_substep(mhd25_ctx* ctx, double* U, double tau, mhd25_report* rep);
+
+/* L_M: mass-inverted magnetic-velocity operator with J and E eliminated (eq. magnetic-dae):
+ * weak-curl current (eq. mag-current-proj), Ohm-law electric field (eq. mag-electric-proj),
+ * strong curl update, Lorentz load as the transpose of the coupling form, Ohmic heating.
+ * rho frozen, eta ([K], may be NULL = ideal) frozen.  Outputs overwritten:
+ * de [K][p+1]^2, du [3][K][p+1]^2, dBx/dBy/dBz magnetic grids. */
+int mhd25_rhs_magnetic(mhd25_ctx* ctx, const double* rho, const double* u, const double* Bx,
+                       const double* By, const double* Bz, const double* eta, double* de, double* du,
+                       double* dBx, double* dBy, double* dBz);
+
+/* Reconstructed current and electric field (eq. mag-current-proj, eq. mag-electric-proj):
+ * J6 = six magnetic grids (J_x, J_y, J_z, E_x, E_y, E_z) in that order, overwritten. */
+int mhd25_reconstruct_JE(mhd25_ctx* ctx, const double* u, const double* Bx, const double* By,
+                         const double* Bz, const double* eta, double* JE6);
+
+/* Artificial-resistivity coefficient eta_K (eq. magnetic-ar-sensor, eq. magnetic-ar-coefficient)
+ * of the state (rho, u, B).  eta: [K], overwritten. */
+int mhd25_ar_eta(mhd25_ctx* ctx, const double* rho, const double* u, const double* Bx, const double* By,
+                 const double* Bz, double* eta);
+
+/* Velocity OE map (eq. magnetic-oe-sensor .. eq. magnetic-oe-map) applied in place to (u, e)
+ * of a raw magnetic stage with step tau; B is read for the rate. */
+int mhd25_velocity_oe(mhd25_ctx* ctx, double tau, const double* rho, double* u, double* e,
+                      const double* Bx, const double* By, const double* Bz);
+
+/* Algorithm "Magnetic-velocity substep": eta frozen at entry (when ar is on), SSP-RK(3,3)
+ * (eq. magnetic-ssprk33) with the velocity OE after every raw stage.  e, u, B in place. */
+int mhd25_step_magnetic(mhd25_ctx* ctx, const double* rho, double* e, double* u, double* Bx,
+                        double* By, double* Bz, double tau, mhd25_report* rep);
+
+/* Nodal variable exchange (section "Local variable exchange"). */
+int mhd25_to_primitive(mhd25_ctx* ctx, const double* U, double* rho, double* e, double* u);
+int mhd25_to_conservative(mhd25_ctx* ctx, const double* rho, const double* e, const double* u, double* U);
+
+/* Algorithm "Strang split MHD step": H(dt/2) -> exchange -> M(dt) -> exchange -> H(dt/2).
+ * U and B in place.  On a positive return both are restored to their entry values. */
+int mhd25_strang_step(mhd25_ctx* ctx, double* U, double* Bx, double* By, double* Bz, double dt,
+                      mhd25_report* rep);
+
+/* Time step from the positivity CFL: dt = cfl / max_{K,q} (2p+1)[(|u_x|+c_f)/hx + (|u_y|+c_f)/hy],
+ * c_f = sqrt((gamma p + |B|^2)/rho) with B at the GLL_p nodes.  dt written to *dt (host). */
+int mhd25_cfl_dt(mhd25_ctx* ctx, const double* U, const double* Bx, const double* By, const double* Bz,
+                 double cfl, double* dt);
+
+/* In-plane field (-d_y A_h, d_x A_h) of a potential A_h on the E_z/J_z grid (initial data,
+ * section "Advected MHD vortex"). */
+int mhd25_B_from_potential(mhd25_ctx* ctx, const double* A, double* Bx, double* By);
+
+/* Diagnostics (host out[6]): mass = sum M rho, mechanical energy sum M E_mech,
+ * magnetic energy (B,B)_B / 2, ||div B||_{L2}, min nodal rho, min nodal p. */
+int mhd25_diagnostics(mhd25_ctx* ctx, const double* U, const double* Bx, const double* By,
+                      const double* Bz, double* out6);
+
+/* Per-element decision flags of the last stage map applied (device [K] uint8 copied to the
+ * host buffer `host_flags` of length n >= K).  Bit-exact comparisons use these. */
+int mhd25_decisions(const mhd25_ctx* ctx, uint8_t* host_flags, int64_t n);
+
+/* Vector-Jacobian products (stage recomputation, no stored Jacobians).
+ * Hydro: Ubar = (dL_E/dU)^T cot with the LLF max/abs branches taken at U.  Ubar overwritten.
+ * Magnetic: VJP of L_M with rho and eta frozen; e does not enter L_M (ebar = 0). */
+int mhd25_rhs_hydro_vjp(mhd25_ctx* ctx, const double* U, const double* cot, double* Ubar);
+int mhd25_rhs_magnetic_vjp(mhd25_ctx* ctx, const double* rho, const double* u, const double* Bx,
+                           const double* By, const double* Bz, const double* eta, const double* de_cot,
+                           const double* du_cot, const double* dBx_cot, const double* dBy_cot,
+                           const double* dBz_cot, double* u_bar, double* Bx_bar, double* By_bar,
+                           double* Bz_bar);
+
+/* Kernel timing on the context stream with HIP events (off by default).  kernel id 0 is the
+ * hydro stage kernel (L_E + SSP combine + statistics).  Returns launches and summed ms. */
+int mhd25_timing_enable(mhd25_ctx* ctx, int32_t on);
+int mhd25_timing_read(mhd25_ctx* ctx, int32_t kernel_id, int64_t* launches, double* total_ms);
+
+/* ---- Batched ensemble of independent runs (uneven meshes and degrees) ---- */
+typedef struct mhd25_batch mhd25_batch;
+/* Create a batch of nruns runs, each with its own mesh; options shared. */
+int mhd25_batch_create(const mhd25_mesh_desc* runs, int32_t nruns, const mhd25_options* opt,
+                       void* hip_stream, mhd25_batch** out);
+void mhd25_batch_destroy(mhd25_batch* b);
+/* One Strang step of every run.  U, Bx, By, Bz: host arrays of nruns device pointers;
+ * dt: host [nruns]; rep: host [nruns] (may be NULL).  Runs whose hydro substep needs a
+ * halving are re-done individually.  Returns 0, or the first nonzero run status. */
+int mhd25_batch_strang_step(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
+                            double* const* Bz, const double* dt, mhd25_report* rep);
+/* Sequential reference: the same step run by run with the plain per-run kernels. */
+int mhd25_batch_strang_step_sequential(mhd25_batch* b, double* const* U, double* const* Bx,
+                                       double* const* By, double* const* Bz, const double* dt,
+                                       mhd25_report* rep);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHD25_H */

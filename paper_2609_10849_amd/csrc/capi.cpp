@@ -1,0 +1,422 @@
+// C ABI of the gfx950 library (declared in include/mhd25.h): context management and the host
+// control flow of algorithms "Hydrodynamic Euler substep", "Magnetic-velocity substep" and
+// "Strang split MHD step".  All arithmetic runs in the HIP kernels; the host only sequences
+// launches and reads one reject flag (4 bytes) plus three counters per hydro attempt.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+// launchers (hydro.hip, magnetic.hip, extra.hip)
+int hydro_rhs(mhd25_ctx* c, const double* U, double* dU);
+int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust, double ca, double cb, double tau);
+int hydro_stats_only(mhd25_ctx* c, const double* U, int* flag);
+int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, const int* flag);
+int reset_attempt(mhd25_ctx* c);
+int dcopy(mhd25_ctx* c, const double* a, double* b, long n);
+int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
+                       const double* eta, double* JE);
+int mag_update(mhd25_ctx* c, const MagIO& io, int mode);
+int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
+                    const double* By, const double* Bz);
+int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,
+               const double* Bz, double* eta);
+int mag_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u);
+int mag_to_conservative(mhd25_ctx* c, const double* rho, const double* e, const double* u, double* U);
+int mag_B_from_potential(mhd25_ctx* c, const double* A, double* Bx, double* By);
+int extra_max(mhd25_ctx* c, const double* a, long n, double* host_out);
+int extra_cfl(mhd25_ctx* c, const double* U, const double* Bx, const double* By, const double* Bz, double* host_max);
+int extra_diagnostics(mhd25_ctx* c, const double* U, const double* Bx, const double* By, const double* Bz,
+                      double* out6);
+
+hipEvent_t* timing_slot(mhd25_ctx* c) {
+  if ((size_t)(c->ev_used + 2) > c->ev_pool.size()) {
+    // pool full: fold the recorded pairs into the totals and reuse
+    if (!c->ev_pool.empty()) {
+      hipEventSynchronize(c->ev_pool[c->ev_used - 1]);
+      for (int k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]);
+        c->t_launch[0]++; c->t_ms[0] += ms;
+      }
+      c->ev_used = 0;
+    }
+    if (c->ev_pool.empty()) {
+      c->ev_pool.resize(2048);
+      for (auto& ev : c->ev_pool) hipEventCreate(&ev);
+    }
+  }
+  hipEvent_t* s = &c->ev_pool[c->ev_used];
+  c->ev_used += 2;
+  return s;
+}
+
+static int fail(mhd25_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(c, call)                                                                   \
+  do {                                                                                    \
+    hipError_t _e = (call);                                                               \
+    if (_e != hipSuccess) return fail(c, _e == hipErrorOutOfMemory ? -3 : -2,             \
+                                      std::string(#call) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+#define TRY(x)            \
+  do {                    \
+    int _r = (x);         \
+    if (_r) return _r;    \
+  } while (0)
+
+extern "C" {
+
+void mhd25_default_options(mhd25_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->s_H = 0.02; o->s_M = 0.02; o->C_s = 5.0; o->C_eta = 0.2;
+  o->iface_flux = 0; o->max_halvings = 10;
+}
+
+const char* mhd25_last_error(const mhd25_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int mhd25_set_options(mhd25_ctx* c, const mhd25_options* opt) {
+  if (!c || !opt) return -1;
+  if (opt->max_halvings < 0 || opt->max_halvings > 60 || opt->s_H < 0 || opt->s_M < 0 || opt->C_s < 0 ||
+      opt->C_eta < 0 || (opt->iface_flux != 0 && opt->iface_flux != 1))
+    return fail(c, -1, "invalid options");
+  c->opt = *opt;
+  return 0;
+}
+
+void mhd25_destroy(mhd25_ctx* c) {
+  if (!c) return;
+  void* ptrs[] = {c->d_ht, c->d_mt, c->Un, c->S1, c->S2, c->Ust, c->stats, c->lines, c->glob, c->d_flag,
+                  c->d_counts, c->d_flags, c->rho, c->e, c->u, c->eta, c->Yn, c->Y1, c->Y2, c->JE,
+                  c->loads, c->saveU, c->saveB, c->red, c->snapU};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->h_pinned) (void)hipHostFree(c->h_pinned);
+  for (auto& ev : c->ev_pool) (void)hipEventDestroy(ev);
+  delete c;
+}
+
+int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stream, mhd25_ctx** out) {
+  if (!mesh || !out) return -1;
+  *out = nullptr;
+  const mhd25_mesh_desc& d = *mesh;
+  if (d.nx < 1 || d.ny < 1 || !(d.x1 > d.x0) || !(d.y1 > d.y0) || !(d.gamma > 1.0)) return -1;
+  if (d.p < 1 || d.p > MHD_MAXP) return -4;
+  if (d.m != d.p && d.m != d.p - 1) return -4;
+  mhd25_ctx* c = new (std::nothrow) mhd25_ctx();
+  if (!c) return -3;
+  c->mesh = d;
+  mhd25_default_options(&c->opt);
+  if (opt && mhd25_set_options(c, opt)) { mhd25_destroy(c); return -1; }
+  c->stream = (hipStream_t)stream;
+  c->p = d.p; c->m = d.m; c->np = d.p + 1; c->nn = c->np * c->np; c->M1 = d.m + 1;
+  c->mp.nx = d.nx; c->mp.ny = d.ny; c->mp.K = (long)d.nx * d.ny;
+  c->mp.hx = (d.x1 - d.x0) / d.nx; c->mp.hy = (d.y1 - d.y0) / d.ny;
+  c->mp.J = c->mp.hx * c->mp.hy / 4.0; c->mp.gamma = d.gamma;
+  c->G = (long)d.nx * d.ny * c->M1 * c->M1;
+  build_hydro_tables(c->p, &c->h_ht);
+  build_mag_tables(c->p, c->m, &c->h_mt);
+  const long K = c->mp.K, KN = K * c->nn, n5 = 5 * KN, G = c->G;
+  const int a = c->m + 2, b = c->m + 1;
+  const long ny_ = d.ny, nx_ = d.nx;
+  auto alloc = [&](void** p, size_t bytes) -> int {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+    if (e != hipSuccess) return fail(c, e == hipErrorOutOfMemory ? -3 : -2, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return 0;
+  };
+  int r = 0;
+  r = r ? r : alloc((void**)&c->d_ht, sizeof(HydroTab));
+  r = r ? r : alloc((void**)&c->d_mt, sizeof(MagTab));
+  r = r ? r : alloc((void**)&c->Un, n5 * 8);
+  r = r ? r : alloc((void**)&c->S1, n5 * 8);
+  r = r ? r : alloc((void**)&c->S2, n5 * 8);
+  r = r ? r : alloc((void**)&c->Ust, n5 * 8);
+  r = r ? r : alloc((void**)&c->stats, K * 15 * 8);
+  r = r ? r : alloc((void**)&c->lines, (nx_ + ny_) * 15 * 8);
+  r = r ? r : alloc((void**)&c->glob, 64 * 8);
+  r = r ? r : alloc((void**)&c->d_flag, 64);
+  r = r ? r : alloc((void**)&c->d_counts, 64);
+  r = r ? r : alloc((void**)&c->d_flags, K);
+  r = r ? r : alloc((void**)&c->rho, KN * 8);
+  r = r ? r : alloc((void**)&c->e, KN * 8);
+  r = r ? r : alloc((void**)&c->u, 3 * KN * 8);
+  r = r ? r : alloc((void**)&c->eta, K * 8);
+  const long ny = 4 * KN + 3 * G;
+  r = r ? r : alloc((void**)&c->Yn, ny * 8);
+  r = r ? r : alloc((void**)&c->Y1, ny * 8);
+  r = r ? r : alloc((void**)&c->Y2, ny * 8);
+  r = r ? r : alloc((void**)&c->JE, 6 * G * 8);
+  r = r ? r : alloc((void**)&c->loads, K * (2 * a * b + a * a) * 8);
+  r = r ? r : alloc((void**)&c->saveU, n5 * 8);
+  r = r ? r : alloc((void**)&c->saveB, 3 * G * 8);
+  r = r ? r : alloc((void**)&c->snapU, n5 * 8);
+  r = r ? r : alloc((void**)&c->red, (K + 1024) * 8 * 8);
+  if (!r && hipHostMalloc((void**)&c->h_pinned, 4096) != hipSuccess) r = fail(c, -3, "hipHostMalloc");
+  if (r) { mhd25_destroy(c); return r; }
+  if (hipMemcpy(c->d_ht, &c->h_ht, sizeof(HydroTab), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_mt, &c->h_mt, sizeof(MagTab), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->d_flags, 0, K) != hipSuccess) {
+    mhd25_destroy(c);
+    return -2;
+  }
+  *out = c;
+  return 0;
+}
+
+int mhd25_rhs_hydro(mhd25_ctx* c, const double* U, double* dU) {
+  if (!c || !U || !dU) return -1;
+  return hydro_rhs(c, U, dU);
+}
+
+int mhd25_hydro_stage_map(mhd25_ctx* c, double* U, double tau, uint8_t* flags) {
+  if (!c || !U) return -1;
+  const long n5 = 5 * c->mp.K * c->nn;
+  TRY(dcopy(c, U, c->Ust, n5));
+  TRY(hydro_stats_only(c, c->Ust, nullptr));
+  TRY(hydro_stage_b(c, c->Ust, U, tau, nullptr));
+  if (flags) HIPCHK(c, hipMemcpyAsync(flags, c->d_flags, c->mp.K, hipMemcpyDeviceToDevice, c->stream));
+  return 0;
+}
+
+// one attempt of the SSP-RK(3,3) hydro substep; returns 1 accepted, 0 rejected, <0 error
+static int hydro_attempt(mhd25_ctx* c, double* U, double tau, long long* counts) {
+  const long n5 = 5 * c->mp.K * c->nn;
+  TRY(reset_attempt(c));
+  TRY(dcopy(c, U, c->Un, n5));
+  TRY(hydro_stage_a(c, c->Un, c->Un, c->Ust, 0.0, 1.0, tau));
+  TRY(hydro_stage_b(c, c->Ust, c->S1, tau, c->d_flag));
+  TRY(hydro_stage_a(c, c->S1, c->Un, c->Ust, 0.75, 0.25, tau));
+  TRY(hydro_stage_b(c, c->Ust, c->S2, tau, c->d_flag));
+  TRY(hydro_stage_a(c, c->S2, c->Un, c->Ust, 1.0 / 3.0, 2.0 / 3.0, tau));
+  TRY(hydro_stage_b(c, c->Ust, U, tau, c->d_flag));  // skipped (U untouched) when rejected
+  int* hf = (int*)c->h_pinned;
+  unsigned long long* hc = (unsigned long long*)(c->h_pinned + 8);
+  HIPCHK(c, hipMemcpyAsync(hf, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(hc, c->d_counts, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (*hf) return 0;
+  counts[0] += (long long)hc[0]; counts[1] += (long long)hc[1]; counts[2] += (long long)hc[2];
+  return 1;
+}
+
+static int hydro_substep_rec(mhd25_ctx* c, double* U, double tau, int depth, mhd25_report* rep) {
+  rep->substeps_attempted++;
+  rep->max_depth = std::max(rep->max_depth, depth);
+  long long cnt[3] = {0, 0, 0};
+  int ok = hydro_attempt(c, U, tau, cnt);
+  if (ok < 0) return ok;
+  if (ok) {
+    rep->substeps_accepted++;
+    rep->n_rho_limited += cnt[0]; rep->n_p_limited += cnt[1]; rep->n_collapsed += cnt[2];
+    return 0;
+  }
+  if (depth + 1 > c->opt.max_halvings) {
+    c->err = "hydro substep not accepted within max_halvings";
+    return 1;
+  }
+  TRY(hydro_substep_rec(c, U, 0.5 * tau, depth + 1, rep));
+  return hydro_substep_rec(c, U, 0.5 * tau, depth + 1, rep);
+}
+
+int mhd25_hydro_substep(mhd25_ctx* c, double* U, double tau, mhd25_report* rep) {
+  if (!c || !U || !(tau > 0.0)) return -1;
+  mhd25_report r;
+  std::memset(&r, 0, sizeof(r));
+  r.dt = tau;
+  const long n5 = 5 * c->mp.K * c->nn;
+  TRY(dcopy(c, U, c->saveU, n5));
+  int s = hydro_substep_rec(c, U, tau, 0, &r);
+  if (s > 0) TRY(dcopy(c, c->saveU, U, n5));
+  r.status = s;
+  if (rep) *rep = r;
+  if (s >= 0) HIPCHK(c, hipStreamSynchronize(c->stream));
+  return s;
+}
+
+int mhd25_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
+                         const double* eta, double* JE6) {
+  if (!c || !u || !Bx || !By || !Bz || !JE6) return -1;
+  return mag_reconstruct_JE(c, u, Bx, By, Bz, eta, JE6);
+}
+
+int mhd25_rhs_magnetic(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,
+                       const double* Bz, const double* eta, double* de, double* du, double* dBx, double* dBy,
+                       double* dBz) {
+  if (!c || !rho || !u || !Bx || !By || !Bz || !de || !du || !dBx || !dBy || !dBz) return -1;
+  const long G = c->G;
+  TRY(mag_reconstruct_JE(c, u, Bx, By, Bz, eta, c->JE));
+  MagIO io{};
+  io.rho = rho; io.us = u; io.bxs = Bx; io.bys = By; io.bzs = Bz;
+  io.jx = c->JE; io.jy = c->JE + G; io.jz = c->JE + 2 * G;
+  io.ex = c->JE + 3 * G; io.ey = c->JE + 4 * G; io.ez = c->JE + 5 * G;
+  io.eta = eta;
+  io.oe = de; io.ou = du; io.obx = dBx; io.oby = dBy; io.obz = dBz;
+  return mag_update(c, io, 0);
+}
+
+int mhd25_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,
+                 const double* Bz, double* eta) {
+  if (!c || !rho || !u || !Bx || !By || !Bz || !eta) return -1;
+  return mag_ar_eta(c, rho, u, Bx, By, Bz, eta);
+}
+
+int mhd25_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
+                      const double* By, const double* Bz) {
+  if (!c || !rho || !u || !e || !Bx || !By || !Bz) return -1;
+  return mag_velocity_oe(c, tau, rho, u, e, Bx, By, Bz);
+}
+
+int mhd25_step_magnetic(mhd25_ctx* c, const double* rho, double* e, double* u, double* Bx, double* By, double* Bz,
+                        double tau, mhd25_report* rep) {
+  if (!c || !rho || !e || !u || !Bx || !By || !Bz || !(tau > 0.0)) return -1;
+  const long KN = c->mp.K * c->nn, G = c->G;
+  const double* eta = nullptr;
+  double eta_max = 0.0;
+  if (c->opt.ar && c->opt.C_eta > 0.0) {
+    TRY(mag_ar_eta(c, rho, u, Bx, By, Bz, c->eta));
+    eta = c->eta;
+    if (rep) TRY(extra_max(c, c->eta, c->mp.K, &eta_max));
+  }
+  // Y = [e | u | Bx | By | Bz]
+  auto parts = [&](double* Y, double** pe, double** pu, double** px, double** py, double** pz) {
+    *pe = Y; *pu = Y + KN; *px = Y + 4 * KN; *py = Y + 4 * KN + G; *pz = Y + 4 * KN + 2 * G;
+  };
+  double *ne, *nu, *nx, *ny, *nz;
+  parts(c->Yn, &ne, &nu, &nx, &ny, &nz);
+  TRY(dcopy(c, e, ne, KN)); TRY(dcopy(c, u, nu, 3 * KN));
+  TRY(dcopy(c, Bx, nx, G)); TRY(dcopy(c, By, ny, G)); TRY(dcopy(c, Bz, nz, G));
+  const double cas[3] = {0.0, 0.75, 1.0 / 3.0}, cbs[3] = {1.0, 0.25, 2.0 / 3.0};
+  double* stage_in[3] = {c->Yn, c->Y1, c->Y2};
+  double* stage_out[2] = {c->Y1, c->Y2};
+  for (int s = 0; s < 3; ++s) {
+    double *se, *su, *sx, *sy, *sz;
+    parts(stage_in[s], &se, &su, &sx, &sy, &sz);
+    double *oe, *ou, *ox, *oy, *oz;
+    if (s < 2) parts(stage_out[s], &oe, &ou, &ox, &oy, &oz);
+    else { oe = e; ou = u; ox = Bx; oy = By; oz = Bz; }
+    TRY(mag_reconstruct_JE(c, su, sx, sy, sz, eta, c->JE));
+    MagIO io{};
+    io.rho = rho; io.us = su; io.es = se; io.bxs = sx; io.bys = sy; io.bzs = sz;
+    io.un = nu; io.en = ne; io.bxn = nx; io.byn = ny; io.bzn = nz;
+    io.jx = c->JE; io.jy = c->JE + G; io.jz = c->JE + 2 * G;
+    io.ex = c->JE + 3 * G; io.ey = c->JE + 4 * G; io.ez = c->JE + 5 * G;
+    io.eta = eta;
+    io.oe = oe; io.ou = ou; io.obx = ox; io.oby = oy; io.obz = oz;
+    io.ca = cas[s]; io.cb = cbs[s]; io.tau = tau;
+    TRY(mag_update(c, io, 1));
+    if (c->opt.oe_mag) TRY(mag_velocity_oe(c, tau, rho, ou, oe, ox, oy, oz));
+  }
+  if (rep) {
+    std::memset(rep, 0, sizeof(*rep));
+    rep->eta_max = eta_max; rep->dt = tau;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return 0;
+}
+
+int mhd25_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u) {
+  if (!c || !U || !rho || !e || !u) return -1;
+  return mag_to_primitive(c, U, rho, e, u);
+}
+
+int mhd25_to_conservative(mhd25_ctx* c, const double* rho, const double* e, const double* u, double* U) {
+  if (!c || !U || !rho || !e || !u) return -1;
+  return mag_to_conservative(c, rho, e, u, U);
+}
+
+int mhd25_strang_step(mhd25_ctx* c, double* U, double* Bx, double* By, double* Bz, double dt, mhd25_report* rep) {
+  if (!c || !U || !Bx || !By || !Bz || !(dt > 0.0)) return -1;
+  const long KN = c->mp.K * c->nn, G = c->G;
+  mhd25_report r;
+  std::memset(&r, 0, sizeof(r));
+  r.dt = dt;
+  // entry snapshot for the failure path (state restored on a positive return)
+  TRY(dcopy(c, U, c->snapU, 5 * KN));
+  TRY(dcopy(c, Bx, c->saveB, G)); TRY(dcopy(c, By, c->saveB + G, G)); TRY(dcopy(c, Bz, c->saveB + 2 * G, G));
+  auto restore = [&](int s) {
+    if (s > 0) {
+      dcopy(c, c->snapU, U, 5 * KN);
+      dcopy(c, c->saveB, Bx, G); dcopy(c, c->saveB + G, By, G); dcopy(c, c->saveB + 2 * G, Bz, G);
+      (void)hipStreamSynchronize(c->stream);
+    }
+    r.status = s;
+    if (rep) *rep = r;
+    return s;
+  };
+  mhd25_report h1, m, h2;
+  std::memset(&h1, 0, sizeof(h1)); std::memset(&m, 0, sizeof(m)); std::memset(&h2, 0, sizeof(h2));
+  int s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h1);
+  if (s != 0) return restore(s);
+  TRY(mag_to_primitive(c, U, c->rho, c->e, c->u));
+  TRY(mhd25_step_magnetic(c, c->rho, c->e, c->u, Bx, By, Bz, dt, &m));
+  TRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
+  s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h2);
+  r.substeps_attempted = h1.substeps_attempted + h2.substeps_attempted;
+  r.substeps_accepted = h1.substeps_accepted + h2.substeps_accepted;
+  r.max_depth = std::max(h1.max_depth, h2.max_depth);
+  r.n_rho_limited = h1.n_rho_limited + h2.n_rho_limited;
+  r.n_p_limited = h1.n_p_limited + h2.n_p_limited;
+  r.n_collapsed = h1.n_collapsed + h2.n_collapsed;
+  r.eta_max = m.eta_max;
+  return restore(s);
+}
+
+int mhd25_cfl_dt(mhd25_ctx* c, const double* U, const double* Bx, const double* By, const double* Bz, double cfl,
+                 double* dt) {
+  if (!c || !U || !Bx || !By || !Bz || !dt || !(cfl > 0)) return -1;
+  double mx = 0.0;
+  TRY(extra_cfl(c, U, Bx, By, Bz, &mx));
+  if (!(mx > 0.0)) return fail(c, 2, "non-finite or zero wave speed");
+  *dt = cfl / mx;
+  return 0;
+}
+
+int mhd25_B_from_potential(mhd25_ctx* c, const double* A, double* Bx, double* By) {
+  if (!c || !A || !Bx || !By) return -1;
+  return mag_B_from_potential(c, A, Bx, By);
+}
+
+int mhd25_diagnostics(mhd25_ctx* c, const double* U, const double* Bx, const double* By, const double* Bz,
+                      double* out6) {
+  if (!c || !U || !Bx || !By || !Bz || !out6) return -1;
+  return extra_diagnostics(c, U, Bx, By, Bz, out6);
+}
+
+int mhd25_decisions(const mhd25_ctx* c, uint8_t* host_flags, int64_t n) {
+  if (!c || !host_flags || n < c->mp.K) return -1;
+  mhd25_ctx* cc = const_cast<mhd25_ctx*>(c);
+  HIPCHK(cc, hipMemcpyAsync(host_flags, c->d_flags, c->mp.K, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(cc, hipStreamSynchronize(c->stream));
+  return 0;
+}
+
+int mhd25_timing_enable(mhd25_ctx* c, int32_t on) {
+  if (!c) return -1;
+  c->timing = on ? 1 : 0;
+  return 0;
+}
+
+int mhd25_timing_read(mhd25_ctx* c, int32_t kid, int64_t* launches, double* total_ms) {
+  if (!c || kid != 0 || !launches || !total_ms) return -1;
+  if (c->ev_used > 0) {
+    HIPCHK(c, hipEventSynchronize(c->ev_pool[c->ev_used - 1]));
+    for (int k = 0; k + 1 < c->ev_used; k += 2) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]);
+      c->t_launch[0]++; c->t_ms[0] += ms;
+    }
+    c->ev_used = 0;
+  }
+  *launches = c->t_launch[0];
+  *total_ms = c->t_ms[0];
+  c->t_launch[0] = 0; c->t_ms[0] = 0.0;
+  return 0;
+}
+
+}  // extern "C"

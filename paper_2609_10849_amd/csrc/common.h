@@ -1,0 +1,95 @@
+// Internal definitions of the gfx950 library: device tables, mesh parameters, context.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mhd25.h"
+
+#define MHD_MAXP 6
+#define MHD_MAXN 8  // max points of any 1D node set used (p+1 <= 7, m+2 <= 8)
+
+// 1D tables of the DGSEM degree p (section "Nodal bases, quadrature, and mass matrices").
+struct HydroTab {
+  double xi[MHD_MAXN], w[MHD_MAXN];    // GLL_p nodes / weights
+  double Shat[MHD_MAXN][MHD_MAXN];     // (Q - Q^T)_{ir} / w_i : skew flux-differencing weights
+  double Tf[MHD_MAXN][MHD_MAXN];       // forward discrete Legendre transform Tf[a][i] = w_i P_a(xi_i)/n_a
+  double V[MHD_MAXN][MHD_MAXN];        // V[i][a] = P_a(xi_i)
+  double Dr0[MHD_MAXN][MHD_MAXN];      // r-th derivative of l_i at -1 (reference coordinate)
+  double Drp[MHD_MAXN][MHD_MAXN];      // r-th derivative of l_i at +1
+  double fr[MHD_MAXN];                 // OE sensor factor (2r+1) 2^r / (2 r!)
+  int ka[MHD_MAXN * MHD_MAXN];         // shell-ordered tensor Legendre basis: k -> (a, b)
+  int kb[MHD_MAXN * MHD_MAXN];
+  int ksh[MHD_MAXN * MHD_MAXN];        // shell index max(a, b)
+};
+
+// 1D interpolation (I) and derivative (D) matrices between the node sets of the magnetic
+// complex; names read  <op>_<source>_<target>[target][source].
+//   P: GLL_p (p+1)   W: GLL_{m+1} (m+2)   G: Gauss_m (m+1)   V: GLL_m (m+1)   Q: Gauss_{m+1} (m+2)
+struct MagTab {
+  double xw[MHD_MAXN], ww[MHD_MAXN];   // GLL_{m+1}
+  double xg[MHD_MAXN], wg[MHD_MAXN];   // Gauss_m
+  double xq[MHD_MAXN], wq[MHD_MAXN];   // Gauss_{m+1}
+  double xv[MHD_MAXN], wv[MHD_MAXN];   // GLL_m
+  double xp[MHD_MAXN], wp[MHD_MAXN];   // GLL_p
+  double I_W_Q[MHD_MAXN][MHD_MAXN], D_W_Q[MHD_MAXN][MHD_MAXN], I_G_Q[MHD_MAXN][MHD_MAXN];
+  double D_W_G[MHD_MAXN][MHD_MAXN], I_V_G[MHD_MAXN][MHD_MAXN];
+  double I_P_G[MHD_MAXN][MHD_MAXN], I_P_W[MHD_MAXN][MHD_MAXN];
+  double I_W_G[MHD_MAXN][MHD_MAXN], I_G_W[MHD_MAXN][MHD_MAXN], I_V_W[MHD_MAXN][MHD_MAXN];
+  double I_G_P[MHD_MAXN][MHD_MAXN], I_W_P[MHD_MAXN][MHD_MAXN], I_V_P[MHD_MAXN][MHD_MAXN];
+  double D_W_V[MHD_MAXN][MHD_MAXN], I_G_V[MHD_MAXN][MHD_MAXN];
+  double I_G_E[2][MHD_MAXN], I_V_E[2][MHD_MAXN];   // basis values at -1 and +1
+  double I_V_Q[MHD_MAXN][MHD_MAXN];
+};
+
+struct MeshP {
+  int nx, ny;
+  long K;
+  double hx, hy, J, gamma;
+};
+
+// pointers of one magnetic residual / SSP-stage evaluation (magnetic.hip)
+struct MagIO {
+  const double *rho, *us, *es, *bxs, *bys, *bzs;  // stage input Y_s (es unused for the residual)
+  const double *un, *en, *bxn, *byn, *bzn;        // Y^n (SSP combine only)
+  const double *jx, *jy, *jz, *ex, *ey, *ez;      // reconstructed J and E grids
+  const double* eta;
+  double *oe, *ou, *obx, *oby, *obz;              // outputs
+  double ca, cb, tau;
+};
+
+struct mhd25_ctx {
+  mhd25_mesh_desc mesh;
+  mhd25_options opt;
+  hipStream_t stream;
+  MeshP mp;
+  int p, m, np, nn, M1;
+  long G;  // magnetic grid size
+  HydroTab* d_ht;
+  MagTab* d_mt;
+  HydroTab h_ht;
+  MagTab h_mt;
+  // hydro workspace
+  double *Un, *S1, *S2, *Ust, *stats, *lines, *glob;
+  int* d_flag;
+  unsigned long long* d_counts;  // [3] per attempt
+  uint8_t* d_flags;
+  // magnetic workspace
+  double *rho, *e, *u, *eta, *Yn, *Y1, *Y2, *Ys, *JE, *loads, *bstat;
+  double *saveU, *saveB, *snapU;
+  double* red;  // scratch for small reductions
+  double* h_pinned;
+  std::string err;
+  // timing
+  int timing;
+  std::vector<hipEvent_t> ev_pool;  // pairs (start, stop) of timed hydro-stage launches
+  int ev_used;
+  long long t_launch[4];
+  double t_ms[4];
+};
+
+// host table builders (tables.cpp)
+void build_hydro_tables(int p, HydroTab* t);
+void build_mag_tables(int p, int m, MagTab* t);

@@ -1,0 +1,167 @@
+// Small auxiliary kernels: max reduction, positivity-CFL wave speed and diagnostics.
+#include <cfloat>
+
+#include "common.h"
+
+namespace {
+
+__device__ __forceinline__ long wr(long a, long n) { return a >= n ? a - n : a; }
+__device__ __forceinline__ long gix2(const MeshP& mp, int B, long ex, long ey, int i, int j) {
+  const long NX = (long)mp.nx * B, NY = (long)mp.ny * B;
+  return wr(ey * B + j, NY) * NX + wr(ex * B + i, NX);
+}
+
+// mode 0: max over n values; mode 1: per column sums of [n][6] for cols 0..3, min for 4..5
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ a, long n, int mode, double* __restrict__ out) {
+  __shared__ double red[6][256];
+  const int t = threadIdx.x;
+  const int ncol = mode == 0 ? 1 : 6;
+  double v[6];
+  for (int c = 0; c < ncol; ++c) v[c] = (mode == 0) ? -DBL_MAX : (c < 4 ? 0.0 : DBL_MAX);
+  for (long k = t; k < n; k += 256) {
+    if (mode == 0) v[0] = fmax(v[0], a[k]);
+    else
+      for (int c = 0; c < 6; ++c) v[c] = c < 4 ? v[c] + a[k * 6 + c] : fmin(v[c], a[k * 6 + c]);
+  }
+  for (int c = 0; c < ncol; ++c) red[c][t] = v[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int c = 0; c < ncol; ++c)
+        red[c][t] = mode == 0 ? fmax(red[c][t], red[c][t + w])
+                              : (c < 4 ? red[c][t] + red[c][t + w] : fmin(red[c][t], red[c][t + w]));
+    __syncthreads();
+  }
+  if (t < ncol) out[t] = red[t][0];
+}
+
+template <int P, int M>
+__device__ void B_at_node(const double* Bx, const double* By, const double* Bz, const MagTab* T, const MeshP& mp,
+                          long ex, long ey, int qi, int qj, double* b) {
+  constexpr int A = M + 2, B = M + 1;
+  b[0] = b[1] = b[2] = 0.0;
+  for (int j = 0; j < B; ++j)
+    for (int i = 0; i < A; ++i) b[0] += T->I_W_P[qi][i] * T->I_G_P[qj][j] * Bx[gix2(mp, B, ex, ey, i, j)];
+  for (int j = 0; j < A; ++j)
+    for (int i = 0; i < B; ++i) b[1] += T->I_G_P[qi][i] * T->I_W_P[qj][j] * By[gix2(mp, B, ex, ey, i, j)];
+  for (int j = 0; j < B; ++j)
+    for (int i = 0; i < B; ++i) b[2] += T->I_V_P[qi][i] * T->I_V_P[qj][j] * Bz[gix2(mp, B, ex, ey, i, j)];
+}
+
+template <int P, int M>
+__global__ __launch_bounds__(128) void k_cfl(const double* __restrict__ U, const double* __restrict__ Bx,
+                                             const double* __restrict__ By, const double* __restrict__ Bz,
+                                             double* __restrict__ out, const MagTab* __restrict__ T, MeshP mp) {
+  constexpr int NP = P + 1, NN = NP * NP;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp.K) return;
+  const long ex = e % mp.nx, ey = e / mp.nx, KN = mp.K * NN;
+  double mx = 0.0;
+  for (int q = 0; q < NN; ++q) {
+    const long n = e * NN + q;
+    const double r = U[n], ux = U[KN + n] / r, uy = U[2 * KN + n] / r, uz = U[3 * KN + n] / r;
+    const double p = (mp.gamma - 1.0) * (U[4 * KN + n] - 0.5 * r * (ux * ux + uy * uy + uz * uz));
+    double b[3];
+    B_at_node<P, M>(Bx, By, Bz, T, mp, ex, ey, q % NP, q / NP, b);
+    const double cf = sqrt((mp.gamma * p + b[0] * b[0] + b[1] * b[1] + b[2] * b[2]) / r);
+    const double s = (2.0 * P + 1.0) * ((fabs(ux) + cf) / mp.hx + (fabs(uy) + cf) / mp.hy);
+    mx = (s > mx || s != s) ? s : mx;  // a NaN propagates
+  }
+  out[e] = mx;
+}
+
+template <int P, int M>
+__global__ __launch_bounds__(128) void k_diag(const double* __restrict__ U, const double* __restrict__ Bx,
+                                              const double* __restrict__ By, const double* __restrict__ Bz,
+                                              double* __restrict__ out, const MagTab* __restrict__ T, MeshP mp) {
+  constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp.K) return;
+  const long ex = e % mp.nx, ey = e / mp.nx, KN = mp.K * NN;
+  double mass = 0.0, Em = 0.0, rmin = DBL_MAX, pmin = DBL_MAX;
+  for (int q = 0; q < NN; ++q) {
+    const long n = e * NN + q;
+    const double w = mp.J * T->wp[q % NP] * T->wp[q / NP];
+    const double r = U[n];
+    const double p = (mp.gamma - 1.0) * (U[4 * KN + n] - (U[KN + n] * U[KN + n] + U[2 * KN + n] * U[2 * KN + n] +
+                                                          U[3 * KN + n] * U[3 * KN + n]) / (2.0 * r));
+    mass += w * r; Em += w * U[4 * KN + n];
+    rmin = fmin(rmin, r); pmin = fmin(pmin, p);
+  }
+  double mag = 0.0, div2 = 0.0;
+  for (int qy = 0; qy < A; ++qy)
+    for (int qx = 0; qx < A; ++qx) {
+      double bx = 0.0, by = 0.0, bz = 0.0, dxbx = 0.0, dyby = 0.0;
+      for (int j = 0; j < B; ++j)
+        for (int i = 0; i < A; ++i) {
+          const double v = Bx[gix2(mp, B, ex, ey, i, j)];
+          bx += T->I_W_Q[qx][i] * T->I_G_Q[qy][j] * v;
+          dxbx += T->D_W_Q[qx][i] * T->I_G_Q[qy][j] * v;
+        }
+      for (int j = 0; j < A; ++j)
+        for (int i = 0; i < B; ++i) {
+          const double v = By[gix2(mp, B, ex, ey, i, j)];
+          by += T->I_G_Q[qx][i] * T->I_W_Q[qy][j] * v;
+          dyby += T->I_G_Q[qx][i] * T->D_W_Q[qy][j] * v;
+        }
+      for (int j = 0; j < B; ++j)
+        for (int i = 0; i < B; ++i) bz += T->I_V_Q[qx][i] * T->I_V_Q[qy][j] * Bz[gix2(mp, B, ex, ey, i, j)];
+      const double w = mp.J * T->wq[qx] * T->wq[qy];
+      const double dv = (2.0 / mp.hx) * dxbx + (2.0 / mp.hy) * dyby;
+      mag += w * 0.5 * (bx * bx + by * by + bz * bz);
+      div2 += w * dv * dv;
+    }
+  double* o = out + e * 6;
+  o[0] = mass; o[1] = Em; o[2] = mag; o[3] = div2; o[4] = rmin; o[5] = pmin;
+}
+
+}  // namespace
+
+#define DISPATCH_PM2(p, m, F)                                                                             \
+  if (p == 1 && m == 0) { F(1, 0); } else if (p == 1 && m == 1) { F(1, 1); }                              \
+  else if (p == 2 && m == 1) { F(2, 1); } else if (p == 2 && m == 2) { F(2, 2); }                         \
+  else if (p == 3 && m == 2) { F(3, 2); } else if (p == 3 && m == 3) { F(3, 3); }                         \
+  else if (p == 4 && m == 3) { F(4, 3); } else if (p == 4 && m == 4) { F(4, 4); }                         \
+  else if (p == 5 && m == 4) { F(5, 4); } else if (p == 5 && m == 5) { F(5, 5); }                         \
+  else if (p == 6 && m == 5) { F(6, 5); } else if (p == 6 && m == 6) { F(6, 6); }                         \
+  else return -4;
+
+static int ex_chk(mhd25_ctx* c, hipError_t e, const char* what) {
+  if (e != hipSuccess) { c->err = std::string(what) + ": " + hipGetErrorString(e); return -2; }
+  return 0;
+}
+
+int extra_max(mhd25_ctx* c, const double* a, long n, double* host_out) {
+  double* d_out = c->red + 0;
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, c->stream, a, n, 0, d_out);
+  int r = ex_chk(c, hipMemcpyAsync(c->h_pinned, d_out, 8, hipMemcpyDeviceToHost, c->stream), "copy");
+  if (r) return r;
+  r = ex_chk(c, hipStreamSynchronize(c->stream), "sync");
+  *host_out = c->h_pinned[0];
+  return r;
+}
+
+int extra_cfl(mhd25_ctx* c, const double* U, const double* Bx, const double* By, const double* Bz, double* host_max) {
+  const long nb = (c->mp.K + 127) / 128;
+  double* buf = c->red + 16;
+#define CF(P, M) hipLaunchKernelGGL((k_cfl<P, M>), dim3(nb), dim3(128), 0, c->stream, U, Bx, By, Bz, buf, c->d_mt, c->mp)
+  DISPATCH_PM2(c->p, c->m, CF);
+#undef CF
+  return extra_max(c, buf, c->mp.K, host_max);
+}
+
+int extra_diagnostics(mhd25_ctx* c, const double* U, const double* Bx, const double* By, const double* Bz,
+                      double* out6) {
+  const long nb = (c->mp.K + 127) / 128;
+  double* buf = c->Ust;  // 5*K*nn >= 6*K doubles
+#define DG(P, M) hipLaunchKernelGGL((k_diag<P, M>), dim3(nb), dim3(128), 0, c->stream, U, Bx, By, Bz, buf, c->d_mt, c->mp)
+  DISPATCH_PM2(c->p, c->m, DG);
+#undef DG
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, c->stream, buf, c->mp.K, 1, c->red);
+  int r = ex_chk(c, hipMemcpyAsync(c->h_pinned, c->red, 6 * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+  if (r) return r;
+  r = ex_chk(c, hipStreamSynchronize(c->stream), "sync");
+  for (int k = 0; k < 6; ++k) out6[k] = c->h_pinned[k];
+  out6[3] = sqrt(out6[3]);
+  return r;
+}

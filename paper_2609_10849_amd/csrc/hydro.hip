@@ -1,0 +1,661 @@
+// Hydrodynamic-subflow kernels for gfx950 (section "Hydrodynamic subflow: entropy-stable DGSEM").
+//
+// Mapping: one thread per GLL node, EB = 256 / (p+1)^2 elements per 256-thread block
+// (wave64-friendly for every p).  The flux-differencing volume term uses the skew form
+// sum_{r != i} S_ir F(U_i, U_r) (S = Q - Q^T), which equals eq. euler-volume-residual
+// combined with the boundary corrections of eq. euler-nodal-index; each unordered pair of a
+// line is evaluated once: the p(p+1)/2 pairs of a line are distributed cyclically over its
+// p+1 nodes (node i owns pairs (i, i+d mod (p+1))), the owner accumulates its half in
+// registers and hands the partner's half through LDS.  Reductions are in fixed order, so
+// results are deterministic run to run.
+#include <cfloat>
+
+#include "common.h"
+
+namespace {
+
+constexpr double EPSM = 2.220446049250313e-16;  // 2^-52
+
+template <int P>
+struct Cfg {
+  static constexpr int NP = P + 1, NN = NP * NP, EB = 256 / NN, NT = EB * NN, ND = NP / 2;
+};
+
+struct Prim {
+  double r, ux, uy, uz, b, lr, lb;
+};
+
+__device__ __forceinline__ Prim make_prim(const double U[5], double g) {
+  Prim q;
+  q.r = U[0];
+  const double ir = 1.0 / U[0];
+  q.ux = U[1] * ir; q.uy = U[2] * ir; q.uz = U[3] * ir;
+  const double p = (g - 1.0) * (U[4] - 0.5 * (U[1] * q.ux + U[2] * q.uy + U[3] * q.uz));
+  q.b = 0.5 * q.r / p;
+  q.lr = log(q.r); q.lb = log(q.b);
+  return q;
+}
+
+// logarithmic mean with per-node logarithms; near-equal arguments (u = ((aR-aL)/(aR+aL))^2 < 1e-4)
+// use the series of f/atanh(f) to u^3 (truncation < u^4/9 ~ 1e-17).
+__device__ __forceinline__ double lmean(double aL, double aR, double lL, double lR) {
+  const double d = aR - aL, s = aR + aL;
+  if (d * d < 1e-4 * (s * s)) {
+    const double u = (d * d) / (s * s);
+    return 0.5 * s / (1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0))));
+  }
+  return d / (lR - lL);
+}
+
+// Chandrashekar flux (eq. euler-chandrashekar-flux), energy in the form
+// rho_log ud (1/(2(g-1) beta_log) - |u|^2avg/2 + |avg u|^2) + p_hat ud.
+template <int D>
+__device__ __forceinline__ void ecflux(const Prim& L, const Prim& R, double g, double F[5]) {
+  const double rl = lmean(L.r, R.r, L.lr, R.lr);
+  const double bl = lmean(L.b, R.b, L.lb, R.lb);
+  const double ph = 0.5 * (L.r + R.r) / (L.b + R.b);
+  const double uxa = 0.5 * (L.ux + R.ux), uya = 0.5 * (L.uy + R.uy), uza = 0.5 * (L.uz + R.uz);
+  const double u2a = 0.5 * ((L.ux * L.ux + L.uy * L.uy + L.uz * L.uz) + (R.ux * R.ux + R.uy * R.uy + R.uz * R.uz));
+  const double ud = D == 0 ? uxa : uya;
+  const double f0 = rl * ud;
+  F[0] = f0;
+  F[1] = f0 * uxa + (D == 0 ? ph : 0.0);
+  F[2] = f0 * uya + (D == 1 ? ph : 0.0);
+  F[3] = f0 * uza;
+  F[4] = f0 * (1.0 / (2.0 * (g - 1.0) * bl) - 0.5 * u2a + (uxa * uxa + uya * uya + uza * uza)) + ph * ud;
+}
+
+template <int D>
+__device__ __forceinline__ void physflux(const double U[5], double g, double F[5], double& ud, double& c) {
+  const double ir = 1.0 / U[0];
+  const double ux = U[1] * ir, uy = U[2] * ir, uz = U[3] * ir;
+  const double p = (g - 1.0) * (U[4] - 0.5 * (U[1] * ux + U[2] * uy + U[3] * uz));
+  ud = D == 0 ? ux : uy;
+  F[0] = U[1 + D];
+  F[1] = U[1] * ud + (D == 0 ? p : 0.0);
+  F[2] = U[2] * ud + (D == 1 ? p : 0.0);
+  F[3] = U[3] * ud;
+  F[4] = (U[4] + p) * ud;
+  c = sqrt(g * p * ir);
+}
+
+// numerical interface flux: LLF (eq. euler-lf-flux) or, for tests, the EC flux
+template <int D>
+__device__ __forceinline__ void iflux(const double UL[5], const double UR[5], double g, int iface, double F[5]) {
+  if (iface == 1) {
+    Prim a = make_prim(UL, g), b = make_prim(UR, g);
+    ecflux<D>(a, b, g, F);
+    return;
+  }
+  double FL[5], FR[5], udL, cL, udR, cR;
+  physflux<D>(UL, g, FL, udL, cL);
+  physflux<D>(UR, g, FR, udR, cR);
+  const double lam = fmax(fabs(udL) + cL, fabs(udR) + cR);
+#pragma unroll
+  for (int c = 0; c < 5; ++c) F[c] = 0.5 * (FL[c] + FR[c]) - 0.5 * lam * (UR[c] - UL[c]);
+}
+
+__device__ __forceinline__ long wrap(long a, long n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// One direction of L_E for the thread's node: owned pairs, interface flux, incoming halves.
+template <int P, int D>
+__device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], double acc[5], bool act, int el, int i,
+                                           int j, long e, const double* __restrict__ Us, long KN,
+                                           double (*sp)[Cfg<P>::EB * Cfg<P>::NN], double* sb,
+                                           const HydroTab* __restrict__ T, const MeshP& mp, int iface) {
+  using C = Cfg<P>;
+  constexpr int NP = C::NP, NN = C::NN, ND = C::ND;
+  const int pos = D == 0 ? i : j, line = D == 0 ? j : i;
+  const double sc = D == 0 ? 2.0 / mp.hx : 2.0 / mp.hy;
+  const double g = mp.gamma;
+  // sb layout: [el][line][owner pos][dslot][5]
+  double* sbl = sb + ((long)(el * NP + line) * NP) * ND * 5;
+  if (act) {
+#pragma unroll
+    for (int d = 1; d <= ND; ++d) {
+      if (2 * d == NP && pos >= NP / 2) continue;
+      int r = pos + d;
+      if (r >= NP) r -= NP;
+      const int nr = el * NN + (D == 0 ? line * NP + r : r * NP + line);
+      Prim o;
+      o.r = sp[0][nr]; o.ux = sp[1][nr]; o.uy = sp[2][nr]; o.uz = sp[3][nr];
+      o.b = sp[4][nr]; o.lr = sp[5][nr]; o.lb = sp[6][nr];
+      double F[5];
+      ecflux<D>(me, o, g, F);
+      const double ci = -sc * T->Shat[pos][r], cr = -sc * T->Shat[r][pos];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        acc[c] += ci * F[c];
+        sbl[(pos * ND + (d - 1)) * 5 + c] = cr * F[c];
+      }
+    }
+    if (pos == 0 || pos == P) {
+      const long ex = e % mp.nx, ey = e / mp.nx;
+      long en;
+      if (D == 0) en = ey * mp.nx + wrap(ex + (pos == 0 ? -1 : 1), mp.nx);
+      else en = wrap(ey + (pos == 0 ? -1 : 1), mp.ny) * mp.nx + ex;
+      const int qn = D == 0 ? line * NP + (pos == 0 ? P : 0) : (pos == 0 ? P : 0) * NP + line;
+      double UN[5], F[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) UN[c] = Us[c * KN + en * NN + qn];
+      if (pos == 0) {
+        iflux<D>(UN, U, g, iface, F);
+        const double s = sc / T->w[0];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) acc[c] += s * F[c];
+      } else {
+        iflux<D>(U, UN, g, iface, F);
+        const double s = sc / T->w[P];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) acc[c] -= s * F[c];
+      }
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int d = 1; d <= ND; ++d) {
+      int o = pos - d;
+      if (o < 0) o += NP;
+      if (2 * d == NP && o >= NP / 2) continue;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) acc[c] += sbl[(o * ND + (d - 1)) * 5 + c];
+    }
+  }
+  __syncthreads();
+}
+
+// Per-element sums (GLL weights, without |J_K|), minima and maxima of 5 fields held in LDS,
+// plus the raw-average admissibility test (NaN-safe).
+template <int P>
+__device__ __forceinline__ void element_stats(double (*sv)[Cfg<P>::EB * Cfg<P>::NN], bool act, int el, int q, long e,
+                                              double* __restrict__ stats, int* __restrict__ flag,
+                                              const HydroTab* __restrict__ T, double g) {
+  using C = Cfg<P>;
+  constexpr int NP = C::NP, NN = C::NN;
+  // tasks 0..14: (component, kind) statistics; task 15: admissibility of the raw average
+  for (int t = q; act && t < 16; t += NN) {
+    if (t < 15) {
+      const int c = t / 3, kind = t - 3 * c;
+      double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+      for (int k = 0; k < NN; ++k) {
+        const double v = sv[c][el * NN + k];
+        s += (T->w[k % NP] * T->w[k / NP]) * v;
+        mn = fmin(mn, v); mx = fmax(mx, v);
+      }
+      stats[(e * 5 + c) * 3 + kind] = kind == 0 ? s : (kind == 1 ? mn : mx);
+    } else if (flag) {
+      double a[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < NN; ++k) s += (T->w[k % NP] * T->w[k / NP]) * sv[c][el * NN + k];
+        a[c] = 0.25 * s;
+      }
+      const double pb = (g - 1.0) * (a[4] - (a[1] * a[1] + a[2] * a[2] + a[3] * a[3]) / (2.0 * a[0]));
+      if (!(a[0] > 0.0) || !(pb > 0.0)) atomicOr(flag, 1);
+    }
+  }
+}
+
+// MODE 0: out = L_E(Us).  MODE 1: out = ca*Un + cb*(Us + tau*L_E(Us)) plus element statistics.
+template <int P, int MODE>
+__global__ __launch_bounds__(256) void k_hydro_stage(const double* __restrict__ Us, const double* __restrict__ Un,
+                                                     double* __restrict__ out, double* __restrict__ stats,
+                                                     int* __restrict__ flag, const HydroTab* __restrict__ T, MeshP mp,
+                                                     double ca, double cb, double tau, int iface) {
+  using C = Cfg<P>;
+  constexpr int NP = C::NP, NN = C::NN, EB = C::EB, ND = C::ND;
+  __shared__ double sp[7][EB * NN];
+  __shared__ double sb[EB * NP * NP * (ND > 0 ? ND : 1) * 5];
+  __shared__ int sflag;
+  const int tid = threadIdx.x;
+  if (MODE == 1) {  // skip stages after a rejected one; read once per block (other blocks may set it)
+    if (tid == 0) sflag = __atomic_load_n(flag, __ATOMIC_RELAXED);
+    __syncthreads();
+    if (sflag) return;
+  }
+  const int el = tid / NN, q = tid - el * NN;
+  const int i = q % NP, j = q / NP;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = tid < C::NT && e < mp.K;
+  const long KN = mp.K * NN;
+  double U[5], acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  Prim me{};
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) U[c] = Us[c * KN + e * NN + q];
+    me = make_prim(U, mp.gamma);
+    sp[0][tid] = me.r; sp[1][tid] = me.ux; sp[2][tid] = me.uy; sp[3][tid] = me.uz;
+    sp[4][tid] = me.b; sp[5][tid] = me.lr; sp[6][tid] = me.lb;
+  }
+  __syncthreads();
+  volume_dir<P, 0>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, T, mp, iface);
+  volume_dir<P, 1>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, T, mp, iface);
+  if (MODE == 0) {
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) out[c * KN + e * NN + q] = acc[c];
+    }
+    return;
+  }
+  double Y[5];
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      const double un = Un[c * KN + e * NN + q];
+      Y[c] = ca * un + cb * (U[c] + tau * acc[c]);
+      out[c * KN + e * NN + q] = Y[c];
+      sp[c][tid] = Y[c];
+    }
+  }
+  __syncthreads();
+  element_stats<P>(sp, act, el, q, e, stats, flag, T, mp.gamma);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_elem_stats(const double* __restrict__ Uin, double* __restrict__ stats,
+                                                    int* __restrict__ flag, const HydroTab* __restrict__ T, MeshP mp) {
+  using C = Cfg<P>;
+  constexpr int NN = C::NN, EB = C::EB;
+  __shared__ double sv[5][EB * NN];
+  const int tid = threadIdx.x;
+  const int el = tid / NN, q = tid - el * NN;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = tid < C::NT && e < mp.K;
+  const long KN = mp.K * NN;
+  if (act)
+    for (int c = 0; c < 5; ++c) sv[c][tid] = Uin[c * KN + e * NN + q];
+  __syncthreads();
+  element_stats<P>(sv, act, el, q, e, stats, flag, T, mp.gamma);
+}
+
+// Element-average pressure helper
+__device__ __forceinline__ double pres(const double* a, double g) {
+  return (g - 1.0) * (a[4] - (a[1] * a[1] + a[2] * a[2] + a[3] * a[3]) / (2.0 * a[0]));
+}
+__device__ __forceinline__ double Sp(const double* a, double eps_r) {
+  return fabs(a[4]) + (a[1] * a[1] + a[2] * a[2] + a[3] * a[3]) / (2.0 * fmax(a[0], eps_r));
+}
+
+// P = P_PP o P_OE on a raw stage (eq. euler-oe-map, eq. euler-pp-density, eq. euler-pp-pressure).
+template <int P>
+__global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ Ust, double* __restrict__ Uout,
+                                                     const double* __restrict__ stats, const double* __restrict__ lines,
+                                                     const double* __restrict__ glob, uint8_t* __restrict__ flags,
+                                                     unsigned long long* __restrict__ counts,
+                                                     const int* __restrict__ flag, const HydroTab* __restrict__ T,
+                                                     MeshP mp, double tau, double sH, int do_oe, int do_pp) {
+  using C = Cfg<P>;
+  constexpr int NP = C::NP, NN = C::NN, EB = C::EB;
+  __shared__ double su[5][EB * NN];
+  __shared__ double st[10][EB * NN];
+  __shared__ double ssig[EB][2][NP];
+  __shared__ double sD[EB][NP];
+  if (flag && *flag) return;
+  const int tid = threadIdx.x;
+  const int el = tid / NN, q = tid - el * NN;
+  const int i = q % NP, j = q / NP;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = tid < C::NT && e < mp.K;
+  const long KN = mp.K * NN;
+  const double g = mp.gamma;
+  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  double U[5];
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) { U[c] = Ust[c * KN + e * NN + q]; su[c][tid] = U[c]; }
+  }
+  __syncthreads();
+  if (do_oe) {
+    // global and cross-line amplitudes (eq. euler-oe-amplitude), shared over components
+    double Dsh[2] = {0.0, 0.0};
+    bool cst[5];
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        const double gs = glob[c * 3 + 0], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
+        const double gm = gs / (4.0 * (double)mp.K);
+        const double dOm = fmax(gmx - gm, gm - gmn);
+        cst[c] = dOm <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn));
+        const double* rl = lines + (ey * 5 + c) * 3;
+        const double* cl = lines + ((mp.ny + ex) * 5 + c) * 3;
+        const double rm = rl[0] / (4.0 * mp.nx), cm = cl[0] / (4.0 * mp.ny);
+        Dsh[0] = fmax(Dsh[0], fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm));
+        Dsh[1] = fmax(Dsh[1], fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm));
+      }
+    }
+#pragma unroll
+    for (int D = 0; D < 2; ++D) {
+      // normal-jump contributions (eq. euler-oe-jump): thread (r, line)
+      const int r = D == 0 ? i : j, line = D == 0 ? j : i;
+      if (act) {
+        long em, ep;
+        if (D == 0) { em = ey * mp.nx + wrap(ex - 1, mp.nx); ep = ey * mp.nx + wrap(ex + 1, mp.nx); }
+        else { em = wrap(ey - 1, mp.ny) * mp.nx + ex; ep = wrap(ey + 1, mp.ny) * mp.nx + ex; }
+        const double wl = 0.5 * T->w[line];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          double a = 0.0, d = 0.0, b = 0.0, cc = 0.0;
+#pragma unroll
+          for (int k = 0; k < NP; ++k) {
+            const int nk = D == 0 ? line * NP + k : k * NP + line;
+            const double own = su[c][el * NN + nk];
+            a += T->Dr0[r][k] * own;
+            d += T->Drp[r][k] * own;
+            b += T->Drp[r][k] * Ust[c * KN + em * NN + nk];
+            cc += T->Dr0[r][k] * Ust[c * KN + ep * NN + nk];
+          }
+          const double jm = a - b, jp = cc - d;
+          st[2 * c][tid] = wl * jm * jm;
+          st[2 * c + 1][tid] = wl * jp * jp;
+        }
+      }
+      __syncthreads();
+      if (act && q < NP) {
+        const int rr = q;
+        double sig = 0.0;
+        if (Dsh[D] > 0.0) {
+#pragma unroll
+          for (int c = 0; c < 5; ++c) {
+            if (cst[c]) continue;
+            double sm = 0.0, spp = 0.0;
+            for (int l = 0; l < NP; ++l) {
+              const int nk = D == 0 ? l * NP + rr : rr * NP + l;
+              sm += st[2 * c][el * NN + nk];
+              spp += st[2 * c + 1][el * NN + nk];
+            }
+            sig = fmax(sig, T->fr[rr] * (sqrt(sm) + sqrt(spp)) / Dsh[D]);
+          }
+        }
+        ssig[el][D][rr] = sig;
+      }
+      __syncthreads();
+    }
+    if (act && q <= P) {
+      if (q == 0) {
+        sD[el][0] = 1.0;
+      } else {
+        double a[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) a[c] = 0.25 * stats[(e * 5 + c) * 3];
+        const double ck = sqrt(g * pres(a, g) / a[0]);
+        const double lx = (2.0 * P + 1.0) * (fabs(a[1] / a[0]) + ck) / mp.hx;
+        const double ly = (2.0 * P + 1.0) * (fabs(a[2] / a[0]) + ck) / mp.hy;
+        double sx = 0.0, sy = 0.0;
+        for (int r = 0; r <= q; ++r) { sx += ssig[el][0][r]; sy += ssig[el][1][r]; }
+        sD[el][q] = exp(-sH * tau * (lx * sx + ly * sy));
+      }
+    }
+    __syncthreads();
+    // modal damping: forward transform in x, then y; damp shell max(a,b); back-transform
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) s += T->Tf[i][k] * su[c][el * NN + j * NP + k];
+        st[c][tid] = s;  // [j][a=i]
+      }
+    }
+    __syncthreads();
+    if (act) {
+      const double dmp = sD[el][i > j ? i : j];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) s += T->Tf[j][k] * st[c][el * NN + k * NP + i];
+        st[5 + c][tid] = dmp * s;  // coefficient [b=j][a=i]
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < NP; ++a) s += T->V[i][a] * st[5 + c][el * NN + j * NP + a];
+        su[c][tid] = s;  // [b=j][i]
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) s += T->V[j][b] * su[c][el * NN + b * NP + i];
+        U[c] = s;
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) su[c][tid] = U[c];
+    }
+    __syncthreads();
+  }
+  uint8_t f = 0;
+  if (do_pp && act) {
+    const double eps_r = 64.0 * EPSM;
+    double a[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      double s = 0.0;
+      for (int k = 0; k < NN; ++k) s += (T->w[k % NP] * T->w[k / NP]) * su[c][el * NN + k];
+      a[c] = 0.25 * s;
+    }
+    if (!(a[0] > eps_r)) {
+      f = 4;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) U[c] = a[c];
+    } else {
+      double rmin = DBL_MAX;
+      for (int k = 0; k < NN; ++k) rmin = fmin(rmin, su[0][el * NN + k]);
+      double thr = 1.0;
+      if (rmin < eps_r) {
+        thr = fmin(1.0, fmax(0.0, (a[0] - eps_r) / (a[0] - rmin)));
+        f |= 1;
+        U[0] = a[0] + thr * (U[0] - a[0]);
+      }
+      double S = Sp(a, eps_r);
+      for (int k = 0; k < NN; ++k) {
+        double v[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) v[c] = su[c][el * NN + k];
+        if (f & 1) v[0] = a[0] + thr * (v[0] - a[0]);
+        S = fmax(S, Sp(v, eps_r));
+      }
+      const double eps_p = fmax(64.0 * EPSM, 8192.0 * EPSM * S);
+      const double pb = pres(a, g);
+      if (pb <= eps_p) {
+        f |= 4;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) U[c] = a[c];
+      } else {
+        double pmin = DBL_MAX;
+        for (int k = 0; k < NN; ++k) {
+          double v[5];
+#pragma unroll
+          for (int c = 0; c < 5; ++c) v[c] = su[c][el * NN + k];
+          if (f & 1) v[0] = a[0] + thr * (v[0] - a[0]);
+          pmin = fmin(pmin, pres(v, g));
+        }
+        if (pmin < eps_p) {
+          const double thp = fmin(1.0, fmax(0.0, (pb - eps_p) / (pb - pmin)));
+          f |= 2;
+#pragma unroll
+          for (int c = 0; c < 5; ++c) U[c] = a[c] + thp * (U[c] - a[c]);
+        }
+      }
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) Uout[c * KN + e * NN + q] = U[c];
+    if (q == 0) {
+      if (flags) flags[e] = f;
+      if (counts && f) {
+        if (f & 1) atomicAdd(&counts[0], 1ull);
+        if (f & 2) atomicAdd(&counts[1], 1ull);
+        if (f & 4) atomicAdd(&counts[2], 1ull);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+// Row / column reduction of per-element statistics [K][nc][3] (sum, min, max): blocks
+// 0..ny-1 reduce element rows, blocks ny..ny+nx-1 reduce element columns.  Fixed order.
+__global__ __launch_bounds__(256) void k_line_reduce(const double* __restrict__ stats, double* __restrict__ lines,
+                                                     int nx, int ny, int nc, const int* __restrict__ flag) {
+  __shared__ double red[3][256];
+  if (flag && *flag) return;
+  const int b = blockIdx.x, t = threadIdx.x;
+  const bool row = b < ny;
+  const int len = row ? nx : ny;
+  for (int c = 0; c < nc; ++c) {
+    double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+    for (int k = t; k < len; k += 256) {
+      const long e = row ? (long)b * nx + k : (long)k * nx + (b - ny);
+      const double* st = stats + (e * nc + c) * 3;
+      s += st[0]; mn = fmin(mn, st[1]); mx = fmax(mx, st[2]);
+    }
+    red[0][t] = s; red[1][t] = mn; red[2][t] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) {
+        red[0][t] += red[0][t + w];
+        red[1][t] = fmin(red[1][t], red[1][t + w]);
+        red[2][t] = fmax(red[2][t], red[2][t + w]);
+      }
+      __syncthreads();
+    }
+    if (t == 0) {
+      lines[((long)b * nc + c) * 3 + 0] = red[0][0];
+      lines[((long)b * nc + c) * 3 + 1] = red[1][0];
+      lines[((long)b * nc + c) * 3 + 2] = red[2][0];
+    }
+    __syncthreads();
+  }
+}
+
+// Global reduction of the first `n` line results (the rows) into glob[nc][3].
+__global__ __launch_bounds__(256) void k_global_reduce(const double* __restrict__ lines, double* __restrict__ glob,
+                                                       int n, int nc, const int* __restrict__ flag) {
+  __shared__ double red[3][256];
+  if (flag && *flag) return;
+  const int t = threadIdx.x;
+  for (int c = 0; c < nc; ++c) {
+    double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+    for (int k = t; k < n; k += 256) {
+      const double* st = lines + ((long)k * nc + c) * 3;
+      s += st[0]; mn = fmin(mn, st[1]); mx = fmax(mx, st[2]);
+    }
+    red[0][t] = s; red[1][t] = mn; red[2][t] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) {
+        red[0][t] += red[0][t + w];
+        red[1][t] = fmin(red[1][t], red[1][t + w]);
+        red[2][t] = fmax(red[2][t], red[2][t + w]);
+      }
+      __syncthreads();
+    }
+    if (t == 0) { glob[c * 3] = red[0][0]; glob[c * 3 + 1] = red[1][0]; glob[c * 3 + 2] = red[2][0]; }
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset_attempt(int* flag, unsigned long long* counts) {
+  if (threadIdx.x == 0) { *flag = 0; counts[0] = 0; counts[1] = 0; counts[2] = 0; }
+}
+
+__global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, long n) {
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) b[k] = a[k];
+}
+
+// ---------------------------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------------------------
+#define DISPATCH_P(p, F) \
+  switch (p) { case 1: F(1); break; case 2: F(2); break; case 3: F(3); break; \
+               case 4: F(4); break; case 5: F(5); break; case 6: F(6); break; default: return -4; }
+
+hipEvent_t* timing_slot(mhd25_ctx* c);
+static int eb_of(int p) { return 256 / ((p + 1) * (p + 1)); }
+
+static int check(mhd25_ctx* c, hipError_t e, const char* what) {
+  if (e != hipSuccess) { c->err = std::string(what) + ": " + hipGetErrorString(e); return -2; }
+  return 0;
+}
+
+int hydro_rhs(mhd25_ctx* c, const double* U, double* dU) {
+  const long blocks = (c->mp.K + eb_of(c->p) - 1) / eb_of(c->p);
+#define L0(P) hipLaunchKernelGGL((k_hydro_stage<P, 0>), dim3(blocks), dim3(256), 0, c->stream, U, U, dU, nullptr, \
+                                 nullptr, c->d_ht, c->mp, 0.0, 1.0, 0.0, c->opt.iface_flux)
+  DISPATCH_P(c->p, L0);
+#undef L0
+  return check(c, hipGetLastError(), "rhs_hydro launch");
+}
+
+// raw stage + statistics + line/global reductions
+int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust, double ca, double cb, double tau) {
+  const long blocks = (c->mp.K + eb_of(c->p) - 1) / eb_of(c->p);
+  hipEvent_t* ev = c->timing ? timing_slot(c) : nullptr;
+  if (ev) hipEventRecord(ev[0], c->stream);
+#define L1(P) hipLaunchKernelGGL((k_hydro_stage<P, 1>), dim3(blocks), dim3(256), 0, c->stream, Us, Un, Ust, c->stats, \
+                                 c->d_flag, c->d_ht, c->mp, ca, cb, tau, c->opt.iface_flux)
+  DISPATCH_P(c->p, L1);
+#undef L1
+  if (ev) hipEventRecord(ev[1], c->stream);
+  int r = check(c, hipGetLastError(), "hydro stage launch");
+  if (r) return r;
+  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.nx + c->mp.ny), dim3(256), 0, c->stream, c->stats, c->lines,
+                     c->mp.nx, c->mp.ny, 5, c->d_flag);
+  hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, 5, c->d_flag);
+  return check(c, hipGetLastError(), "reduce launch");
+}
+
+int line_global_reduce(mhd25_ctx* c, const double* stats, int nc, const int* flag) {
+  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.nx + c->mp.ny), dim3(256), 0, c->stream, stats, c->lines,
+                     c->mp.nx, c->mp.ny, nc, flag);
+  hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, nc, flag);
+  return check(c, hipGetLastError(), "reduce launch");
+}
+
+int hydro_stats_only(mhd25_ctx* c, const double* U, int* flag) {
+  const long blocks = (c->mp.K + eb_of(c->p) - 1) / eb_of(c->p);
+#define LS(P) hipLaunchKernelGGL((k_elem_stats<P>), dim3(blocks), dim3(256), 0, c->stream, U, c->stats, flag, c->d_ht, c->mp)
+  DISPATCH_P(c->p, LS);
+#undef LS
+  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.nx + c->mp.ny), dim3(256), 0, c->stream, c->stats, c->lines,
+                     c->mp.nx, c->mp.ny, 5, nullptr);
+  hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, 5, nullptr);
+  return check(c, hipGetLastError(), "stats launch");
+}
+
+int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, const int* flag) {
+  const long blocks = (c->mp.K + eb_of(c->p) - 1) / eb_of(c->p);
+#define LB(P) hipLaunchKernelGGL((k_hydro_oe_pp<P>), dim3(blocks), dim3(256), 0, c->stream, Ust, Uout, c->stats, \
+                                 c->lines, c->glob, c->d_flags, c->d_counts, flag, c->d_ht, c->mp, tau, c->opt.s_H, \
+                                 c->opt.oe_hydro, c->opt.pp)
+  DISPATCH_P(c->p, LB);
+#undef LB
+  return check(c, hipGetLastError(), "stage map launch");
+}
+
+int reset_attempt(mhd25_ctx* c) {
+  hipLaunchKernelGGL(k_reset_attempt, dim3(1), dim3(64), 0, c->stream, c->d_flag, c->d_counts);
+  return check(c, hipGetLastError(), "reset launch");
+}
+
+int dcopy(mhd25_ctx* c, const double* a, double* b, long n) {
+  long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, c->stream, a, b, n);
+  return check(c, hipGetLastError(), "copy launch");
+}

@@ -1,0 +1,987 @@
+// Magnetic-velocity subflow kernels for gfx950 (section "Magnetic--velocity subflow:
+// compatible finite elements").
+//
+// Element-local kernels use one block per tile of EB elements and NT = max((p+1)^2,(m+2)^2)
+// threads per element; element data are staged in LDS.  Loads of shared degrees of freedom
+// are written per element and summed by a per-node gather in a fixed order (no floating-point
+// atomics), then divided by the lumped weights (eq. quad-hcurl-element, eq. quad-cg-element).
+#include <cfloat>
+
+#include "common.h"
+
+namespace {
+
+constexpr double EPSM = 2.220446049250313e-16;
+
+template <int P, int M>
+struct MC {
+  static constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1, AA = A * A, AB = A * B, BB = B * B;
+  static constexpr int NT = NN > AA ? NN : AA;
+  static constexpr int EB = 256 / NT;
+};
+
+__device__ __forceinline__ long wrapl(long a, long n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+// global index of local node (i, j) of element (ex, ey) on a magnetic grid
+__device__ __forceinline__ long gix(const MeshP& mp, int B, long ex, long ey, int i, int j) {
+  const long NX = (long)mp.nx * B, NY = (long)mp.ny * B;
+  long gx = ex * B + i, gy = ey * B + j;
+  if (gx >= NX) gx -= NX;
+  if (gy >= NY) gy -= NY;
+  return gy * NX + gx;
+}
+
+template <int P, int M>
+__device__ __forceinline__ void load_B(double* bx, double* by, double* bz, const double* __restrict__ Bx,
+                                       const double* __restrict__ By, const double* __restrict__ Bz, const MeshP& mp,
+                                       long ex, long ey, int t) {
+  using C = MC<P, M>;
+  for (int k = t; k < C::AB; k += C::NT) {
+    bx[k] = Bx[gix(mp, C::B, ex, ey, k % C::A, k / C::A)];  // [j<B][i<A]
+    by[k] = By[gix(mp, C::B, ex, ey, k % C::B, k / C::B)];  // [j<A][i<B]
+  }
+  for (int k = t; k < C::BB; k += C::NT) bz[k] = Bz[gix(mp, C::B, ex, ey, k % C::B, k / C::B)];
+}
+
+// ---------------------------------------------------------------------------------------------
+// Current loads (eq. mag-current-proj): W part int B_x d_y phi - B_y d_x phi with the (m+2)-point
+// Gauss rule; N parts int B_z (-d_y psi) and int B_z d_x psi with the (m+1)-point rule.
+// ---------------------------------------------------------------------------------------------
+template <int P, int M>
+__global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, const double* __restrict__ By,
+                                                 const double* __restrict__ Bz, double* __restrict__ Lx,
+                                                 double* __restrict__ Ly, double* __restrict__ Lz,
+                                                 const MagTab* __restrict__ T, MeshP mp) {
+  using C = MC<P, M>;
+  constexpr int A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB, NT = C::NT;
+  __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB], swx[EB][AA], swy[EB][AA], szg[EB][BB];
+  const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = el < EB && e < mp.K;
+  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  if (act) load_B<P, M>(sbx[el], sby[el], sbz[el], Bx, By, Bz, mp, ex, ey, t);
+  __syncthreads();
+  if (act && t < AA) {
+    const int qx = t % A, qy = t / A;
+    double bxq = 0.0, byq = 0.0;
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < A; ++i) s += T->I_W_Q[qx][i] * sbx[el][j * A + i];
+      bxq += T->I_G_Q[qy][j] * s;
+    }
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) s += T->I_G_Q[qx][i] * sby[el][j * B + i];
+      byq += T->I_W_Q[qy][j] * s;
+    }
+    const double wgt = mp.J * T->wq[qx] * T->wq[qy];
+    swx[el][t] = wgt * bxq;
+    swy[el][t] = wgt * byq;
+  }
+  if (act && t < BB) {
+    const int gx = t % B, gy = t / B;
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) s += T->I_V_G[gx][i] * sbz[el][j * B + i];
+      v += T->I_V_G[gy][j] * s;
+    }
+    szg[el][t] = v;
+  }
+  __syncthreads();
+  if (!act) return;
+  if (t < AA) {
+    const int i = t % A, j = t / A;
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int qy = 0; qy < A; ++qy)
+#pragma unroll
+      for (int qx = 0; qx < A; ++qx) {
+        sx += swx[el][qy * A + qx] * (T->I_W_Q[qx][i] * T->D_W_Q[qy][j]);
+        sy += swy[el][qy * A + qx] * (T->D_W_Q[qx][i] * T->I_W_Q[qy][j]);
+      }
+    Lz[e * AA + t] = (2.0 / mp.hy) * sx - (2.0 / mp.hx) * sy;
+  }
+  if (t < AB) {
+    {  // N_x node: i Gauss (B), j GLL (A); index j*B + i
+      const int i = t % B, j = t / B;
+      double s = 0.0;
+#pragma unroll
+      for (int qy = 0; qy < B; ++qy) s += T->wg[qy] * szg[el][qy * B + i] * T->D_W_G[qy][j];
+      Lx[e * AB + t] = -(2.0 / mp.hy) * mp.J * T->wg[i] * s;
+    }
+    {  // N_y node: i GLL (A), j Gauss (B); index j*A + i
+      const int i = t % A, j = t / A;
+      double s = 0.0;
+#pragma unroll
+      for (int qx = 0; qx < B; ++qx) s += T->wg[qx] * szg[el][j * B + qx] * T->D_W_G[qx][i];
+      Ly[e * AB + t] = (2.0 / mp.hx) * mp.J * T->wg[j] * s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Electric-field loads (eq. mag-electric-proj): w_a (-u x B)|_K at the element's own auxiliary
+// nodes, plus eta_K sum_q M_q J(x_q) . phi_a(x_q) by the degree-p GLL rule.
+// ---------------------------------------------------------------------------------------------
+template <int P, int M>
+__global__ __launch_bounds__(256) void k_E_loads(const double* __restrict__ u, const double* __restrict__ Bx,
+                                                 const double* __restrict__ By, const double* __restrict__ Bz,
+                                                 const double* __restrict__ Jx, const double* __restrict__ Jy,
+                                                 const double* __restrict__ Jz, const double* __restrict__ eta,
+                                                 double* __restrict__ Lx, double* __restrict__ Ly,
+                                                 double* __restrict__ Lz, const MagTab* __restrict__ T, MeshP mp) {
+  using C = MC<P, M>;
+  constexpr int NP = C::NP, NN = C::NN, A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB,
+                NT = C::NT;
+  __shared__ double su[EB][3][NN], sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
+  __shared__ double sjx[EB][AB], sjy[EB][AB], sjz[EB][AA], swj[EB][3][NN];
+  const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = el < EB && e < mp.K;
+  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  const long KN = mp.K * NN;
+  const double et = (act && eta) ? eta[e] : 0.0;
+  if (act) {
+    for (int k = t; k < NN; k += NT)
+      for (int d = 0; d < 3; ++d) su[el][d][k] = u[d * KN + e * NN + k];
+    load_B<P, M>(sbx[el], sby[el], sbz[el], Bx, By, Bz, mp, ex, ey, t);
+    if (et != 0.0) {
+      for (int k = t; k < AB; k += NT) {
+        sjx[el][k] = Jx[gix(mp, B, ex, ey, k % B, k / B)];
+        sjy[el][k] = Jy[gix(mp, B, ex, ey, k % A, k / A)];
+      }
+      for (int k = t; k < AA; k += NT) sjz[el][k] = Jz[gix(mp, B, ex, ey, k % A, k / A)];
+    }
+  }
+  __syncthreads();
+  if (act && et != 0.0 && t < NN) {
+    const int qi = t % NP, qj = t / NP;
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) s += T->I_G_P[qi][i] * sjx[el][j * B + i];
+      jx += T->I_W_P[qj][j] * s;
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sjy[el][j * A + i];
+      jy += T->I_G_P[qj][j] * s;
+    }
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sjz[el][j * A + i];
+      jz += T->I_W_P[qj][j] * s;
+    }
+    const double w = et * mp.J * T->wp[qi] * T->wp[qj];
+    swj[el][0][t] = w * jx; swj[el][1][t] = w * jy; swj[el][2][t] = w * jz;
+  }
+  __syncthreads();
+  if (!act) return;
+  auto u_at = [&](int d, const double (*Ix)[MHD_MAXN], int ai, const double (*Iy)[MHD_MAXN], int aj) {
+    double v = 0.0;
+#pragma unroll
+    for (int qj = 0; qj < NP; ++qj) {
+      double s = 0.0;
+#pragma unroll
+      for (int qi = 0; qi < NP; ++qi) s += Ix[ai][qi] * su[el][d][qj * NP + qi];
+      v += Iy[aj][qj] * s;
+    }
+    return v;
+  };
+  auto eta_term = [&](int c, const double (*Px)[MHD_MAXN], int ai, const double (*Py)[MHD_MAXN], int aj) {
+    double v = 0.0;
+#pragma unroll
+    for (int qj = 0; qj < NP; ++qj)
+#pragma unroll
+      for (int qi = 0; qi < NP; ++qi) v += swj[el][c][qj * NP + qi] * (Px[qi][ai] * Py[qj][aj]);
+    return v;
+  };
+  if (t < AA) {  // W node (xw[i], xw[j]): z-component
+    const int i = t % A, j = t / A;
+    const double ux = u_at(0, T->I_P_W, i, T->I_P_W, j), uy = u_at(1, T->I_P_W, i, T->I_P_W, j);
+    double bxv = 0.0, byv = 0.0;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      bxv += T->I_G_W[j][k] * sbx[el][k * A + i];
+      byv += T->I_G_W[i][k] * sby[el][j * B + k];
+    }
+    double s = mp.J * T->ww[i] * T->ww[j] * (-(ux * byv - uy * bxv));
+    if (et != 0.0) s += eta_term(2, T->I_W_P, i, T->I_W_P, j);
+    Lz[e * AA + t] = s;
+  }
+  if (t < AB) {
+    {  // N_x node (xg[i], xw[j]): x-component; B_y lives on these nodes
+      const int i = t % B, j = t / B;
+      const double uy = u_at(1, T->I_P_G, i, T->I_P_W, j), uz = u_at(2, T->I_P_G, i, T->I_P_W, j);
+      const double byv = sby[el][t];
+      double bzv = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < B; ++jj) {
+        double s = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < B; ++ii) s += T->I_V_G[i][ii] * sbz[el][jj * B + ii];
+        bzv += T->I_V_W[j][jj] * s;
+      }
+      double s = mp.J * T->wg[i] * T->ww[j] * (-(uy * bzv - uz * byv));
+      if (et != 0.0) s += eta_term(0, T->I_G_P, i, T->I_W_P, j);
+      Lx[e * AB + t] = s;
+    }
+    {  // N_y node (xw[i], xg[j]): y-component; B_x lives on these nodes
+      const int i = t % A, j = t / A;
+      const double ux = u_at(0, T->I_P_W, i, T->I_P_G, j), uz = u_at(2, T->I_P_W, i, T->I_P_G, j);
+      const double bxv = sbx[el][t];
+      double bzv = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < B; ++jj) {
+        double s = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < B; ++ii) s += T->I_V_W[i][ii] * sbz[el][jj * B + ii];
+        bzv += T->I_V_G[j][jj] * s;
+      }
+      double s = mp.J * T->ww[i] * T->wg[j] * (-(uz * bxv - ux * bzv));
+      if (et != 0.0) s += eta_term(1, T->I_W_P, i, T->I_G_P, j);
+      Ly[e * AB + t] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Curl update, Lorentz transpose and Ohmic heating (eq. magnetic-dae with J, E eliminated).
+// MODE 0: write L_M.  MODE 1: write the SSP stage ca*Y^n + cb*(Y_s + tau*L_M(Y_s)).
+// ---------------------------------------------------------------------------------------------
+
+template <int P, int M, int MODE>
+__global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __restrict__ T, MeshP mp) {
+  using C = MC<P, M>;
+  constexpr int NP = C::NP, NN = C::NN, A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB,
+                NT = C::NT;
+  __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
+  __shared__ double sex[EB][AB], sey[EB][AB], sez[EB][AA];
+  __shared__ double sjx[EB][AB], sjy[EB][AB], sjz[EB][AA];
+  __shared__ double fz[EB][2][AA], fx[EB][2][AB], fy[EB][2][AB];
+  const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = el < EB && e < mp.K;
+  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  const long KN = mp.K * NN;
+  if (act) {
+    load_B<P, M>(sbx[el], sby[el], sbz[el], io.bxs, io.bys, io.bzs, mp, ex, ey, t);
+    for (int k = t; k < AB; k += NT) {
+      const long gN_x = gix(mp, B, ex, ey, k % B, k / B), gN_y = gix(mp, B, ex, ey, k % A, k / A);
+      sex[el][k] = io.ex[gN_x]; sjx[el][k] = io.jx[gN_x];
+      sey[el][k] = io.ey[gN_y]; sjy[el][k] = io.jy[gN_y];
+    }
+    for (int k = t; k < AA; k += NT) {
+      const long g = gix(mp, B, ex, ey, k % A, k / A);
+      sez[el][k] = io.ez[g]; sjz[el][k] = io.jz[g];
+    }
+  }
+  __syncthreads();
+  if (act && t < BB) {  // strong curl at the element's owned B nodes
+    const int i = t % B, j = t / B;
+    const long g = gix(mp, B, ex, ey, i, j);
+    double dbx = 0.0, dby = 0.0;
+#pragma unroll
+    for (int k = 0; k < A; ++k) {
+      dbx += T->D_W_G[j][k] * sez[el][k * A + i];
+      dby += T->D_W_G[i][k] * sez[el][j * A + k];
+    }
+    dbx *= -(2.0 / mp.hy);
+    dby *= (2.0 / mp.hx);
+    double dxey = 0.0, dyex = 0.0;
+#pragma unroll
+    for (int l = 0; l < B; ++l) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < A; ++k) s += T->D_W_V[i][k] * sey[el][l * A + k];
+      dxey += T->I_G_V[j][l] * s;
+    }
+#pragma unroll
+    for (int l = 0; l < A; ++l) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < B; ++k) s += T->I_G_V[i][k] * sex[el][l * B + k];
+      dyex += T->D_W_V[j][l] * s;
+    }
+    const double dbz = -((2.0 / mp.hx) * dxey - (2.0 / mp.hy) * dyex);
+    if (MODE == 0) {
+      io.obx[g] = dbx; io.oby[g] = dby; io.obz[g] = dbz;
+    } else {
+      io.obx[g] = io.ca * io.bxn[g] + io.cb * (io.bxs[g] + io.tau * dbx);
+      io.oby[g] = io.ca * io.byn[g] + io.cb * (io.bys[g] + io.tau * dby);
+      io.obz[g] = io.ca * io.bzn[g] + io.cb * (io.bzs[g] + io.tau * dbz);
+    }
+  }
+  // weighted Lorentz loads f_a at the auxiliary nodes (transpose of the coupling form)
+  if (act && t < AA) {
+    const int i = t % A, j = t / A;
+    double bxv = 0.0, byv = 0.0;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      bxv += T->I_G_W[j][k] * sbx[el][k * A + i];
+      byv += T->I_G_W[i][k] * sby[el][j * B + k];
+    }
+    const double w = mp.J * T->ww[i] * T->ww[j] * sjz[el][t];
+    fz[el][0][t] = -byv * w;  // x
+    fz[el][1][t] = bxv * w;   // y
+  }
+  if (act && t < AB) {
+    {
+      const int i = t % B, j = t / B;  // N_x node: (0, -B_z J_x, B_y J_x)
+      double bzv = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < B; ++jj) {
+        double s = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < B; ++ii) s += T->I_V_G[i][ii] * sbz[el][jj * B + ii];
+        bzv += T->I_V_W[j][jj] * s;
+      }
+      const double w = mp.J * T->wg[i] * T->ww[j] * sjx[el][t];
+      fx[el][0][t] = -bzv * w;          // y
+      fx[el][1][t] = sby[el][t] * w;    // z
+    }
+    {
+      const int i = t % A, j = t / A;  // N_y node: (B_z J_y, 0, -B_x J_y)
+      double bzv = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < B; ++jj) {
+        double s = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < B; ++ii) s += T->I_V_W[i][ii] * sbz[el][jj * B + ii];
+        bzv += T->I_V_G[j][jj] * s;
+      }
+      const double w = mp.J * T->ww[i] * T->wg[j] * sjy[el][t];
+      fy[el][0][t] = bzv * w;           // x
+      fy[el][1][t] = -sbx[el][t] * w;   // z
+    }
+  }
+  __syncthreads();
+  if (!act || t >= NN) return;
+  const int qi = t % NP, qj = t / NP;
+  double du[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < A; ++j)
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+      const double I = T->I_P_W[i][qi] * T->I_P_W[j][qj];
+      du[0] += I * fz[el][0][j * A + i];
+      du[1] += I * fz[el][1][j * A + i];
+    }
+#pragma unroll
+  for (int j = 0; j < A; ++j)
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      const double I = T->I_P_G[i][qi] * T->I_P_W[j][qj];
+      du[1] += I * fx[el][0][j * B + i];
+      du[2] += I * fx[el][1][j * B + i];
+    }
+#pragma unroll
+  for (int j = 0; j < B; ++j)
+#pragma unroll
+    for (int i = 0; i < A; ++i) {
+      const double I = T->I_P_W[i][qi] * T->I_P_G[j][qj];
+      du[0] += I * fy[el][0][j * A + i];
+      du[2] += I * fy[el][1][j * A + i];
+    }
+  const long n = e * NN + t;
+  const double rq = io.rho[n];
+  const double Mq = mp.J * T->wp[qi] * T->wp[qj];
+  const double et = io.eta ? io.eta[e] : 0.0;
+  double de = 0.0;
+  if (et != 0.0) {
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) s += T->I_G_P[qi][i] * sjx[el][j * B + i];
+      jx += T->I_W_P[qj][j] * s;
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sjy[el][j * A + i];
+      jy += T->I_G_P[qj][j] * s;
+    }
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sjz[el][j * A + i];
+      jz += T->I_W_P[qj][j] * s;
+    }
+    de = et * (jx * jx + jy * jy + jz * jz) / rq;
+  }
+  if (MODE == 0) {
+    for (int d = 0; d < 3; ++d) io.ou[d * KN + n] = du[d] / (rq * Mq);
+    io.oe[n] = de;
+  } else {
+    for (int d = 0; d < 3; ++d)
+      io.ou[d * KN + n] = io.ca * io.un[d * KN + n] + io.cb * (io.us[d * KN + n] + io.tau * (du[d] / (rq * Mq)));
+    io.oe[n] = io.ca * io.en[n] + io.cb * (io.es[n] + io.tau * de);
+  }
+}
+
+// per-element statistics of NC nodal fields [NC][K][NN] -> [K][NC][3] (GLL-weighted sum, min, max)
+template <int P, int NC>
+__global__ __launch_bounds__(256) void k_field_stats(const double* __restrict__ f, double* __restrict__ stats,
+                                                     const MagTab* __restrict__ T, MeshP mp) {
+  constexpr int NP = P + 1, NN = NP * NP, EB = 256 / NN;
+  __shared__ double sv[NC][EB * NN];
+  const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = el < EB && e < mp.K;
+  const long KN = mp.K * NN;
+  if (act)
+    for (int c = 0; c < NC; ++c) sv[c][tid] = f[c * KN + e * NN + q];
+  __syncthreads();
+  for (int tk = q; act && tk < NC * 3; tk += NN) {
+    const int c = tk / 3, kind = tk - 3 * c;
+    double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+    for (int k = 0; k < NN; ++k) {
+      const double v = sv[c][el * NN + k];
+      s += (T->wp[k % NP] * T->wp[k / NP]) * v;
+      mn = fmin(mn, v); mx = fmax(mx, v);
+    }
+    stats[(e * NC + c) * 3 + kind] = kind == 0 ? s : (kind == 1 ? mn : mx);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Velocity OE (eq. magnetic-oe-sensor .. eq. magnetic-oe-map).  The rho-weighted projections use
+// the shell-ordered tensor Legendre basis orthonormalised by a Cholesky factor of its Gram
+// matrix (computed in LDS), so increments of shell l are sums over that shell's modes.
+// ---------------------------------------------------------------------------------------------
+template <int P, int M>
+struct VC {
+  static constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1;
+  static constexpr int PER = NN * (NN + 1) + 13 * NN + 3 * NP + 2 * A * B + B * B;  // LDS doubles per element
+  static constexpr int EB0 = 256 / NN, EBL = (64 * 1024) / (8 * PER);
+  static constexpr int EB = EB0 < EBL ? EB0 : (EBL > 0 ? EBL : 1);
+};
+
+template <int P, int M>
+__global__ __launch_bounds__(256) void k_vel_oe(const double* __restrict__ rho, double* __restrict__ u,
+                                                double* __restrict__ en, const double* __restrict__ Bx,
+                                                const double* __restrict__ By, const double* __restrict__ Bz,
+                                                const double* __restrict__ lines, const double* __restrict__ glob,
+                                                const HydroTab* __restrict__ H, const MagTab* __restrict__ T,
+                                                MeshP mp, double tau, double sM) {
+  constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1, AB = A * B, BB = B * B;
+  constexpr int EB = VC<P, M>::EB;
+  __shared__ double su[EB][3][NN], sw[EB][NN], sG[EB][NN][NN + 1];
+  __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
+  __shared__ double sjmp[EB][6][NN], ssig[EB][2][NP], sD[EB][NP], sva[EB][2][NN], sc[EB][NN];
+  const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
+  const int qi = q % NP, qj = q / NP;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = el < EB && e < mp.K;
+  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  const long KN = mp.K * NN;
+  double uu[3] = {0.0, 0.0, 0.0}, rq = 1.0;
+  if (act) {
+    for (int d = 0; d < 3; ++d) { uu[d] = u[d * KN + e * NN + q]; su[el][d][q] = uu[d]; }
+    rq = rho[e * NN + q];
+    sw[el][q] = mp.J * H->w[qi] * H->w[qj] * rq;
+    // B at GLL_p nodes: element locals
+    for (int k = q; k < AB; k += NN) {
+      sbx[el][k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];
+      sby[el][k] = By[gix(mp, B, ex, ey, k % B, k / B)];
+    }
+    for (int k = q; k < BB; k += NN) sbz[el][k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
+  }
+  __syncthreads();
+  // amplitudes of u components
+  double Dsh[2] = {0.0, 0.0};
+  bool cst[3] = {false, false, false};
+  if (act) {
+    for (int c = 0; c < 3; ++c) {
+      const double gs = glob[c * 3], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
+      const double gm = gs / (4.0 * (double)mp.K);
+      const double dOm = fmax(gmx - gm, gm - gmn);
+      cst[c] = dOm <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn));
+      const double* rl = lines + (ey * 3 + c) * 3;
+      const double* cl = lines + ((mp.ny + ex) * 3 + c) * 3;
+      const double rm = rl[0] / (4.0 * mp.nx), cm = cl[0] / (4.0 * mp.ny);
+      Dsh[0] = fmax(Dsh[0], fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm));
+      Dsh[1] = fmax(Dsh[1], fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm));
+    }
+    // rate: |u_I| + |B|/sqrt(rho) at this node
+    double bxv = 0.0, byv = 0.0, bzv = 0.0;
+    for (int j = 0; j < B; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sbx[el][j * A + i];
+      bxv += T->I_G_P[qj][j] * s;
+    }
+    for (int j = 0; j < A; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < B; ++i) s += T->I_G_P[qi][i] * sby[el][j * B + i];
+      byv += T->I_W_P[qj][j] * s;
+    }
+    for (int j = 0; j < B; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < B; ++i) s += T->I_V_P[qi][i] * sbz[el][j * B + i];
+      bzv += T->I_V_P[qj][j] * s;
+    }
+    const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) / sqrt(rq);
+    sva[el][0][q] = fabs(uu[0]) + va;
+    sva[el][1][q] = fabs(uu[1]) + va;
+  }
+  for (int D = 0; D < 2; ++D) {
+    const int r = D == 0 ? qi : qj, line = D == 0 ? qj : qi;
+    if (act) {
+      long em, ep;
+      if (D == 0) { em = ey * mp.nx + wrapl(ex - 1, mp.nx); ep = ey * mp.nx + wrapl(ex + 1, mp.nx); }
+      else { em = wrapl(ey - 1, mp.ny) * mp.nx + ex; ep = wrapl(ey + 1, mp.ny) * mp.nx + ex; }
+      const double wl = 0.5 * H->w[line];
+      for (int c = 0; c < 3; ++c) {
+        double a = 0.0, d = 0.0, b = 0.0, cc = 0.0;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          const int nk = D == 0 ? line * NP + k : k * NP + line;
+          const double own = su[el][c][nk];
+          a += H->Dr0[r][k] * own;
+          d += H->Drp[r][k] * own;
+          b += H->Drp[r][k] * u[c * KN + em * NN + nk];
+          cc += H->Dr0[r][k] * u[c * KN + ep * NN + nk];
+        }
+        const double jm = a - b, jp = cc - d;
+        sjmp[el][2 * c][q] = wl * jm * jm;
+        sjmp[el][2 * c + 1][q] = wl * jp * jp;
+      }
+    }
+    __syncthreads();
+    if (act && q < NP) {
+      double sig = 0.0;
+      if (Dsh[D] > 0.0) {
+        for (int c = 0; c < 3; ++c) {
+          if (cst[c]) continue;
+          double sm = 0.0, spp = 0.0;
+          for (int l = 0; l < NP; ++l) {
+            const int nk = D == 0 ? l * NP + q : q * NP + l;
+            sm += sjmp[el][2 * c][nk];
+            spp += sjmp[el][2 * c + 1][nk];
+          }
+          sig = fmax(sig, H->fr[q] * (sqrt(sm) + sqrt(spp)) / Dsh[D]);
+        }
+      }
+      ssig[el][D][q] = sig;
+    }
+    __syncthreads();
+  }
+  if (act && q <= P) {
+    if (q == 0) {
+      sD[el][0] = 1.0;
+    } else {
+      double ax = 0.0, ay = 0.0;
+      for (int k = 0; k < NN; ++k) { ax = fmax(ax, sva[el][0][k]); ay = fmax(ay, sva[el][1][k]); }
+      const double lx = (2.0 * P + 1.0) / mp.hx * ax, ly = (2.0 * P + 1.0) / mp.hy * ay;
+      double sx = 0.0, sy = 0.0;
+      for (int r = 0; r <= q; ++r) { sx += ssig[el][0][r]; sy += ssig[el][1][r]; }
+      sD[el][q] = exp(-sM * tau * (lx * sx + ly * sy));
+    }
+  }
+  // Gram matrix of the shell-ordered basis in the rho-weighted product: row q of the element
+  if (act) {
+    const int ka = H->ka[q], kb = H->kb[q];
+    for (int k2 = 0; k2 <= q; ++k2) {
+      const int a2 = H->ka[k2], b2 = H->kb[k2];
+      double s = 0.0;
+      for (int n = 0; n < NN; ++n) {
+        const int ni = n % NP, nj = n / NP;
+        s += sw[el][n] * (H->V[ni][ka] * H->V[nj][kb]) * (H->V[ni][a2] * H->V[nj][b2]);
+      }
+      sG[el][q][k2] = s;
+    }
+  }
+  __syncthreads();
+  // Cholesky G = L L^T in place (lower triangle), two barriers per column
+  for (int k = 0; k < NN; ++k) {
+    if (act && q > k) sG[el][q][k] /= sqrt(sG[el][k][k]);
+    __syncthreads();
+    if (act) {
+      if (q == k) sG[el][k][k] = sqrt(sG[el][k][k]);
+      else if (q > k)
+        for (int jj = k + 1; jj <= q; ++jj) sG[el][q][jj] -= sG[el][q][k] * sG[el][jj][k];
+    }
+    __syncthreads();
+  }
+  // Psi[q][k] = psi_k(x_q), psi = phi L^{-T}: forward substitution for the thread's node
+  double psi[NN];
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    double s = act ? H->V[qi][H->ka[k]] * H->V[qj][H->kb[k]] : 0.0;
+#pragma unroll
+    for (int k2 = 0; k2 < k; ++k2) s -= (act ? sG[el][k][k2] : 0.0) * psi[k2];
+    psi[k] = act ? s / sG[el][k][k] : 0.0;
+  }
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int k = 0; k < NN; ++k) sG[el][q][k] = psi[k];
+  __syncthreads();
+  double up[3], heat = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    if (act) {  // c_k = (u_d, psi_k)_rho for k = q
+      double s = 0.0;
+      for (int n = 0; n < NN; ++n) s += sw[el][n] * su[el][d][n] * sG[el][n][q];
+      sc[el][q] = s;
+    }
+    __syncthreads();
+    double wl[NP];
+#pragma unroll
+    for (int l = 0; l < NP; ++l) wl[l] = 0.0;
+    if (act) {
+#pragma unroll
+      for (int k = 0; k < NN; ++k) wl[H->ksh[k]] += sc[el][k] * psi[k];
+    }
+    double v = wl[0];
+#pragma unroll
+    for (int l = 1; l < NP; ++l) {
+      const double Dl = act ? sD[el][l] : 1.0;
+      v += Dl * wl[l];
+      heat += 0.5 * (1.0 - Dl * Dl) * wl[l] * wl[l];
+    }
+    up[d] = v;
+    __syncthreads();
+  }
+  if (act) {
+    for (int d = 0; d < 3; ++d) u[d * KN + e * NN + q] = up[d];
+    en[e * NN + q] += heat;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Artificial resistivity (eq. magnetic-ar-sensor, eq. magnetic-ar-coefficient); one thread per element.
+// bglob[3][3]: (integral, min, max) of B_x, B_y, B_z over the domain.
+// ---------------------------------------------------------------------------------------------
+template <int P, int M>
+__global__ __launch_bounds__(128) void k_ar_eta(const double* __restrict__ rho, const double* __restrict__ u,
+                                                const double* __restrict__ Bx, const double* __restrict__ By,
+                                                const double* __restrict__ Bz, const double* __restrict__ bglob,
+                                                double* __restrict__ eta, const MagTab* __restrict__ T, MeshP mp,
+                                                double Cs, double Ceta) {
+  constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp.K) return;
+  const long ex = e % mp.nx, ey = e / mp.nx;
+  double dOm[3];
+  bool cf[3];
+  const double area = (double)mp.K * mp.hx * mp.hy;
+  for (int c = 0; c < 3; ++c) {
+    const double mean = bglob[c * 3] / area, mn = bglob[c * 3 + 1], mx = bglob[c * 3 + 2];
+    dOm[c] = fmax(mx - mean, mean - mn);
+    cf[c] = dOm[c] <= 1024.0 * EPSM * fmax(fabs(mx), fabs(mn));
+  }
+  double R[2];
+  for (int dir = 0; dir < 2; ++dir) {
+    const int t0 = dir == 0 ? 1 : 0;
+    const double DB = fmax(cf[t0] ? 0.0 : dOm[t0], cf[2] ? 0.0 : dOm[2]);
+    double sig = 0.0;
+    if (DB > 0.0) {
+      const long em = dir == 0 ? ey * mp.nx + wrapl(ex - 1, mp.nx) : wrapl(ey - 1, mp.ny) * mp.nx + ex;
+      const long ep = dir == 0 ? ey * mp.nx + wrapl(ex + 1, mp.nx) : wrapl(ey + 1, mp.ny) * mp.nx + ex;
+      const int tcs[2] = {t0, 2};
+      for (int it = 0; it < 2; ++it) {
+        const int tc = tcs[it];
+        if (cf[tc]) continue;
+        // trace of component tc of element `el` on its side s (0: -1, 1: +1) at face Gauss point k
+        auto trace = [&](long el, int s, int k) {
+          const long exl = el % mp.nx, eyl = el / mp.nx;
+          double v = 0.0;
+          if (tc == 2) {  // B_z: GLL_m x GLL_m
+            for (int j = 0; j < B; ++j)
+              for (int i = 0; i < B; ++i) {
+                const double wgt = dir == 0 ? T->I_V_E[s][i] * T->I_V_Q[k][j] : T->I_V_Q[k][i] * T->I_V_E[s][j];
+                v += wgt * Bz[gix(mp, B, exl, eyl, i, j)];
+              }
+          } else if (dir == 0) {  // B_y on x-faces: Gauss_m in x, GLL_{m+1} in y
+            for (int j = 0; j < A; ++j)
+              for (int i = 0; i < B; ++i) v += T->I_G_E[s][i] * T->I_W_Q[k][j] * By[gix(mp, B, exl, eyl, i, j)];
+          } else {  // B_x on y-faces: GLL_{m+1} in x, Gauss_m in y
+            for (int j = 0; j < B; ++j)
+              for (int i = 0; i < A; ++i) v += T->I_W_Q[k][i] * T->I_G_E[s][j] * Bx[gix(mp, B, exl, eyl, i, j)];
+          }
+          return v;
+        };
+        double sm = 0.0, sp = 0.0;
+        for (int k = 0; k < A; ++k) {
+          const double jm = trace(e, 0, k) - trace(em, 1, k);
+          const double jp = trace(ep, 0, k) - trace(e, 1, k);
+          sm += 0.5 * T->wq[k] * jm * jm;
+          sp += 0.5 * T->wq[k] * jp * jp;
+        }
+        sig = fmax(sig, (sqrt(sm) + sqrt(sp)) / (2.0 * DB));
+      }
+    }
+    R[dir] = fmin(Cs * sig, 1.0);
+  }
+  const long KN = mp.K * NN;
+  double ax = 0.0, ay = 0.0;
+  for (int qj = 0; qj < NP; ++qj)
+    for (int qi = 0; qi < NP; ++qi) {
+      double bxv = 0.0, byv = 0.0, bzv = 0.0;
+      for (int j = 0; j < B; ++j)
+        for (int i = 0; i < A; ++i) bxv += T->I_W_P[qi][i] * T->I_G_P[qj][j] * Bx[gix(mp, B, ex, ey, i, j)];
+      for (int j = 0; j < A; ++j)
+        for (int i = 0; i < B; ++i) byv += T->I_G_P[qi][i] * T->I_W_P[qj][j] * By[gix(mp, B, ex, ey, i, j)];
+      for (int j = 0; j < B; ++j)
+        for (int i = 0; i < B; ++i) bzv += T->I_V_P[qi][i] * T->I_V_P[qj][j] * Bz[gix(mp, B, ex, ey, i, j)];
+      const int q = qj * NP + qi;
+      const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) / sqrt(rho[e * NN + q]);
+      ax = fmax(ax, fabs(u[e * NN + q]) + va);
+      ay = fmax(ay, fabs(u[KN + e * NN + q]) + va);
+    }
+  const double v0 = mp.hx / (2.0 * P + 1.0) * ax * R[0];
+  const double v1 = mp.hy / (2.0 * P + 1.0) * ay * R[1];
+  eta[e] = Ceta * fmax(v0, v1);
+}
+
+// per-element exact integral and owned-node min / max of each B component -> [K][3][3]
+template <int M>
+__global__ __launch_bounds__(256) void k_B_stats(const double* __restrict__ Bx, const double* __restrict__ By,
+                                                 const double* __restrict__ Bz, double* __restrict__ stats,
+                                                 const MagTab* __restrict__ T, MeshP mp) {
+  constexpr int A = M + 2, B = M + 1;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp.K) return;
+  const long ex = e % mp.nx, ey = e / mp.nx;
+  double s[3] = {0, 0, 0}, mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+  for (int j = 0; j < B; ++j)
+    for (int i = 0; i < A; ++i) {
+      const double v = Bx[gix(mp, B, ex, ey, i, j)];
+      s[0] += T->ww[i] * T->wg[j] * v;
+      if (i < B) { mn[0] = fmin(mn[0], v); mx[0] = fmax(mx[0], v); }
+    }
+  for (int j = 0; j < A; ++j)
+    for (int i = 0; i < B; ++i) {
+      const double v = By[gix(mp, B, ex, ey, i, j)];
+      s[1] += T->wg[i] * T->ww[j] * v;
+      if (j < B) { mn[1] = fmin(mn[1], v); mx[1] = fmax(mx[1], v); }
+    }
+  for (int j = 0; j < B; ++j)
+    for (int i = 0; i < B; ++i) {
+      const double v = Bz[gix(mp, B, ex, ey, i, j)];
+      s[2] += T->wv[i] * T->wv[j] * v;
+      mn[2] = fmin(mn[2], v); mx[2] = fmax(mx[2], v);
+    }
+  for (int c = 0; c < 3; ++c) {
+    stats[(e * 3 + c) * 3] = mp.J * s[c];
+    stats[(e * 3 + c) * 3 + 1] = mn[c];
+    stats[(e * 3 + c) * 3 + 2] = mx[c];
+  }
+}
+
+}  // namespace
+
+// gather of per-element loads at shared nodes and division by the lumped weights
+template <int M>
+__global__ __launch_bounds__(256) void k_gather(const double* __restrict__ Lx, const double* __restrict__ Ly,
+                                                const double* __restrict__ Lz, double* __restrict__ Ox,
+                                                double* __restrict__ Oy, double* __restrict__ Oz,
+                                                const MagTab* __restrict__ T, MeshP mp) {
+  constexpr int A = M + 2, B = M + 1, AA = A * A, AB = A * B;
+  const long NX = (long)mp.nx * B, G = NX * mp.ny * B;
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const long gy = g / NX, gx = g - gy * NX;
+  const long ex = gx / B, ey = gy / B;
+  const int i = gx - ex * B, j = gy - ey * B;
+  const long e = ey * mp.nx + ex;
+  const long eL = ey * mp.nx + wrapl(ex - 1, mp.nx), eD = wrapl(ey - 1, mp.ny) * mp.nx + ex;
+  const long eLD = wrapl(ey - 1, mp.ny) * mp.nx + wrapl(ex - 1, mp.nx);
+  {  // W node
+    double s = Lz[e * AA + j * A + i], w = T->ww[i] * T->ww[j];
+    if (i == 0) { s += Lz[eL * AA + j * A + (A - 1)]; w += T->ww[A - 1] * T->ww[j]; }
+    if (j == 0) { s += Lz[eD * AA + (A - 1) * A + i]; w += T->ww[i] * T->ww[A - 1]; }
+    if (i == 0 && j == 0) { s += Lz[eLD * AA + (A - 1) * A + (A - 1)]; w += T->ww[A - 1] * T->ww[A - 1]; }
+    Oz[g] = s / (mp.J * w);
+  }
+  {  // N_x node: Gauss in x (i), GLL in y (j); local index j*B + i
+    double s = Lx[e * AB + j * B + i], w = T->wg[i] * T->ww[j];
+    if (j == 0) { s += Lx[eD * AB + (A - 1) * B + i]; w += T->wg[i] * T->ww[A - 1]; }
+    Ox[g] = s / (mp.J * w);
+  }
+  {  // N_y node: GLL in x (i), Gauss in y (j); local index j*A + i
+    double s = Ly[e * AB + j * A + i], w = T->ww[i] * T->wg[j];
+    if (i == 0) { s += Ly[eL * AB + j * A + (A - 1)]; w += T->ww[A - 1] * T->wg[j]; }
+    Oy[g] = s / (mp.J * w);
+  }
+}
+
+__global__ void k_to_primitive(const double* __restrict__ U, double* __restrict__ rho, double* __restrict__ e,
+                               double* __restrict__ u, long n) {
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    const double r = U[k], ux = U[n + k] / r, uy = U[2 * n + k] / r, uz = U[3 * n + k] / r;
+    rho[k] = r; u[k] = ux; u[n + k] = uy; u[2 * n + k] = uz;
+    e[k] = (U[4 * n + k] - 0.5 * r * (ux * ux + uy * uy + uz * uz)) / r;
+  }
+}
+
+__global__ void k_to_conservative(const double* __restrict__ rho, const double* __restrict__ e,
+                                  const double* __restrict__ u, double* __restrict__ U, long n) {
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    const double r = rho[k], ux = u[k], uy = u[n + k], uz = u[2 * n + k];
+    U[k] = r; U[n + k] = r * ux; U[2 * n + k] = r * uy; U[3 * n + k] = r * uz;
+    U[4 * n + k] = r * e[k] + 0.5 * r * (ux * ux + uy * uy + uz * uz);
+  }
+}
+
+// B_par = (-d_y A, d_x A) for A on the E_z grid
+template <int M>
+__global__ void k_B_from_potential(const double* __restrict__ Az, double* __restrict__ Bx, double* __restrict__ By,
+                                   const MagTab* __restrict__ T, MeshP mp) {
+  constexpr int A = M + 2, B = M + 1;
+  const long NX = (long)mp.nx * B, G = NX * mp.ny * B;
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= G) return;
+  const long gy = g / NX, gx = g - gy * NX;
+  const long ex = gx / B, ey = gy / B;
+  const int i = gx - ex * B, j = gy - ey * B;
+  double bx = 0.0, by = 0.0;
+  for (int k = 0; k < A; ++k) {
+    bx += T->D_W_G[j][k] * Az[gix(mp, B, ex, ey, i, k)];  // B_x node: GLL i, Gauss j
+    by += T->D_W_G[i][k] * Az[gix(mp, B, ex, ey, k, j)];  // B_y node: Gauss i, GLL j
+  }
+  Bx[g] = -(2.0 / mp.hy) * bx;
+  By[g] = (2.0 / mp.hx) * by;
+}
+
+// ---------------------------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------------------------
+int line_global_reduce(mhd25_ctx* c, const double* stats, int nc, const int* flag);
+
+static int chk(mhd25_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) { c->err = std::string(what) + ": " + hipGetErrorString(e); return -2; }
+  return 0;
+}
+
+#define DISPATCH_PM(p, m, F)                                                                              \
+  if (p == 1 && m == 0) { F(1, 0); } else if (p == 1 && m == 1) { F(1, 1); }                              \
+  else if (p == 2 && m == 1) { F(2, 1); } else if (p == 2 && m == 2) { F(2, 2); }                         \
+  else if (p == 3 && m == 2) { F(3, 2); } else if (p == 3 && m == 3) { F(3, 3); }                         \
+  else if (p == 4 && m == 3) { F(4, 3); } else if (p == 4 && m == 4) { F(4, 4); }                         \
+  else if (p == 5 && m == 4) { F(5, 4); } else if (p == 5 && m == 5) { F(5, 5); }                         \
+  else if (p == 6 && m == 5) { F(6, 5); } else if (p == 6 && m == 6) { F(6, 6); }                         \
+  else return -4;
+
+#define DISPATCH_M(m, F) \
+  switch (m) { case 0: F(0); break; case 1: F(1); break; case 2: F(2); break; case 3: F(3); break; \
+               case 4: F(4); break; case 5: F(5); break; case 6: F(6); break; default: return -4; }
+
+static long mblocks(int p, int m, long K) {
+  const int nn = (p + 1) * (p + 1), aa = (m + 2) * (m + 2);
+  const int eb = 256 / (nn > aa ? nn : aa);
+  return (K + eb - 1) / eb;
+}
+
+int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
+                       const double* eta, double* JE) {
+  const long K = c->mp.K, G = c->G;
+  const int a = c->m + 2, b = c->m + 1;
+  double* Lx = c->loads;
+  double* Ly = Lx + K * a * b;
+  double* Lz = Ly + K * a * b;
+  const long nb = mblocks(c->p, c->m, K);
+  const long gb = (G + 255) / 256;
+#define LJ(P, M) hipLaunchKernelGGL((k_J_loads<P, M>), dim3(nb), dim3(256), 0, c->stream, Bx, By, Bz, Lx, Ly, Lz, c->d_mt, c->mp)
+  DISPATCH_PM(c->p, c->m, LJ);
+#undef LJ
+#define GJ(M) hipLaunchKernelGGL((k_gather<M>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE, JE + G, JE + 2 * G, c->d_mt, c->mp)
+  DISPATCH_M(c->m, GJ);
+#undef GJ
+#define LE(P, M) hipLaunchKernelGGL((k_E_loads<P, M>), dim3(nb), dim3(256), 0, c->stream, u, Bx, By, Bz, JE, JE + G, \
+                                    JE + 2 * G, eta, Lx, Ly, Lz, c->d_mt, c->mp)
+  DISPATCH_PM(c->p, c->m, LE);
+#undef LE
+#define GE(M) hipLaunchKernelGGL((k_gather<M>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE + 3 * G, JE + 4 * G, \
+                                 JE + 5 * G, c->d_mt, c->mp)
+  DISPATCH_M(c->m, GE);
+#undef GE
+  return chk(c, "reconstruct launch");
+}
+
+int mag_update(mhd25_ctx* c, const MagIO& io, int mode) {
+  const long nb = mblocks(c->p, c->m, c->mp.K);
+  if (mode == 0) {
+#define U0(P, M) hipLaunchKernelGGL((k_mag_update<P, M, 0>), dim3(nb), dim3(256), 0, c->stream, io, c->d_mt, c->mp)
+    DISPATCH_PM(c->p, c->m, U0);
+#undef U0
+  } else {
+#define U1(P, M) hipLaunchKernelGGL((k_mag_update<P, M, 1>), dim3(nb), dim3(256), 0, c->stream, io, c->d_mt, c->mp)
+    DISPATCH_PM(c->p, c->m, U1);
+#undef U1
+  }
+  return chk(c, "magnetic update launch");
+}
+
+int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
+                    const double* By, const double* Bz) {
+  const long K = c->mp.K;
+  const int nn = (c->p + 1) * (c->p + 1), eb = 256 / nn;
+  const long nb = (K + eb - 1) / eb;
+#define FS(P) hipLaunchKernelGGL((k_field_stats<P, 3>), dim3(nb), dim3(256), 0, c->stream, u, c->stats, c->d_mt, c->mp)
+  switch (c->p) { case 1: FS(1); break; case 2: FS(2); break; case 3: FS(3); break; case 4: FS(4); break;
+                  case 5: FS(5); break; case 6: FS(6); break; default: return -4; }
+#undef FS
+  line_global_reduce(c, c->stats, 3, nullptr);
+#define VO(P, M) hipLaunchKernelGGL((k_vel_oe<P, M>), dim3((K + VC<P, M>::EB - 1) / VC<P, M>::EB), dim3(256), 0, c->stream, rho, u, e, Bx, By, Bz, c->lines, \
+                                    c->glob, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M)
+  DISPATCH_PM(c->p, c->m, VO);
+#undef VO
+  return chk(c, "velocity OE launch");
+}
+
+int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,
+               const double* Bz, double* eta) {
+  const long K = c->mp.K;
+  const long nb = (K + 255) / 256;
+#define BS(M) hipLaunchKernelGGL((k_B_stats<M>), dim3(nb), dim3(256), 0, c->stream, Bx, By, Bz, c->stats, c->d_mt, c->mp)
+  DISPATCH_M(c->m, BS);
+#undef BS
+  line_global_reduce(c, c->stats, 3, nullptr);
+  const long nb2 = (K + 127) / 128;
+#define AR(P, M) hipLaunchKernelGGL((k_ar_eta<P, M>), dim3(nb2), dim3(128), 0, c->stream, rho, u, Bx, By, Bz, c->glob, eta, \
+                                    c->d_mt, c->mp, c->opt.C_s, c->opt.C_eta)
+  DISPATCH_PM(c->p, c->m, AR);
+#undef AR
+  return chk(c, "A.R. launch");
+}
+
+int mag_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u) {
+  const long n = c->mp.K * c->nn;
+  long nb = (n + 255) / 256; if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_to_primitive, dim3(nb), dim3(256), 0, c->stream, U, rho, e, u, n);
+  return chk(c, "exchange launch");
+}
+
+int mag_to_conservative(mhd25_ctx* c, const double* rho, const double* e, const double* u, double* U) {
+  const long n = c->mp.K * c->nn;
+  long nb = (n + 255) / 256; if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(k_to_conservative, dim3(nb), dim3(256), 0, c->stream, rho, e, u, U, n);
+  return chk(c, "exchange launch");
+}
+
+int mag_B_from_potential(mhd25_ctx* c, const double* A, double* Bx, double* By) {
+  const long gb = (c->G + 255) / 256;
+#define BP(M) hipLaunchKernelGGL((k_B_from_potential<M>), dim3(gb), dim3(256), 0, c->stream, A, Bx, By, c->d_mt, c->mp)
+  DISPATCH_M(c->m, BP);
+#undef BP
+  return chk(c, "potential launch");
+}
