@@ -1,0 +1,157 @@
+"""Benchmark: DOF-stage updates/s (FP64) per Strang step on one MI355X.
+
+Workload: the blast-like stress state on [-0.5, 0.5]^2, 1024 x 1024 elements, DGSEM degree
+N = 4, magnetic degree k = 3, FP64, rho = 1, u = 0, p = 0.1 outside and 1000 inside r < 0.1,
+B = (1, 1, 0)/sqrt(2); full Strang step with hydro OE, positivity scaling, velocity OE and
+artificial resistivity; dt from the positivity CFL rule at CFL 0.3 before every step.
+One Strang step = 6 hydro + 3 magnetic stages; value = K (N+1)^2 * 9 / t_step.
+
+Prints one JSON line.  The roofline object describes the dominant kernel (the hydro stage:
+L_E + SSP combine + element statistics), timed with HIP events on the library's stream.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hydro_stage_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2609_10849_amd", "csrc", "hydro.hip")
+
+
+def stage_bytes(K, nn):
+    """Algorithmic HBM bytes of one hydro-stage launch: read U_s and U^n, write the raw stage
+    (5 fields x K x nn doubles each), write 15 statistics per element."""
+    return 3 * 5 * K * nn * 8 + K * 15 * 8
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per hydro-stage launch from the committed rocprofv3 counter runs, or None
+    when they are missing or were taken on a different kernel source."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_src_sha") != kernel_sha():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(seconds_hint=20.0):
+    """The plain FP64 oracle, timed on this host: two Strang steps of the same blast workload on
+    a 128 x 128 sub-resolution mesh (same domain, N = 4, k = 3, same options)."""
+    import numpy as np
+
+    import oracle as O
+    from paper_2609_10849_amd import workloads as W
+
+    n = 128
+    L, U, Bx, By, Bz = W.blast(n, n, 4, 3)
+    M = O.Mesh(L.nx, L.ny, L.p, L.m, L.x0, L.x1, L.y0, L.y1, L.gamma)
+    threads = O.set_threads(0)
+    dt = 2.0e-5
+    steps = 2
+    t0 = time.perf_counter()
+    st = (U, Bx, By, Bz)
+    for _ in range(steps):
+        st = O.strang_step(M, O.Options.full(), *st, dt)[:4]
+    t = time.perf_counter() - t0
+    rate = M.K * 25 * 9 * steps / t
+    return {"value": rate, "unit": "DOF-stage updates/s", "cores": threads, "kind": "oracle",
+            "sample": "blast workload at 128x128 elements (N=4, k=3, full stabilisation), %d Strang steps, "
+                      "%.1f s on %d OpenMP threads" % (steps, t, threads)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1024, help="elements per direction")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
+              "'How the path would shard')", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2609_10849_amd as pk
+    from paper_2609_10849_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n, N, k = args.n, 4, 3
+    L, U, Bx, By, Bz = W.blast(n, n, N, k)
+    S = pk.Solver.from_layout(L, pk.Options.full())
+    g = [torch.from_numpy(a).to("cuda") for a in (U, Bx, By, Bz)]
+    del U, Bx, By, Bz
+    K = L.K
+    nn = (N + 1) ** 2
+
+    def step():
+        dt = S.cfl_dt(*g, 0.3)
+        r, rep = S.strang_step(*g, dt)
+        if r != 0:
+            raise RuntimeError("strang step failed: %r" % (rep,))
+        return rep
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    S.timing_read()  # discard
+    S.timing(True)
+    attempted = accepted = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rep = step()
+        attempted += rep["substeps_attempted"]
+        accepted += rep["substeps_accepted"]
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    S.timing(False)
+    launches, kms = S.timing_read()
+    ms_per_step = 1e3 * t / args.steps
+    value = K * nn * 9 / (t / args.steps)
+    avg_ms = kms / max(launches, 1)
+    ach = stage_bytes(K, nn) / (avg_ms * 1e-3) / 1e9
+    tr = traffic_per_launch()
+    out = {
+        "metric": "DOF-stage updates/s (FP64) per Strang step",
+        "value": value,
+        "unit": "DOF-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "blast-like stress state, [-0.5,0.5]^2 periodic, %dx%d elements, N=%d, k=%d, "
+                               "p_in/p_out=1e4, full stabilisation (OE, PP, velocity OE, A.R.), CFL 0.3" % (n, n, N, k),
+                   "elements": K, "N": N, "k": k, "dofs": K * nn},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                     "traffic": tr, "kernel": "k_hydro_stage<4,1> (L_E + SSP combine + element statistics)",
+                     "avg_ms": avg_ms, "launches": launches},
+        "accepted_substep_rate": accepted / max(attempted, 1),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
