@@ -184,6 +184,17 @@ int mhd25_batch_strang_step_sequential(mhd25_batch* b, double* const* U, double*
                                        double* const* By, double* const* Bz, const double* dt,
                                        mhd25_report* rep);
 
+/* Tuning knobs of the batch: number of concurrent branch streams of the captured step
+ * (1..8; <= 0 leaves it) and the hydro-stage tile (128 or 256 threads per block) for runs of
+ * degree p (p <= 0: all runs).  Invalidates the captured graph. */
+int mhd25_batch_set_tuning(mhd25_batch* b, int32_t branches, int32_t p, int32_t hydro_bs);
+/* Autotuner: times the hydro-stage tiles per degree and the branch counts on scratch copies of
+ * the given states (the states are not modified), applies the fastest, and appends the choice to
+ * the JSON-lines file `cache_path` (may be NULL); a matching line in the cache is reused without
+ * timing.  *best_branches (host, may be NULL) receives the chosen branch count. */
+int mhd25_batch_autotune(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
+                         double* const* Bz, const double* dt, const char* cache_path, int32_t* best_branches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,8 @@ _SIGS = {
     "mhd25_batch_destroy": (None, [_dp]),
     "mhd25_batch_strang_step": (ctypes.c_int, [_dp] * 6 + [ctypes.POINTER(Report)]),
     "mhd25_batch_strang_step_sequential": (ctypes.c_int, [_dp] * 6 + [ctypes.POINTER(Report)]),
+    "mhd25_batch_set_tuning": (ctypes.c_int, [_dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "mhd25_batch_autotune": (ctypes.c_int, [_dp] * 6 + [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
 }
 
 _lib = None
@@ -286,3 +288,64 @@ class Solver:
         n = ctypes.c_int64(); ms = ctypes.c_double()
         self._chk(self.lib.mhd25_timing_read(self.h, kernel_id, ctypes.byref(n), ctypes.byref(ms)), "timing_read")
         return n.value, ms.value
+
+
+class Batch:
+    """Ensemble of independent runs advanced together (wraps an mhd25_batch): one Strang step of
+    every run is replayed from a captured HIP graph with concurrent branches."""
+
+    def __init__(self, layouts, options=None):
+        if not torch.cuda.is_available():
+            raise MHD25Error("no GPU visible: the HIP library has no CPU path")
+        self.lib = load_library()
+        self.n = len(layouts)
+        arr = (MeshDesc * self.n)(*[MeshDesc(L.nx, L.ny, L.x0, L.x1, L.y0, L.y1, L.p, L.m, L.gamma) for L in layouts])
+        self.options = options if options is not None else Options.make()
+        h = ctypes.c_void_p()
+        r = self.lib.mhd25_batch_create(arr, self.n, ctypes.byref(self.options), _stream(), ctypes.byref(h))
+        if r != 0:
+            raise MHD25Error("mhd25_batch_create failed with %d" % r)
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mhd25_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _ptrs(ts):
+        return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def _args(self, U, Bx, By, Bz, dt):
+        for t in (*U, *Bx, *By, *Bz):
+            _ptr(t)
+        return (self._ptrs(U), self._ptrs(Bx), self._ptrs(By), self._ptrs(Bz), (ctypes.c_double * self.n)(*dt))
+
+    def strang_step(self, U, Bx, By, Bz, dt, sequential=False):
+        reps = (Report * self.n)()
+        fn = self.lib.mhd25_batch_strang_step_sequential if sequential else self.lib.mhd25_batch_strang_step
+        a = self._args(U, Bx, By, Bz, dt)
+        r = fn(self.h, *a, reps)
+        if r < 0:
+            raise MHD25Error("batch strang step failed (%d)" % r)
+        return r, [x.as_dict() for x in reps]
+
+    def set_tuning(self, branches=0, p=0, hydro_bs=0):
+        r = self.lib.mhd25_batch_set_tuning(self.h, branches, p, hydro_bs)
+        if r:
+            raise MHD25Error("set_tuning failed (%d)" % r)
+
+    def autotune(self, U, Bx, By, Bz, dt, cache_path=None):
+        best = ctypes.c_int32()
+        a = self._args(U, Bx, By, Bz, dt)
+        r = self.lib.mhd25_batch_autotune(self.h, *a, cache_path.encode() if cache_path else None,
+                                          ctypes.byref(best))
+        if r:
+            raise MHD25Error("autotune failed (%d)" % r)
+        return best.value

@@ -94,7 +94,7 @@ void mhd25_destroy(mhd25_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->d_ht, c->d_mt, c->Un, c->S1, c->S2, c->Ust, c->stats, c->lines, c->glob, c->d_flag,
                   c->d_counts, c->d_flags, c->rho, c->e, c->u, c->eta, c->Yn, c->Y1, c->Y2, c->JE,
-                  c->loads, c->saveU, c->saveB, c->red, c->snapU};
+                  c->loads, c->saveU, c->saveB, c->red, c->snapU, c->vjp_scratch};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);

@@ -80,10 +80,12 @@ struct mhd25_ctx {
   double *rho, *e, *u, *eta, *Yn, *Y1, *Y2, *Ys, *JE, *loads, *bstat;
   double *saveU, *saveB, *snapU;
   double* red;  // scratch for small reductions
+  double* vjp_scratch;  // allocated on the first magnetic VJP
   double* h_pinned;
   std::string err;
   // timing
   int timing;
+  int hydro_bs;  // threads per block of the hydro stage kernel (128 or 256; tuned)
   std::vector<hipEvent_t> ev_pool;  // pairs (start, stop) of timed hydro-stage launches
   int ev_used;
   long long t_launch[4];

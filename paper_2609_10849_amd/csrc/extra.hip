@@ -35,6 +35,32 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ a, lo
   if (t < ncol) out[t] = red[t][0];
 }
 
+// first level: each block reduces a contiguous chunk of the input into one partial
+__global__ __launch_bounds__(256) void k_reduce_partial(const double* __restrict__ a, long n, int mode, long chunk,
+                                                        double* __restrict__ part) {
+  __shared__ double red[6][256];
+  const int t = threadIdx.x;
+  const int ncol = mode == 0 ? 1 : 6;
+  const long lo = (long)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double v[6];
+  for (int c = 0; c < ncol; ++c) v[c] = (mode == 0) ? -DBL_MAX : (c < 4 ? 0.0 : DBL_MAX);
+  for (long k = lo + t; k < hi; k += 256) {
+    if (mode == 0) v[0] = fmax(v[0], a[k]);
+    else
+      for (int c = 0; c < 6; ++c) v[c] = c < 4 ? v[c] + a[k * 6 + c] : fmin(v[c], a[k * 6 + c]);
+  }
+  for (int c = 0; c < ncol; ++c) red[c][t] = v[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int c = 0; c < ncol; ++c)
+        red[c][t] = mode == 0 ? fmax(red[c][t], red[c][t + w])
+                              : (c < 4 ? red[c][t] + red[c][t + w] : fmin(red[c][t], red[c][t + w]));
+    __syncthreads();
+  }
+  if (t < ncol) part[(long)blockIdx.x * ncol + t] = red[t][0];
+}
+
 template <int P, int M>
 __device__ void B_at_node(const double* Bx, const double* By, const double* Bz, const MagTab* T, const MeshP& mp,
                           long ex, long ey, int qi, int qj, double* b) {
@@ -131,9 +157,25 @@ static int ex_chk(mhd25_ctx* c, hipError_t e, const char* what) {
   return 0;
 }
 
+// two-level deterministic reduction (fixed partition): mode 0 max of a[n]; mode 1 column sums / mins of a[n][6]
+static void reduce2(mhd25_ctx* c, const double* a, long n, int mode, double* d_out) {
+  double* part = c->red + 16 + c->mp.K + 64;
+  long nb = (n + 4095) / 4096;
+  if (nb > 1024) nb = 1024;
+  if (nb < 1) nb = 1;
+  const long chunk = (n + nb - 1) / nb;
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nb), dim3(256), 0, c->stream, a, n, mode, chunk, part);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, c->stream, part, nb, mode, d_out);
+}
+
+int extra_max_dev(mhd25_ctx* c, const double* a, long n, double* d_out) {
+  reduce2(c, a, n, 0, d_out);
+  return ex_chk(c, hipGetLastError(), "reduce");
+}
+
 int extra_max(mhd25_ctx* c, const double* a, long n, double* host_out) {
   double* d_out = c->red + 0;
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, c->stream, a, n, 0, d_out);
+  reduce2(c, a, n, 0, d_out);
   int r = ex_chk(c, hipMemcpyAsync(c->h_pinned, d_out, 8, hipMemcpyDeviceToHost, c->stream), "copy");
   if (r) return r;
   r = ex_chk(c, hipStreamSynchronize(c->stream), "sync");
@@ -157,7 +199,7 @@ int extra_diagnostics(mhd25_ctx* c, const double* U, const double* Bx, const dou
 #define DG(P, M) hipLaunchKernelGGL((k_diag<P, M>), dim3(nb), dim3(128), 0, c->stream, U, Bx, By, Bz, buf, c->d_mt, c->mp)
   DISPATCH_PM2(c->p, c->m, DG);
 #undef DG
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, c->stream, buf, c->mp.K, 1, c->red);
+  reduce2(c, buf, c->mp.K, 1, c->red);
   int r = ex_chk(c, hipMemcpyAsync(c->h_pinned, c->red, 6 * 8, hipMemcpyDeviceToHost, c->stream), "copy");
   if (r) return r;
   r = ex_chk(c, hipStreamSynchronize(c->stream), "sync");

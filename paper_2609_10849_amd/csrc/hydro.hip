@@ -16,9 +16,9 @@ namespace {
 
 constexpr double EPSM = 2.220446049250313e-16;  // 2^-52
 
-template <int P>
+template <int P, int BS = 256>
 struct Cfg {
-  static constexpr int NP = P + 1, NN = NP * NP, EB = 256 / NN, NT = EB * NN, ND = NP / 2;
+  static constexpr int NP = P + 1, NN = NP * NP, EB = BS / NN, NT = EB * NN, ND = NP / 2;
 };
 
 struct Prim {
@@ -98,12 +98,12 @@ __device__ __forceinline__ void iflux(const double UL[5], const double UR[5], do
 __device__ __forceinline__ long wrap(long a, long n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 // One direction of L_E for the thread's node: owned pairs, interface flux, incoming halves.
-template <int P, int D>
+template <int P, int D, int BS>
 __device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], double acc[5], bool act, int el, int i,
                                            int j, long e, const double* __restrict__ Us, long KN,
-                                           double (*sp)[Cfg<P>::EB * Cfg<P>::NN], double* sb,
+                                           double (*sp)[Cfg<P, BS>::EB * Cfg<P, BS>::NN], double* sb,
                                            const HydroTab* __restrict__ T, const MeshP& mp, int iface) {
-  using C = Cfg<P>;
+  using C = Cfg<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, ND = C::ND;
   const int pos = D == 0 ? i : j, line = D == 0 ? j : i;
   const double sc = D == 0 ? 2.0 / mp.hx : 2.0 / mp.hy;
@@ -167,19 +167,19 @@ __device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], do
 
 // Per-element sums (GLL weights, without |J_K|), minima and maxima of 5 fields held in LDS,
 // plus the raw-average admissibility test (NaN-safe).
-template <int P>
-__device__ __forceinline__ void element_stats(double (*sv)[Cfg<P>::EB * Cfg<P>::NN], bool act, int el, int q, long e,
+template <class C>
+__device__ __forceinline__ void element_stats(const double* svf, bool act, int el, int q, long e,
                                               double* __restrict__ stats, int* __restrict__ flag,
                                               const HydroTab* __restrict__ T, double g) {
-  using C = Cfg<P>;
-  constexpr int NP = C::NP, NN = C::NN;
+  constexpr int NP = C::NP, NN = C::NN, S = C::EB * C::NN;
+  auto sv = [&](int c, int k) { return svf[c * S + k]; };
   // tasks 0..14: (component, kind) statistics; task 15: admissibility of the raw average
   for (int t = q; act && t < 16; t += NN) {
     if (t < 15) {
       const int c = t / 3, kind = t - 3 * c;
       double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
       for (int k = 0; k < NN; ++k) {
-        const double v = sv[c][el * NN + k];
+        const double v = sv(c, el * NN + k);
         s += (T->w[k % NP] * T->w[k / NP]) * v;
         mn = fmin(mn, v); mx = fmax(mx, v);
       }
@@ -189,7 +189,7 @@ __device__ __forceinline__ void element_stats(double (*sv)[Cfg<P>::EB * Cfg<P>::
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         double s = 0.0;
-        for (int k = 0; k < NN; ++k) s += (T->w[k % NP] * T->w[k / NP]) * sv[c][el * NN + k];
+        for (int k = 0; k < NN; ++k) s += (T->w[k % NP] * T->w[k / NP]) * sv(c, el * NN + k);
         a[c] = 0.25 * s;
       }
       const double pb = (g - 1.0) * (a[4] - (a[1] * a[1] + a[2] * a[2] + a[3] * a[3]) / (2.0 * a[0]));
@@ -199,12 +199,12 @@ __device__ __forceinline__ void element_stats(double (*sv)[Cfg<P>::EB * Cfg<P>::
 }
 
 // MODE 0: out = L_E(Us).  MODE 1: out = ca*Un + cb*(Us + tau*L_E(Us)) plus element statistics.
-template <int P, int MODE>
-__global__ __launch_bounds__(256) void k_hydro_stage(const double* __restrict__ Us, const double* __restrict__ Un,
-                                                     double* __restrict__ out, double* __restrict__ stats,
-                                                     int* __restrict__ flag, const HydroTab* __restrict__ T, MeshP mp,
-                                                     double ca, double cb, double tau, int iface) {
-  using C = Cfg<P>;
+template <int P, int MODE, int BS>
+__global__ __launch_bounds__(BS) void k_hydro_stage(const double* __restrict__ Us, const double* __restrict__ Un,
+                                                    double* __restrict__ out, double* __restrict__ stats,
+                                                    int* __restrict__ flag, const HydroTab* __restrict__ T, MeshP mp,
+                                                    double ca, double cb, double tau, int iface) {
+  using C = Cfg<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, ND = C::ND;
   __shared__ double sp[7][EB * NN];
   __shared__ double sb[EB * NP * NP * (ND > 0 ? ND : 1) * 5];
@@ -230,8 +230,8 @@ __global__ __launch_bounds__(256) void k_hydro_stage(const double* __restrict__ 
     sp[4][tid] = me.b; sp[5][tid] = me.lr; sp[6][tid] = me.lb;
   }
   __syncthreads();
-  volume_dir<P, 0>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, T, mp, iface);
-  volume_dir<P, 1>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, T, mp, iface);
+  volume_dir<P, 0, BS>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, T, mp, iface);
+  volume_dir<P, 1, BS>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, T, mp, iface);
   if (MODE == 0) {
     if (act) {
 #pragma unroll
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void k_hydro_stage(const double* __restrict__ 
     }
   }
   __syncthreads();
-  element_stats<P>(sp, act, el, q, e, stats, flag, T, mp.gamma);
+  element_stats<C>(&sp[0][0], act, el, q, e, stats, flag, T, mp.gamma);
 }
 
 template <int P>
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_elem_stats(const double* __restrict__ U
   if (act)
     for (int c = 0; c < 5; ++c) sv[c][tid] = Uin[c * KN + e * NN + q];
   __syncthreads();
-  element_stats<P>(sv, act, el, q, e, stats, flag, T, mp.gamma);
+  element_stats<Cfg<P>>(&sv[0][0], act, el, q, e, stats, flag, T, mp.gamma);
 }
 
 // Element-average pressure helper
@@ -593,9 +593,14 @@ static int check(mhd25_ctx* c, hipError_t e, const char* what) {
 }
 
 int hydro_rhs(mhd25_ctx* c, const double* U, double* dU) {
-  const long blocks = (c->mp.K + eb_of(c->p) - 1) / eb_of(c->p);
-#define L0(P) hipLaunchKernelGGL((k_hydro_stage<P, 0>), dim3(blocks), dim3(256), 0, c->stream, U, U, dU, nullptr, \
-                                 nullptr, c->d_ht, c->mp, 0.0, 1.0, 0.0, c->opt.iface_flux)
+  const int bs = c->hydro_bs == 128 ? 128 : 256;
+  const int eb = bs / ((c->p + 1) * (c->p + 1));
+  const long blocks = (c->mp.K + eb - 1) / eb;
+#define L0(P)                                                                                                      \
+  if (bs == 128) hipLaunchKernelGGL((k_hydro_stage<P, 0, 128>), dim3(blocks), dim3(128), 0, c->stream, U, U, dU,  \
+                                    nullptr, nullptr, c->d_ht, c->mp, 0.0, 1.0, 0.0, c->opt.iface_flux);          \
+  else hipLaunchKernelGGL((k_hydro_stage<P, 0, 256>), dim3(blocks), dim3(256), 0, c->stream, U, U, dU, nullptr,    \
+                          nullptr, c->d_ht, c->mp, 0.0, 1.0, 0.0, c->opt.iface_flux)
   DISPATCH_P(c->p, L0);
 #undef L0
   return check(c, hipGetLastError(), "rhs_hydro launch");
@@ -603,11 +608,16 @@ int hydro_rhs(mhd25_ctx* c, const double* U, double* dU) {
 
 // raw stage + statistics + line/global reductions
 int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust, double ca, double cb, double tau) {
-  const long blocks = (c->mp.K + eb_of(c->p) - 1) / eb_of(c->p);
+  const int bs = c->hydro_bs == 128 ? 128 : 256;
+  const int eb = bs / ((c->p + 1) * (c->p + 1));
+  const long blocks = (c->mp.K + eb - 1) / eb;
   hipEvent_t* ev = c->timing ? timing_slot(c) : nullptr;
   if (ev) hipEventRecord(ev[0], c->stream);
-#define L1(P) hipLaunchKernelGGL((k_hydro_stage<P, 1>), dim3(blocks), dim3(256), 0, c->stream, Us, Un, Ust, c->stats, \
-                                 c->d_flag, c->d_ht, c->mp, ca, cb, tau, c->opt.iface_flux)
+#define L1(P)                                                                                                      \
+  if (bs == 128) hipLaunchKernelGGL((k_hydro_stage<P, 1, 128>), dim3(blocks), dim3(128), 0, c->stream, Us, Un, Ust, \
+                                    c->stats, c->d_flag, c->d_ht, c->mp, ca, cb, tau, c->opt.iface_flux);          \
+  else hipLaunchKernelGGL((k_hydro_stage<P, 1, 256>), dim3(blocks), dim3(256), 0, c->stream, Us, Un, Ust, c->stats, \
+                          c->d_flag, c->d_ht, c->mp, ca, cb, tau, c->opt.iface_flux)
   DISPATCH_P(c->p, L1);
 #undef L1
   if (ev) hipEventRecord(ev[1], c->stream);

@@ -1,0 +1,105 @@
+"""Batched ensemble through the C ABI: one Strang step of uneven runs replayed from a captured
+HIP graph with concurrent branches must equal, bit for bit, each run stepped alone with the plain
+entry point (same kernels); one member is checked against the oracle; a member that needs a
+halving takes the uncaptured fallback; the autotuner writes and reuses its cache."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2609_10849_amd import workloads as W
+from tests._gpu import announce, assert_parity, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def runs_small():
+    specs = [(12, 10, 2, 1, 0.3, (0.1, 0.05)), (16, 16, 3, 2, 0.5, (0.0, 0.2)), (8, 14, 4, 3, 0.7, (0.25, 0.0)),
+             (20, 12, 2, 2, 0.2, (0.1, 0.1)), (10, 10, 3, 3, 0.6, (0.0, 0.0))]
+    out = []
+    for nx, ny, p, m, kappa, B in specs:
+        L, U, Bx, By, Bz = W.isentropic_vortex(nx, ny, p, m, kappa=kappa, B=B, background=(0.3, -0.2))
+        out.append((L, U, Bx, By, Bz))
+    return out
+
+
+def to_dev(run):
+    return [dev(a) for a in run[1:]]
+
+
+def test_batch_equals_individual_and_oracle():
+    import paper_2609_10849_amd as pk
+    announce("batch vs individual")
+    runs = runs_small()
+    opts = pk.Options.full()
+    B = pk.Batch([r[0] for r in runs], opts)
+    dts = []
+    single = []
+    for r in runs:
+        S = pk.Solver.from_layout(r[0], opts)
+        g = to_dev(r)
+        dts.append(0.5 * S.cfl_dt(*g, 0.3))
+        single.append((S, g))
+    bat = [to_dev(r) for r in runs]
+    for step in range(3):  # every graph replay is checked against the eager path
+        st, reps = B.strang_step([b[0] for b in bat], [b[1] for b in bat], [b[2] for b in bat], [b[3] for b in bat],
+                                 dts)
+        assert st == 0
+        for k, (S, g) in enumerate(single):
+            r, rep = S.strang_step(*g, dts[k])
+            assert r == 0
+            for a, b in zip(bat[k], g):
+                assert (host(a) == host(b)).all(), (step, k)
+            assert reps[k]["n_p_limited"] == rep["n_p_limited"]
+            assert reps[k]["eta_max"] == rep["eta_max"]
+    # one member against the oracle (3 steps)
+    L, U, Bx, By, Bz = runs[1]
+    M = O.Mesh(L.nx, L.ny, L.p, L.m, L.x0, L.x1, L.y0, L.y1, L.gamma)
+    st = (U, Bx, By, Bz)
+    for _ in range(3):
+        st = O.strang_step(M, O.Options.full(), *st, dts[1])[:4]
+    for a, r in zip(bat[1], st):
+        if np.abs(r).max() > 0:
+            assert_parity(host(a), r, 1e-12, "batched member vs oracle")
+
+
+def test_batch_rejection_fallback():
+    import paper_2609_10849_amd as pk
+    announce("batch rejection fallback")
+    runs = runs_small()[:2]
+    Lb, Ub, Bxb, Byb, Bzb = W.blast(8, 8, 2, 1, p_in=1000.0)
+    runs.append((Lb, Ub, Bxb, Byb, Bzb))
+    opts = pk.Options.make(oe_hydro=1, pp=1)
+    B = pk.Batch([r[0] for r in runs], opts)
+    dts = [1e-3, 1e-3, 1e-2]  # the blast member needs halvings at this step
+    bat = [to_dev(r) for r in runs]
+    st, reps = B.strang_step([b[0] for b in bat], [b[1] for b in bat], [b[2] for b in bat], [b[3] for b in bat], dts)
+    assert st == 0
+    assert reps[2]["substeps_attempted"] > reps[2]["substeps_accepted"]
+    for k, r in enumerate(runs):
+        S = pk.Solver.from_layout(r[0], opts)
+        g = to_dev(r)
+        S.strang_step(*g, dts[k])
+        for a, b in zip(bat[k], g):
+            assert (host(a) == host(b)).all(), k
+
+
+def test_batch_autotune_cache(tmp_path):
+    import paper_2609_10849_amd as pk
+    announce("batch autotune")
+    runs = runs_small()
+    B = pk.Batch([r[0] for r in runs], pk.Options.full())
+    bat = [to_dev(r) for r in runs]
+    before = [host(a).copy() for b in bat for a in b]
+    cache = str(tmp_path / "tune.jsonl")
+    dts = [1e-3] * len(runs)
+    S1 = B.autotune([b[0] for b in bat], [b[1] for b in bat], [b[2] for b in bat], [b[3] for b in bat], dts, cache)
+    assert S1 in (1, 2, 4, 8)
+    after = [host(a) for b in bat for a in b]
+    assert all((x == y).all() for x, y in zip(before, after))  # tuning works on scratch copies
+    line = json.loads(open(cache).read().strip().splitlines()[-1])
+    assert line["branches"] == S1
+    S2 = B.autotune([b[0] for b in bat], [b[1] for b in bat], [b[2] for b in bat], [b[3] for b in bat], dts, cache)
+    assert S2 == S1
