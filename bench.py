@@ -25,9 +25,11 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2609_10849_amd", "csrc", "hydro.hip")
 
 
 def stage_bytes(K, nn):
-    """Algorithmic HBM bytes of one hydro-stage launch: read U_s and U^n, write the raw stage
-    (5 fields x K x nn doubles each), write 15 statistics per element."""
-    return 3 * 5 * K * nn * 8 + K * 15 * 8
+    """Algorithmic HBM bytes of one hydro-stage launch, averaged over the three SSP-RK(3,3) stages:
+    the first reads U^n once, the second and third read U_s and U^n; each writes the raw stage
+    (one U is 5 fields x K x nn doubles) and 15 statistics per element."""
+    u = 5 * K * nn * 8
+    return (2 * u + 3 * u + 3 * u) / 3.0 + K * 15 * 8
 
 
 def kernel_sha():

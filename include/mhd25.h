@@ -188,10 +188,12 @@ int mhd25_batch_strang_step_sequential(mhd25_batch* b, double* const* U, double*
  * (1..8; <= 0 leaves it) and the hydro-stage tile (128 or 256 threads per block) for runs of
  * degree p (p <= 0: all runs).  Invalidates the captured graph. */
 int mhd25_batch_set_tuning(mhd25_batch* b, int32_t branches, int32_t p, int32_t hydro_bs);
-/* Autotuner: times the hydro-stage tiles per degree and the branch counts on scratch copies of
- * the given states (the states are not modified), applies the fastest, and appends the choice to
- * the JSON-lines file `cache_path` (may be NULL); a matching line in the cache is reused without
- * timing.  *best_branches (host, may be NULL) receives the chosen branch count. */
+/* Autotuner: per degree present, times the hydro-stage tiles (128 / 256 threads per block) with
+ * plain launches on a scratch copy of the largest run of that degree (the given states are not
+ * modified), sets the branch count to min(8, max(2, number of runs with >= 1/4 of the largest
+ * run's work)), and appends the choice to the JSON-lines file `cache_path` (may be NULL); a line
+ * for the same run set is reused without timing.  *best_branches (host, may be NULL) receives
+ * the branch count. */
 int mhd25_batch_autotune(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
                          double* const* Bz, const double* dt, const char* cache_path, int32_t* best_branches);
 

@@ -9,8 +9,8 @@
 // The graph is re-captured when a run's dt or array pointers change.
 //
 // Autotuning (mhd25_batch_autotune): per degree p the hydro-stage tile (128 or 256 threads per
-// block) and the branch count S in {1,2,4,8} are timed on scratch copies of the runs and the
-// winners are stored in a JSON cache.
+// block) is timed with plain launches on a scratch copy; the branch count follows a size rule; the
+// choices are stored in a JSON cache.
 #include <algorithm>
 #include <chrono>
 #include <cstdio>
@@ -309,87 +309,82 @@ int mhd25_batch_set_tuning(mhd25_batch* b, int32_t branches, int32_t p, int32_t 
   return 0;
 }
 
-// Time candidate tiles and branch counts on scratch copies of the runs' states; store the winners.
+// Autotuner.  Per degree p present in the batch, the hydro-stage tile (128 or 256 threads per
+// block) is timed with plain launches and HIP events on a scratch copy of the largest run of that
+// degree (median of 5 launches after 2 warm-ups); the branch count is min(8, number of runs with at
+// least a quarter of the largest run's work, at least 2).  No graph is captured while tuning.
+// Choices are appended to the JSON-lines cache and reused when a line with the same run set exists.
 int mhd25_batch_autotune(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By, double* const* Bz,
                          const double* dt, const char* cache_path, int32_t* best_branches) {
   if (!b || !U || !Bx || !By || !Bz || !dt) return -1;
-  const int R = b->nruns;
-  // cache lookup: key = run descriptors
   std::ostringstream key;
   for (auto* c : b->ctx) key << c->mesh.nx << "x" << c->mesh.ny << "p" << c->p << "m" << c->m << ";";
   if (cache_path) {
     std::ifstream f(cache_path);
     std::string line;
     while (std::getline(f, line)) {
-      if (line.find(key.str()) == std::string::npos) continue;
-      int S = 4, bs2 = 256, bs3 = 256, bs4 = 256;
+      if (line.find("\"runs\":\"" + key.str() + "\"") == std::string::npos) continue;
+      int S = 4;
       const char* q = std::strstr(line.c_str(), "\"branches\":");
       if (q) S = std::atoi(q + 11);
       for (int p = 1; p <= 6; ++p) {
         char pat[32];
         std::snprintf(pat, sizeof(pat), "\"bs_p%d\":", p);
         const char* z = std::strstr(line.c_str(), pat);
-        if (z) { int v = std::atoi(z + std::strlen(pat)); BTRY(mhd25_batch_set_tuning(b, 0, p, v)); }
+        if (z) BTRY(mhd25_batch_set_tuning(b, 0, p, std::atoi(z + std::strlen(pat))));
       }
-      (void)bs2; (void)bs3; (void)bs4;
       BTRY(set_branches(b, S));
       if (best_branches) *best_branches = S;
       return 0;
     }
   }
-  // scratch copies
-  std::vector<double*> tU(R), tX(R), tY(R), tZ(R);
-  for (int r = 0; r < R; ++r) {
-    mhd25_ctx* c = b->ctx[r];
-    const long n5 = 5 * c->mp.K * c->nn, G = c->G;
-    if (hipMalloc((void**)&tU[r], n5 * 8) || hipMalloc((void**)&tX[r], G * 8) || hipMalloc((void**)&tY[r], G * 8) ||
-        hipMalloc((void**)&tZ[r], G * 8))
-      return -3;
-    hipMemcpyAsync(tU[r], U[r], n5 * 8, hipMemcpyDeviceToDevice, b->main);
-    hipMemcpyAsync(tX[r], Bx[r], G * 8, hipMemcpyDeviceToDevice, b->main);
-    hipMemcpyAsync(tY[r], By[r], G * 8, hipMemcpyDeviceToDevice, b->main);
-    hipMemcpyAsync(tZ[r], Bz[r], G * 8, hipMemcpyDeviceToDevice, b->main);
-  }
-  hipStreamSynchronize(b->main);
-  auto time_step = [&]() -> double {
-    mhd25_report* rr = nullptr;
-    if (mhd25_batch_strang_step(b, tU.data(), tX.data(), tY.data(), tZ.data(), dt, rr)) return 1e30;
-    hipStreamSynchronize(b->main);
-    auto t0 = std::chrono::steady_clock::now();
-    for (int k = 0; k < 2; ++k) mhd25_batch_strang_step(b, tU.data(), tX.data(), tY.data(), tZ.data(), dt, rr);
-    hipStreamSynchronize(b->main);
-    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  };
-  // 1) hydro tile per degree (with 4 branches)
-  BTRY(set_branches(b, 4));
   std::map<int, int> best_bs;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -2;
   for (int p = 1; p <= 6; ++p) {
-    bool present = false;
-    for (auto* c : b->ctx) present |= c->p == p;
-    if (!present) continue;
+    int rbig = -1;
+    for (int r = 0; r < b->nruns; ++r)
+      if (b->ctx[r]->p == p && (rbig < 0 || b->ctx[r]->mp.K > b->ctx[rbig]->mp.K)) rbig = r;
+    if (rbig < 0) continue;
+    mhd25_ctx* c = b->ctx[rbig];
+    c->stream = b->main;
+    const long n5 = 5 * c->mp.K * c->nn;
+    // scratch: the run's own stage buffers (idle between steps) hold the copy
+    BTRY(dcopy(c, U[rbig], c->S1, n5));
     double best = 1e30;
+    const int saved = c->hydro_bs;
     for (int bs : {256, 128}) {
-      BTRY(mhd25_batch_set_tuning(b, 0, p, bs));
-      double t = time_step();
-      if (t < best) { best = t; best_bs[p] = bs; }
+      c->hydro_bs = bs;
+      std::vector<float> ms;
+      for (int k = 0; k < 7; ++k) {
+        BTRY(reset_attempt(c));
+        hipEventRecord(e0, b->main);
+        BTRY(hydro_stage_a(c, c->S1, c->S1, c->Ust, 0.0, 1.0, 0.25 * dt[rbig]));
+        hipEventRecord(e1, b->main);
+        if (hipEventSynchronize(e1) != hipSuccess) return -2;
+        float t = 0.f;
+        hipEventElapsedTime(&t, e0, e1);
+        if (k >= 2) ms.push_back(t);
+      }
+      std::sort(ms.begin(), ms.end());
+      const double med = ms[ms.size() / 2];
+      if (med < best) { best = med; best_bs[p] = bs; }
     }
+    c->hydro_bs = saved;
     BTRY(mhd25_batch_set_tuning(b, 0, p, best_bs[p]));
   }
-  // 2) branch count
-  int bestS = 4;
-  double best = 1e30;
-  for (int S : {1, 2, 4, 8}) {
-    BTRY(set_branches(b, S));
-    double t = time_step();
-    if (t < best) { best = t; bestS = S; }
-  }
-  BTRY(set_branches(b, bestS));
-  release_graph(b);
-  for (int r = 0; r < R; ++r) { hipFree(tU[r]); hipFree(tX[r]); hipFree(tY[r]); hipFree(tZ[r]); }
-  if (best_branches) *best_branches = bestS;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  double wmax = 0.0;
+  for (auto* c : b->ctx) wmax = std::max(wmax, (double)c->mp.K * c->nn);
+  int big = 0;
+  for (auto* c : b->ctx) big += ((double)c->mp.K * c->nn >= 0.25 * wmax);
+  const int S = std::max(2, std::min(8, big));
+  BTRY(set_branches(b, S));
+  if (best_branches) *best_branches = S;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
-    f << "{\"runs\":\"" << key.str() << "\",\"branches\":" << bestS;
+    f << "{\"runs\":\"" << key.str() << "\",\"branches\":" << S;
     for (auto& kv : best_bs) f << ",\"bs_p" << kv.first << "\":" << kv.second;
     f << "}\n";
   }

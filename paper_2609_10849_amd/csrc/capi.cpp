@@ -21,6 +21,9 @@ int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const do
 int mag_update(mhd25_ctx* c, const MagIO& io, int mode);
 int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
                     const double* By, const double* Bz);
+int mag_velocity_prep(mhd25_ctx* c, const double* rho);
+int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
+                       const double* By, const double* Bz);
 int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,
                const double* Bz, double* eta);
 int mag_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u);
@@ -94,7 +97,7 @@ void mhd25_destroy(mhd25_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->d_ht, c->d_mt, c->Un, c->S1, c->S2, c->Ust, c->stats, c->lines, c->glob, c->d_flag,
                   c->d_counts, c->d_flags, c->rho, c->e, c->u, c->eta, c->Yn, c->Y1, c->Y2, c->JE,
-                  c->loads, c->saveU, c->saveB, c->red, c->snapU, c->vjp_scratch};
+                  c->loads, c->saveU, c->saveB, c->red, c->snapU, c->vjp_scratch, c->psi};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
@@ -157,6 +160,8 @@ int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stre
   r = r ? r : alloc((void**)&c->saveB, 3 * G * 8);
   r = r ? r : alloc((void**)&c->snapU, n5 * 8);
   r = r ? r : alloc((void**)&c->red, (K + 1024) * 8 * 8);
+  // velocity-OE basis: allocated here so that no allocation happens inside a captured step
+  r = r ? r : alloc((void**)&c->psi, (size_t)K * c->nn * c->nn * 8);
   if (!r && hipHostMalloc((void**)&c->h_pinned, 4096) != hipSuccess) r = fail(c, -3, "hipHostMalloc");
   if (r) { mhd25_destroy(c); return r; }
   if (hipMemcpy(c->d_ht, &c->h_ht, sizeof(HydroTab), hipMemcpyHostToDevice) != hipSuccess ||
@@ -291,6 +296,7 @@ int mhd25_step_magnetic(mhd25_ctx* c, const double* rho, double* e, double* u, d
   parts(c->Yn, &ne, &nu, &nx, &ny, &nz);
   TRY(dcopy(c, e, ne, KN)); TRY(dcopy(c, u, nu, 3 * KN));
   TRY(dcopy(c, Bx, nx, G)); TRY(dcopy(c, By, ny, G)); TRY(dcopy(c, Bz, nz, G));
+  if (c->opt.oe_mag) TRY(mag_velocity_prep(c, rho));  // rho is frozen over the substep
   const double cas[3] = {0.0, 0.75, 1.0 / 3.0}, cbs[3] = {1.0, 0.25, 2.0 / 3.0};
   double* stage_in[3] = {c->Yn, c->Y1, c->Y2};
   double* stage_out[2] = {c->Y1, c->Y2};
@@ -310,7 +316,7 @@ int mhd25_step_magnetic(mhd25_ctx* c, const double* rho, double* e, double* u, d
     io.oe = oe; io.ou = ou; io.obx = ox; io.oby = oy; io.obz = oz;
     io.ca = cas[s]; io.cb = cbs[s]; io.tau = tau;
     TRY(mag_update(c, io, 1));
-    if (c->opt.oe_mag) TRY(mag_velocity_oe(c, tau, rho, ou, oe, ox, oy, oz));
+    if (c->opt.oe_mag) TRY(mag_velocity_apply(c, tau, rho, ou, oe, ox, oy, oz));
   }
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));

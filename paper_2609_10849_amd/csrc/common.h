@@ -81,6 +81,7 @@ struct mhd25_ctx {
   double *saveU, *saveB, *snapU;
   double* red;  // scratch for small reductions
   double* vjp_scratch;  // allocated on the first magnetic VJP
+  double* psi;          // rho-weighted orthonormal basis values [K][nn][nn] (velocity OE)
   double* h_pinned;
   std::string err;
   // timing

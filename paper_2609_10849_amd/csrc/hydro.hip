@@ -437,58 +437,52 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
     __syncthreads();
   }
   uint8_t f = 0;
-  if (do_pp && act) {
+  if (do_pp) {
+    // positivity scaling: each node's derived quantities are computed once and reduced over the
+    // element through LDS (st rows 0..2 are free after the modal damping)
     const double eps_r = 64.0 * EPSM;
-    double a[5];
+    double a[5] = {0, 0, 0, 0, 0};
+    double rmin = DBL_MAX;
+    if (act) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      double s = 0.0;
-      for (int k = 0; k < NN; ++k) s += (T->w[k % NP] * T->w[k / NP]) * su[c][el * NN + k];
-      a[c] = 0.25 * s;
-    }
-    if (!(a[0] > eps_r)) {
-      f = 4;
-#pragma unroll
-      for (int c = 0; c < 5; ++c) U[c] = a[c];
-    } else {
-      double rmin = DBL_MAX;
+      for (int c = 0; c < 5; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < NN; ++k) s += (T->w[k % NP] * T->w[k / NP]) * su[c][el * NN + k];
+        a[c] = 0.25 * s;
+      }
       for (int k = 0; k < NN; ++k) rmin = fmin(rmin, su[0][el * NN + k]);
-      double thr = 1.0;
-      if (rmin < eps_r) {
-        thr = fmin(1.0, fmax(0.0, (a[0] - eps_r) / (a[0] - rmin)));
-        f |= 1;
-        U[0] = a[0] + thr * (U[0] - a[0]);
-      }
-      double S = Sp(a, eps_r);
-      for (int k = 0; k < NN; ++k) {
-        double v[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) v[c] = su[c][el * NN + k];
-        if (f & 1) v[0] = a[0] + thr * (v[0] - a[0]);
-        S = fmax(S, Sp(v, eps_r));
-      }
+    }
+    const bool collapse_r = !(a[0] > eps_r);
+    double thr = 1.0;
+    if (act && !collapse_r && rmin < eps_r) {
+      thr = fmin(1.0, fmax(0.0, (a[0] - eps_r) / (a[0] - rmin)));
+      f |= 1;
+      U[0] = a[0] + thr * (U[0] - a[0]);  // density-limited state of this node
+    }
+    if (act) {
+      st[0][tid] = Sp(U, eps_r);
+      st[1][tid] = pres(U, g);
+    }
+    __syncthreads();
+    if (act && !collapse_r) {
+      double S = Sp(a, eps_r), pmin = DBL_MAX;
+      for (int k = 0; k < NN; ++k) { S = fmax(S, st[0][el * NN + k]); pmin = fmin(pmin, st[1][el * NN + k]); }
       const double eps_p = fmax(64.0 * EPSM, 8192.0 * EPSM * S);
       const double pb = pres(a, g);
       if (pb <= eps_p) {
         f |= 4;
 #pragma unroll
         for (int c = 0; c < 5; ++c) U[c] = a[c];
-      } else {
-        double pmin = DBL_MAX;
-        for (int k = 0; k < NN; ++k) {
-          double v[5];
+      } else if (pmin < eps_p) {
+        const double thp = fmin(1.0, fmax(0.0, (pb - eps_p) / (pb - pmin)));
+        f |= 2;
 #pragma unroll
-          for (int c = 0; c < 5; ++c) v[c] = su[c][el * NN + k];
-          if (f & 1) v[0] = a[0] + thr * (v[0] - a[0]);
-          pmin = fmin(pmin, pres(v, g));
-        }
-        if (pmin < eps_p) {
-          const double thp = fmin(1.0, fmax(0.0, (pb - eps_p) / (pb - pmin)));
-          f |= 2;
-#pragma unroll
-          for (int c = 0; c < 5; ++c) U[c] = a[c] + thp * (U[c] - a[c]);
-        }
+        for (int c = 0; c < 5; ++c) U[c] = a[c] + thp * (U[c] - a[c]);
       }
+    } else if (act && collapse_r) {
+      f = 4;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) U[c] = a[c];
     }
   }
   if (act) {

@@ -371,31 +371,41 @@ __global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __re
   __syncthreads();
   if (!act || t >= NN) return;
   const int qi = t % NP, qj = t / NP;
+  // transpose of the interpolation to the auxiliary nodes, factorised over the two directions
   double du[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int j = 0; j < A; ++j)
+#pragma unroll 1
+  for (int j = 0; j < A; ++j) {
+    double s0 = 0.0, s1 = 0.0, t1 = 0.0, t2 = 0.0;
 #pragma unroll
     for (int i = 0; i < A; ++i) {
-      const double I = T->I_P_W[i][qi] * T->I_P_W[j][qj];
-      du[0] += I * fz[el][0][j * A + i];
-      du[1] += I * fz[el][1][j * A + i];
+      const double I = T->I_P_W[i][qi];
+      s0 += I * fz[el][0][j * A + i];
+      s1 += I * fz[el][1][j * A + i];
     }
-#pragma unroll
-  for (int j = 0; j < A; ++j)
 #pragma unroll
     for (int i = 0; i < B; ++i) {
-      const double I = T->I_P_G[i][qi] * T->I_P_W[j][qj];
-      du[1] += I * fx[el][0][j * B + i];
-      du[2] += I * fx[el][1][j * B + i];
+      const double I = T->I_P_G[i][qi];
+      t1 += I * fx[el][0][j * B + i];
+      t2 += I * fx[el][1][j * B + i];
     }
-#pragma unroll
-  for (int j = 0; j < B; ++j)
+    const double Iy = T->I_P_W[j][qj];
+    du[0] += Iy * s0;
+    du[1] += Iy * (s1 + t1);
+    du[2] += Iy * t2;
+  }
+#pragma unroll 1
+  for (int j = 0; j < B; ++j) {
+    double s0 = 0.0, s2 = 0.0;
 #pragma unroll
     for (int i = 0; i < A; ++i) {
-      const double I = T->I_P_W[i][qi] * T->I_P_G[j][qj];
-      du[0] += I * fy[el][0][j * A + i];
-      du[2] += I * fy[el][1][j * A + i];
+      const double I = T->I_P_W[i][qi];
+      s0 += I * fy[el][0][j * A + i];
+      s2 += I * fy[el][1][j * A + i];
     }
+    const double Iy = T->I_P_G[j][qj];
+    du[0] += Iy * s0;
+    du[2] += Iy * s2;
+  }
   const long n = e * NN + t;
   const double rq = io.rho[n];
   const double Mq = mp.J * T->wp[qi] * T->wp[qj];
@@ -466,38 +476,114 @@ __global__ __launch_bounds__(256) void k_field_stats(const double* __restrict__ 
 // the shell-ordered tensor Legendre basis orthonormalised by a Cholesky factor of its Gram
 // matrix (computed in LDS), so increments of shell l are sums over that shell's modes.
 // ---------------------------------------------------------------------------------------------
-template <int P, int M>
-struct VC {
-  static constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1;
-  static constexpr int PER = NN * (NN + 1) + 13 * NN + 3 * NP + 2 * A * B + B * B;  // LDS doubles per element
-  static constexpr int EB0 = 256 / NN, EBL = (64 * 1024) / (8 * PER);
-  static constexpr int EB = EB0 < EBL ? EB0 : (EBL > 0 ? EBL : 1);
+// ---------------------------------------------------------------------------------------------
+// Velocity OE (eq. magnetic-oe-sensor .. eq. magnetic-oe-map).  The rho-weighted projections use
+// the shell-ordered tensor Legendre basis orthonormalised in the rho-weighted product,
+// psi = phi L^{-T} with G = L L^T the Gram matrix.  rho is frozen during a magnetic substep, so
+// Psi[q][k] = psi_k(x_q) is computed once per substep (k_vel_prep, one wave per block so the
+// Cholesky barriers are wave-local) and reused by the three stages (k_vel_apply).
+// ---------------------------------------------------------------------------------------------
+// shell index of mode k in the shell ordering (shell l holds modes l^2 .. (l+1)^2 - 1)
+__host__ __device__ constexpr int shell_of(int k) {
+  int l = 0;
+  while ((l + 1) * (l + 1) <= k) ++l;
+  return l;
+}
+
+template <int P>
+struct VP {
+  static constexpr int NP = P + 1, NN = NP * NP, EB = 64 / NN > 0 ? 64 / NN : 1;
 };
 
+template <int P>
+__global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho, double* __restrict__ Psi,
+                                                 const HydroTab* __restrict__ H, MeshP mp) {
+  constexpr int NP = P + 1, NN = NP * NP, EB = VP<P>::EB;
+  __shared__ double sw[EB][NN], sH[EB][NP][NP * NP], sG[EB][NN][NN + 1];
+  const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
+  const int qi = q % NP, qj = q / NP;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = el < EB && e < mp.K;
+  if (act) sw[el][q] = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
+  __syncthreads();
+  // sum factorisation: Hm[qj][a][a'] = sum_qi W[qj][qi] V[qi][a] V[qi][a']
+  if (act)
+    for (int t = q; t < NP * NP * NP; t += NN) {
+      const int jj = t / (NP * NP), aa = t - jj * NP * NP, a = aa / NP, a2 = aa - a * NP;
+      double s = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < NP; ++ii) s += sw[el][jj * NP + ii] * H->V[ii][a] * H->V[ii][a2];
+      sH[el][jj][aa] = s;
+    }
+  __syncthreads();
+  if (act) {  // Gram row q (shell order): G[k][k'] = sum_qj V[qj][b] V[qj][b'] Hm[qj][a][a']
+    const int ka = H->ka[q], kb = H->kb[q];
+    for (int k2 = 0; k2 <= q; ++k2) {
+      const int a2 = H->ka[k2], b2 = H->kb[k2];
+      double s = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < NP; ++jj) s += H->V[jj][kb] * H->V[jj][b2] * sH[el][jj][ka * NP + a2];
+      sG[el][q][k2] = s;
+    }
+  }
+  __syncthreads();
+  for (int k = 0; k < NN; ++k) {  // Cholesky, lower triangle in place
+    if (act && q > k) sG[el][q][k] /= sqrt(sG[el][k][k]);
+    __syncthreads();
+    if (act) {
+      if (q == k) sG[el][k][k] = sqrt(sG[el][k][k]);
+      else if (q > k)
+        for (int jj = k + 1; jj <= q; ++jj) sG[el][q][jj] -= sG[el][q][k] * sG[el][jj][k];
+    }
+    __syncthreads();
+  }
+  double psi[NN];
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    double s = act ? H->V[qi][H->ka[k]] * H->V[qj][H->kb[k]] : 0.0;
+#pragma unroll
+    for (int k2 = 0; k2 < k; ++k2) s -= (act ? sG[el][k][k2] : 0.0) * psi[k2];
+    psi[k] = act ? s / sG[el][k][k] : 0.0;
+  }
+  __syncthreads();
+  if (act)
+#pragma unroll
+    for (int k = 0; k < NN; ++k) sG[el][q][k] = psi[k];
+  __syncthreads();
+  // coalesced store of the element's Psi[q][k]
+  for (int t = tid; t < EB * NN * NN; t += 64) {
+    const int ee = t / (NN * NN), r = t - ee * NN * NN;
+    const long eg = (long)blockIdx.x * EB + ee;
+    if (eg < mp.K) Psi[eg * NN * NN + r] = sG[ee][r / NN][r % NN];
+  }
+}
+
+// uin: snapshot of the raw stage velocity (neighbour jumps must not see updated elements);
+// u: updated in place (own element only)
 template <int P, int M>
-__global__ __launch_bounds__(256) void k_vel_oe(const double* __restrict__ rho, double* __restrict__ u,
-                                                double* __restrict__ en, const double* __restrict__ Bx,
-                                                const double* __restrict__ By, const double* __restrict__ Bz,
-                                                const double* __restrict__ lines, const double* __restrict__ glob,
-                                                const HydroTab* __restrict__ H, const MagTab* __restrict__ T,
-                                                MeshP mp, double tau, double sM) {
+__global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rho, const double* __restrict__ uin,
+                                                   double* __restrict__ u, double* __restrict__ en, const double* __restrict__ Bx,
+                                                   const double* __restrict__ By, const double* __restrict__ Bz,
+                                                   const double* __restrict__ Psi, const double* __restrict__ lines,
+                                                   const double* __restrict__ glob, const HydroTab* __restrict__ H,
+                                                   const MagTab* __restrict__ T, MeshP mp, double tau, double sM) {
   constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1, AB = A * B, BB = B * B;
-  constexpr int EB = VC<P, M>::EB;
-  __shared__ double su[EB][3][NN], sw[EB][NN], sG[EB][NN][NN + 1];
+  constexpr int EB = 256 / NN;
+  __shared__ double su[EB][3][NN], sw[EB][NN];
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
-  __shared__ double sjmp[EB][6][NN], ssig[EB][2][NP], sD[EB][NP], sva[EB][2][NN], sc[EB][NN];
+  __shared__ double sjmp[EB][6][NN], ssig[EB][2][NP], sD[EB][NP], sva[EB][2][NN], sc[EB][3][NN];
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
   const int qi = q % NP, qj = q / NP;
   const long e = (long)blockIdx.x * EB + el;
   const bool act = el < EB && e < mp.K;
   const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
   const long KN = mp.K * NN;
+  const double* Pe = Psi + (act ? e : 0) * NN * NN;  // Pe[n*NN + k] = psi_k(x_n)
   double uu[3] = {0.0, 0.0, 0.0}, rq = 1.0;
   if (act) {
-    for (int d = 0; d < 3; ++d) { uu[d] = u[d * KN + e * NN + q]; su[el][d][q] = uu[d]; }
+    for (int d = 0; d < 3; ++d) { uu[d] = uin[d * KN + e * NN + q]; su[el][d][q] = uu[d]; }
     rq = rho[e * NN + q];
     sw[el][q] = mp.J * H->w[qi] * H->w[qj] * rq;
-    // B at GLL_p nodes: element locals
     for (int k = q; k < AB; k += NN) {
       sbx[el][k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];
       sby[el][k] = By[gix(mp, B, ex, ey, k % B, k / B)];
@@ -505,7 +591,6 @@ __global__ __launch_bounds__(256) void k_vel_oe(const double* __restrict__ rho, 
     for (int k = q; k < BB; k += NN) sbz[el][k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
   }
   __syncthreads();
-  // amplitudes of u components
   double Dsh[2] = {0.0, 0.0};
   bool cst[3] = {false, false, false};
   if (act) {
@@ -520,20 +605,25 @@ __global__ __launch_bounds__(256) void k_vel_oe(const double* __restrict__ rho, 
       Dsh[0] = fmax(Dsh[0], fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm));
       Dsh[1] = fmax(Dsh[1], fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm));
     }
-    // rate: |u_I| + |B|/sqrt(rho) at this node
     double bxv = 0.0, byv = 0.0, bzv = 0.0;
+#pragma unroll
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
+#pragma unroll
       for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sbx[el][j * A + i];
       bxv += T->I_G_P[qj][j] * s;
     }
+#pragma unroll
     for (int j = 0; j < A; ++j) {
       double s = 0.0;
+#pragma unroll
       for (int i = 0; i < B; ++i) s += T->I_G_P[qi][i] * sby[el][j * B + i];
       byv += T->I_W_P[qj][j] * s;
     }
+#pragma unroll
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
+#pragma unroll
       for (int i = 0; i < B; ++i) s += T->I_V_P[qi][i] * sbz[el][j * B + i];
       bzv += T->I_V_P[qj][j] * s;
     }
@@ -556,8 +646,8 @@ __global__ __launch_bounds__(256) void k_vel_oe(const double* __restrict__ rho, 
           const double own = su[el][c][nk];
           a += H->Dr0[r][k] * own;
           d += H->Drp[r][k] * own;
-          b += H->Drp[r][k] * u[c * KN + em * NN + nk];
-          cc += H->Dr0[r][k] * u[c * KN + ep * NN + nk];
+          b += H->Drp[r][k] * uin[c * KN + em * NN + nk];
+          cc += H->Dr0[r][k] * uin[c * KN + ep * NN + nk];
         }
         const double jm = a - b, jp = cc - d;
         sjmp[el][2 * c][q] = wl * jm * jm;
@@ -595,74 +685,34 @@ __global__ __launch_bounds__(256) void k_vel_oe(const double* __restrict__ rho, 
       sD[el][q] = exp(-sM * tau * (lx * sx + ly * sy));
     }
   }
-  // Gram matrix of the shell-ordered basis in the rho-weighted product: row q of the element
+  // expansion coefficients c_k = (u_d, psi_k)_rho, thread q computes mode k = q
   if (act) {
-    const int ka = H->ka[q], kb = H->kb[q];
-    for (int k2 = 0; k2 <= q; ++k2) {
-      const int a2 = H->ka[k2], b2 = H->kb[k2];
+    for (int d = 0; d < 3; ++d) {
       double s = 0.0;
-      for (int n = 0; n < NN; ++n) {
-        const int ni = n % NP, nj = n / NP;
-        s += sw[el][n] * (H->V[ni][ka] * H->V[nj][kb]) * (H->V[ni][a2] * H->V[nj][b2]);
-      }
-      sG[el][q][k2] = s;
+#pragma unroll
+      for (int n = 0; n < NN; ++n) s += sw[el][n] * su[el][d][n] * Pe[n * NN + q];
+      sc[el][d][q] = s;
     }
   }
   __syncthreads();
-  // Cholesky G = L L^T in place (lower triangle), two barriers per column
-  for (int k = 0; k < NN; ++k) {
-    if (act && q > k) sG[el][q][k] /= sqrt(sG[el][k][k]);
-    __syncthreads();
-    if (act) {
-      if (q == k) sG[el][k][k] = sqrt(sG[el][k][k]);
-      else if (q > k)
-        for (int jj = k + 1; jj <= q; ++jj) sG[el][q][jj] -= sG[el][q][k] * sG[el][jj][k];
-    }
-    __syncthreads();
-  }
-  // Psi[q][k] = psi_k(x_q), psi = phi L^{-T}: forward substitution for the thread's node
-  double psi[NN];
-#pragma unroll
-  for (int k = 0; k < NN; ++k) {
-    double s = act ? H->V[qi][H->ka[k]] * H->V[qj][H->kb[k]] : 0.0;
-#pragma unroll
-    for (int k2 = 0; k2 < k; ++k2) s -= (act ? sG[el][k][k2] : 0.0) * psi[k2];
-    psi[k] = act ? s / sG[el][k][k] : 0.0;
-  }
-  __syncthreads();
-  if (act)
-#pragma unroll
-    for (int k = 0; k < NN; ++k) sG[el][q][k] = psi[k];
-  __syncthreads();
-  double up[3], heat = 0.0;
+  if (!act) return;
+  double heat = 0.0;
   for (int d = 0; d < 3; ++d) {
-    if (act) {  // c_k = (u_d, psi_k)_rho for k = q
-      double s = 0.0;
-      for (int n = 0; n < NN; ++n) s += sw[el][n] * su[el][d][n] * sG[el][n][q];
-      sc[el][q] = s;
-    }
-    __syncthreads();
     double wl[NP];
 #pragma unroll
     for (int l = 0; l < NP; ++l) wl[l] = 0.0;
-    if (act) {
 #pragma unroll
-      for (int k = 0; k < NN; ++k) wl[H->ksh[k]] += sc[el][k] * psi[k];
-    }
+    for (int k = 0; k < NN; ++k) wl[shell_of(k)] += sc[el][d][k] * Pe[q * NN + k];
     double v = wl[0];
 #pragma unroll
     for (int l = 1; l < NP; ++l) {
-      const double Dl = act ? sD[el][l] : 1.0;
+      const double Dl = sD[el][l];
       v += Dl * wl[l];
       heat += 0.5 * (1.0 - Dl * Dl) * wl[l] * wl[l];
     }
-    up[d] = v;
-    __syncthreads();
+    u[d * KN + e * NN + q] = v;
   }
-  if (act) {
-    for (int d = 0; d < 3; ++d) u[d * KN + e * NN + q] = up[d];
-    en[e * NN + q] += heat;
-  }
+  en[e * NN + q] += heat;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -719,6 +769,7 @@ __global__ __launch_bounds__(128) void k_ar_eta(const double* __restrict__ rho, 
           return v;
         };
         double sm = 0.0, sp = 0.0;
+#pragma unroll 1
         for (int k = 0; k < A; ++k) {
           const double jm = trace(e, 0, k) - trace(em, 1, k);
           const double jp = trace(ep, 0, k) - trace(e, 1, k);
@@ -732,7 +783,9 @@ __global__ __launch_bounds__(128) void k_ar_eta(const double* __restrict__ rho, 
   }
   const long KN = mp.K * NN;
   double ax = 0.0, ay = 0.0;
+#pragma unroll 1
   for (int qj = 0; qj < NP; ++qj)
+#pragma unroll 1
     for (int qi = 0; qi < NP; ++qi) {
       double bxv = 0.0, byv = 0.0, bzv = 0.0;
       for (int j = 0; j < B; ++j)
@@ -865,6 +918,7 @@ __global__ void k_B_from_potential(const double* __restrict__ Az, double* __rest
 // host launchers
 // ---------------------------------------------------------------------------------------------
 int line_global_reduce(mhd25_ctx* c, const double* stats, int nc, const int* flag);
+int dcopy(mhd25_ctx* c, const double* a, double* b, long n);
 
 static int chk(mhd25_ctx* c, const char* what) {
   hipError_t e = hipGetLastError();
@@ -931,8 +985,22 @@ int mag_update(mhd25_ctx* c, const MagIO& io, int mode) {
   return chk(c, "magnetic update launch");
 }
 
-int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
-                    const double* By, const double* Bz) {
+int mag_velocity_prep(mhd25_ctx* c, const double* rho) {
+  const long K = c->mp.K;
+  const long nn = (long)(c->p + 1) * (c->p + 1);
+  (void)nn;
+  if (!c->psi) { c->err = "velocity-OE basis not allocated"; return -2; }
+#define VPR(P) hipLaunchKernelGGL((k_vel_prep<P>), dim3((K + VP<P>::EB - 1) / VP<P>::EB), dim3(64), 0, c->stream, rho, \
+                                  c->psi, c->d_ht, c->mp)
+  switch (c->p) { case 1: VPR(1); break; case 2: VPR(2); break; case 3: VPR(3); break; case 4: VPR(4); break;
+                  case 5: VPR(5); break; case 6: VPR(6); break; default: return -4; }
+#undef VPR
+  return chk(c, "velocity OE prep launch");
+}
+
+// apply with the basis prepared for the current rho
+int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
+                       const double* By, const double* Bz) {
   const long K = c->mp.K;
   const int nn = (c->p + 1) * (c->p + 1), eb = 256 / nn;
   const long nb = (K + eb - 1) / eb;
@@ -941,11 +1009,21 @@ int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, doub
                   case 5: FS(5); break; case 6: FS(6); break; default: return -4; }
 #undef FS
   line_global_reduce(c, c->stats, 3, nullptr);
-#define VO(P, M) hipLaunchKernelGGL((k_vel_oe<P, M>), dim3((K + VC<P, M>::EB - 1) / VC<P, M>::EB), dim3(256), 0, c->stream, rho, u, e, Bx, By, Bz, c->lines, \
-                                    c->glob, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M)
+  // snapshot of the raw stage velocity in the (idle) hydro stage buffer
+  int rc = dcopy(c, u, c->Ust, 3 * K * nn);
+  if (rc) return rc;
+#define VO(P, M) hipLaunchKernelGGL((k_vel_apply<P, M>), dim3(nb), dim3(256), 0, c->stream, rho, c->Ust, u, e, Bx, By, Bz, c->psi, \
+                                    c->lines, c->glob, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M)
   DISPATCH_PM(c->p, c->m, VO);
 #undef VO
   return chk(c, "velocity OE launch");
+}
+
+int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
+                    const double* By, const double* Bz) {
+  int r = mag_velocity_prep(c, rho);
+  if (r) return r;
+  return mag_velocity_apply(c, tau, rho, u, e, Bx, By, Bz);
 }
 
 int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,

@@ -86,9 +86,11 @@ def test_batch_rejection_fallback():
             assert (host(a) == host(b)).all(), k
 
 
-def test_batch_autotune_cache(tmp_path):
+def test_batch_autotune_event_timed(tmp_path):
+    """Tile choice timed with plain launches (no graph capture while tuning), cache written and
+    reused, states untouched."""
     import paper_2609_10849_amd as pk
-    announce("batch autotune")
+    announce("batch autotune (event-timed tiles)")
     runs = runs_small()
     B = pk.Batch([r[0] for r in runs], pk.Options.full())
     bat = [to_dev(r) for r in runs]
@@ -96,7 +98,7 @@ def test_batch_autotune_cache(tmp_path):
     cache = str(tmp_path / "tune.jsonl")
     dts = [1e-3] * len(runs)
     S1 = B.autotune([b[0] for b in bat], [b[1] for b in bat], [b[2] for b in bat], [b[3] for b in bat], dts, cache)
-    assert S1 in (1, 2, 4, 8)
+    assert 2 <= S1 <= 8
     after = [host(a) for b in bat for a in b]
     assert all((x == y).all() for x, y in zip(before, after))  # tuning works on scratch copies
     line = json.loads(open(cache).read().strip().splitlines()[-1])
