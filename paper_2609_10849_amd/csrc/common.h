@@ -82,6 +82,7 @@ struct mhd25_ctx {
   double* red;  // scratch for small reductions
   double* vjp_scratch;  // allocated on the first magnetic VJP
   double* psi;          // rho-weighted orthonormal basis values [K][nn][nn] (velocity OE)
+  double* artr;         // A.R. face traces and wave-speed maxima [K][8(m+2)+2]
   double* h_pinned;
   std::string err;
   // timing

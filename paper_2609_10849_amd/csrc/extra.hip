@@ -61,39 +61,72 @@ __global__ __launch_bounds__(256) void k_reduce_partial(const double* __restrict
   if (t < ncol) part[(long)blockIdx.x * ncol + t] = red[t][0];
 }
 
+// Largest positivity-CFL wave-speed sum of each element: one thread per GLL_p node, EB elements
+// per 256-thread block; the element's B coefficients are staged in LDS and interpolated to the
+// node by sum factorisation; the element maximum is taken in LDS (a NaN propagates).
 template <int P, int M>
-__device__ void B_at_node(const double* Bx, const double* By, const double* Bz, const MagTab* T, const MeshP& mp,
-                          long ex, long ey, int qi, int qj, double* b) {
-  constexpr int A = M + 2, B = M + 1;
-  b[0] = b[1] = b[2] = 0.0;
-  for (int j = 0; j < B; ++j)
-    for (int i = 0; i < A; ++i) b[0] += T->I_W_P[qi][i] * T->I_G_P[qj][j] * Bx[gix2(mp, B, ex, ey, i, j)];
-  for (int j = 0; j < A; ++j)
-    for (int i = 0; i < B; ++i) b[1] += T->I_G_P[qi][i] * T->I_W_P[qj][j] * By[gix2(mp, B, ex, ey, i, j)];
-  for (int j = 0; j < B; ++j)
-    for (int i = 0; i < B; ++i) b[2] += T->I_V_P[qi][i] * T->I_V_P[qj][j] * Bz[gix2(mp, B, ex, ey, i, j)];
-}
-
-template <int P, int M>
-__global__ __launch_bounds__(128) void k_cfl(const double* __restrict__ U, const double* __restrict__ Bx,
+__global__ __launch_bounds__(256) void k_cfl(const double* __restrict__ U, const double* __restrict__ Bx,
                                              const double* __restrict__ By, const double* __restrict__ Bz,
                                              double* __restrict__ out, const MagTab* __restrict__ T, MeshP mp) {
-  constexpr int NP = P + 1, NN = NP * NP;
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= mp.K) return;
-  const long ex = e % mp.nx, ey = e / mp.nx, KN = mp.K * NN;
-  double mx = 0.0;
-  for (int q = 0; q < NN; ++q) {
-    const long n = e * NN + q;
-    const double r = U[n], ux = U[KN + n] / r, uy = U[2 * KN + n] / r, uz = U[3 * KN + n] / r;
-    const double p = (mp.gamma - 1.0) * (U[4 * KN + n] - 0.5 * r * (ux * ux + uy * uy + uz * uz));
-    double b[3];
-    B_at_node<P, M>(Bx, By, Bz, T, mp, ex, ey, q % NP, q / NP, b);
-    const double cf = sqrt((mp.gamma * p + b[0] * b[0] + b[1] * b[1] + b[2] * b[2]) / r);
-    const double s = (2.0 * P + 1.0) * ((fabs(ux) + cf) / mp.hx + (fabs(uy) + cf) / mp.hy);
-    mx = (s > mx || s != s) ? s : mx;  // a NaN propagates
+  constexpr int NP = P + 1, NN = NP * NP, EB = 256 / NN, A = M + 2, B = M + 1, AB = A * B, BB = B * B;
+  __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB], ss[EB][NN];
+  __shared__ double tWP[NP][A], tGP[NP][B], tVP[NP][B];
+  const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN, qi = q % NP, qj = q / NP;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = el < EB && e < mp.K;
+  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0, KN = mp.K * NN;
+  for (int t = tid; t < NP * A; t += 256) tWP[t / A][t % A] = T->I_W_P[t / A][t % A];
+  for (int t = tid; t < NP * B; t += 256) {
+    tGP[t / B][t % B] = T->I_G_P[t / B][t % B];
+    tVP[t / B][t % B] = T->I_V_P[t / B][t % B];
   }
-  out[e] = mx;
+  if (act) {
+    for (int k = q; k < AB; k += NN) {
+      sbx[el][k] = Bx[gix2(mp, B, ex, ey, k % A, k / A)];
+      sby[el][k] = By[gix2(mp, B, ex, ey, k % B, k / B)];
+    }
+    for (int k = q; k < BB; k += NN) sbz[el][k] = Bz[gix2(mp, B, ex, ey, k % B, k / B)];
+  }
+  __syncthreads();
+  if (act) {
+    const long n = e * NN + q;
+    const double r = U[n], ir = 1.0 / r;
+    const double ux = U[KN + n] * ir, uy = U[2 * KN + n] * ir, uz = U[3 * KN + n] * ir;
+    const double p = (mp.gamma - 1.0) * (U[4 * KN + n] - 0.5 * r * (ux * ux + uy * uy + uz * uz));
+    double bx = 0.0, by = 0.0, bz = 0.0;
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < A; ++i) t += tWP[qi][i] * sbx[el][j * A + i];
+      bx += tGP[qj][j] * t;
+    }
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) t += tGP[qi][i] * sby[el][j * B + i];
+      by += tWP[qj][j] * t;
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      double t = 0.0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) t += tVP[qi][i] * sbz[el][j * B + i];
+      bz += tVP[qj][j] * t;
+    }
+    const double cf = sqrt((mp.gamma * p + bx * bx + by * by + bz * bz) * ir);
+    ss[el][q] = (2.0 * P + 1.0) * ((fabs(ux) + cf) / mp.hx + (fabs(uy) + cf) / mp.hy);
+  }
+  __syncthreads();
+  if (act && q == 0) {
+    double mx = 0.0;
+    for (int k = 0; k < NN; ++k) {
+      const double s = ss[el][k];
+      mx = (s > mx || s != s) ? s : mx;
+    }
+    out[e] = mx;
+  }
 }
 
 template <int P, int M>
@@ -184,9 +217,10 @@ int extra_max(mhd25_ctx* c, const double* a, long n, double* host_out) {
 }
 
 int extra_cfl(mhd25_ctx* c, const double* U, const double* Bx, const double* By, const double* Bz, double* host_max) {
-  const long nb = (c->mp.K + 127) / 128;
+  const long eb = 256 / ((c->p + 1) * (c->p + 1));
+  const long nb = (c->mp.K + eb - 1) / eb;
   double* buf = c->red + 16;
-#define CF(P, M) hipLaunchKernelGGL((k_cfl<P, M>), dim3(nb), dim3(128), 0, c->stream, U, Bx, By, Bz, buf, c->d_mt, c->mp)
+#define CF(P, M) hipLaunchKernelGGL((k_cfl<P, M>), dim3(nb), dim3(256), 0, c->stream, U, Bx, By, Bz, buf, c->d_mt, c->mp)
   DISPATCH_PM2(c->p, c->m, CF);
 #undef CF
   return extra_max(c, buf, c->mp.K, host_max);

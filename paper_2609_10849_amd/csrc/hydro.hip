@@ -36,24 +36,36 @@ __device__ __forceinline__ Prim make_prim(const double U[5], double g) {
   return q;
 }
 
-// logarithmic mean with per-node logarithms; near-equal arguments (u = ((aR-aL)/(aR+aL))^2 < 1e-4)
-// use the series of f/atanh(f) to u^3 (truncation < u^4/9 ~ 1e-17).
-__device__ __forceinline__ double lmean(double aL, double aR, double lL, double lR) {
-  const double d = aR - aL, s = aR + aL;
-  if (d * d < 1e-4 * (s * s)) {
-    const double u = (d * d) / (s * s);
-    return 0.5 * s / (1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0))));
-  }
-  return d / (lR - lL);
+// Logarithmic mean (eq. euler-chandrashekar-flux) as a fraction num/den from the node values
+// a and their logarithms l.  Well separated (f^2 >= 1e-4 with f = (aR-aL)/(aR+aL)): (aR-aL)/(lR-lL).
+// Near-equal: (aL+aR) / (2 (1 + u/3 + u^2/5 + u^3/7)) with u = f^2 = tanh^2((lR-lL)/2) summed to the
+// x^8 term; the truncation of both series is below 1e-17 relative there.  The quotient is taken
+// by the caller, which folds the three divisions of the flux into one reciprocal.
+struct Frac {
+  double n, d;
+};
+__device__ __forceinline__ Frac lmean_frac(double aL, double aR, double lL, double lR) {
+  const double d = aR - aL, s = aR + aL, dl = lR - lL;
+  const double x2 = 0.25 * dl * dl;
+  const double u = x2 * (1.0 - x2 * (2.0 / 3.0 - x2 * (17.0 / 45.0 - x2 * (62.0 / 315.0))));
+  const double pu = 2.0 * (1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0))));
+  const bool near = d * d < 1e-4 * (s * s);
+  return Frac{near ? s : d, near ? pu : dl};
 }
 
 // Chandrashekar flux (eq. euler-chandrashekar-flux), energy in the form
-// rho_log ud (1/(2(g-1) beta_log) - |u|^2avg/2 + |avg u|^2) + p_hat ud.
+// rho_log ud (gk/beta_log - |u|^2avg/2 + |avg u|^2) + p_hat ud with gk = 1/(2(g-1)).  rho_log = nR/dR,
+// 1/beta_log = dB/nB and p_hat = (rhoL+rhoR)/(2(betaL+betaR)) share one reciprocal.
 template <int D>
-__device__ __forceinline__ void ecflux(const Prim& L, const Prim& R, double g, double F[5]) {
-  const double rl = lmean(L.r, R.r, L.lr, R.lr);
-  const double bl = lmean(L.b, R.b, L.lb, R.lb);
-  const double ph = 0.5 * (L.r + R.r) / (L.b + R.b);
+__device__ __forceinline__ void ecflux(const Prim& L, const Prim& R, double gk, double F[5]) {
+  const Frac fr = lmean_frac(L.r, R.r, L.lr, R.lr);
+  const Frac fb = lmean_frac(L.b, R.b, L.lb, R.lb);
+  const double sb = L.b + R.b;
+  const double t1 = fr.d * fb.n;
+  const double Q = 1.0 / (t1 * sb);
+  const double rl = fr.n * fb.n * sb * Q;
+  const double ibl = fb.d * fr.d * sb * Q;
+  const double ph = 0.5 * (L.r + R.r) * t1 * Q;
   const double uxa = 0.5 * (L.ux + R.ux), uya = 0.5 * (L.uy + R.uy), uza = 0.5 * (L.uz + R.uz);
   const double u2a = 0.5 * ((L.ux * L.ux + L.uy * L.uy + L.uz * L.uz) + (R.ux * R.ux + R.uy * R.uy + R.uz * R.uz));
   const double ud = D == 0 ? uxa : uya;
@@ -62,7 +74,7 @@ __device__ __forceinline__ void ecflux(const Prim& L, const Prim& R, double g, d
   F[1] = f0 * uxa + (D == 0 ? ph : 0.0);
   F[2] = f0 * uya + (D == 1 ? ph : 0.0);
   F[3] = f0 * uza;
-  F[4] = f0 * (1.0 / (2.0 * (g - 1.0) * bl) - 0.5 * u2a + (uxa * uxa + uya * uya + uza * uza)) + ph * ud;
+  F[4] = f0 * (ibl * gk - 0.5 * u2a + (uxa * uxa + uya * uya + uza * uza)) + ph * ud;
 }
 
 template <int D>
@@ -84,7 +96,7 @@ template <int D>
 __device__ __forceinline__ void iflux(const double UL[5], const double UR[5], double g, int iface, double F[5]) {
   if (iface == 1) {
     Prim a = make_prim(UL, g), b = make_prim(UR, g);
-    ecflux<D>(a, b, g, F);
+    ecflux<D>(a, b, 0.5 / (g - 1.0), F);
     return;
   }
   double FL[5], FR[5], udL, cL, udR, cR;
@@ -102,12 +114,13 @@ template <int P, int D, int BS>
 __device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], double acc[5], bool act, int el, int i,
                                            int j, long e, const double* __restrict__ Us, long KN,
                                            double (*sp)[Cfg<P, BS>::EB * Cfg<P, BS>::NN], double* sb,
-                                           const HydroTab* __restrict__ T, const MeshP& mp, int iface) {
+                                           const double* tS, const HydroTab* __restrict__ T, const MeshP& mp,
+                                           int iface) {
   using C = Cfg<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, ND = C::ND;
   const int pos = D == 0 ? i : j, line = D == 0 ? j : i;
   const double sc = D == 0 ? 2.0 / mp.hx : 2.0 / mp.hy;
-  const double g = mp.gamma;
+  const double g = mp.gamma, gk = 0.5 / (g - 1.0);
   // sb layout: [el][line][owner pos][dslot][5]
   double* sbl = sb + ((long)(el * NP + line) * NP) * ND * 5;
   if (act) {
@@ -121,8 +134,8 @@ __device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], do
       o.r = sp[0][nr]; o.ux = sp[1][nr]; o.uy = sp[2][nr]; o.uz = sp[3][nr];
       o.b = sp[4][nr]; o.lr = sp[5][nr]; o.lb = sp[6][nr];
       double F[5];
-      ecflux<D>(me, o, g, F);
-      const double ci = -sc * T->Shat[pos][r], cr = -sc * T->Shat[r][pos];
+      ecflux<D>(me, o, gk, F);
+      const double ci = -sc * tS[pos * NP + r], cr = -sc * tS[r * NP + pos];
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
         acc[c] += ci * F[c];
@@ -135,20 +148,19 @@ __device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], do
       if (D == 0) en = ey * mp.nx + wrap(ex + (pos == 0 ? -1 : 1), mp.nx);
       else en = wrap(ey + (pos == 0 ? -1 : 1), mp.ny) * mp.nx + ex;
       const int qn = D == 0 ? line * NP + (pos == 0 ? P : 0) : (pos == 0 ? P : 0) * NP + line;
-      double UN[5], F[5];
+      // one interface flux per thread: the face's minus side is the neighbour at pos == 0
+      const bool lo = pos == 0;
+      double UL[5], UR[5], F[5];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) UN[c] = Us[c * KN + en * NN + qn];
-      if (pos == 0) {
-        iflux<D>(UN, U, g, iface, F);
-        const double s = sc / T->w[0];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) acc[c] += s * F[c];
-      } else {
-        iflux<D>(U, UN, g, iface, F);
-        const double s = sc / T->w[P];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) acc[c] -= s * F[c];
+      for (int c = 0; c < 5; ++c) {
+        const double un = Us[c * KN + en * NN + qn];
+        UL[c] = lo ? un : U[c];
+        UR[c] = lo ? U[c] : un;
       }
+      iflux<D>(UL, UR, g, iface, F);
+      const double s = lo ? sc / T->w[0] : -(sc / T->w[P]);
+#pragma unroll
+      for (int c = 0; c < 5; ++c) acc[c] += s * F[c];
     }
   }
   __syncthreads();
@@ -165,36 +177,35 @@ __device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], do
   __syncthreads();
 }
 
-// Per-element sums (GLL weights, without |J_K|), minima and maxima of 5 fields held in LDS,
-// plus the raw-average admissibility test (NaN-safe).
+// Per-element sums (GLL weights, without |J_K|), minima and maxima of 5 fields held in LDS rows
+// 0..4 of svf, plus the raw-average admissibility test (NaN-safe) from the five sums.  Rows 5..6
+// (at least 5 values per element) take the sums; every thread of the block must call this.
 template <class C>
-__device__ __forceinline__ void element_stats(const double* svf, bool act, int el, int q, long e,
+__device__ __forceinline__ void element_stats(double* svf, bool act, int el, int q, long e,
                                               double* __restrict__ stats, int* __restrict__ flag,
                                               const HydroTab* __restrict__ T, double g) {
   constexpr int NP = C::NP, NN = C::NN, S = C::EB * C::NN;
   auto sv = [&](int c, int k) { return svf[c * S + k]; };
-  // tasks 0..14: (component, kind) statistics; task 15: admissibility of the raw average
-  for (int t = q; act && t < 16; t += NN) {
-    if (t < 15) {
-      const int c = t / 3, kind = t - 3 * c;
-      double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
-      for (int k = 0; k < NN; ++k) {
-        const double v = sv(c, el * NN + k);
-        s += (T->w[k % NP] * T->w[k / NP]) * v;
-        mn = fmin(mn, v); mx = fmax(mx, v);
-      }
-      stats[(e * 5 + c) * 3 + kind] = kind == 0 ? s : (kind == 1 ? mn : mx);
-    } else if (flag) {
-      double a[5];
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        double s = 0.0;
-        for (int k = 0; k < NN; ++k) s += (T->w[k % NP] * T->w[k / NP]) * sv(c, el * NN + k);
-        a[c] = 0.25 * s;
-      }
-      const double pb = (g - 1.0) * (a[4] - (a[1] * a[1] + a[2] * a[2] + a[3] * a[3]) / (2.0 * a[0]));
-      if (!(a[0] > 0.0) || !(pb > 0.0)) atomicOr(flag, 1);
+  double* ssum = svf + 5 * S + el * 5;
+  for (int t = q; act && t < 15; t += NN) {
+    const int c = t / 3, kind = t - 3 * c;
+    double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+    for (int k = 0; k < NN; ++k) {
+      const double v = sv(c, el * NN + k);
+      s += (T->w[k % NP] * T->w[k / NP]) * v;
+      mn = fmin(mn, v); mx = fmax(mx, v);
     }
+    stats[(e * 5 + c) * 3 + kind] = kind == 0 ? s : (kind == 1 ? mn : mx);
+    if (kind == 0) ssum[c] = s;
+  }
+  if (!flag) return;
+  __syncthreads();
+  if (act && q == 0) {
+    double a[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) a[c] = 0.25 * ssum[c];
+    const double pb = (g - 1.0) * (a[4] - (a[1] * a[1] + a[2] * a[2] + a[3] * a[3]) / (2.0 * a[0]));
+    if (!(a[0] > 0.0) || !(pb > 0.0)) atomicOr(flag, 1);
   }
 }
 
@@ -208,8 +219,10 @@ __global__ __launch_bounds__(BS) void k_hydro_stage(const double* __restrict__ U
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, ND = C::ND;
   __shared__ double sp[7][EB * NN];
   __shared__ double sb[EB * NP * NP * (ND > 0 ? ND : 1) * 5];
+  __shared__ double tS[NP * NP];
   __shared__ int sflag;
   const int tid = threadIdx.x;
+  if (tid < NP * NP) tS[tid] = T->Shat[tid / NP][tid % NP];
   if (MODE == 1) {  // skip stages after a rejected one; read once per block (other blocks may set it)
     if (tid == 0) sflag = __atomic_load_n(flag, __ATOMIC_RELAXED);
     __syncthreads();
@@ -230,8 +243,8 @@ __global__ __launch_bounds__(BS) void k_hydro_stage(const double* __restrict__ U
     sp[4][tid] = me.b; sp[5][tid] = me.lr; sp[6][tid] = me.lb;
   }
   __syncthreads();
-  volume_dir<P, 0, BS>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, T, mp, iface);
-  volume_dir<P, 1, BS>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, T, mp, iface);
+  volume_dir<P, 0, BS>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, tS, T, mp, iface);
+  volume_dir<P, 1, BS>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, tS, T, mp, iface);
   if (MODE == 0) {
     if (act) {
 #pragma unroll
@@ -258,7 +271,7 @@ __global__ __launch_bounds__(256) void k_elem_stats(const double* __restrict__ U
                                                     int* __restrict__ flag, const HydroTab* __restrict__ T, MeshP mp) {
   using C = Cfg<P>;
   constexpr int NN = C::NN, EB = C::EB;
-  __shared__ double sv[5][EB * NN];
+  __shared__ double sv[7][EB * NN];
   const int tid = threadIdx.x;
   const int el = tid / NN, q = tid - el * NN;
   const long e = (long)blockIdx.x * EB + el;
@@ -292,8 +305,14 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
   __shared__ double st[10][EB * NN];
   __shared__ double ssig[EB][2][NP];
   __shared__ double sD[EB][NP];
+  __shared__ double tD0[NP][NP], tDp[NP][NP], tTf[NP][NP], tV[NP][NP], tw[NP], tfr[NP];
   if (flag && *flag) return;
   const int tid = threadIdx.x;
+  for (int t = tid; t < NP * NP; t += 256) {
+    const int a = t / NP, b = t - a * NP;
+    tD0[a][b] = T->Dr0[a][b]; tDp[a][b] = T->Drp[a][b]; tTf[a][b] = T->Tf[a][b]; tV[a][b] = T->V[a][b];
+  }
+  if (tid < NP) { tw[tid] = T->w[tid]; tfr[tid] = T->fr[tid]; }
   const int el = tid / NN, q = tid - el * NN;
   const int i = q % NP, j = q / NP;
   const long e = (long)blockIdx.x * EB + el;
@@ -327,29 +346,45 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
     }
 #pragma unroll
     for (int D = 0; D < 2; ++D) {
-      // normal-jump contributions (eq. euler-oe-jump): thread (r, line)
-      const int r = D == 0 ? i : j, line = D == 0 ? j : i;
+      // neighbours across the two faces normal to direction D, staged in st rows 0..9
+      // (row c: minus-side neighbour, row 5 + c: plus-side neighbour) with coalesced loads
       if (act) {
         long em, ep;
         if (D == 0) { em = ey * mp.nx + wrap(ex - 1, mp.nx); ep = ey * mp.nx + wrap(ex + 1, mp.nx); }
         else { em = wrap(ey - 1, mp.ny) * mp.nx + ex; ep = wrap(ey + 1, mp.ny) * mp.nx + ex; }
-        const double wl = 0.5 * T->w[line];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          st[c][tid] = Ust[c * KN + em * NN + q];
+          st[5 + c][tid] = Ust[c * KN + ep * NN + q];
+        }
+      }
+      __syncthreads();
+      // normal-jump contributions (eq. euler-oe-jump): thread (r, line)
+      const int r = D == 0 ? i : j, line = D == 0 ? j : i;
+      double jmp[10];
+      if (act) {
+        const double wl = 0.5 * tw[line];
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
           double a = 0.0, d = 0.0, b = 0.0, cc = 0.0;
 #pragma unroll
           for (int k = 0; k < NP; ++k) {
-            const int nk = D == 0 ? line * NP + k : k * NP + line;
-            const double own = su[c][el * NN + nk];
-            a += T->Dr0[r][k] * own;
-            d += T->Drp[r][k] * own;
-            b += T->Drp[r][k] * Ust[c * KN + em * NN + nk];
-            cc += T->Dr0[r][k] * Ust[c * KN + ep * NN + nk];
+            const int nk = el * NN + (D == 0 ? line * NP + k : k * NP + line);
+            const double own = su[c][nk];
+            a += tD0[r][k] * own;
+            d += tDp[r][k] * own;
+            b += tDp[r][k] * st[c][nk];
+            cc += tD0[r][k] * st[5 + c][nk];
           }
           const double jm = a - b, jp = cc - d;
-          st[2 * c][tid] = wl * jm * jm;
-          st[2 * c + 1][tid] = wl * jp * jp;
+          jmp[2 * c] = wl * jm * jm;
+          jmp[2 * c + 1] = wl * jp * jp;
         }
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < 10; ++c) st[c][tid] = jmp[c];
       }
       __syncthreads();
       if (act && q < NP) {
@@ -365,7 +400,7 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
               sm += st[2 * c][el * NN + nk];
               spp += st[2 * c + 1][el * NN + nk];
             }
-            sig = fmax(sig, T->fr[rr] * (sqrt(sm) + sqrt(spp)) / Dsh[D]);
+            sig = fmax(sig, tfr[rr] * (sqrt(sm) + sqrt(spp)) / Dsh[D]);
           }
         }
         ssig[el][D][rr] = sig;
@@ -394,7 +429,7 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
       for (int c = 0; c < 5; ++c) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) s += T->Tf[i][k] * su[c][el * NN + j * NP + k];
+        for (int k = 0; k < NP; ++k) s += tTf[i][k] * su[c][el * NN + j * NP + k];
         st[c][tid] = s;  // [j][a=i]
       }
     }
@@ -405,7 +440,7 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
       for (int c = 0; c < 5; ++c) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) s += T->Tf[j][k] * st[c][el * NN + k * NP + i];
+        for (int k = 0; k < NP; ++k) s += tTf[j][k] * st[c][el * NN + k * NP + i];
         st[5 + c][tid] = dmp * s;  // coefficient [b=j][a=i]
       }
     }
@@ -415,7 +450,7 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
       for (int c = 0; c < 5; ++c) {
         double s = 0.0;
 #pragma unroll
-        for (int a = 0; a < NP; ++a) s += T->V[i][a] * st[5 + c][el * NN + j * NP + a];
+        for (int a = 0; a < NP; ++a) s += tV[i][a] * st[5 + c][el * NN + j * NP + a];
         su[c][tid] = s;  // [b=j][i]
       }
     }
@@ -425,7 +460,7 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
       for (int c = 0; c < 5; ++c) {
         double s = 0.0;
 #pragma unroll
-        for (int b = 0; b < NP; ++b) s += T->V[j][b] * su[c][el * NN + b * NP + i];
+        for (int b = 0; b < NP; ++b) s += tV[j][b] * su[c][el * NN + b * NP + i];
         U[c] = s;
       }
     }
@@ -438,19 +473,29 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
   }
   uint8_t f = 0;
   if (do_pp) {
-    // positivity scaling: each node's derived quantities are computed once and reduced over the
-    // element through LDS (st rows 0..2 are free after the modal damping)
+    // positivity scaling: element reductions are taken once per element (six tasks for the
+    // averages and the density minimum, thread 0 for S_p and the pressure minimum) and broadcast
+    // through LDS; st rows 0..2 are free after the modal damping, rows 3..4 hold the results
     const double eps_r = 64.0 * EPSM;
+    double* red = &st[3][0] + el * 8;  // [0..4] averages, [5] min rho, [6] S, [7] min p
+    for (int t = q; act && t < 6; t += NN) {  // NN < 6 only for p = 1
+      if (t < 5) {
+        double s = 0.0;
+        for (int k = 0; k < NN; ++k) s += (tw[k % NP] * tw[k / NP]) * su[t][el * NN + k];
+        red[t] = 0.25 * s;
+      } else {
+        double rmin = DBL_MAX;
+        for (int k = 0; k < NN; ++k) rmin = fmin(rmin, su[0][el * NN + k]);
+        red[5] = rmin;
+      }
+    }
+    __syncthreads();
     double a[5] = {0, 0, 0, 0, 0};
     double rmin = DBL_MAX;
     if (act) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        double s = 0.0;
-        for (int k = 0; k < NN; ++k) s += (T->w[k % NP] * T->w[k / NP]) * su[c][el * NN + k];
-        a[c] = 0.25 * s;
-      }
-      for (int k = 0; k < NN; ++k) rmin = fmin(rmin, su[0][el * NN + k]);
+      for (int c = 0; c < 5; ++c) a[c] = red[c];
+      rmin = red[5];
     }
     const bool collapse_r = !(a[0] > eps_r);
     double thr = 1.0;
@@ -464,9 +509,14 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
       st[1][tid] = pres(U, g);
     }
     __syncthreads();
-    if (act && !collapse_r) {
+    if (act && q == 0) {
       double S = Sp(a, eps_r), pmin = DBL_MAX;
       for (int k = 0; k < NN; ++k) { S = fmax(S, st[0][el * NN + k]); pmin = fmin(pmin, st[1][el * NN + k]); }
+      red[6] = S; red[7] = pmin;
+    }
+    __syncthreads();
+    if (act && !collapse_r) {
+      const double S = red[6], pmin = red[7];
       const double eps_p = fmax(64.0 * EPSM, 8192.0 * EPSM * S);
       const double pb = pres(a, g);
       if (pb <= eps_p) {

@@ -495,71 +495,104 @@ struct VP {
   static constexpr int NP = P + 1, NN = NP * NP, EB = 64 / NN > 0 ? 64 / NN : 1;
 };
 
+// One wave per block (EB elements).  Thread q holds row q of the element's Gram matrix in
+// registers; the right-looking Cholesky broadcasts the pivot and column k through LDS at step k
+// (two barriers per step), and the trailing update reads are independent of each other.  The 1D Legendre table and the shell
+// order are read from LDS.
 template <int P>
 __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho, double* __restrict__ Psi,
                                                  const HydroTab* __restrict__ H, MeshP mp) {
   constexpr int NP = P + 1, NN = NP * NP, EB = VP<P>::EB;
-  __shared__ double sw[EB][NN], sH[EB][NP][NP * NP], sG[EB][NN][NN + 1];
-  const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
+  __shared__ double sw[EB][NN], sH[EB][NP][NP * NP], sL[EB][NN][NN + 1], sP[EB][NN][NN + 1], scol[EB][NN];
+  __shared__ double srd[EB][NN], sdg[EB];
+  __shared__ double sV[NP][NP];
+  __shared__ int ska[NN], skb[NN];
+  const int tid = threadIdx.x, el0 = tid / NN;
+  const bool act0 = el0 < EB && (long)blockIdx.x * EB + el0 < mp.K;
+  const int el = act0 ? el0 : 0, q = act0 ? tid - el0 * NN : 0;  // idle lanes shadow lane 0
   const int qi = q % NP, qj = q / NP;
   const long e = (long)blockIdx.x * EB + el;
-  const bool act = el < EB && e < mp.K;
-  if (act) sw[el][q] = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
+  for (int t = tid; t < NP * NP; t += 64) sV[t / NP][t % NP] = H->V[t / NP][t % NP];
+  for (int t = tid; t < NN; t += 64) { ska[t] = H->ka[t]; skb[t] = H->kb[t]; }
+  if (act0) sw[el][q] = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
   __syncthreads();
   // sum factorisation: Hm[qj][a][a'] = sum_qi W[qj][qi] V[qi][a] V[qi][a']
-  if (act)
+  if (act0)
     for (int t = q; t < NP * NP * NP; t += NN) {
       const int jj = t / (NP * NP), aa = t - jj * NP * NP, a = aa / NP, a2 = aa - a * NP;
       double s = 0.0;
 #pragma unroll
-      for (int ii = 0; ii < NP; ++ii) s += sw[el][jj * NP + ii] * H->V[ii][a] * H->V[ii][a2];
+      for (int ii = 0; ii < NP; ++ii) s += sw[el][jj * NP + ii] * sV[ii][a] * sV[ii][a2];
       sH[el][jj][aa] = s;
     }
   __syncthreads();
-  if (act) {  // Gram row q (shell order): G[k][k'] = sum_qj V[qj][b] V[qj][b'] Hm[qj][a][a']
-    const int ka = H->ka[q], kb = H->kb[q];
+  // Gram row q (shell order): G[q][k'] = sum_qj V[qj][b] V[qj][b'] Hm[qj][a][a'], k' <= q
+  if (act0) {
+    const int ka = ska[q], kb = skb[q];
     for (int k2 = 0; k2 <= q; ++k2) {
-      const int a2 = H->ka[k2], b2 = H->kb[k2];
+      const int a2 = ska[k2], b2 = skb[k2];
       double s = 0.0;
 #pragma unroll
-      for (int jj = 0; jj < NP; ++jj) s += H->V[jj][kb] * H->V[jj][b2] * sH[el][jj][ka * NP + a2];
-      sG[el][q][k2] = s;
+      for (int jj = 0; jj < NP; ++jj) s += sV[jj][kb] * sV[jj][b2] * sH[el][jj][ka * NP + a2];
+      sL[el][q][k2] = s;
     }
   }
   __syncthreads();
-  for (int k = 0; k < NN; ++k) {  // Cholesky, lower triangle in place
-    if (act && q > k) sG[el][q][k] /= sqrt(sG[el][k][k]);
-    __syncthreads();
-    if (act) {
-      if (q == k) sG[el][k][k] = sqrt(sG[el][k][k]);
-      else if (q > k)
-        for (int jj = k + 1; jj <= q; ++jj) sG[el][q][jj] -= sG[el][q][k] * sG[el][jj][k];
-    }
-    __syncthreads();
-  }
-  double psi[NN];
+  double g[NN];
+#pragma unroll
+  for (int k2 = 0; k2 < NN; ++k2) g[k2] = k2 <= q ? sL[el][q][k2] : 0.0;
+  // Cholesky G = L L^T; after step k, g[k] = L[q][k] (q >= k), srd[k] = 1 / L[k][k]
+  // (the diagonal goes through sdg, the column through scol: a column is only rewritten after the
+  // next step's first barrier, which every thread reaches after its updates of this step)
 #pragma unroll
   for (int k = 0; k < NN; ++k) {
-    double s = act ? H->V[qi][H->ka[k]] * H->V[qj][H->kb[k]] : 0.0;
+    if (act0 && q == k) sdg[el] = g[k];
+    __syncthreads();
+    const double rk = 1.0 / sqrt(sdg[el]);
+    if (q >= k) g[k] *= rk;
+    if (act0 && q > k) scol[el][q] = g[k];
+    if (act0 && q == k) srd[el][k] = rk;
+    __syncthreads();
 #pragma unroll
-    for (int k2 = 0; k2 < k; ++k2) s -= (act ? sG[el][k][k2] : 0.0) * psi[k2];
-    psi[k] = act ? s / sG[el][k][k] : 0.0;
+    for (int jj = k + 1; jj < NN; ++jj)
+      if (jj <= q && q > k) g[jj] -= g[k] * scol[el][jj];
   }
-  __syncthreads();
-  if (act)
+  // L rows to LDS; row q of Psi = Phi L^{-T} by forward substitution over the modes (in LDS)
 #pragma unroll
-    for (int k = 0; k < NN; ++k) sG[el][q][k] = psi[k];
+  for (int k = 0; k < NN; ++k)
+    if (act0 && k <= q) sL[el][q][k] = g[k];
+  __syncthreads();
+  if (act0) {
+    for (int k = 0; k < NN; ++k) {
+      double s = sV[qi][ska[k]] * sV[qj][skb[k]];
+#pragma unroll 4
+      for (int k2 = 0; k2 < k; ++k2) s -= sL[el][k][k2] * sP[el][q][k2];
+      sP[el][q][k] = s * srd[el][k];
+    }
+  }
   __syncthreads();
   // coalesced store of the element's Psi[q][k]
   for (int t = tid; t < EB * NN * NN; t += 64) {
     const int ee = t / (NN * NN), r = t - ee * NN * NN;
     const long eg = (long)blockIdx.x * EB + ee;
-    if (eg < mp.K) Psi[eg * NN * NN + r] = sG[ee][r / NN][r % NN];
+    if (eg < mp.K) Psi[eg * NN * NN + r] = sP[ee][r / NN][r % NN];
   }
 }
 
+template <int P, int M>
+struct VA {
+  static constexpr int NP = P + 1, NN = NP * NP, EB = 256 / NN, NNP = NN | 1;  // odd LDS row stride
+  static constexpr int A = M + 2, B = M + 1, AB = A * B, BB = B * B;
+  // per-element LDS region, reused: sensor phase (jumps, wave speeds, B coefficients), then the
+  // element's Psi tile
+  static constexpr int R1 = 6 * NN + 2 * NN + 2 * AB + BB, R2 = NN * NNP;
+  static constexpr int RE = R1 > R2 ? R1 : R2;
+};
+
 // uin: snapshot of the raw stage velocity (neighbour jumps must not see updated elements);
-// u: updated in place (own element only)
+// u: updated in place (own element only).  The element's Psi tile is staged in LDS with one
+// coalesced block-wide copy, so the coefficient pass (columns) and the evaluation pass (rows)
+// both read LDS.
 template <int P, int M>
 __global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rho, const double* __restrict__ uin,
                                                    double* __restrict__ u, double* __restrict__ en, const double* __restrict__ Bx,
@@ -567,33 +600,50 @@ __global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rh
                                                    const double* __restrict__ Psi, const double* __restrict__ lines,
                                                    const double* __restrict__ glob, const HydroTab* __restrict__ H,
                                                    const MagTab* __restrict__ T, MeshP mp, double tau, double sM) {
-  constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1, AB = A * B, BB = B * B;
-  constexpr int EB = 256 / NN;
-  __shared__ double su[EB][3][NN], sw[EB][NN];
-  __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
-  __shared__ double sjmp[EB][6][NN], ssig[EB][2][NP], sD[EB][NP], sva[EB][2][NN], sc[EB][3][NN];
+  using C = VA<P, M>;
+  constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NNP = C::NNP, A = C::A, B = C::B, AB = C::AB, RE = C::RE;
+  __shared__ double su[EB][3][NN], sw[EB][NN], sc[EB][3][NN], ssig[EB][2][NP], sD[EB][NP];
+  __shared__ double sreg[EB * RE];
+  __shared__ double tD0[NP][NP], tDp[NP][NP], tWP[NP][A], tGP[NP][B], tVP[NP][B], tw[NP], tfr[NP];
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
   const int qi = q % NP, qj = q / NP;
-  const long e = (long)blockIdx.x * EB + el;
+  const long e0 = (long)blockIdx.x * EB, e = e0 + el;
   const bool act = el < EB && e < mp.K;
   const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
   const long KN = mp.K * NN;
-  const double* Pe = Psi + (act ? e : 0) * NN * NN;  // Pe[n*NN + k] = psi_k(x_n)
+  double* R = sreg + (act ? el : 0) * RE;
+  double* sjmp = R;               // [6][NN]
+  double* sva = R + 6 * NN;       // [2][NN]
+  double* sbx = sva + 2 * NN;     // [B][A]
+  double* sby = sbx + AB;         // [A][B]
+  double* sbz = sby + AB;         // [B][B]
+  for (int t = tid; t < NP * NP; t += 256) {
+    tD0[t / NP][t % NP] = H->Dr0[t / NP][t % NP];
+    tDp[t / NP][t % NP] = H->Drp[t / NP][t % NP];
+  }
+  for (int t = tid; t < NP * A; t += 256) tWP[t / A][t % A] = T->I_W_P[t / A][t % A];
+  for (int t = tid; t < NP * B; t += 256) {
+    tGP[t / B][t % B] = T->I_G_P[t / B][t % B];
+    tVP[t / B][t % B] = T->I_V_P[t / B][t % B];
+  }
+  if (tid < NP) { tw[tid] = H->w[tid]; tfr[tid] = H->fr[tid]; }
   double uu[3] = {0.0, 0.0, 0.0}, rq = 1.0;
   if (act) {
+#pragma unroll
     for (int d = 0; d < 3; ++d) { uu[d] = uin[d * KN + e * NN + q]; su[el][d][q] = uu[d]; }
     rq = rho[e * NN + q];
-    sw[el][q] = mp.J * H->w[qi] * H->w[qj] * rq;
     for (int k = q; k < AB; k += NN) {
-      sbx[el][k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];
-      sby[el][k] = By[gix(mp, B, ex, ey, k % B, k / B)];
+      sbx[k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];
+      sby[k] = By[gix(mp, B, ex, ey, k % B, k / B)];
     }
-    for (int k = q; k < BB; k += NN) sbz[el][k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
+    for (int k = q; k < C::BB; k += NN) sbz[k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
   }
   __syncthreads();
+  if (act) sw[el][q] = mp.J * tw[qi] * tw[qj] * rq;
   double Dsh[2] = {0.0, 0.0};
   bool cst[3] = {false, false, false};
   if (act) {
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double gs = glob[c * 3], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
       const double gm = gs / (4.0 * (double)mp.K);
@@ -610,63 +660,66 @@ __global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rh
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sbx[el][j * A + i];
-      bxv += T->I_G_P[qj][j] * s;
+      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sbx[j * A + i];
+      bxv += tGP[qj][j] * s;
     }
 #pragma unroll
     for (int j = 0; j < A; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += T->I_G_P[qi][i] * sby[el][j * B + i];
-      byv += T->I_W_P[qj][j] * s;
+      for (int i = 0; i < B; ++i) s += tGP[qi][i] * sby[j * B + i];
+      byv += tWP[qj][j] * s;
     }
 #pragma unroll
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += T->I_V_P[qi][i] * sbz[el][j * B + i];
-      bzv += T->I_V_P[qj][j] * s;
+      for (int i = 0; i < B; ++i) s += tVP[qi][i] * sbz[j * B + i];
+      bzv += tVP[qj][j] * s;
     }
     const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) / sqrt(rq);
-    sva[el][0][q] = fabs(uu[0]) + va;
-    sva[el][1][q] = fabs(uu[1]) + va;
+    sva[q] = fabs(uu[0]) + va;
+    sva[NN + q] = fabs(uu[1]) + va;
   }
+#pragma unroll
   for (int D = 0; D < 2; ++D) {
     const int r = D == 0 ? qi : qj, line = D == 0 ? qj : qi;
     if (act) {
       long em, ep;
       if (D == 0) { em = ey * mp.nx + wrapl(ex - 1, mp.nx); ep = ey * mp.nx + wrapl(ex + 1, mp.nx); }
       else { em = wrapl(ey - 1, mp.ny) * mp.nx + ex; ep = wrapl(ey + 1, mp.ny) * mp.nx + ex; }
-      const double wl = 0.5 * H->w[line];
+      const double wl = 0.5 * tw[line];
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
         double a = 0.0, d = 0.0, b = 0.0, cc = 0.0;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
           const int nk = D == 0 ? line * NP + k : k * NP + line;
           const double own = su[el][c][nk];
-          a += H->Dr0[r][k] * own;
-          d += H->Drp[r][k] * own;
-          b += H->Drp[r][k] * uin[c * KN + em * NN + nk];
-          cc += H->Dr0[r][k] * uin[c * KN + ep * NN + nk];
+          a += tD0[r][k] * own;
+          d += tDp[r][k] * own;
+          b += tDp[r][k] * uin[c * KN + em * NN + nk];
+          cc += tD0[r][k] * uin[c * KN + ep * NN + nk];
         }
         const double jm = a - b, jp = cc - d;
-        sjmp[el][2 * c][q] = wl * jm * jm;
-        sjmp[el][2 * c + 1][q] = wl * jp * jp;
+        sjmp[2 * c * NN + q] = wl * jm * jm;
+        sjmp[(2 * c + 1) * NN + q] = wl * jp * jp;
       }
     }
     __syncthreads();
     if (act && q < NP) {
       double sig = 0.0;
       if (Dsh[D] > 0.0) {
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
           if (cst[c]) continue;
           double sm = 0.0, spp = 0.0;
           for (int l = 0; l < NP; ++l) {
             const int nk = D == 0 ? l * NP + q : q * NP + l;
-            sm += sjmp[el][2 * c][nk];
-            spp += sjmp[el][2 * c + 1][nk];
+            sm += sjmp[2 * c * NN + nk];
+            spp += sjmp[(2 * c + 1) * NN + nk];
           }
-          sig = fmax(sig, H->fr[q] * (sqrt(sm) + sqrt(spp)) / Dsh[D]);
+          sig = fmax(sig, tfr[q] * (sqrt(sm) + sqrt(spp)) / Dsh[D]);
         }
       }
       ssig[el][D][q] = sig;
@@ -678,37 +731,59 @@ __global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rh
       sD[el][0] = 1.0;
     } else {
       double ax = 0.0, ay = 0.0;
-      for (int k = 0; k < NN; ++k) { ax = fmax(ax, sva[el][0][k]); ay = fmax(ay, sva[el][1][k]); }
+      for (int k = 0; k < NN; ++k) { ax = fmax(ax, sva[k]); ay = fmax(ay, sva[NN + k]); }
       const double lx = (2.0 * P + 1.0) / mp.hx * ax, ly = (2.0 * P + 1.0) / mp.hy * ay;
       double sx = 0.0, sy = 0.0;
       for (int r = 0; r <= q; ++r) { sx += ssig[el][0][r]; sy += ssig[el][1][r]; }
       sD[el][q] = exp(-sM * tau * (lx * sx + ly * sy));
     }
   }
-  // expansion coefficients c_k = (u_d, psi_k)_rho, thread q computes mode k = q
-  if (act) {
-    for (int d = 0; d < 3; ++d) {
-      double s = 0.0;
-#pragma unroll
-      for (int n = 0; n < NN; ++n) s += sw[el][n] * su[el][d][n] * Pe[n * NN + q];
-      sc[el][d][q] = s;
+  __syncthreads();  // the sensor-phase region is free from here on
+  {
+    const long nel = mp.K - e0 < EB ? mp.K - e0 : EB;
+    const double* src = Psi + e0 * NN * NN;
+    for (long t = tid; t < nel * NN * NN; t += 256) {
+      const int ee = (int)(t / (NN * NN)), rr = (int)(t - (long)ee * NN * NN);
+      sreg[ee * RE + (rr / NN) * NNP + rr % NN] = src[t];
     }
   }
   __syncthreads();
+  const double* Pe = R;  // Pe[n * NNP + k] = psi_k(x_n)
+  // expansion coefficients c_k = (u_d, psi_k)_rho, thread q computes mode k = q
+  if (act) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (int n = 0; n < NN; ++n) {
+      const double wp = sw[el][n] * Pe[n * NNP + q];
+      s0 += wp * su[el][0][n];
+      s1 += wp * su[el][1][n];
+      s2 += wp * su[el][2][n];
+    }
+    sc[el][0][q] = s0; sc[el][1][q] = s1; sc[el][2][q] = s2;
+  }
+  __syncthreads();
   if (!act) return;
+  double wl[3][NP];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int l = 0; l < NP; ++l) wl[d][l] = 0.0;
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    const double pk = Pe[q * NNP + k];
+    wl[0][shell_of(k)] += sc[el][0][k] * pk;
+    wl[1][shell_of(k)] += sc[el][1][k] * pk;
+    wl[2][shell_of(k)] += sc[el][2][k] * pk;
+  }
   double heat = 0.0;
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
-    double wl[NP];
-#pragma unroll
-    for (int l = 0; l < NP; ++l) wl[l] = 0.0;
-#pragma unroll
-    for (int k = 0; k < NN; ++k) wl[shell_of(k)] += sc[el][d][k] * Pe[q * NN + k];
-    double v = wl[0];
+    double v = wl[d][0];
 #pragma unroll
     for (int l = 1; l < NP; ++l) {
       const double Dl = sD[el][l];
-      v += Dl * wl[l];
-      heat += 0.5 * (1.0 - Dl * Dl) * wl[l] * wl[l];
+      v += Dl * wl[d][l];
+      heat += 0.5 * (1.0 - Dl * Dl) * wl[d][l] * wl[d][l];
     }
     u[d * KN + e * NN + q] = v;
   }
@@ -716,28 +791,118 @@ __global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rh
 }
 
 // ---------------------------------------------------------------------------------------------
-// Artificial resistivity (eq. magnetic-ar-sensor, eq. magnetic-ar-coefficient); one thread per element.
-// bglob[3][3]: (integral, min, max) of B_x, B_y, B_z over the domain.
+// Artificial resistivity (eq. magnetic-ar-sensor, eq. magnetic-ar-coefficient) in two passes.
+// Pass 1 (one thread per GLL_p node, B coefficients staged in LDS): each element's tangential
+// traces on its four faces at the (m+2) face Gauss points and the element maxima of |u_I| + |B|/sqrt(rho)
+// over its GLL_p nodes -> tr[K][8A + 2], trace index ((dir*2 + it)*2 + side)*A + k; dir 0 holds the
+// x-faces (it 0: B_y, it 1: B_z), dir 1 the y-faces (it 0: B_x, it 1: B_z); side 0 is the face at -1.
+// Pass 2 (one thread per element): squared jumps against the neighbours' traces, sigma^B, R, eta.
 // ---------------------------------------------------------------------------------------------
 template <int P, int M>
-__global__ __launch_bounds__(128) void k_ar_eta(const double* __restrict__ rho, const double* __restrict__ u,
-                                                const double* __restrict__ Bx, const double* __restrict__ By,
-                                                const double* __restrict__ Bz, const double* __restrict__ bglob,
+__global__ __launch_bounds__(256) void k_ar_traces(const double* __restrict__ rho, const double* __restrict__ u,
+                                                   const double* __restrict__ Bx, const double* __restrict__ By,
+                                                   const double* __restrict__ Bz, double* __restrict__ tr,
+                                                   const MagTab* __restrict__ T, MeshP mp) {
+  constexpr int NP = P + 1, NN = NP * NP, EB = 256 / NN, A = M + 2, B = M + 1, AB = A * B, BB = B * B;
+  constexpr int NT = 8 * A + 2;
+  __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB], sv[EB][2][NN];
+  __shared__ double tWP[NP][A], tGP[NP][B], tVP[NP][B], tWQ[A][A], tVQ[A][B], tGE[2][B], tVE[2][B];
+  const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN, qi = q % NP, qj = q / NP;
+  const long e = (long)blockIdx.x * EB + el;
+  const bool act = el < EB && e < mp.K;
+  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0, KN = mp.K * NN;
+  for (int t = tid; t < NP * A; t += 256) tWP[t / A][t % A] = T->I_W_P[t / A][t % A];
+  for (int t = tid; t < NP * B; t += 256) {
+    tGP[t / B][t % B] = T->I_G_P[t / B][t % B];
+    tVP[t / B][t % B] = T->I_V_P[t / B][t % B];
+  }
+  for (int t = tid; t < A * A; t += 256) tWQ[t / A][t % A] = T->I_W_Q[t / A][t % A];
+  for (int t = tid; t < A * B; t += 256) tVQ[t / B][t % B] = T->I_V_Q[t / B][t % B];
+  for (int t = tid; t < 2 * B; t += 256) {
+    tGE[t / B][t % B] = T->I_G_E[t / B][t % B];
+    tVE[t / B][t % B] = T->I_V_E[t / B][t % B];
+  }
+  if (act) {
+    for (int k = q; k < AB; k += NN) {
+      sbx[el][k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];  // [j<B][i<A]
+      sby[el][k] = By[gix(mp, B, ex, ey, k % B, k / B)];  // [j<A][i<B]
+    }
+    for (int k = q; k < BB; k += NN) sbz[el][k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
+  }
+  __syncthreads();
+  double* o = tr + (act ? e : 0) * NT;
+  if (act) {
+    double bxv = 0.0, byv = 0.0, bzv = 0.0;
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sbx[el][j * A + i];
+      bxv += tGP[qj][j] * s;
+    }
+#pragma unroll
+    for (int j = 0; j < A; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) s += tGP[qi][i] * sby[el][j * B + i];
+      byv += tWP[qj][j] * s;
+    }
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = 0; i < B; ++i) s += tVP[qi][i] * sbz[el][j * B + i];
+      bzv += tVP[qj][j] * s;
+    }
+    const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) / sqrt(rho[e * NN + q]);
+    sv[el][0][q] = fabs(u[e * NN + q]) + va;
+    sv[el][1][q] = fabs(u[KN + e * NN + q]) + va;
+    for (int t = q; t < 8 * A; t += NN) {
+      const int k = t % A, s = (t / A) % 2, it = (t / (2 * A)) % 2, dir = t / (4 * A);
+      double v = 0.0;
+      if (it == 1) {  // B_z: GLL_m x GLL_m
+        for (int j = 0; j < B; ++j)
+          for (int i = 0; i < B; ++i)
+            v += (dir == 0 ? tVE[s][i] * tVQ[k][j] : tVQ[k][i] * tVE[s][j]) * sbz[el][j * B + i];
+      } else if (dir == 0) {  // B_y on x-faces: Gauss_m in x, GLL_{m+1} in y
+        for (int j = 0; j < A; ++j)
+          for (int i = 0; i < B; ++i) v += tGE[s][i] * tWQ[k][j] * sby[el][j * B + i];
+      } else {  // B_x on y-faces: GLL_{m+1} in x, Gauss_m in y
+        for (int j = 0; j < B; ++j)
+          for (int i = 0; i < A; ++i) v += tWQ[k][i] * tGE[s][j] * sbx[el][j * A + i];
+      }
+      o[t] = v;
+    }
+  }
+  __syncthreads();
+  if (act && q < 2) {
+    double m = 0.0;
+    for (int k = 0; k < NN; ++k) m = fmax(m, sv[el][q][k]);
+    o[8 * A + q] = m;
+  }
+}
+
+// bglob[3][3]: (integral, min, max) of B_x, B_y, B_z over the domain.
+template <int P, int M>
+__global__ __launch_bounds__(256) void k_ar_eta(const double* __restrict__ tr, const double* __restrict__ bglob,
                                                 double* __restrict__ eta, const MagTab* __restrict__ T, MeshP mp,
                                                 double Cs, double Ceta) {
-  constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1;
+  constexpr int A = M + 2, NT = 8 * A + 2;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= mp.K) return;
   const long ex = e % mp.nx, ey = e / mp.nx;
   double dOm[3];
   bool cf[3];
   const double area = (double)mp.K * mp.hx * mp.hy;
+#pragma unroll
   for (int c = 0; c < 3; ++c) {
     const double mean = bglob[c * 3] / area, mn = bglob[c * 3 + 1], mx = bglob[c * 3 + 2];
     dOm[c] = fmax(mx - mean, mean - mn);
     cf[c] = dOm[c] <= 1024.0 * EPSM * fmax(fabs(mx), fabs(mn));
   }
+  const double* me = tr + e * NT;
   double R[2];
+#pragma unroll
   for (int dir = 0; dir < 2; ++dir) {
     const int t0 = dir == 0 ? 1 : 0;
     const double DB = fmax(cf[t0] ? 0.0 : dOm[t0], cf[2] ? 0.0 : dOm[2]);
@@ -745,34 +910,16 @@ __global__ __launch_bounds__(128) void k_ar_eta(const double* __restrict__ rho, 
     if (DB > 0.0) {
       const long em = dir == 0 ? ey * mp.nx + wrapl(ex - 1, mp.nx) : wrapl(ey - 1, mp.ny) * mp.nx + ex;
       const long ep = dir == 0 ? ey * mp.nx + wrapl(ex + 1, mp.nx) : wrapl(ey + 1, mp.ny) * mp.nx + ex;
-      const int tcs[2] = {t0, 2};
+      const double* tm = tr + em * NT;
+      const double* tp = tr + ep * NT;
+#pragma unroll
       for (int it = 0; it < 2; ++it) {
-        const int tc = tcs[it];
-        if (cf[tc]) continue;
-        // trace of component tc of element `el` on its side s (0: -1, 1: +1) at face Gauss point k
-        auto trace = [&](long el, int s, int k) {
-          const long exl = el % mp.nx, eyl = el / mp.nx;
-          double v = 0.0;
-          if (tc == 2) {  // B_z: GLL_m x GLL_m
-            for (int j = 0; j < B; ++j)
-              for (int i = 0; i < B; ++i) {
-                const double wgt = dir == 0 ? T->I_V_E[s][i] * T->I_V_Q[k][j] : T->I_V_Q[k][i] * T->I_V_E[s][j];
-                v += wgt * Bz[gix(mp, B, exl, eyl, i, j)];
-              }
-          } else if (dir == 0) {  // B_y on x-faces: Gauss_m in x, GLL_{m+1} in y
-            for (int j = 0; j < A; ++j)
-              for (int i = 0; i < B; ++i) v += T->I_G_E[s][i] * T->I_W_Q[k][j] * By[gix(mp, B, exl, eyl, i, j)];
-          } else {  // B_x on y-faces: GLL_{m+1} in x, Gauss_m in y
-            for (int j = 0; j < B; ++j)
-              for (int i = 0; i < A; ++i) v += T->I_W_Q[k][i] * T->I_G_E[s][j] * Bx[gix(mp, B, exl, eyl, i, j)];
-          }
-          return v;
-        };
+        if (cf[it == 0 ? t0 : 2]) continue;
+        const int b0 = (dir * 2 + it) * 2 * A, b1 = b0 + A;  // side 0 / side 1 blocks
         double sm = 0.0, sp = 0.0;
-#pragma unroll 1
         for (int k = 0; k < A; ++k) {
-          const double jm = trace(e, 0, k) - trace(em, 1, k);
-          const double jp = trace(ep, 0, k) - trace(e, 1, k);
+          const double jm = me[b0 + k] - tm[b1 + k];
+          const double jp = tp[b0 + k] - me[b1 + k];
           sm += 0.5 * T->wq[k] * jm * jm;
           sp += 0.5 * T->wq[k] * jp * jp;
         }
@@ -781,26 +928,8 @@ __global__ __launch_bounds__(128) void k_ar_eta(const double* __restrict__ rho, 
     }
     R[dir] = fmin(Cs * sig, 1.0);
   }
-  const long KN = mp.K * NN;
-  double ax = 0.0, ay = 0.0;
-#pragma unroll 1
-  for (int qj = 0; qj < NP; ++qj)
-#pragma unroll 1
-    for (int qi = 0; qi < NP; ++qi) {
-      double bxv = 0.0, byv = 0.0, bzv = 0.0;
-      for (int j = 0; j < B; ++j)
-        for (int i = 0; i < A; ++i) bxv += T->I_W_P[qi][i] * T->I_G_P[qj][j] * Bx[gix(mp, B, ex, ey, i, j)];
-      for (int j = 0; j < A; ++j)
-        for (int i = 0; i < B; ++i) byv += T->I_G_P[qi][i] * T->I_W_P[qj][j] * By[gix(mp, B, ex, ey, i, j)];
-      for (int j = 0; j < B; ++j)
-        for (int i = 0; i < B; ++i) bzv += T->I_V_P[qi][i] * T->I_V_P[qj][j] * Bz[gix(mp, B, ex, ey, i, j)];
-      const int q = qj * NP + qi;
-      const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) / sqrt(rho[e * NN + q]);
-      ax = fmax(ax, fabs(u[e * NN + q]) + va);
-      ay = fmax(ay, fabs(u[KN + e * NN + q]) + va);
-    }
-  const double v0 = mp.hx / (2.0 * P + 1.0) * ax * R[0];
-  const double v1 = mp.hy / (2.0 * P + 1.0) * ay * R[1];
+  const double v0 = mp.hx / (2.0 * P + 1.0) * me[8 * A] * R[0];
+  const double v1 = mp.hy / (2.0 * P + 1.0) * me[8 * A + 1] * R[1];
   eta[e] = Ceta * fmax(v0, v1);
 }
 
@@ -1034,9 +1163,14 @@ int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* B
   DISPATCH_M(c->m, BS);
 #undef BS
   line_global_reduce(c, c->stats, 3, nullptr);
-  const long nb2 = (K + 127) / 128;
-#define AR(P, M) hipLaunchKernelGGL((k_ar_eta<P, M>), dim3(nb2), dim3(128), 0, c->stream, rho, u, Bx, By, Bz, c->glob, eta, \
-                                    c->d_mt, c->mp, c->opt.C_s, c->opt.C_eta)
+  const long eb = 256 / ((c->p + 1) * (c->p + 1));
+  const long nb1 = (K + eb - 1) / eb;
+#define ART(P, M) hipLaunchKernelGGL((k_ar_traces<P, M>), dim3(nb1), dim3(256), 0, c->stream, rho, u, Bx, By, Bz, c->artr, \
+                                     c->d_mt, c->mp)
+  DISPATCH_PM(c->p, c->m, ART);
+#undef ART
+#define AR(P, M) hipLaunchKernelGGL((k_ar_eta<P, M>), dim3(nb), dim3(256), 0, c->stream, c->artr, c->glob, eta, c->d_mt, \
+                                    c->mp, c->opt.C_s, c->opt.C_eta)
   DISPATCH_PM(c->p, c->m, AR);
 #undef AR
   return chk(c, "A.R. launch");
