@@ -97,7 +97,7 @@ void mhd25_destroy(mhd25_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->d_ht, c->d_mt, c->Un, c->S1, c->S2, c->Ust, c->stats, c->lines, c->glob, c->d_flag,
                   c->d_counts, c->d_flags, c->rho, c->e, c->u, c->eta, c->Yn, c->Y1, c->Y2, c->JE,
-                  c->loads, c->saveU, c->saveB, c->red, c->snapU, c->vjp_scratch, c->psi, c->artr};
+                  c->loads, c->saveU, c->saveB, c->red, c->snapU, c->vjp_scratch, c->psi, c->artr, c->dfac};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
@@ -161,7 +161,8 @@ int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stre
   r = r ? r : alloc((void**)&c->snapU, n5 * 8);
   r = r ? r : alloc((void**)&c->red, (K + 1024) * 8 * 8);
   // velocity-OE basis: allocated here so that no allocation happens inside a captured step
-  r = r ? r : alloc((void**)&c->psi, (size_t)K * c->nn * c->nn * 8);
+  r = r ? r : alloc((void**)&c->psi, (size_t)K * psi_stride(c->nn) * 8);
+  r = r ? r : alloc((void**)&c->dfac, (size_t)K * (c->p + 1) * 8);
   r = r ? r : alloc((void**)&c->artr, (size_t)K * (8 * (c->m + 2) + 2) * 8);
   if (!r && hipHostMalloc((void**)&c->h_pinned, 4096) != hipSuccess) r = fail(c, -3, "hipHostMalloc");
   if (r) { mhd25_destroy(c); return r; }

@@ -44,6 +44,10 @@ struct MagTab {
   double I_V_Q[MHD_MAXN][MHD_MAXN];
 };
 
+// per-element stride of the velocity-OE basis table: nn*nn values padded to an even count so
+// that every element's table starts 16-byte aligned
+inline constexpr long psi_stride(int nn) { return ((long)nn * nn + 1) & ~1L; }
+
 struct MeshP {
   int nx, ny;
   long K;
@@ -81,7 +85,8 @@ struct mhd25_ctx {
   double *saveU, *saveB, *snapU;
   double* red;  // scratch for small reductions
   double* vjp_scratch;  // allocated on the first magnetic VJP
-  double* psi;          // rho-weighted orthonormal basis values [K][nn][nn] (velocity OE)
+  double* psi;          // rho-weighted orthonormal basis values [K][psi_stride(nn)] (velocity OE)
+  double* dfac;         // velocity-OE damping factors D_l of the current stage [K][p+1]
   double* artr;         // A.R. face traces and wave-speed maxima [K][8(m+2)+2]
   double* h_pinned;
   std::string err;

@@ -473,15 +473,11 @@ __global__ __launch_bounds__(256) void k_field_stats(const double* __restrict__ 
 
 // ---------------------------------------------------------------------------------------------
 // Velocity OE (eq. magnetic-oe-sensor .. eq. magnetic-oe-map).  The rho-weighted projections use
-// the shell-ordered tensor Legendre basis orthonormalised by a Cholesky factor of its Gram
-// matrix (computed in LDS), so increments of shell l are sums over that shell's modes.
-// ---------------------------------------------------------------------------------------------
-// ---------------------------------------------------------------------------------------------
-// Velocity OE (eq. magnetic-oe-sensor .. eq. magnetic-oe-map).  The rho-weighted projections use
 // the shell-ordered tensor Legendre basis orthonormalised in the rho-weighted product,
 // psi = phi L^{-T} with G = L L^T the Gram matrix.  rho is frozen during a magnetic substep, so
 // Psi[q][k] = psi_k(x_q) is computed once per substep (k_vel_prep, one wave per block so the
-// Cholesky barriers are wave-local) and reused by the three stages (k_vel_apply).
+// Cholesky barriers are cheap) and reused by the three stages: per stage k_vel_sensor forms the
+// damping factors and k_vel_proj applies the map.
 // ---------------------------------------------------------------------------------------------
 // shell index of mode k in the shell ordering (shell l holds modes l^2 .. (l+1)^2 - 1)
 __host__ __device__ constexpr int shell_of(int k) {
@@ -497,14 +493,17 @@ struct VP {
 
 // One wave per block (EB elements).  Thread q holds row q of the element's Gram matrix in
 // registers; the right-looking Cholesky broadcasts the pivot and column k through LDS at step k
-// (two barriers per step), and the trailing update reads are independent of each other.  The 1D Legendre table and the shell
-// order are read from LDS.
+// (two barriers per step).  The trailing update is masked arithmetic, not branches: entries right
+// of the diagonal take garbage updates that are never read.  L is kept packed in LDS for the
+// forward substitution Psi = Phi L^{-T}.
 template <int P>
 __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho, double* __restrict__ Psi,
                                                  const HydroTab* __restrict__ H, MeshP mp) {
-  constexpr int NP = P + 1, NN = NP * NP, EB = VP<P>::EB;
-  __shared__ double sw[EB][NN], sH[EB][NP][NP * NP], sL[EB][NN][NN + 1], sP[EB][NN][NN + 1], scol[EB][NN];
-  __shared__ double srd[EB][NN], sdg[EB];
+  constexpr int NP = P + 1, NN = NP * NP, EB = VP<P>::EB, NL = NN * (NN + 1) / 2;
+  __shared__ double sw[EB][NN], sL[EB][NL], scol[EB][NN], srd[EB][NN], sdg[EB], sdum[64];
+  __shared__ double sHP[EB * (NN * (NN + 1) > NP * NP * NP ? NN * (NN + 1) : NP * NP * NP)];
+  auto sH = reinterpret_cast<double(*)[NP][NP * NP]>(sHP);  // Gram staging [EB][NP][NP^2]
+  auto sP = reinterpret_cast<double(*)[NN][NN + 1]>(sHP);   // Psi rows [EB][NN][NN+1]
   __shared__ double sV[NP][NP];
   __shared__ int ska[NN], skb[NN];
   const int tid = threadIdx.x, el0 = tid / NN;
@@ -526,7 +525,7 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
       sH[el][jj][aa] = s;
     }
   __syncthreads();
-  // Gram row q (shell order): G[q][k'] = sum_qj V[qj][b] V[qj][b'] Hm[qj][a][a'], k' <= q
+  // Gram row q (shell order): G[q][k'] = sum_qj V[qj][b] V[qj][b'] Hm[qj][a][a'], k' <= q (packed)
   if (act0) {
     const int ka = ska[q], kb = skb[q];
     for (int k2 = 0; k2 <= q; ++k2) {
@@ -534,89 +533,87 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
       double s = 0.0;
 #pragma unroll
       for (int jj = 0; jj < NP; ++jj) s += sV[jj][kb] * sV[jj][b2] * sH[el][jj][ka * NP + a2];
-      sL[el][q][k2] = s;
+      sL[el][q * (q + 1) / 2 + k2] = s;
     }
   }
   __syncthreads();
+  // (LDS stores below go through address selects, not branches: a lane that must not write
+  // targets its own dummy slot; this keeps the unrolled steps branch-free)
   double g[NN];
 #pragma unroll
-  for (int k2 = 0; k2 < NN; ++k2) g[k2] = k2 <= q ? sL[el][q][k2] : 0.0;
-  // Cholesky G = L L^T; after step k, g[k] = L[q][k] (q >= k), srd[k] = 1 / L[k][k]
-  // (the diagonal goes through sdg, the column through scol: a column is only rewritten after the
-  // next step's first barrier, which every thread reaches after its updates of this step)
+  for (int k2 = 0; k2 < NN; ++k2) {
+    const double v = sL[el][(q * (q + 1) / 2 + k2) % NL];  // in bounds; used only for k2 <= q
+    g[k2] = k2 <= q ? v : 0.0;
+  }
+  // Cholesky G = L L^T; after step k, g[k] = L[q][k] (q >= k), srd[k] = 1 / L[k][k].  The pivot
+  // goes through sdg, the column through scol: a column is only rewritten after the next step's
+  // first barrier, which every thread reaches after its updates of this step.
 #pragma unroll
   for (int k = 0; k < NN; ++k) {
-    if (act0 && q == k) sdg[el] = g[k];
+    *((act0 && q == k) ? &sdg[el] : &sdum[tid]) = g[k];
     __syncthreads();
     const double rk = 1.0 / sqrt(sdg[el]);
-    if (q >= k) g[k] *= rk;
-    if (act0 && q > k) scol[el][q] = g[k];
-    if (act0 && q == k) srd[el][k] = rk;
+    g[k] = q >= k ? g[k] * rk : g[k];
+    *(act0 ? &scol[el][q] : &sdum[tid]) = g[k];  // entries q <= k are not read at this step
+    *((act0 && q == k) ? &srd[el][k] : &sdum[tid]) = rk;
     __syncthreads();
+    const double f = q > k ? g[k] : 0.0;
 #pragma unroll
-    for (int jj = k + 1; jj < NN; ++jj)
-      if (jj <= q && q > k) g[jj] -= g[k] * scol[el][jj];
+    for (int jj = k + 1; jj < NN; ++jj) g[jj] -= f * scol[el][jj];
   }
-  // L rows to LDS; row q of Psi = Phi L^{-T} by forward substitution over the modes (in LDS)
-#pragma unroll
-  for (int k = 0; k < NN; ++k)
-    if (act0 && k <= q) sL[el][q][k] = g[k];
   __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NN; ++k) *((act0 && k <= q) ? &sL[el][q * (q + 1) / 2 + k] : &sdum[tid]) = g[k];
+  __syncthreads();
+  // row q of Psi = Phi L^{-T}: forward substitution over the modes, the row kept in LDS (sP
+  // aliases the Gram staging sH, dead by now), then stored with coalesced writes
+  double* pr = &sP[el][q][0];
   if (act0) {
     for (int k = 0; k < NN; ++k) {
       double s = sV[qi][ska[k]] * sV[qj][skb[k]];
+      const double* lk = &sL[el][k * (k + 1) / 2];
 #pragma unroll 4
-      for (int k2 = 0; k2 < k; ++k2) s -= sL[el][k][k2] * sP[el][q][k2];
-      sP[el][q][k] = s * srd[el][k];
+      for (int k2 = 0; k2 < k; ++k2) s -= lk[k2] * pr[k2];
+      pr[k] = s * srd[el][k];
     }
   }
   __syncthreads();
-  // coalesced store of the element's Psi[q][k]
+  constexpr long PS = psi_stride(NN);
   for (int t = tid; t < EB * NN * NN; t += 64) {
     const int ee = t / (NN * NN), r = t - ee * NN * NN;
     const long eg = (long)blockIdx.x * EB + ee;
-    if (eg < mp.K) Psi[eg * NN * NN + r] = sP[ee][r / NN][r % NN];
+    if (eg < mp.K) Psi[eg * PS + r] = sP[ee][r / NN][r % NN];
   }
 }
 
 template <int P, int M>
-struct VA {
-  static constexpr int NP = P + 1, NN = NP * NP, EB = 256 / NN, NNP = NN | 1;  // odd LDS row stride
+struct VS {
+  static constexpr int NP = P + 1, NN = NP * NP, EB = 256 / NN;
   static constexpr int A = M + 2, B = M + 1, AB = A * B, BB = B * B;
-  // per-element LDS region, reused: sensor phase (jumps, wave speeds, B coefficients), then the
-  // element's Psi tile
-  static constexpr int R1 = 6 * NN + 2 * NN + 2 * AB + BB, R2 = NN * NNP;
-  static constexpr int RE = R1 > R2 ? R1 : R2;
 };
 
-// uin: snapshot of the raw stage velocity (neighbour jumps must not see updated elements);
-// u: updated in place (own element only).  The element's Psi tile is staged in LDS with one
-// coalesced block-wide copy, so the coefficient pass (columns) and the evaluation pass (rows)
-// both read LDS.
+// Velocity-OE sensor (eq. magnetic-oe-sensor, eq. magnetic-oe-rate, eq. magnetic-oe-factor): one
+// thread per GLL_p node, EB elements per block; writes the element's damping factors D_l
+// (l = 0..p) to Dfac[K][p+1].  Neighbour velocities are staged per direction in LDS with coalesced
+// loads.  u is only read here (the projection kernel that updates it runs afterwards).
 template <int P, int M>
-__global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rho, const double* __restrict__ uin,
-                                                   double* __restrict__ u, double* __restrict__ en, const double* __restrict__ Bx,
-                                                   const double* __restrict__ By, const double* __restrict__ Bz,
-                                                   const double* __restrict__ Psi, const double* __restrict__ lines,
-                                                   const double* __restrict__ glob, const HydroTab* __restrict__ H,
-                                                   const MagTab* __restrict__ T, MeshP mp, double tau, double sM) {
-  using C = VA<P, M>;
-  constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NNP = C::NNP, A = C::A, B = C::B, AB = C::AB, RE = C::RE;
-  __shared__ double su[EB][3][NN], sw[EB][NN], sc[EB][3][NN], ssig[EB][2][NP], sD[EB][NP];
-  __shared__ double sreg[EB * RE];
+__global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ rho, const double* __restrict__ u,
+                                                    const double* __restrict__ Bx, const double* __restrict__ By,
+                                                    const double* __restrict__ Bz, const double* __restrict__ lines,
+                                                    const double* __restrict__ glob, double* __restrict__ Dfac,
+                                                    const HydroTab* __restrict__ H, const MagTab* __restrict__ T,
+                                                    MeshP mp, double tau, double sM) {
+  using C = VS<P, M>;
+  constexpr int NP = C::NP, NN = C::NN, EB = C::EB, A = C::A, B = C::B, AB = C::AB;
+  __shared__ double su[EB][3][NN], sx[EB][6][NN], sva[EB][2][NN], ssig[EB][2][NP];
+  __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][C::BB];
   __shared__ double tD0[NP][NP], tDp[NP][NP], tWP[NP][A], tGP[NP][B], tVP[NP][B], tw[NP], tfr[NP];
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
   const int qi = q % NP, qj = q / NP;
-  const long e0 = (long)blockIdx.x * EB, e = e0 + el;
+  const long e = (long)blockIdx.x * EB + el;
   const bool act = el < EB && e < mp.K;
   const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
   const long KN = mp.K * NN;
-  double* R = sreg + (act ? el : 0) * RE;
-  double* sjmp = R;               // [6][NN]
-  double* sva = R + 6 * NN;       // [2][NN]
-  double* sbx = sva + 2 * NN;     // [B][A]
-  double* sby = sbx + AB;         // [A][B]
-  double* sbz = sby + AB;         // [B][B]
   for (int t = tid; t < NP * NP; t += 256) {
     tD0[t / NP][t % NP] = H->Dr0[t / NP][t % NP];
     tDp[t / NP][t % NP] = H->Drp[t / NP][t % NP];
@@ -630,16 +627,15 @@ __global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rh
   double uu[3] = {0.0, 0.0, 0.0}, rq = 1.0;
   if (act) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) { uu[d] = uin[d * KN + e * NN + q]; su[el][d][q] = uu[d]; }
+    for (int d = 0; d < 3; ++d) { uu[d] = u[d * KN + e * NN + q]; su[el][d][q] = uu[d]; }
     rq = rho[e * NN + q];
     for (int k = q; k < AB; k += NN) {
-      sbx[k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];
-      sby[k] = By[gix(mp, B, ex, ey, k % B, k / B)];
+      sbx[el][k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];
+      sby[el][k] = By[gix(mp, B, ex, ey, k % B, k / B)];
     }
-    for (int k = q; k < C::BB; k += NN) sbz[k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
+    for (int k = q; k < C::BB; k += NN) sbz[el][k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
   }
   __syncthreads();
-  if (act) sw[el][q] = mp.J * tw[qi] * tw[qj] * rq;
   double Dsh[2] = {0.0, 0.0};
   bool cst[3] = {false, false, false};
   if (act) {
@@ -660,34 +656,44 @@ __global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rh
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sbx[j * A + i];
+      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sbx[el][j * A + i];
       bxv += tGP[qj][j] * s;
     }
 #pragma unroll
     for (int j = 0; j < A; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += tGP[qi][i] * sby[j * B + i];
+      for (int i = 0; i < B; ++i) s += tGP[qi][i] * sby[el][j * B + i];
       byv += tWP[qj][j] * s;
     }
 #pragma unroll
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += tVP[qi][i] * sbz[j * B + i];
+      for (int i = 0; i < B; ++i) s += tVP[qi][i] * sbz[el][j * B + i];
       bzv += tVP[qj][j] * s;
     }
     const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) / sqrt(rq);
-    sva[q] = fabs(uu[0]) + va;
-    sva[NN + q] = fabs(uu[1]) + va;
+    sva[el][0][q] = fabs(uu[0]) + va;
+    sva[el][1][q] = fabs(uu[1]) + va;
   }
 #pragma unroll
   for (int D = 0; D < 2; ++D) {
-    const int r = D == 0 ? qi : qj, line = D == 0 ? qj : qi;
+    // neighbours across the faces normal to D: sx rows 0..2 minus side, 3..5 plus side
     if (act) {
       long em, ep;
       if (D == 0) { em = ey * mp.nx + wrapl(ex - 1, mp.nx); ep = ey * mp.nx + wrapl(ex + 1, mp.nx); }
       else { em = wrapl(ey - 1, mp.ny) * mp.nx + ex; ep = wrapl(ey + 1, mp.ny) * mp.nx + ex; }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        sx[el][c][q] = u[c * KN + em * NN + q];
+        sx[el][3 + c][q] = u[c * KN + ep * NN + q];
+      }
+    }
+    __syncthreads();
+    const int r = D == 0 ? qi : qj, line = D == 0 ? qj : qi;
+    double jmp[6];
+    if (act) {
       const double wl = 0.5 * tw[line];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -698,13 +704,18 @@ __global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rh
           const double own = su[el][c][nk];
           a += tD0[r][k] * own;
           d += tDp[r][k] * own;
-          b += tDp[r][k] * uin[c * KN + em * NN + nk];
-          cc += tD0[r][k] * uin[c * KN + ep * NN + nk];
+          b += tDp[r][k] * sx[el][c][nk];
+          cc += tD0[r][k] * sx[el][3 + c][nk];
         }
         const double jm = a - b, jp = cc - d;
-        sjmp[2 * c * NN + q] = wl * jm * jm;
-        sjmp[(2 * c + 1) * NN + q] = wl * jp * jp;
+        jmp[2 * c] = wl * jm * jm;
+        jmp[2 * c + 1] = wl * jp * jp;
       }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) sx[el][c][q] = jmp[c];
     }
     __syncthreads();
     if (act && q < NP) {
@@ -716,8 +727,8 @@ __global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rh
           double sm = 0.0, spp = 0.0;
           for (int l = 0; l < NP; ++l) {
             const int nk = D == 0 ? l * NP + q : q * NP + l;
-            sm += sjmp[2 * c * NN + nk];
-            spp += sjmp[(2 * c + 1) * NN + nk];
+            sm += sx[el][2 * c][nk];
+            spp += sx[el][2 * c + 1][nk];
           }
           sig = fmax(sig, tfr[q] * (sqrt(sm) + sqrt(spp)) / Dsh[D]);
         }
@@ -727,37 +738,74 @@ __global__ __launch_bounds__(256) void k_vel_apply(const double* __restrict__ rh
     __syncthreads();
   }
   if (act && q <= P) {
-    if (q == 0) {
-      sD[el][0] = 1.0;
-    } else {
+    double Dl = 1.0;
+    if (q > 0) {
       double ax = 0.0, ay = 0.0;
-      for (int k = 0; k < NN; ++k) { ax = fmax(ax, sva[k]); ay = fmax(ay, sva[NN + k]); }
+      for (int k = 0; k < NN; ++k) { ax = fmax(ax, sva[el][0][k]); ay = fmax(ay, sva[el][1][k]); }
       const double lx = (2.0 * P + 1.0) / mp.hx * ax, ly = (2.0 * P + 1.0) / mp.hy * ay;
-      double sx = 0.0, sy = 0.0;
-      for (int r = 0; r <= q; ++r) { sx += ssig[el][0][r]; sy += ssig[el][1][r]; }
-      sD[el][q] = exp(-sM * tau * (lx * sx + ly * sy));
+      double sx_ = 0.0, sy_ = 0.0;
+      for (int r = 0; r <= q; ++r) { sx_ += ssig[el][0][r]; sy_ += ssig[el][1][r]; }
+      Dl = exp(-sM * tau * (lx * sx_ + ly * sy_));
     }
+    Dfac[e * NP + q] = Dl;
   }
-  __syncthreads();  // the sensor-phase region is free from here on
+}
+
+// Velocity-OE map (eq. magnetic-oe-map) with the prepared basis: one thread per node, EB elements
+// per 128-thread block.  The block's Psi tiles are copied to LDS first (16-byte loads, rows padded
+// to an odd stride), then the coefficients c_k = (u_d, psi_k)_rho (thread = mode) and the shell
+// increments at the nodes (thread = node) are formed; u and e are updated in place.
+template <int P>
+struct VPJ {
+  static constexpr int NP = P + 1, NN = NP * NP, EB = 128 / NN, NNP = NN | 1;
+  static constexpr long PS = psi_stride(NN);
+};
+
+template <int P>
+__global__ __launch_bounds__(128) void k_vel_proj(const double* __restrict__ rho, double* __restrict__ u,
+                                                  double* __restrict__ en, const double* __restrict__ Psi,
+                                                  const double* __restrict__ Dfac, const HydroTab* __restrict__ H,
+                                                  MeshP mp) {
+  using C = VPJ<P>;
+  constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NNP = C::NNP;
+  constexpr long PS = C::PS;
+  __shared__ double sP[EB * NN * NNP];
+  __shared__ double sv[EB][3][NN], sc[EB][3][NN], sD[EB][NP];
+  const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
+  const int qi = q % NP, qj = q / NP;
+  const long e0 = (long)blockIdx.x * EB, e = e0 + el;
+  const bool act = el < EB && e < mp.K;
+  const long KN = mp.K * NN;
   {
     const long nel = mp.K - e0 < EB ? mp.K - e0 : EB;
-    const double* src = Psi + e0 * NN * NN;
-    for (long t = tid; t < nel * NN * NN; t += 256) {
-      const int ee = (int)(t / (NN * NN)), rr = (int)(t - (long)ee * NN * NN);
-      sreg[ee * RE + (rr / NN) * NNP + rr % NN] = src[t];
+    const double2* src = reinterpret_cast<const double2*>(Psi + e0 * PS);
+    for (long t = tid; t < nel * PS / 2; t += 128) {
+      const double2 v = src[t];
+      const int ee = (int)((2 * t) / PS), r0 = (int)(2 * t - ee * PS);  // PS even: both in element ee
+      if (r0 < NN * NN) sP[ee * NN * NNP + (r0 / NN) * NNP + r0 % NN] = v.x;
+      if (r0 + 1 < NN * NN) sP[ee * NN * NNP + ((r0 + 1) / NN) * NNP + (r0 + 1) % NN] = v.y;
     }
   }
+  double uu[3] = {0.0, 0.0, 0.0};
+  if (act) {
+    const double wq = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      uu[d] = u[d * KN + e * NN + q];
+      sv[el][d][q] = wq * uu[d];
+    }
+    if (q < NP) sD[el][q] = Dfac[e * NP + q];
+  }
   __syncthreads();
-  const double* Pe = R;  // Pe[n * NNP + k] = psi_k(x_n)
-  // expansion coefficients c_k = (u_d, psi_k)_rho, thread q computes mode k = q
+  const double* Pe = sP + (act ? el : 0) * NN * NNP;  // Pe[n * NNP + k] = psi_k(x_n)
   if (act) {
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
     for (int n = 0; n < NN; ++n) {
-      const double wp = sw[el][n] * Pe[n * NNP + q];
-      s0 += wp * su[el][0][n];
-      s1 += wp * su[el][1][n];
-      s2 += wp * su[el][2][n];
+      const double pn = Pe[n * NNP + q];
+      s0 += sv[el][0][n] * pn;
+      s1 += sv[el][1][n] * pn;
+      s2 += sv[el][2][n] * pn;
     }
     sc[el][0][q] = s0; sc[el][1][q] = s1; sc[el][2][q] = s2;
   }
@@ -1127,24 +1175,25 @@ int mag_velocity_prep(mhd25_ctx* c, const double* rho) {
   return chk(c, "velocity OE prep launch");
 }
 
-// apply with the basis prepared for the current rho
+// apply with the basis prepared for the current rho: line statistics of u, sensor, projection
 int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
                        const double* By, const double* Bz) {
   const long K = c->mp.K;
-  const int nn = (c->p + 1) * (c->p + 1), eb = 256 / nn;
-  const long nb = (K + eb - 1) / eb;
+  const int nn = (c->p + 1) * (c->p + 1), eb = 256 / nn, eb2 = 128 / nn;
+  const long nb = (K + eb - 1) / eb, nb2 = (K + eb2 - 1) / eb2;
 #define FS(P) hipLaunchKernelGGL((k_field_stats<P, 3>), dim3(nb), dim3(256), 0, c->stream, u, c->stats, c->d_mt, c->mp)
   switch (c->p) { case 1: FS(1); break; case 2: FS(2); break; case 3: FS(3); break; case 4: FS(4); break;
                   case 5: FS(5); break; case 6: FS(6); break; default: return -4; }
 #undef FS
   line_global_reduce(c, c->stats, 3, nullptr);
-  // snapshot of the raw stage velocity in the (idle) hydro stage buffer
-  int rc = dcopy(c, u, c->Ust, 3 * K * nn);
-  if (rc) return rc;
-#define VO(P, M) hipLaunchKernelGGL((k_vel_apply<P, M>), dim3(nb), dim3(256), 0, c->stream, rho, c->Ust, u, e, Bx, By, Bz, c->psi, \
-                                    c->lines, c->glob, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M)
-  DISPATCH_PM(c->p, c->m, VO);
-#undef VO
+#define VSN(P, M) hipLaunchKernelGGL((k_vel_sensor<P, M>), dim3(nb), dim3(256), 0, c->stream, rho, u, Bx, By, Bz, c->lines, \
+                                     c->glob, c->dfac, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M)
+  DISPATCH_PM(c->p, c->m, VSN);
+#undef VSN
+#define VPR(P) hipLaunchKernelGGL((k_vel_proj<P>), dim3(nb2), dim3(128), 0, c->stream, rho, u, e, c->psi, c->dfac, c->d_ht, c->mp)
+  switch (c->p) { case 1: VPR(1); break; case 2: VPR(2); break; case 3: VPR(3); break; case 4: VPR(4); break;
+                  case 5: VPR(5); break; case 6: VPR(6); break; default: return -4; }
+#undef VPR
   return chk(c, "velocity OE launch");
 }
 
