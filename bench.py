@@ -62,7 +62,7 @@ def cpu_baseline(seconds_hint=20.0):
     M = O.Mesh(L.nx, L.ny, L.p, L.m, L.x0, L.x1, L.y0, L.y1, L.gamma)
     threads = O.set_threads(0)
     dt = 2.0e-5
-    steps = 2
+    steps = 6
     t0 = time.perf_counter()
     st = (U, Bx, By, Bz)
     for _ in range(steps):
@@ -74,6 +74,93 @@ def cpu_baseline(seconds_hint=20.0):
                       "%.1f s on %d OpenMP threads" % (steps, t, threads)}
 
 
+def _event_ms(fn, reps, warm=3):
+    """Average time of fn() in ms from HIP events on torch's current stream (the library's)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def adjoint_ratio():
+    """Cost of the hand-written VJPs relative to their forward operators on the noisy isentropic
+    vortex, 128 x 128 elements, N = 3, k = 2 (cotangents N(0,1), seed 7)."""
+    import numpy as np
+    import torch
+
+    import paper_2609_10849_amd as pk
+    from paper_2609_10849_amd import workloads as W
+
+    L, U, Bx, By, Bz = W.noisy_vortex(128, 128, 3, 2, seed=0)
+    S = pk.Solver.from_layout(L)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    Ud, Bxd, Byd, Bzd = dev(U), dev(Bx), dev(By), dev(Bz)
+    rng = np.random.default_rng(7)
+    cot = dev(rng.standard_normal(U.shape))
+    out, gb = torch.empty_like(Ud), torch.empty_like(Ud)
+    tf = _event_ms(lambda: S.rhs_hydro(Ud, out), 50)
+    tb = _event_ms(lambda: S.rhs_hydro_vjp(Ud, cot, gb), 50)
+    rho, e, u = S.to_primitive(Ud)
+    eta = dev(rng.uniform(0, 1e-3, L.K))
+    cots = [dev(rng.standard_normal(tuple(a.shape))) for a in (e, u, Bxd, Byd, Bzd)]
+    mf = _event_ms(lambda: S.rhs_magnetic(rho, u, Bxd, Byd, Bzd, eta), 50)
+    mb = _event_ms(lambda: S.rhs_magnetic_vjp(rho, u, Bxd, Byd, Bzd, eta, *cots), 50)
+    S.close()
+    return {"hydro": tb / tf, "magnetic": mb / mf, "hydro_fwd_ms": tf, "hydro_vjp_ms": tb,
+            "magnetic_fwd_ms": mf, "magnetic_vjp_ms": mb,
+            "workload": "noisy isentropic vortex, 128x128 elements, N=3, k=2"}
+
+
+def batched_speedup(steps=50):
+    """Ensemble of 64 uneven runs (n in {32..192}, N in {2,3,4}, k = N-1, vortex amplitude and
+    field drawn from PCG64 seed 0; full stabilisation; per-run dt from CFL 0.3 at the start):
+    time per Strang step of all runs, sequential plain launches vs the captured multi-branch graph."""
+    import numpy as np
+    import torch
+
+    import paper_2609_10849_amd as pk
+    from paper_2609_10849_amd import workloads as W
+
+    draws = W.ensemble_draws(64, seed=0)
+    states, layouts = [], []
+    for d in draws:
+        L, U, Bx, By, Bz = W.isentropic_vortex(d["n"], d["n"], d["p"], d["m"], kappa=d["kappa"], B=d["B"])
+        layouts.append(L)
+        states.append((U, Bx, By, Bz))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dts = []
+    for L, st in zip(layouts, states):
+        S = pk.Solver.from_layout(L, pk.Options.full())
+        dts.append(S.cfl_dt(*[dev(a) for a in st], 0.3))
+        S.close()
+    B = pk.Batch(layouts, pk.Options.full())
+
+    def run(sequential, nsteps):
+        g = [[dev(a) for a in st] for st in states]
+        args = [[x[i] for x in g] for i in range(4)]
+        B.strang_step(*args, dts, sequential=sequential)  # warm-up (and capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            r, _ = B.strang_step(*args, dts, sequential=sequential)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / nsteps
+
+    ts = run(True, steps)
+    tb = run(False, steps)
+    B.close()
+    nodes = sum(L.K * (L.p + 1) ** 2 for L in layouts)
+    return {"value": ts / tb, "sequential_ms_per_step": ts, "batched_ms_per_step": tb, "runs": 64,
+            "steps": steps, "nodes": nodes}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +168,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1024, help="elements per direction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the adjoint-ratio and ensemble measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
@@ -150,6 +238,9 @@ def main():
                      "avg_ms": avg_ms, "launches": launches},
         "accepted_substep_rate": accepted / max(attempted, 1),
     }
+    if not args.no_extras:
+        out["adjoint_cost_ratio"] = adjoint_ratio()
+        out["batched_speedup"] = batched_speedup()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
