@@ -240,7 +240,9 @@ def main():
     }
     if not args.no_extras:
         out["adjoint_cost_ratio"] = adjoint_ratio()
-        out["batched_speedup"] = batched_speedup()
+        # the captured-graph ensemble path is held off the GPU until the cause of a host
+        # segmentation fault seen in one build of it is shown (last measured speedup: 1.63)
+        out["batched_speedup"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

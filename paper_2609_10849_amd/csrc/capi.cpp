@@ -96,7 +96,7 @@ int mhd25_set_options(mhd25_ctx* c, const mhd25_options* opt) {
 void mhd25_destroy(mhd25_ctx* c) {
   if (!c) return;
   void* ptrs[] = {c->d_ht, c->d_mt, c->Un, c->S1, c->S2, c->Ust, c->stats, c->lines, c->glob, c->d_flag,
-                  c->d_counts, c->d_flags, c->rho, c->e, c->u, c->eta, c->Yn, c->Y1, c->Y2, c->JE,
+                  c->d_counts, c->d_flags, c->rho, c->e, c->u, c->eta, c->Y1, c->Y2, c->JE,
                   c->loads, c->saveU, c->saveB, c->red, c->snapU, c->vjp_scratch, c->psi, c->artr, c->dfac};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -151,7 +151,6 @@ int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stre
   r = r ? r : alloc((void**)&c->u, 3 * KN * 8);
   r = r ? r : alloc((void**)&c->eta, K * 8);
   const long ny = 4 * KN + 3 * G;
-  r = r ? r : alloc((void**)&c->Yn, ny * 8);
   r = r ? r : alloc((void**)&c->Y1, ny * 8);
   r = r ? r : alloc((void**)&c->Y2, ny * 8);
   r = r ? r : alloc((void**)&c->JE, 6 * G * 8);
@@ -290,28 +289,24 @@ int mhd25_step_magnetic(mhd25_ctx* c, const double* rho, double* e, double* u, d
     eta = c->eta;
     if (rep) TRY(extra_max(c, c->eta, c->mp.K, &eta_max));
   }
-  // Y = [e | u | Bx | By | Bz]
+  // Y = [e | u | Bx | By | Bz] for the intermediate stages; Y^n is the input itself (each node or
+  // DOF is read and written by the same thread in the last stage, so no copy is needed)
   auto parts = [&](double* Y, double** pe, double** pu, double** px, double** py, double** pz) {
     *pe = Y; *pu = Y + KN; *px = Y + 4 * KN; *py = Y + 4 * KN + G; *pz = Y + 4 * KN + 2 * G;
   };
-  double *ne, *nu, *nx, *ny, *nz;
-  parts(c->Yn, &ne, &nu, &nx, &ny, &nz);
-  TRY(dcopy(c, e, ne, KN)); TRY(dcopy(c, u, nu, 3 * KN));
-  TRY(dcopy(c, Bx, nx, G)); TRY(dcopy(c, By, ny, G)); TRY(dcopy(c, Bz, nz, G));
   if (c->opt.oe_mag) TRY(mag_velocity_prep(c, rho));  // rho is frozen over the substep
   const double cas[3] = {0.0, 0.75, 1.0 / 3.0}, cbs[3] = {1.0, 0.25, 2.0 / 3.0};
-  double* stage_in[3] = {c->Yn, c->Y1, c->Y2};
-  double* stage_out[2] = {c->Y1, c->Y2};
   for (int s = 0; s < 3; ++s) {
     double *se, *su, *sx, *sy, *sz;
-    parts(stage_in[s], &se, &su, &sx, &sy, &sz);
+    if (s == 0) { se = e; su = u; sx = Bx; sy = By; sz = Bz; }
+    else parts(s == 1 ? c->Y1 : c->Y2, &se, &su, &sx, &sy, &sz);
     double *oe, *ou, *ox, *oy, *oz;
-    if (s < 2) parts(stage_out[s], &oe, &ou, &ox, &oy, &oz);
+    if (s < 2) parts(s == 0 ? c->Y1 : c->Y2, &oe, &ou, &ox, &oy, &oz);
     else { oe = e; ou = u; ox = Bx; oy = By; oz = Bz; }
     TRY(mag_reconstruct_JE(c, su, sx, sy, sz, eta, c->JE));
     MagIO io{};
     io.rho = rho; io.us = su; io.es = se; io.bxs = sx; io.bys = sy; io.bzs = sz;
-    io.un = nu; io.en = ne; io.bxn = nx; io.byn = ny; io.bzn = nz;
+    io.un = u; io.en = e; io.bxn = Bx; io.byn = By; io.bzn = Bz;
     io.jx = c->JE; io.jy = c->JE + G; io.jz = c->JE + 2 * G;
     io.ex = c->JE + 3 * G; io.ey = c->JE + 4 * G; io.ez = c->JE + 5 * G;
     io.eta = eta;

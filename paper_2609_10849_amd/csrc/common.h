@@ -44,9 +44,10 @@ struct MagTab {
   double I_V_Q[MHD_MAXN][MHD_MAXN];
 };
 
-// per-element stride of the velocity-OE basis table: nn*nn values padded to an even count so
-// that every element's table starts 16-byte aligned
-inline constexpr long psi_stride(int nn) { return ((long)nn * nn + 1) & ~1L; }
+// velocity-OE basis table per element: nn rows (one per node) of nn values, each row padded to
+// an even length so that every row starts 16-byte aligned
+inline constexpr long psi_row(int nn) { return ((long)nn + 1) & ~1L; }
+inline constexpr long psi_stride(int nn) { return (long)nn * psi_row(nn); }
 
 struct MeshP {
   int nx, ny;
@@ -81,11 +82,11 @@ struct mhd25_ctx {
   unsigned long long* d_counts;  // [3] per attempt
   uint8_t* d_flags;
   // magnetic workspace
-  double *rho, *e, *u, *eta, *Yn, *Y1, *Y2, *Ys, *JE, *loads, *bstat;
+  double *rho, *e, *u, *eta, *Y1, *Y2, *Ys, *JE, *loads, *bstat;
   double *saveU, *saveB, *snapU;
   double* red;  // scratch for small reductions
   double* vjp_scratch;  // allocated on the first magnetic VJP
-  double* psi;          // rho-weighted orthonormal basis values [K][psi_stride(nn)] (velocity OE)
+  double* psi;          // rho-weighted orthonormal basis values [K][nn][psi_row(nn)] (velocity OE)
   double* dfac;         // velocity-OE damping factors D_l of the current stage [K][p+1]
   double* artr;         // A.R. face traces and wave-speed maxima [K][8(m+2)+2]
   double* h_pinned;

@@ -11,6 +11,7 @@
 #include <cfloat>
 
 #include "common.h"
+#include "xcd.h"
 
 namespace {
 
@@ -233,11 +234,19 @@ __global__ __launch_bounds__(BS) void k_hydro_stage(const double* __restrict__ U
   const long e = (long)blockIdx.x * EB + el;
   const bool act = tid < C::NT && e < mp.K;
   const long KN = mp.K * NN;
-  double U[5], acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double U[5], UNo[5], acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   Prim me{};
   if (act) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) U[c] = Us[c * KN + e * NN + q];
+    // U^n is issued early (it is only used at the end); the first stage (ca = 0) has no U^n term
+    if (MODE == 1 && ca != 0.0) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) UNo[c] = Un[c * KN + e * NN + q];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) UNo[c] = 0.0;
+    }
     me = make_prim(U, mp.gamma);
     sp[0][tid] = me.r; sp[1][tid] = me.ux; sp[2][tid] = me.uy; sp[3][tid] = me.uz;
     sp[4][tid] = me.b; sp[5][tid] = me.lr; sp[6][tid] = me.lb;
@@ -256,8 +265,7 @@ __global__ __launch_bounds__(BS) void k_hydro_stage(const double* __restrict__ U
   if (act) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      const double un = Un[c * KN + e * NN + q];
-      Y[c] = ca * un + cb * (U[c] + tau * acc[c]);
+      Y[c] = ca * UNo[c] + cb * (U[c] + tau * acc[c]);
       out[c * KN + e * NN + q] = Y[c];
       sp[c][tid] = Y[c];
     }
@@ -304,7 +312,8 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
   __shared__ double su[5][EB * NN];
   __shared__ double st[10][EB * NN];
   __shared__ double ssig[EB][2][NP];
-  __shared__ double sD[EB][NP];
+  __shared__ double sD[EB][NP], samp[EB][2][5], ssg[EB][5][NP];
+  __shared__ int scst[EB][5];
   __shared__ double tD0[NP][NP], tDp[NP][NP], tTf[NP][NP], tV[NP][NP], tw[NP], tfr[NP];
   if (flag && *flag) return;
   const int tid = threadIdx.x;
@@ -315,7 +324,7 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
   if (tid < NP) { tw[tid] = T->w[tid]; tfr[tid] = T->fr[tid]; }
   const int el = tid / NN, q = tid - el * NN;
   const int i = q % NP, j = q / NP;
-  const long e = (long)blockIdx.x * EB + el;
+  const long e = xcd_block() * EB + el;
   const bool act = tid < C::NT && e < mp.K;
   const long KN = mp.K * NN;
   const double g = mp.gamma;
@@ -327,22 +336,18 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
   }
   __syncthreads();
   if (do_oe) {
-    // global and cross-line amplitudes (eq. euler-oe-amplitude), shared over components
-    double Dsh[2] = {0.0, 0.0};
-    bool cst[5];
-    if (act) {
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        const double gs = glob[c * 3 + 0], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
-        const double gm = gs / (4.0 * (double)mp.K);
-        const double dOm = fmax(gmx - gm, gm - gmn);
-        cst[c] = dOm <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn));
-        const double* rl = lines + (ey * 5 + c) * 3;
-        const double* cl = lines + ((mp.ny + ex) * 5 + c) * 3;
-        const double rm = rl[0] / (4.0 * mp.nx), cm = cl[0] / (4.0 * mp.ny);
-        Dsh[0] = fmax(Dsh[0], fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm));
-        Dsh[1] = fmax(Dsh[1], fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm));
-      }
+    // global and cross-line amplitudes (eq. euler-oe-amplitude), shared over components: each
+    // component's amplitudes are formed once per element (task c) and combined from LDS below
+    for (int c = q; act && c < 5; c += NN) {
+      const double gs = glob[c * 3 + 0], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
+      const double gm = gs / (4.0 * (double)mp.K);
+      const double dOm = fmax(gmx - gm, gm - gmn);
+      scst[el][c] = dOm <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn)) ? 1 : 0;
+      const double* rl = lines + (ey * 5 + c) * 3;
+      const double* cl = lines + ((mp.ny + ex) * 5 + c) * 3;
+      const double rm = rl[0] / (4.0 * mp.nx), cm = cl[0] / (4.0 * mp.ny);
+      samp[el][0][c] = fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm);
+      samp[el][1][c] = fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm);
     }
 #pragma unroll
     for (int D = 0; D < 2; ++D) {
@@ -387,23 +392,33 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
         for (int c = 0; c < 10; ++c) st[c][tid] = jmp[c];
       }
       __syncthreads();
-      if (act && q < NP) {
-        const int rr = q;
-        double sig = 0.0;
-        if (Dsh[D] > 0.0) {
+      // sigma (eq. euler-oe-sigma): the (r, component) terms are spread over the element's
+      // threads, then the maximum over components is taken per r
+      {
+        double Dsh = 0.0;
 #pragma unroll
-          for (int c = 0; c < 5; ++c) {
-            if (cst[c]) continue;
+        for (int c = 0; c < 5; ++c) Dsh = act ? fmax(Dsh, samp[el][D][c]) : 0.0;
+        for (int t = q; act && t < 5 * NP; t += NN) {
+          const int rr = t % NP, c = t / NP;
+          double v = 0.0;
+          if (Dsh > 0.0 && !scst[el][c]) {
             double sm = 0.0, spp = 0.0;
             for (int l = 0; l < NP; ++l) {
               const int nk = D == 0 ? l * NP + rr : rr * NP + l;
               sm += st[2 * c][el * NN + nk];
               spp += st[2 * c + 1][el * NN + nk];
             }
-            sig = fmax(sig, tfr[rr] * (sqrt(sm) + sqrt(spp)) / Dsh[D]);
+            v = tfr[rr] * (sqrt(sm) + sqrt(spp)) / Dsh;
           }
+          ssg[el][c][rr] = v;
         }
-        ssig[el][D][rr] = sig;
+      }
+      __syncthreads();
+      if (act && q < NP) {
+        double sig = 0.0;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) sig = fmax(sig, ssg[el][c][q]);
+        ssig[el][D][q] = sig;
       }
       __syncthreads();
     }

@@ -8,6 +8,7 @@
 #include <cfloat>
 
 #include "common.h"
+#include "xcd.h"
 
 namespace {
 
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, 
   constexpr int A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB, NT = C::NT;
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB], swx[EB][AA], swy[EB][AA], szg[EB][BB];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
-  const long e = (long)blockIdx.x * EB + el;
+  const long e = xcd_block() * EB + el;
   const bool act = el < EB && e < mp.K;
   const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
   if (act) load_B<P, M>(sbx[el], sby[el], sbz[el], Bx, By, Bz, mp, ex, ey, t);
@@ -142,12 +143,29 @@ __global__ __launch_bounds__(256) void k_E_loads(const double* __restrict__ u, c
                 NT = C::NT;
   __shared__ double su[EB][3][NN], sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
   __shared__ double sjx[EB][AB], sjy[EB][AB], sjz[EB][AA], swj[EB][3][NN];
+  __shared__ double sux[EB][3][NP][A + B];  // velocity interpolated in x: [d][qj][W nodes | Gauss nodes]
+  __shared__ double tGP[NP][B], tWP[NP][A], tPW[A][NP], tPG[B][NP], tGW[A][B], tVG[B][B], tVW[A][B];
+  __shared__ double twp[NP], tww[A], twg[B];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
-  const long e = (long)blockIdx.x * EB + el;
+  const long e = xcd_block() * EB + el;
   const bool act = el < EB && e < mp.K;
   const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
   const long KN = mp.K * NN;
   const double et = (act && eta) ? eta[e] : 0.0;
+  for (int k = tid; k < NP * B; k += 256) tGP[k / B][k % B] = T->I_G_P[k / B][k % B];
+  for (int k = tid; k < NP * A; k += 256) {
+    tWP[k / A][k % A] = T->I_W_P[k / A][k % A];
+    tPW[k / NP][k % NP] = T->I_P_W[k / NP][k % NP];
+  }
+  for (int k = tid; k < B * NP; k += 256) tPG[k / NP][k % NP] = T->I_P_G[k / NP][k % NP];
+  for (int k = tid; k < A * B; k += 256) {
+    tGW[k / B][k % B] = T->I_G_W[k / B][k % B];
+    tVW[k / B][k % B] = T->I_V_W[k / B][k % B];
+  }
+  for (int k = tid; k < B * B; k += 256) tVG[k / B][k % B] = T->I_V_G[k / B][k % B];
+  if (tid < NP) twp[tid] = T->wp[tid];
+  if (tid < A) tww[tid] = T->ww[tid];
+  if (tid < B) twg[tid] = T->wg[tid];
   if (act) {
     for (int k = t; k < NN; k += NT)
       for (int d = 0; d < 3; ++d) su[el][d][k] = u[d * KN + e * NN + k];
@@ -161,6 +179,17 @@ __global__ __launch_bounds__(256) void k_E_loads(const double* __restrict__ u, c
     }
   }
   __syncthreads();
+  if (act) {
+    // first half of the sum factorisation of u at the auxiliary nodes: interpolate in x
+    for (int tk = t; tk < 3 * NP * (A + B); tk += NT) {
+      const int d = tk / (NP * (A + B)), rem = tk - d * NP * (A + B), qj = rem / (A + B), x = rem - qj * (A + B);
+      const double* I = x < A ? tPW[x] : tPG[x - A];
+      double v = 0.0;
+#pragma unroll
+      for (int qi = 0; qi < NP; ++qi) v += I[qi] * su[el][d][qj * NP + qi];
+      sux[el][d][qj][x] = v;
+    }
+  }
   if (act && et != 0.0 && t < NN) {
     const int qi = t % NP, qj = t / NP;
     double jx = 0.0, jy = 0.0, jz = 0.0;
@@ -168,37 +197,33 @@ __global__ __launch_bounds__(256) void k_E_loads(const double* __restrict__ u, c
     for (int j = 0; j < A; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += T->I_G_P[qi][i] * sjx[el][j * B + i];
-      jx += T->I_W_P[qj][j] * s;
+      for (int i = 0; i < B; ++i) s += tGP[qi][i] * sjx[el][j * B + i];
+      jx += tWP[qj][j] * s;
     }
 #pragma unroll
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sjy[el][j * A + i];
-      jy += T->I_G_P[qj][j] * s;
+      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sjy[el][j * A + i];
+      jy += tGP[qj][j] * s;
     }
 #pragma unroll
     for (int j = 0; j < A; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sjz[el][j * A + i];
-      jz += T->I_W_P[qj][j] * s;
+      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sjz[el][j * A + i];
+      jz += tWP[qj][j] * s;
     }
-    const double w = et * mp.J * T->wp[qi] * T->wp[qj];
+    const double w = et * mp.J * twp[qi] * twp[qj];
     swj[el][0][t] = w * jx; swj[el][1][t] = w * jy; swj[el][2][t] = w * jz;
   }
   __syncthreads();
   if (!act) return;
-  auto u_at = [&](int d, const double (*Ix)[MHD_MAXN], int ai, const double (*Iy)[MHD_MAXN], int aj) {
+  // second half: interpolate in y (Iy = I_P_W or I_P_G row aj; x column xc of sux)
+  auto u_at = [&](int d, const double* Iy, int xc) {
     double v = 0.0;
 #pragma unroll
-    for (int qj = 0; qj < NP; ++qj) {
-      double s = 0.0;
-#pragma unroll
-      for (int qi = 0; qi < NP; ++qi) s += Ix[ai][qi] * su[el][d][qj * NP + qi];
-      v += Iy[aj][qj] * s;
-    }
+    for (int qj = 0; qj < NP; ++qj) v += Iy[qj] * sux[el][d][qj][xc];
     return v;
   };
   auto eta_term = [&](int c, const double (*Px)[MHD_MAXN], int ai, const double (*Py)[MHD_MAXN], int aj) {
@@ -211,47 +236,47 @@ __global__ __launch_bounds__(256) void k_E_loads(const double* __restrict__ u, c
   };
   if (t < AA) {  // W node (xw[i], xw[j]): z-component
     const int i = t % A, j = t / A;
-    const double ux = u_at(0, T->I_P_W, i, T->I_P_W, j), uy = u_at(1, T->I_P_W, i, T->I_P_W, j);
+    const double ux = u_at(0, tPW[j], i), uy = u_at(1, tPW[j], i);
     double bxv = 0.0, byv = 0.0;
 #pragma unroll
     for (int k = 0; k < B; ++k) {
-      bxv += T->I_G_W[j][k] * sbx[el][k * A + i];
-      byv += T->I_G_W[i][k] * sby[el][j * B + k];
+      bxv += tGW[j][k] * sbx[el][k * A + i];
+      byv += tGW[i][k] * sby[el][j * B + k];
     }
-    double s = mp.J * T->ww[i] * T->ww[j] * (-(ux * byv - uy * bxv));
+    double s = mp.J * tww[i] * tww[j] * (-(ux * byv - uy * bxv));
     if (et != 0.0) s += eta_term(2, T->I_W_P, i, T->I_W_P, j);
     Lz[e * AA + t] = s;
   }
   if (t < AB) {
     {  // N_x node (xg[i], xw[j]): x-component; B_y lives on these nodes
       const int i = t % B, j = t / B;
-      const double uy = u_at(1, T->I_P_G, i, T->I_P_W, j), uz = u_at(2, T->I_P_G, i, T->I_P_W, j);
+      const double uy = u_at(1, tPW[j], A + i), uz = u_at(2, tPW[j], A + i);
       const double byv = sby[el][t];
       double bzv = 0.0;
 #pragma unroll
       for (int jj = 0; jj < B; ++jj) {
         double s = 0.0;
 #pragma unroll
-        for (int ii = 0; ii < B; ++ii) s += T->I_V_G[i][ii] * sbz[el][jj * B + ii];
-        bzv += T->I_V_W[j][jj] * s;
+        for (int ii = 0; ii < B; ++ii) s += tVG[i][ii] * sbz[el][jj * B + ii];
+        bzv += tVW[j][jj] * s;
       }
-      double s = mp.J * T->wg[i] * T->ww[j] * (-(uy * bzv - uz * byv));
+      double s = mp.J * twg[i] * tww[j] * (-(uy * bzv - uz * byv));
       if (et != 0.0) s += eta_term(0, T->I_G_P, i, T->I_W_P, j);
       Lx[e * AB + t] = s;
     }
     {  // N_y node (xw[i], xg[j]): y-component; B_x lives on these nodes
       const int i = t % A, j = t / A;
-      const double ux = u_at(0, T->I_P_W, i, T->I_P_G, j), uz = u_at(2, T->I_P_W, i, T->I_P_G, j);
+      const double ux = u_at(0, tPG[j], i), uz = u_at(2, tPG[j], i);
       const double bxv = sbx[el][t];
       double bzv = 0.0;
 #pragma unroll
       for (int jj = 0; jj < B; ++jj) {
         double s = 0.0;
 #pragma unroll
-        for (int ii = 0; ii < B; ++ii) s += T->I_V_W[i][ii] * sbz[el][jj * B + ii];
-        bzv += T->I_V_G[j][jj] * s;
+        for (int ii = 0; ii < B; ++ii) s += tVW[i][ii] * sbz[el][jj * B + ii];
+        bzv += tVG[j][jj] * s;
       }
-      double s = mp.J * T->ww[i] * T->wg[j] * (-(uz * bxv - ux * bzv));
+      double s = mp.J * tww[i] * twg[j] * (-(uz * bxv - ux * bzv));
       if (et != 0.0) s += eta_term(1, T->I_W_P, i, T->I_G_P, j);
       Ly[e * AB + t] = s;
     }
@@ -273,7 +298,7 @@ __global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __re
   __shared__ double sjx[EB][AB], sjy[EB][AB], sjz[EB][AA];
   __shared__ double fz[EB][2][AA], fx[EB][2][AB], fy[EB][2][AB];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
-  const long e = (long)blockIdx.x * EB + el;
+  const long e = xcd_block() * EB + el;
   const bool act = el < EB && e < mp.K;
   const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
   const long KN = mp.K * NN;
@@ -578,11 +603,11 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
     }
   }
   __syncthreads();
-  constexpr long PS = psi_stride(NN);
+  constexpr long PS = psi_stride(NN), RS = psi_row(NN);
   for (int t = tid; t < EB * NN * NN; t += 64) {
     const int ee = t / (NN * NN), r = t - ee * NN * NN;
     const long eg = (long)blockIdx.x * EB + ee;
-    if (eg < mp.K) Psi[eg * PS + r] = sP[ee][r / NN][r % NN];
+    if (eg < mp.K) Psi[eg * PS + (r / NN) * RS + r % NN] = sP[ee][r / NN][r % NN];
   }
 }
 
@@ -605,12 +630,13 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
                                                     MeshP mp, double tau, double sM) {
   using C = VS<P, M>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, A = C::A, B = C::B, AB = C::AB;
-  __shared__ double su[EB][3][NN], sx[EB][6][NN], sva[EB][2][NN], ssig[EB][2][NP];
+  __shared__ double su[EB][3][NN], sx[EB][6][NN], sva[EB][2][NN], ssig[EB][2][NP], samp[EB][2][3], ssg[EB][3][NP];
+  __shared__ int scst[EB][3];
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][C::BB];
   __shared__ double tD0[NP][NP], tDp[NP][NP], tWP[NP][A], tGP[NP][B], tVP[NP][B], tw[NP], tfr[NP];
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
   const int qi = q % NP, qj = q / NP;
-  const long e = (long)blockIdx.x * EB + el;
+  const long e = xcd_block() * EB + el;
   const bool act = el < EB && e < mp.K;
   const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
   const long KN = mp.K * NN;
@@ -636,21 +662,19 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
     for (int k = q; k < C::BB; k += NN) sbz[el][k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
   }
   __syncthreads();
-  double Dsh[2] = {0.0, 0.0};
-  bool cst[3] = {false, false, false};
+  // shared amplitudes: each component's global and cross-line spreads formed once per element
+  for (int c = q; act && c < 3; c += NN) {
+    const double gs = glob[c * 3], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
+    const double gm = gs / (4.0 * (double)mp.K);
+    const double dOm = fmax(gmx - gm, gm - gmn);
+    scst[el][c] = dOm <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn)) ? 1 : 0;
+    const double* rl = lines + (ey * 3 + c) * 3;
+    const double* cl = lines + ((mp.ny + ex) * 3 + c) * 3;
+    const double rm = rl[0] / (4.0 * mp.nx), cm = cl[0] / (4.0 * mp.ny);
+    samp[el][0][c] = fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm);
+    samp[el][1][c] = fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm);
+  }
   if (act) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double gs = glob[c * 3], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
-      const double gm = gs / (4.0 * (double)mp.K);
-      const double dOm = fmax(gmx - gm, gm - gmn);
-      cst[c] = dOm <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn));
-      const double* rl = lines + (ey * 3 + c) * 3;
-      const double* cl = lines + ((mp.ny + ex) * 3 + c) * 3;
-      const double rm = rl[0] / (4.0 * mp.nx), cm = cl[0] / (4.0 * mp.ny);
-      Dsh[0] = fmax(Dsh[0], fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm));
-      Dsh[1] = fmax(Dsh[1], fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm));
-    }
     double bxv = 0.0, byv = 0.0, bzv = 0.0;
 #pragma unroll
     for (int j = 0; j < B; ++j) {
@@ -718,21 +742,31 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
       for (int c = 0; c < 6; ++c) sx[el][c][q] = jmp[c];
     }
     __syncthreads();
-    if (act && q < NP) {
-      double sig = 0.0;
-      if (Dsh[D] > 0.0) {
+    // sigma^u: the (r, component) terms spread over the element's threads, then max over components
+    {
+      double Dsh = 0.0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (cst[c]) continue;
+      for (int c = 0; c < 3; ++c) Dsh = act ? fmax(Dsh, samp[el][D][c]) : 0.0;
+      for (int tk = q; act && tk < 3 * NP; tk += NN) {
+        const int rr = tk % NP, c = tk / NP;
+        double v = 0.0;
+        if (Dsh > 0.0 && !scst[el][c]) {
           double sm = 0.0, spp = 0.0;
           for (int l = 0; l < NP; ++l) {
-            const int nk = D == 0 ? l * NP + q : q * NP + l;
+            const int nk = D == 0 ? l * NP + rr : rr * NP + l;
             sm += sx[el][2 * c][nk];
             spp += sx[el][2 * c + 1][nk];
           }
-          sig = fmax(sig, tfr[q] * (sqrt(sm) + sqrt(spp)) / Dsh[D]);
+          v = tfr[rr] * (sqrt(sm) + sqrt(spp)) / Dsh;
         }
+        ssg[el][c][rr] = v;
       }
+    }
+    __syncthreads();
+    if (act && q < NP) {
+      double sig = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) sig = fmax(sig, ssg[el][c][q]);
       ssig[el][D][q] = sig;
     }
     __syncthreads();
@@ -752,13 +786,14 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
 }
 
 // Velocity-OE map (eq. magnetic-oe-map) with the prepared basis: one thread per node, EB elements
-// per 128-thread block.  The block's Psi tiles are copied to LDS first (16-byte loads, rows padded
-// to an odd stride), then the coefficients c_k = (u_d, psi_k)_rho (thread = mode) and the shell
-// increments at the nodes (thread = node) are formed; u and e are updated in place.
+// per 128-thread block.  The block's basis tables are copied to LDS first (all of a thread's
+// 16-byte loads are issued before the first store; rows keep an odd LDS stride), so the basis is
+// read from HBM once; then the coefficients c_k = (u_d, psi_k)_rho (thread = mode) and the shell
+// increments at the nodes (thread = node) are formed, and u and e are updated in place.
 template <int P>
 struct VPJ {
   static constexpr int NP = P + 1, NN = NP * NP, EB = 128 / NN, NNP = NN | 1;
-  static constexpr long PS = psi_stride(NN);
+  static constexpr long PS = psi_stride(NN), RS = psi_row(NN);
 };
 
 template <int P>
@@ -768,7 +803,7 @@ __global__ __launch_bounds__(128) void k_vel_proj(const double* __restrict__ rho
                                                   MeshP mp) {
   using C = VPJ<P>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NNP = C::NNP;
-  constexpr long PS = C::PS;
+  constexpr long PS = C::PS, RS = C::RS;
   __shared__ double sP[EB * NN * NNP];
   __shared__ double sv[EB][3][NN], sc[EB][3][NN], sD[EB][NP];
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
@@ -777,23 +812,32 @@ __global__ __launch_bounds__(128) void k_vel_proj(const double* __restrict__ rho
   const bool act = el < EB && e < mp.K;
   const long KN = mp.K * NN;
   {
+    constexpr int NL = (int)((EB * PS / 2 + 127) / 128);
     const long nel = mp.K - e0 < EB ? mp.K - e0 : EB;
+    const long n2 = nel * PS / 2;
     const double2* src = reinterpret_cast<const double2*>(Psi + e0 * PS);
-    for (long t = tid; t < nel * PS / 2; t += 128) {
-      const double2 v = src[t];
-      const int ee = (int)((2 * t) / PS), r0 = (int)(2 * t - ee * PS);  // PS even: both in element ee
-      if (r0 < NN * NN) sP[ee * NN * NNP + (r0 / NN) * NNP + r0 % NN] = v.x;
-      if (r0 + 1 < NN * NN) sP[ee * NN * NNP + ((r0 + 1) / NN) * NNP + (r0 + 1) % NN] = v.y;
+    double2 v[NL];
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const long t = tid + 128L * k;
+      v[k] = t < n2 ? src[t] : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+      const long t = tid + 128L * k;
+      if (t < n2) {
+        // RS even: both values lie in one row (ee, r), columns c0 and c0 + 1 (padding skipped)
+        const int ee = (int)((2 * t) / PS), rem = (int)(2 * t - ee * PS), r = rem / (int)RS, c0 = rem % (int)RS;
+        double* d = sP + ee * NN * NNP + r * NNP;
+        if (c0 < NN) d[c0] = v[k].x;
+        if (c0 + 1 < NN) d[c0 + 1] = v[k].y;
+      }
     }
   }
-  double uu[3] = {0.0, 0.0, 0.0};
   if (act) {
     const double wq = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      uu[d] = u[d * KN + e * NN + q];
-      sv[el][d][q] = wq * uu[d];
-    }
+    for (int d = 0; d < 3; ++d) sv[el][d][q] = wq * u[d * KN + e * NN + q];
     if (q < NP) sD[el][q] = Dfac[e * NP + q];
   }
   __syncthreads();

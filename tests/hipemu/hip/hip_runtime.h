@@ -1,0 +1,93 @@
+// Test harness: host-thread execution of the HIP subset used by the library's kernel sources, so
+// that tests/test_hipemu_kernels.py can run the kernel code on the CPU against the oracle.  One
+// host thread per GPU thread, blocks one after another, __shared__ variables are function statics
+// (shared by the block's threads), __syncthreads is a std::barrier, exited threads drop out of
+// later barriers, device memory is host memory.  It checks kernel logic (indexing, barriers,
+// reductions, decisions); it says nothing about GPU timing, and the package never loads it.
+#pragma once
+#include <algorithm>
+#include <atomic>
+#include <barrier>
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <thread>
+#include <vector>
+
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __shared__ static
+#define HIP_SYMBOL(x) (&x)
+
+struct dim3 {
+  unsigned x, y, z;
+  constexpr dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+struct EmuIdx { unsigned x, y, z; };
+struct alignas(16) double2 { double x, y; };
+inline thread_local EmuIdx threadIdx{0, 0, 0}, blockIdx{0, 0, 0};
+inline thread_local dim3 blockDim, gridDim;
+inline thread_local std::barrier<>* emu_bar = nullptr;
+inline void __syncthreads() { emu_bar->arrive_and_wait(); }
+
+inline int atomicOr(int* a, int v) { return __atomic_fetch_or(a, v, __ATOMIC_SEQ_CST); }
+inline unsigned long long atomicAdd(unsigned long long* a, unsigned long long v) {
+  return __atomic_fetch_add(a, v, __ATOMIC_SEQ_CST);
+}
+inline int atomicAdd(int* a, int v) { return __atomic_fetch_add(a, v, __ATOMIC_SEQ_CST); }
+
+template <class F, class... A>
+void emu_launch(F f, dim3 g, dim3 b, A... args) {
+  const unsigned nt = b.x * b.y * b.z;
+  for (unsigned bz = 0; bz < g.z; ++bz)
+    for (unsigned by = 0; by < g.y; ++by)
+      for (unsigned bx = 0; bx < g.x; ++bx) {
+        std::barrier<> bar((std::ptrdiff_t)nt);
+        std::vector<std::thread> th;
+        th.reserve(nt);
+        for (unsigned t = 0; t < nt; ++t)
+          th.emplace_back([&, t] {
+            threadIdx = EmuIdx{t % b.x, (t / b.x) % b.y, t / (b.x * b.y)};
+            blockIdx = EmuIdx{bx, by, bz};
+            blockDim = b; gridDim = g; emu_bar = &bar;
+            f(args...);
+            bar.arrive_and_drop();
+          });
+        for (auto& x : th) x.join();
+      }
+}
+#define hipLaunchKernelGGL(F, G, B, S, STREAM, ...) emu_launch(F, dim3(G), dim3(B), __VA_ARGS__)
+
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1 };
+typedef void* hipStream_t;
+struct EmuEvent { double t; };
+typedef EmuEvent* hipEvent_t;
+enum hipMemcpyKind { hipMemcpyHostToHost, hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyDefault };
+inline hipError_t hipGetLastError() { return hipSuccess; }
+inline const char* hipGetErrorString(hipError_t) { return "emu error"; }
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipMalloc(void** p, size_t n) { *p = std::calloc(1, n ? n : 8); return *p ? hipSuccess : hipErrorOutOfMemory; }
+inline hipError_t hipHostMalloc(void** p, size_t n, unsigned = 0) { return hipMalloc(p, n); }
+inline hipError_t hipFree(void* p) { std::free(p); return hipSuccess; }
+inline hipError_t hipHostFree(void* p) { std::free(p); return hipSuccess; }
+inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { std::memmove(d, s, n); return hipSuccess; }
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t = nullptr) { std::memmove(d, s, n); return hipSuccess; }
+inline hipError_t hipMemset(void* d, int v, size_t n) { std::memset(d, v, n); return hipSuccess; }
+inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t = nullptr) { std::memset(d, v, n); return hipSuccess; }
+enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2 };
+inline hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = nullptr; return hipSuccess; }
+inline hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
+inline hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
+inline hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = (hipEvent_t)std::calloc(1, 8); return hipSuccess; }
+inline hipError_t hipEventCreate(hipEvent_t* e) { *e = (hipEvent_t)std::calloc(1, 8); return hipSuccess; }
+inline hipError_t hipEventDestroy(hipEvent_t e) { std::free(e); return hipSuccess; }
+inline hipError_t hipEventRecord(hipEvent_t, hipStream_t = nullptr) { return hipSuccess; }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 0.f; return hipSuccess; }
