@@ -23,7 +23,7 @@ int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, doub
                     const double* By, const double* Bz);
 int mag_velocity_prep(mhd25_ctx* c, const double* rho);
 int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
-                       const double* By, const double* Bz);
+                       const double* By, const double* Bz, bool stats_ready);
 int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,
                const double* Bz, double* eta);
 int mag_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u);
@@ -192,14 +192,14 @@ int mhd25_hydro_stage_map(mhd25_ctx* c, double* U, double tau, uint8_t* flags) {
 
 // one attempt of the SSP-RK(3,3) hydro substep; returns 1 accepted, 0 rejected, <0 error
 static int hydro_attempt(mhd25_ctx* c, double* U, double tau, long long* counts) {
-  const long n5 = 5 * c->mp.K * c->nn;
+  // U itself serves as U^n: it is written only by the last stage's map, which every thread
+  // does for its own nodes after all reads of U^n, and which is skipped when the attempt is rejected
   TRY(reset_attempt(c));
-  TRY(dcopy(c, U, c->Un, n5));
-  TRY(hydro_stage_a(c, c->Un, c->Un, c->Ust, 0.0, 1.0, tau));
+  TRY(hydro_stage_a(c, U, U, c->Ust, 0.0, 1.0, tau));
   TRY(hydro_stage_b(c, c->Ust, c->S1, tau, c->d_flag));
-  TRY(hydro_stage_a(c, c->S1, c->Un, c->Ust, 0.75, 0.25, tau));
+  TRY(hydro_stage_a(c, c->S1, U, c->Ust, 0.75, 0.25, tau));
   TRY(hydro_stage_b(c, c->Ust, c->S2, tau, c->d_flag));
-  TRY(hydro_stage_a(c, c->S2, c->Un, c->Ust, 1.0 / 3.0, 2.0 / 3.0, tau));
+  TRY(hydro_stage_a(c, c->S2, U, c->Ust, 1.0 / 3.0, 2.0 / 3.0, tau));
   TRY(hydro_stage_b(c, c->Ust, U, tau, c->d_flag));  // skipped (U untouched) when rejected
   int* hf = (int*)c->h_pinned;
   unsigned long long* hc = (unsigned long long*)(c->h_pinned + 8);
@@ -312,8 +312,9 @@ int mhd25_step_magnetic(mhd25_ctx* c, const double* rho, double* e, double* u, d
     io.eta = eta;
     io.oe = oe; io.ou = ou; io.obx = ox; io.oby = oy; io.obz = oz;
     io.ca = cas[s]; io.cb = cbs[s]; io.tau = tau;
+    io.ustats = c->opt.oe_mag ? c->stats : nullptr;  // the update also forms the sensor's u statistics
     TRY(mag_update(c, io, 1));
-    if (c->opt.oe_mag) TRY(mag_velocity_apply(c, tau, rho, ou, oe, ox, oy, oz));
+    if (c->opt.oe_mag) TRY(mag_velocity_apply(c, tau, rho, ou, oe, ox, oy, oz, true));
   }
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));

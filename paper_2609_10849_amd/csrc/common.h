@@ -62,6 +62,7 @@ struct MagIO {
   const double *jx, *jy, *jz, *ex, *ey, *ez;      // reconstructed J and E grids
   const double* eta;
   double *oe, *ou, *obx, *oby, *obz;              // outputs
+  double* ustats;                                 // optional: [K][3][3] statistics of the new u (SSP combine)
   double ca, cb, tau;
 };
 

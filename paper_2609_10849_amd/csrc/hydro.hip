@@ -566,38 +566,59 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
 
 }  // namespace
 
-// Row / column reduction of per-element statistics [K][nc][3] (sum, min, max): blocks
-// 0..ny-1 reduce element rows, blocks ny..ny+nx-1 reduce element columns.  Fixed order.
+// Row / column reduction of per-element statistics [K][nc][3] (sum, min, max), nc <= 5, fixed
+// order.  Blocks 0..ny-1 reduce one element row each: thread t takes elements t, t+256, ... of
+// the row and reads each element's nc*3 values as one contiguous record.  Blocks ny.. reduce
+// LRC adjacent element columns each: thread (column j, phase p) takes rows p, p+LRP, ... of
+// column j, so a wave reads adjacent elements of one row.  Partial results are combined in LDS
+// by a fixed tree.
+constexpr int LRC = 8, LRP = 256 / LRC;
+
 __global__ __launch_bounds__(256) void k_line_reduce(const double* __restrict__ stats, double* __restrict__ lines,
                                                      int nx, int ny, int nc, const int* __restrict__ flag) {
-  __shared__ double red[3][256];
+  __shared__ double red[15][256];
   if (flag && *flag) return;
   const int b = blockIdx.x, t = threadIdx.x;
-  const bool row = b < ny;
-  const int len = row ? nx : ny;
-  for (int c = 0; c < nc; ++c) {
-    double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
-    for (int k = t; k < len; k += 256) {
-      const long e = row ? (long)b * nx + k : (long)k * nx + (b - ny);
-      const double* st = stats + (e * nc + c) * 3;
-      s += st[0]; mn = fmin(mn, st[1]); mx = fmax(mx, st[2]);
-    }
-    red[0][t] = s; red[1][t] = mn; red[2][t] = mx;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (t < w) {
-        red[0][t] += red[0][t + w];
-        red[1][t] = fmin(red[1][t], red[1][t + w]);
-        red[2][t] = fmax(red[2][t], red[2][t + w]);
+  const int nv = nc * 3;
+  double v[15];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) v[k] = (k % 3 == 0) ? 0.0 : (k % 3 == 1 ? DBL_MAX : -DBL_MAX);
+  auto take = [&](long e) {
+    const double* st = stats + e * nv;
+#pragma unroll
+    for (int c = 0; c < 5; ++c)
+      if (c < nc) {
+        v[3 * c] += st[3 * c];
+        v[3 * c + 1] = fmin(v[3 * c + 1], st[3 * c + 1]);
+        v[3 * c + 2] = fmax(v[3 * c + 2], st[3 * c + 2]);
       }
-      __syncthreads();
-    }
-    if (t == 0) {
-      lines[((long)b * nc + c) * 3 + 0] = red[0][0];
-      lines[((long)b * nc + c) * 3 + 1] = red[1][0];
-      lines[((long)b * nc + c) * 3 + 2] = red[2][0];
-    }
+  };
+  if (b < ny) {
+    for (int k = t; k < nx; k += 256) take((long)b * nx + k);
+  } else {
+    const int col = (b - ny) * LRC + t % LRC, ph = t / LRC;
+    if (col < nx)
+      for (int r = ph; r < ny; r += LRP) take((long)r * nx + col);
+  }
+#pragma unroll
+  for (int k = 0; k < 15; ++k) red[k][t] = v[k];
+  __syncthreads();
+  // rows: tree over all 256 threads; columns: tree over the LRP phases of each column
+  const int lo = b < ny ? 1 : LRC;
+  for (int w = 128; w >= lo; w >>= 1) {
+    if (t < w)
+      for (int c = 0; c < nc; ++c) {
+        red[3 * c][t] += red[3 * c][t + w];
+        red[3 * c + 1][t] = fmin(red[3 * c + 1][t], red[3 * c + 1][t + w]);
+        red[3 * c + 2][t] = fmax(red[3 * c + 2][t], red[3 * c + 2][t + w]);
+      }
     __syncthreads();
+  }
+  if (b < ny) {
+    if (t < nv) lines[(long)b * nv + t] = red[t][0];
+  } else if (t < LRC * nv) {
+    const int j = t % LRC, k = t / LRC, col = (b - ny) * LRC + j;
+    if (col < nx) lines[((long)ny + col) * nv + k] = red[k][j];
   }
 }
 
@@ -682,14 +703,14 @@ int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust,
   if (ev) hipEventRecord(ev[1], c->stream);
   int r = check(c, hipGetLastError(), "hydro stage launch");
   if (r) return r;
-  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.nx + c->mp.ny), dim3(256), 0, c->stream, c->stats, c->lines,
+  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.ny + (c->mp.nx + LRC - 1) / LRC), dim3(256), 0, c->stream, c->stats, c->lines,
                      c->mp.nx, c->mp.ny, 5, c->d_flag);
   hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, 5, c->d_flag);
   return check(c, hipGetLastError(), "reduce launch");
 }
 
 int line_global_reduce(mhd25_ctx* c, const double* stats, int nc, const int* flag) {
-  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.nx + c->mp.ny), dim3(256), 0, c->stream, stats, c->lines,
+  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.ny + (c->mp.nx + LRC - 1) / LRC), dim3(256), 0, c->stream, stats, c->lines,
                      c->mp.nx, c->mp.ny, nc, flag);
   hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, nc, flag);
   return check(c, hipGetLastError(), "reduce launch");
@@ -700,7 +721,7 @@ int hydro_stats_only(mhd25_ctx* c, const double* U, int* flag) {
 #define LS(P) hipLaunchKernelGGL((k_elem_stats<P>), dim3(blocks), dim3(256), 0, c->stream, U, c->stats, flag, c->d_ht, c->mp)
   DISPATCH_P(c->p, LS);
 #undef LS
-  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.nx + c->mp.ny), dim3(256), 0, c->stream, c->stats, c->lines,
+  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.ny + (c->mp.nx + LRC - 1) / LRC), dim3(256), 0, c->stream, c->stats, c->lines,
                      c->mp.nx, c->mp.ny, 5, nullptr);
   hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, 5, nullptr);
   return check(c, hipGetLastError(), "stats launch");

@@ -296,12 +296,47 @@ __global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __re
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
   __shared__ double sex[EB][AB], sey[EB][AB], sez[EB][AA];
   __shared__ double sjx[EB][AB], sjy[EB][AB], sjz[EB][AA];
-  __shared__ double fz[EB][2][AA], fx[EB][2][AB], fy[EB][2][AB];
+  __shared__ double fz[EB][2][AA], fx[EB][2][AB], fy[EB][2][AB], snew[EB][3][NN];
+  __shared__ double tDWG[B][A], tDWV[B][A], tIGV[B][B], tIGW[A][B], tIVG[B][B], tIVW[A][B], tIPW[A][NP], tIPG[B][NP], tIGP[NP][B], tIWP[NP][A];
+  __shared__ double tww[A], twg[B], twp[NP];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
   const long e = xcd_block() * EB + el;
   const bool act = el < EB && e < mp.K;
   const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
   const long KN = mp.K * NN;
+  for (int k = tid; k < B * A; k += 256) tDWG[k / A][k % A] = T->D_W_G[k / A][k % A];
+  for (int k = tid; k < B * A; k += 256) tDWV[k / A][k % A] = T->D_W_V[k / A][k % A];
+  for (int k = tid; k < B * B; k += 256) tIGV[k / B][k % B] = T->I_G_V[k / B][k % B];
+  for (int k = tid; k < A * B; k += 256) tIGW[k / B][k % B] = T->I_G_W[k / B][k % B];
+  for (int k = tid; k < B * B; k += 256) tIVG[k / B][k % B] = T->I_V_G[k / B][k % B];
+  for (int k = tid; k < A * B; k += 256) tIVW[k / B][k % B] = T->I_V_W[k / B][k % B];
+  for (int k = tid; k < A * NP; k += 256) tIPW[k / NP][k % NP] = T->I_P_W[k / NP][k % NP];
+  for (int k = tid; k < B * NP; k += 256) tIPG[k / NP][k % NP] = T->I_P_G[k / NP][k % NP];
+  for (int k = tid; k < NP * B; k += 256) tIGP[k / B][k % B] = T->I_G_P[k / B][k % B];
+  for (int k = tid; k < NP * A; k += 256) tIWP[k / A][k % A] = T->I_W_P[k / A][k % A];
+  if (tid < A) tww[tid] = T->ww[tid];
+  if (tid < B) twg[tid] = T->wg[tid];
+  if (tid < NP) twp[tid] = T->wp[tid];
+  // values used only at the end are loaded first, so that their latency overlaps the work
+  double rq = 1.0, et = 0.0, yn[5] = {0, 0, 0, 0, 0}, ys[5] = {0, 0, 0, 0, 0}, bn[3] = {0, 0, 0}, bs[3] = {0, 0, 0};
+  long gown = 0;
+  if (act && t < NN) {
+    const long n = e * NN + t;
+    rq = io.rho[n];
+    et = io.eta ? io.eta[e] : 0.0;
+    if (MODE == 1) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) { yn[d] = io.un[d * KN + n]; ys[d] = io.us[d * KN + n]; }
+      yn[3] = io.en[n]; ys[3] = io.es[n];
+    }
+  }
+  if (act && t < BB) {
+    gown = gix(mp, B, ex, ey, t % B, t / B);
+    if (MODE == 1) {
+      bn[0] = io.bxn[gown]; bn[1] = io.byn[gown]; bn[2] = io.bzn[gown];
+      bs[0] = io.bxs[gown]; bs[1] = io.bys[gown]; bs[2] = io.bzs[gown];
+    }
+  }
   if (act) {
     load_B<P, M>(sbx[el], sby[el], sbz[el], io.bxs, io.bys, io.bzs, mp, ex, ey, t);
     for (int k = t; k < AB; k += NT) {
@@ -317,12 +352,12 @@ __global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __re
   __syncthreads();
   if (act && t < BB) {  // strong curl at the element's owned B nodes
     const int i = t % B, j = t / B;
-    const long g = gix(mp, B, ex, ey, i, j);
+    const long g = gown;
     double dbx = 0.0, dby = 0.0;
 #pragma unroll
     for (int k = 0; k < A; ++k) {
-      dbx += T->D_W_G[j][k] * sez[el][k * A + i];
-      dby += T->D_W_G[i][k] * sez[el][j * A + k];
+      dbx += tDWG[j][k] * sez[el][k * A + i];
+      dby += tDWG[i][k] * sez[el][j * A + k];
     }
     dbx *= -(2.0 / mp.hy);
     dby *= (2.0 / mp.hx);
@@ -331,23 +366,23 @@ __global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __re
     for (int l = 0; l < B; ++l) {
       double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < A; ++k) s += T->D_W_V[i][k] * sey[el][l * A + k];
-      dxey += T->I_G_V[j][l] * s;
+      for (int k = 0; k < A; ++k) s += tDWV[i][k] * sey[el][l * A + k];
+      dxey += tIGV[j][l] * s;
     }
 #pragma unroll
     for (int l = 0; l < A; ++l) {
       double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < B; ++k) s += T->I_G_V[i][k] * sex[el][l * B + k];
-      dyex += T->D_W_V[j][l] * s;
+      for (int k = 0; k < B; ++k) s += tIGV[i][k] * sex[el][l * B + k];
+      dyex += tDWV[j][l] * s;
     }
     const double dbz = -((2.0 / mp.hx) * dxey - (2.0 / mp.hy) * dyex);
     if (MODE == 0) {
       io.obx[g] = dbx; io.oby[g] = dby; io.obz[g] = dbz;
     } else {
-      io.obx[g] = io.ca * io.bxn[g] + io.cb * (io.bxs[g] + io.tau * dbx);
-      io.oby[g] = io.ca * io.byn[g] + io.cb * (io.bys[g] + io.tau * dby);
-      io.obz[g] = io.ca * io.bzn[g] + io.cb * (io.bzs[g] + io.tau * dbz);
+      io.obx[g] = io.ca * bn[0] + io.cb * (bs[0] + io.tau * dbx);
+      io.oby[g] = io.ca * bn[1] + io.cb * (bs[1] + io.tau * dby);
+      io.obz[g] = io.ca * bn[2] + io.cb * (bs[2] + io.tau * dbz);
     }
   }
   // weighted Lorentz loads f_a at the auxiliary nodes (transpose of the coupling form)
@@ -356,10 +391,10 @@ __global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __re
     double bxv = 0.0, byv = 0.0;
 #pragma unroll
     for (int k = 0; k < B; ++k) {
-      bxv += T->I_G_W[j][k] * sbx[el][k * A + i];
-      byv += T->I_G_W[i][k] * sby[el][j * B + k];
+      bxv += tIGW[j][k] * sbx[el][k * A + i];
+      byv += tIGW[i][k] * sby[el][j * B + k];
     }
-    const double w = mp.J * T->ww[i] * T->ww[j] * sjz[el][t];
+    const double w = mp.J * tww[i] * tww[j] * sjz[el][t];
     fz[el][0][t] = -byv * w;  // x
     fz[el][1][t] = bxv * w;   // y
   }
@@ -371,10 +406,10 @@ __global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __re
       for (int jj = 0; jj < B; ++jj) {
         double s = 0.0;
 #pragma unroll
-        for (int ii = 0; ii < B; ++ii) s += T->I_V_G[i][ii] * sbz[el][jj * B + ii];
-        bzv += T->I_V_W[j][jj] * s;
+        for (int ii = 0; ii < B; ++ii) s += tIVG[i][ii] * sbz[el][jj * B + ii];
+        bzv += tIVW[j][jj] * s;
       }
-      const double w = mp.J * T->wg[i] * T->ww[j] * sjx[el][t];
+      const double w = mp.J * twg[i] * tww[j] * sjx[el][t];
       fx[el][0][t] = -bzv * w;          // y
       fx[el][1][t] = sby[el][t] * w;    // z
     }
@@ -385,89 +420,108 @@ __global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __re
       for (int jj = 0; jj < B; ++jj) {
         double s = 0.0;
 #pragma unroll
-        for (int ii = 0; ii < B; ++ii) s += T->I_V_W[i][ii] * sbz[el][jj * B + ii];
-        bzv += T->I_V_G[j][jj] * s;
+        for (int ii = 0; ii < B; ++ii) s += tIVW[i][ii] * sbz[el][jj * B + ii];
+        bzv += tIVG[j][jj] * s;
       }
-      const double w = mp.J * T->ww[i] * T->wg[j] * sjy[el][t];
+      const double w = mp.J * tww[i] * twg[j] * sjy[el][t];
       fy[el][0][t] = bzv * w;           // x
       fy[el][1][t] = -sbx[el][t] * w;   // z
     }
   }
   __syncthreads();
-  if (!act || t >= NN) return;
-  const int qi = t % NP, qj = t / NP;
-  // transpose of the interpolation to the auxiliary nodes, factorised over the two directions
-  double du[3] = {0.0, 0.0, 0.0};
+  const bool node = act && t < NN;
+  if (node) {
+    const int qi = t % NP, qj = t / NP;
+    // transpose of the interpolation to the auxiliary nodes, factorised over the two directions
+    double du[3] = {0.0, 0.0, 0.0};
 #pragma unroll 1
-  for (int j = 0; j < A; ++j) {
-    double s0 = 0.0, s1 = 0.0, t1 = 0.0, t2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < A; ++i) {
-      const double I = T->I_P_W[i][qi];
-      s0 += I * fz[el][0][j * A + i];
-      s1 += I * fz[el][1][j * A + i];
-    }
-#pragma unroll
-    for (int i = 0; i < B; ++i) {
-      const double I = T->I_P_G[i][qi];
-      t1 += I * fx[el][0][j * B + i];
-      t2 += I * fx[el][1][j * B + i];
-    }
-    const double Iy = T->I_P_W[j][qj];
-    du[0] += Iy * s0;
-    du[1] += Iy * (s1 + t1);
-    du[2] += Iy * t2;
-  }
-#pragma unroll 1
-  for (int j = 0; j < B; ++j) {
-    double s0 = 0.0, s2 = 0.0;
-#pragma unroll
-    for (int i = 0; i < A; ++i) {
-      const double I = T->I_P_W[i][qi];
-      s0 += I * fy[el][0][j * A + i];
-      s2 += I * fy[el][1][j * A + i];
-    }
-    const double Iy = T->I_P_G[j][qj];
-    du[0] += Iy * s0;
-    du[2] += Iy * s2;
-  }
-  const long n = e * NN + t;
-  const double rq = io.rho[n];
-  const double Mq = mp.J * T->wp[qi] * T->wp[qj];
-  const double et = io.eta ? io.eta[e] : 0.0;
-  double de = 0.0;
-  if (et != 0.0) {
-    double jx = 0.0, jy = 0.0, jz = 0.0;
-#pragma unroll
     for (int j = 0; j < A; ++j) {
-      double s = 0.0;
+      double s0 = 0.0, s1 = 0.0, t1 = 0.0, t2 = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += T->I_G_P[qi][i] * sjx[el][j * B + i];
-      jx += T->I_W_P[qj][j] * s;
+      for (int i = 0; i < A; ++i) {
+        const double I = tIPW[i][qi];
+        s0 += I * fz[el][0][j * A + i];
+        s1 += I * fz[el][1][j * A + i];
+      }
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        const double I = tIPG[i][qi];
+        t1 += I * fx[el][0][j * B + i];
+        t2 += I * fx[el][1][j * B + i];
+      }
+      const double Iy = tIPW[j][qj];
+      du[0] += Iy * s0;
+      du[1] += Iy * (s1 + t1);
+      du[2] += Iy * t2;
     }
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < B; ++j) {
-      double s = 0.0;
+      double s0 = 0.0, s2 = 0.0;
 #pragma unroll
-      for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sjy[el][j * A + i];
-      jy += T->I_G_P[qj][j] * s;
+      for (int i = 0; i < A; ++i) {
+        const double I = tIPW[i][qi];
+        s0 += I * fy[el][0][j * A + i];
+        s2 += I * fy[el][1][j * A + i];
+      }
+      const double Iy = tIPG[j][qj];
+      du[0] += Iy * s0;
+      du[2] += Iy * s2;
     }
+    const long n = e * NN + t;
+    const double Mq = mp.J * twp[qi] * twp[qj];
+    double de = 0.0;
+    if (et != 0.0) {
+      double jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
-    for (int j = 0; j < A; ++j) {
-      double s = 0.0;
+      for (int j = 0; j < A; ++j) {
+        double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < A; ++i) s += T->I_W_P[qi][i] * sjz[el][j * A + i];
-      jz += T->I_W_P[qj][j] * s;
+        for (int i = 0; i < B; ++i) s += tIGP[qi][i] * sjx[el][j * B + i];
+        jx += tIWP[qj][j] * s;
+      }
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < A; ++i) s += tIWP[qi][i] * sjy[el][j * A + i];
+        jy += tIGP[qj][j] * s;
+      }
+#pragma unroll
+      for (int j = 0; j < A; ++j) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < A; ++i) s += tIWP[qi][i] * sjz[el][j * A + i];
+        jz += tIWP[qj][j] * s;
+      }
+      de = et * (jx * jx + jy * jy + jz * jz) / rq;
     }
-    de = et * (jx * jx + jy * jy + jz * jz) / rq;
+    if (MODE == 0) {
+      for (int d = 0; d < 3; ++d) io.ou[d * KN + n] = du[d] / (rq * Mq);
+      io.oe[n] = de;
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double v = io.ca * yn[d] + io.cb * (ys[d] + io.tau * (du[d] / (rq * Mq)));
+        io.ou[d * KN + n] = v;
+        snew[el][d][t] = v;
+      }
+      io.oe[n] = io.ca * yn[3] + io.cb * (ys[3] + io.tau * de);
+    }
   }
-  if (MODE == 0) {
-    for (int d = 0; d < 3; ++d) io.ou[d * KN + n] = du[d] / (rq * Mq);
-    io.oe[n] = de;
-  } else {
-    for (int d = 0; d < 3; ++d)
-      io.ou[d * KN + n] = io.ca * io.un[d * KN + n] + io.cb * (io.us[d * KN + n] + io.tau * (du[d] / (rq * Mq)));
-    io.oe[n] = io.ca * io.en[n] + io.cb * (io.es[n] + io.tau * de);
+  if (MODE == 1 && io.ustats) {
+    // element statistics of the new velocity (GLL-weighted sum, min, max), as the velocity-OE
+    // sensor needs them
+    __syncthreads();
+    for (int tk = t; act && tk < 9; tk += NT) {
+      const int c = tk / 3, kind = tk - 3 * c;
+      double sm = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+      for (int k = 0; k < NN; ++k) {
+        const double v = snew[el][c][k];
+        sm += (twp[k % NP] * twp[k / NP]) * v;
+        mn = fmin(mn, v); mx = fmax(mx, v);
+      }
+      io.ustats[(e * 3 + c) * 3 + kind] = kind == 0 ? sm : (kind == 1 ? mn : mx);
+    }
   }
 }
 
@@ -590,18 +644,19 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
 #pragma unroll
   for (int k = 0; k < NN; ++k) *((act0 && k <= q) ? &sL[el][q * (q + 1) / 2 + k] : &sdum[tid]) = g[k];
   __syncthreads();
-  // row q of Psi = Phi L^{-T}: forward substitution over the modes, the row kept in LDS (sP
-  // aliases the Gram staging sH, dead by now), then stored with coalesced writes
-  double* pr = &sP[el][q][0];
-  if (act0) {
-    for (int k = 0; k < NN; ++k) {
-      double s = sV[qi][ska[k]] * sV[qj][skb[k]];
-      const double* lk = &sL[el][k * (k + 1) / 2];
-#pragma unroll 4
-      for (int k2 = 0; k2 < k; ++k2) s -= lk[k2] * pr[k2];
-      pr[k] = s * srd[el][k];
-    }
+  // row q of Psi = Phi L^{-T}: forward substitution over the modes with the row in registers
+  // (L is read from LDS as broadcasts), then staged in LDS (sP aliases the Gram staging sH, dead
+  // by now) for a coalesced store
+  double psi[NN];
+#pragma unroll
+  for (int k = 0; k < NN; ++k) {
+    double s = sV[qi][ska[k]] * sV[qj][skb[k]];
+#pragma unroll
+    for (int k2 = 0; k2 < k; ++k2) s -= sL[el][k * (k + 1) / 2 + k2] * psi[k2];
+    psi[k] = s * srd[el][k];
   }
+#pragma unroll
+  for (int k = 0; k < NN; ++k) *(act0 ? &sP[el][q][k] : &sdum[tid]) = psi[k];
   __syncthreads();
   constexpr long PS = psi_stride(NN), RS = psi_row(NN);
   for (int t = tid; t < EB * NN * NN; t += 64) {
@@ -1221,14 +1276,16 @@ int mag_velocity_prep(mhd25_ctx* c, const double* rho) {
 
 // apply with the basis prepared for the current rho: line statistics of u, sensor, projection
 int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
-                       const double* By, const double* Bz) {
+                       const double* By, const double* Bz, bool stats_ready) {
   const long K = c->mp.K;
   const int nn = (c->p + 1) * (c->p + 1), eb = 256 / nn, eb2 = 128 / nn;
   const long nb = (K + eb - 1) / eb, nb2 = (K + eb2 - 1) / eb2;
+  if (!stats_ready) {
 #define FS(P) hipLaunchKernelGGL((k_field_stats<P, 3>), dim3(nb), dim3(256), 0, c->stream, u, c->stats, c->d_mt, c->mp)
-  switch (c->p) { case 1: FS(1); break; case 2: FS(2); break; case 3: FS(3); break; case 4: FS(4); break;
-                  case 5: FS(5); break; case 6: FS(6); break; default: return -4; }
+    switch (c->p) { case 1: FS(1); break; case 2: FS(2); break; case 3: FS(3); break; case 4: FS(4); break;
+                    case 5: FS(5); break; case 6: FS(6); break; default: return -4; }
 #undef FS
+  }
   line_global_reduce(c, c->stats, 3, nullptr);
 #define VSN(P, M) hipLaunchKernelGGL((k_vel_sensor<P, M>), dim3(nb), dim3(256), 0, c->stream, rho, u, Bx, By, Bz, c->lines, \
                                      c->glob, c->dfac, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M)
@@ -1245,7 +1302,7 @@ int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, doub
                     const double* By, const double* Bz) {
   int r = mag_velocity_prep(c, rho);
   if (r) return r;
-  return mag_velocity_apply(c, tau, rho, u, e, Bx, By, Bz);
+  return mag_velocity_apply(c, tau, rho, u, e, Bx, By, Bz, false);
 }
 
 int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,

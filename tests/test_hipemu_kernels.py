@@ -97,3 +97,22 @@ def test_emulated_strang_step_full_stabilisation(emu, n, p, m):
     for a, r in zip(st, ref[:4]):
         if np.abs(r).max() > 0:
             assert np.abs(a - r).max() <= 1e-12 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("p,m,with_eta", [(2, 2, True), (4, 3, False), (4, 3, True)])
+def test_emulated_rhs_magnetic(emu, p, m, with_eta):
+    lib, pk = emu
+    L, U, Bx, By, Bz = W.random_state(5, 4, p, m, seed=3, domain=(0, 1.5, 0, 1.0), amp=0.3)
+    M = omesh(L)
+    rho, e, u = O.to_primitive(M, U)
+    eta = np.random.default_rng(5).uniform(0, 0.05, M.K) if with_eta else None
+    ref = O.rhs_magnetic(M, rho, u, Bx, By, Bz, eta)
+    h = context(lib, pk, L, pk.Options.make())
+    outs = [np.zeros_like(a) for a in ref]
+    ins = [np.ascontiguousarray(a) for a in (rho, u, Bx, By, Bz)]
+    assert lib.mhd25_rhs_magnetic(h, *[ptr(a) for a in ins], None if eta is None else ptr(eta),
+                                  *[ptr(a) for a in outs]) == 0
+    lib.mhd25_destroy(h)
+    for a, r in zip(outs, ref):
+        if np.abs(r).max() > 0:
+            assert np.abs(a - r).max() <= 1e-12 * np.abs(r).max()
