@@ -56,10 +56,21 @@ __global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, 
   using C = MC<P, M>;
   constexpr int A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB, NT = C::NT;
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB], swx[EB][AA], swy[EB][AA], szg[EB][BB];
+  __shared__ double sh[EB][2][AA];  // first half of the sum factorisation of the W loads
+  __shared__ double tWQ[A][A], tGQ[A][B], tDWQ[A][A], tVG[B][B], tDWG[B][A], twq[A], twg[B];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
   const long e = xcd_block() * EB + el;
   const bool act = el < EB && e < mp.K;
   const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  for (int k = tid; k < A * A; k += 256) {
+    tWQ[k / A][k % A] = T->I_W_Q[k / A][k % A];
+    tDWQ[k / A][k % A] = T->D_W_Q[k / A][k % A];
+  }
+  for (int k = tid; k < A * B; k += 256) tGQ[k / B][k % B] = T->I_G_Q[k / B][k % B];
+  for (int k = tid; k < B * B; k += 256) tVG[k / B][k % B] = T->I_V_G[k / B][k % B];
+  for (int k = tid; k < B * A; k += 256) tDWG[k / A][k % A] = T->D_W_G[k / A][k % A];
+  if (tid < A) twq[tid] = T->wq[tid];
+  if (tid < B) twg[tid] = T->wg[tid];
   if (act) load_B<P, M>(sbx[el], sby[el], sbz[el], Bx, By, Bz, mp, ex, ey, t);
   __syncthreads();
   if (act && t < AA) {
@@ -69,17 +80,17 @@ __global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, 
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < A; ++i) s += T->I_W_Q[qx][i] * sbx[el][j * A + i];
-      bxq += T->I_G_Q[qy][j] * s;
+      for (int i = 0; i < A; ++i) s += tWQ[qx][i] * sbx[el][j * A + i];
+      bxq += tGQ[qy][j] * s;
     }
 #pragma unroll
     for (int j = 0; j < A; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += T->I_G_Q[qx][i] * sby[el][j * B + i];
-      byq += T->I_W_Q[qy][j] * s;
+      for (int i = 0; i < B; ++i) s += tGQ[qx][i] * sby[el][j * B + i];
+      byq += tWQ[qy][j] * s;
     }
-    const double wgt = mp.J * T->wq[qx] * T->wq[qy];
+    const double wgt = mp.J * twq[qx] * twq[qy];
     swx[el][t] = wgt * bxq;
     swy[el][t] = wgt * byq;
   }
@@ -90,10 +101,23 @@ __global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, 
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += T->I_V_G[gx][i] * sbz[el][j * B + i];
-      v += T->I_V_G[gy][j] * s;
+      for (int i = 0; i < B; ++i) s += tVG[gx][i] * sbz[el][j * B + i];
+      v += tVG[gy][j] * s;
     }
     szg[el][t] = v;
+  }
+  __syncthreads();
+  // W loads, factorised: sh[0][qy][i] = sum_qx I_W_Q[qx][i] swx[qy][qx], sh[1][qy][i] = sum_qx D_W_Q[qx][i] swy[qy][qx]
+  if (act && t < AA) {
+    const int i = t % A, qy = t / A;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int qx = 0; qx < A; ++qx) {
+      a0 += tWQ[qx][i] * swx[el][qy * A + qx];
+      a1 += tDWQ[qx][i] * swy[el][qy * A + qx];
+    }
+    sh[el][0][t] = a0;
+    sh[el][1][t] = a1;
   }
   __syncthreads();
   if (!act) return;
@@ -101,12 +125,10 @@ __global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, 
     const int i = t % A, j = t / A;
     double sx = 0.0, sy = 0.0;
 #pragma unroll
-    for (int qy = 0; qy < A; ++qy)
-#pragma unroll
-      for (int qx = 0; qx < A; ++qx) {
-        sx += swx[el][qy * A + qx] * (T->I_W_Q[qx][i] * T->D_W_Q[qy][j]);
-        sy += swy[el][qy * A + qx] * (T->D_W_Q[qx][i] * T->I_W_Q[qy][j]);
-      }
+    for (int qy = 0; qy < A; ++qy) {
+      sx += tDWQ[qy][j] * sh[el][0][qy * A + i];
+      sy += tWQ[qy][j] * sh[el][1][qy * A + i];
+    }
     Lz[e * AA + t] = (2.0 / mp.hy) * sx - (2.0 / mp.hx) * sy;
   }
   if (t < AB) {
@@ -114,15 +136,15 @@ __global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, 
       const int i = t % B, j = t / B;
       double s = 0.0;
 #pragma unroll
-      for (int qy = 0; qy < B; ++qy) s += T->wg[qy] * szg[el][qy * B + i] * T->D_W_G[qy][j];
-      Lx[e * AB + t] = -(2.0 / mp.hy) * mp.J * T->wg[i] * s;
+      for (int qy = 0; qy < B; ++qy) s += twg[qy] * szg[el][qy * B + i] * tDWG[qy][j];
+      Lx[e * AB + t] = -(2.0 / mp.hy) * mp.J * twg[i] * s;
     }
     {  // N_y node: i GLL (A), j Gauss (B); index j*A + i
       const int i = t % A, j = t / A;
       double s = 0.0;
 #pragma unroll
-      for (int qx = 0; qx < B; ++qx) s += T->wg[qx] * szg[el][j * B + qx] * T->D_W_G[qx][i];
-      Ly[e * AB + t] = (2.0 / mp.hx) * mp.J * T->wg[j] * s;
+      for (int qx = 0; qx < B; ++qx) s += twg[qx] * szg[el][j * B + qx] * tDWG[qx][i];
+      Ly[e * AB + t] = (2.0 / mp.hx) * mp.J * twg[j] * s;
     }
   }
 }
@@ -580,9 +602,7 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
                                                  const HydroTab* __restrict__ H, MeshP mp) {
   constexpr int NP = P + 1, NN = NP * NP, EB = VP<P>::EB, NL = NN * (NN + 1) / 2;
   __shared__ double sw[EB][NN], sL[EB][NL], scol[EB][NN], srd[EB][NN], sdg[EB], sdum[64];
-  __shared__ double sHP[EB * (NN * (NN + 1) > NP * NP * NP ? NN * (NN + 1) : NP * NP * NP)];
-  auto sH = reinterpret_cast<double(*)[NP][NP * NP]>(sHP);  // Gram staging [EB][NP][NP^2]
-  auto sP = reinterpret_cast<double(*)[NN][NN + 1]>(sHP);   // Psi rows [EB][NN][NN+1]
+  __shared__ double sH[EB][NP][NP * NP];  // Gram staging
   __shared__ double sV[NP][NP];
   __shared__ int ska[NN], skb[NN];
   const int tid = threadIdx.x, el0 = tid / NN;
@@ -645,8 +665,7 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
   for (int k = 0; k < NN; ++k) *((act0 && k <= q) ? &sL[el][q * (q + 1) / 2 + k] : &sdum[tid]) = g[k];
   __syncthreads();
   // row q of Psi = Phi L^{-T}: forward substitution over the modes with the row in registers
-  // (L is read from LDS as broadcasts), then staged in LDS (sP aliases the Gram staging sH, dead
-  // by now) for a coalesced store
+  // (L is read from LDS as broadcasts)
   double psi[NN];
 #pragma unroll
   for (int k = 0; k < NN; ++k) {
@@ -655,14 +674,13 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
     for (int k2 = 0; k2 < k; ++k2) s -= sL[el][k * (k + 1) / 2 + k2] * psi[k2];
     psi[k] = s * srd[el][k];
   }
+  // row q of the element's table, stored directly (rows are 16-byte aligned: psi_row is even)
+  if (act0) {
+    constexpr long PS = psi_stride(NN), RS = psi_row(NN);
+    double2* out = reinterpret_cast<double2*>(Psi + e * PS + q * RS);
 #pragma unroll
-  for (int k = 0; k < NN; ++k) *(act0 ? &sP[el][q][k] : &sdum[tid]) = psi[k];
-  __syncthreads();
-  constexpr long PS = psi_stride(NN), RS = psi_row(NN);
-  for (int t = tid; t < EB * NN * NN; t += 64) {
-    const int ee = t / (NN * NN), r = t - ee * NN * NN;
-    const long eg = (long)blockIdx.x * EB + ee;
-    if (eg < mp.K) Psi[eg * PS + (r / NN) * RS + r % NN] = sP[ee][r / NN][r % NN];
+    for (int k2 = 0; k2 < NN / 2; ++k2) out[k2] = double2{psi[2 * k2], psi[2 * k2 + 1]};
+    if (NN % 2) Psi[e * PS + q * RS + NN - 1] = psi[NN - 1];
   }
 }
 
