@@ -116,3 +116,58 @@ def test_emulated_rhs_magnetic(emu, p, m, with_eta):
     for a, r in zip(outs, ref):
         if np.abs(r).max() > 0:
             assert np.abs(a - r).max() <= 1e-12 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("nx,ny,p", [(1, 1, 1), (1, 3, 2), (3, 1, 4), (2, 2, 6)])
+def test_emulated_rhs_hydro_degenerate_meshes(emu, nx, ny, p):
+    """Meshes whose periodic neighbours are the element itself (1 x 1), rows or columns of one
+    element, and the extreme degrees p = 1 and p = 6; LLF and EC interfaces."""
+    lib, pk = emu
+    L, U, *_ = W.random_state(nx, ny, p, p - 1, seed=11 + p, amp=0.3)
+    for iface in (0, 1):
+        ref = O.rhs_hydro(omesh(L), U, iface_flux=iface)
+        h = context(lib, pk, L, pk.Options.make(iface_flux=iface))
+        got = np.zeros_like(U)
+        assert lib.mhd25_rhs_hydro(h, ptr(np.ascontiguousarray(U)), ptr(got)) == 0
+        lib.mhd25_destroy(h)
+        # On one p = 1 element whose periodic neighbours are itself the EC volume and surface
+        # terms cancel exactly, so the RHS is round-off; the bound is floored at the state's size.
+        scale = max(np.abs(ref).max(), np.abs(U).max())
+        for c in range(5):
+            assert np.abs(got[c] - ref[c]).max() <= 1e-12 * scale, (iface, c)
+
+
+def test_emulated_strang_step_single_element_mesh(emu):
+    lib, pk = emu
+    L, U, Bx, By, Bz = W.random_state(1, 2, 3, 2, seed=5, amp=0.2)
+    h = context(lib, pk, L, pk.Options.full())
+    st = [np.ascontiguousarray(a.copy()) for a in (U, Bx, By, Bz)]
+    rep = pk.Report()
+    assert lib.mhd25_strang_step(h, *[ptr(a) for a in st], 1e-3, ctypes.byref(rep)) == 0
+    lib.mhd25_destroy(h)
+    ref = O.strang_step(omesh(L), O.Options.full(), U, Bx, By, Bz, 1e-3)
+    for a, r in zip(st, ref[:4]):
+        if np.abs(r).max() > 0:
+            assert np.abs(a - r).max() <= 1e-12 * np.abs(r).max()
+
+
+def test_emulated_invalid_arguments(emu):
+    """Argument errors are reported by return code before any device work."""
+    lib, pk = emu
+    h = ctypes.c_void_p()
+    ok = pk.MeshDesc(4, 4, 0.0, 1.0, 0.0, 1.0, 2, 2, 5.0 / 3.0)
+    assert lib.mhd25_init(None, None, None, ctypes.byref(h)) == -1
+    for bad, code in ((pk.MeshDesc(0, 4, 0.0, 1.0, 0.0, 1.0, 2, 2, 5.0 / 3.0), -1),
+                      (pk.MeshDesc(4, 4, 1.0, 0.0, 0.0, 1.0, 2, 2, 5.0 / 3.0), -1),
+                      (pk.MeshDesc(4, 4, 0.0, 1.0, 0.0, 1.0, 2, 2, 1.0), -1),
+                      (pk.MeshDesc(4, 4, 0.0, 1.0, 0.0, 1.0, 7, 7, 5.0 / 3.0), -4),
+                      (pk.MeshDesc(4, 4, 0.0, 1.0, 0.0, 1.0, 3, 1, 5.0 / 3.0), -4)):
+        assert lib.mhd25_init(ctypes.byref(bad), None, None, ctypes.byref(h)) == code
+    opts = pk.Options.make(iface_flux=2)
+    assert lib.mhd25_init(ctypes.byref(ok), ctypes.byref(opts), None, ctypes.byref(h)) == -1
+    assert lib.mhd25_init(ctypes.byref(ok), None, None, ctypes.byref(h)) == 0
+    U = np.ones((5, 16, 3, 3))
+    assert lib.mhd25_rhs_hydro(h, None, ptr(U)) == -1
+    assert lib.mhd25_hydro_substep(h, ptr(U), 0.0, None) == -1
+    assert lib.mhd25_strang_step(h, ptr(U), None, None, None, 1e-3, None) == -1
+    lib.mhd25_destroy(h)

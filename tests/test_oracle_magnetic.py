@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 from paper_2609_10849_amd import workloads as W
-from tests._poly import Fields, B_product, div_max
+from tests._poly import B_product, Fields, div_max, ev2d, fit2d
 
 G = 5.0 / 3.0
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -161,9 +161,6 @@ def l2_errors(L, M, u, Bx, By, Bz, JE, fields):
             px = L.x0 + (ex + 0.5 * (X + 1)) * L.hx; py = L.y0 + (ey + 0.5 * (Y + 1)) * L.hy
             Bex, uex = fields(px, py)
             th = px + py - math.sqrt(2) * fields.t
-            for d in range(3):
-                eu += (Wt * (F.u(u[d], e) and 0 or 0)).sum() if False else 0
-            from tests._poly import ev2d, fit2d
             xi = W.gll_nodes(L.p)
             for d in range(3):
                 uh = ev2d(fit2d(xi, xi, u[d][e]), X, Y)
