@@ -73,7 +73,9 @@ typedef struct {
 void mhd25_default_options(mhd25_options* opt);
 
 /* Create a context for one mesh.  `hip_stream` is a hipStream_t (NULL = default stream).
- * Allocates all device workspace (about 12 state-sized arrays).  Returns 0 or <0. */
+ * Allocates all device workspace (about 12 state-sized arrays).  Returns 0, or -1 for a null
+ * pointer, nx or ny < 1, an empty domain, gamma <= 1, nx * ny * (m + 1) above 2^31 - 2^16 (far beyond
+ * device memory) or invalid options; -4 for p outside 1..6 or m not in {p - 1, p}; -3 when host or device memory runs out. */
 int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* hip_stream, mhd25_ctx** out);
 void mhd25_destroy(mhd25_ctx* ctx);
 /* Replace the options of an existing context (host-side only). */

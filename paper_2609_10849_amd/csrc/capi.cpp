@@ -112,6 +112,7 @@ int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stre
   if (d.nx < 1 || d.ny < 1 || !(d.x1 > d.x0) || !(d.y1 > d.y0) || !(d.gamma > 1.0)) return -1;
   if (d.p < 1 || d.p > MHD_MAXP) return -4;
   if (d.m != d.p && d.m != d.p - 1) return -4;
+  if ((long)d.nx * d.ny * (d.m + 1) > MHD_MAX_ELEMENTS) return -1;
   mhd25_ctx* c = new (std::nothrow) mhd25_ctx();
   if (!c) return -3;
   c->mesh = d;
@@ -120,6 +121,7 @@ int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stre
   c->stream = (hipStream_t)stream;
   c->p = d.p; c->m = d.m; c->np = d.p + 1; c->nn = c->np * c->np; c->M1 = d.m + 1;
   c->mp.nx = d.nx; c->mp.ny = d.ny; c->mp.K = (long)d.nx * d.ny;
+  meshp_set_division(c->mp);
   c->mp.hx = (d.x1 - d.x0) / d.nx; c->mp.hy = (d.y1 - d.y0) / d.ny;
   c->mp.J = c->mp.hx * c->mp.hy / 4.0; c->mp.gamma = d.gamma;
   c->G = (long)d.nx * d.ny * c->M1 * c->M1;

@@ -53,7 +53,36 @@ struct MeshP {
   int nx, ny;
   long K;
   double hx, hy, J, gamma;
+  unsigned nx_mul;  // element row of e: (e * nx_mul) >> nx_sh, see elem_xy
+  int nx_sh;
 };
+
+// Largest element count times (m + 1) a context accepts: element indices, grid indices divided
+// by m + 1 (and the few idle indices past the end that a block may form) stay below 2^31, which
+// row_of relies on.
+constexpr long MHD_MAX_ELEMENTS = (1L << 31) - (1L << 16);
+
+// Multiplier and shift for dividing element indices n < 2^31 by nx: with s = ceil(log2 nx) and
+// m = ceil(2^(31+s) / nx), m * nx lies in [2^(31+s), 2^(31+s) + 2^s], so floor(n / nx) =
+// floor(n * m / 2^(31+s)) for every n < 2^31 (Granlund and Montgomery, "Division by invariant
+// integers using multiplication", 1994, Theorem 4.2); m < 2^32 because nx > 2^(s-1).
+inline void meshp_set_division(MeshP& mp) {
+  int s = 0;
+  while ((1L << s) < (long)mp.nx) ++s;
+  mp.nx_sh = 31 + s;
+  mp.nx_mul = (unsigned)(((1ULL << mp.nx_sh) + (unsigned long long)mp.nx - 1) / (unsigned long long)mp.nx);
+}
+
+// floor(n / nx) for 0 <= n < 2^31
+__host__ __device__ __forceinline__ long row_of(const MeshP& mp, long n) {
+  return (long)(((unsigned long long)(unsigned)n * mp.nx_mul) >> mp.nx_sh);
+}
+
+// Element e = ey * nx + ex split into its column ex and row ey (row-major element order).
+__host__ __device__ __forceinline__ void elem_xy(const MeshP& mp, long e, long& ex, long& ey) {
+  ey = row_of(mp, e);
+  ex = e - ey * mp.nx;
+}
 
 // pointers of one magnetic residual / SSP-stage evaluation (magnetic.hip)
 struct MagIO {

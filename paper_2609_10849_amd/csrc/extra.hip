@@ -74,7 +74,9 @@ __global__ __launch_bounds__(256) void k_cfl(const double* __restrict__ U, const
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN, qi = q % NP, qj = q / NP;
   const long e = (long)blockIdx.x * EB + el;
   const bool act = el < EB && e < mp.K;
-  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0, KN = mp.K * NN;
+  long ex, ey;
+  elem_xy(mp, act ? e : 0, ex, ey);
+  const long KN = mp.K * NN;
   for (int t = tid; t < NP * A; t += 256) tWP[t / A][t % A] = T->I_W_P[t / A][t % A];
   for (int t = tid; t < NP * B; t += 256) {
     tGP[t / B][t % B] = T->I_G_P[t / B][t % B];
@@ -136,7 +138,9 @@ __global__ __launch_bounds__(128) void k_diag(const double* __restrict__ U, cons
   constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= mp.K) return;
-  const long ex = e % mp.nx, ey = e / mp.nx, KN = mp.K * NN;
+  long ex, ey;
+  elem_xy(mp, e, ex, ey);
+  const long KN = mp.K * NN;
   double mass = 0.0, Em = 0.0, rmin = DBL_MAX, pmin = DBL_MAX;
   for (int q = 0; q < NN; ++q) {
     const long n = e * NN + q;

@@ -144,7 +144,8 @@ __device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], do
       }
     }
     if (pos == 0 || pos == P) {
-      const long ex = e % mp.nx, ey = e / mp.nx;
+      long ex, ey;
+      elem_xy(mp, e, ex, ey);
       long en;
       if (D == 0) en = ey * mp.nx + wrap(ex + (pos == 0 ? -1 : 1), mp.nx);
       else en = wrap(ey + (pos == 0 ? -1 : 1), mp.ny) * mp.nx + ex;
@@ -300,6 +301,11 @@ __device__ __forceinline__ double Sp(const double* a, double eps_r) {
 }
 
 // P = P_PP o P_OE on a raw stage (eq. euler-oe-map, eq. euler-pp-density, eq. euler-pp-pressure).
+// The derivative jumps and the modal transforms run as line tasks: task (c, line) holds one grid
+// line of component c in registers (five tasks per line index), so a line is read from LDS once
+// per pass instead of once per output node; the 1D tables are read with uniform (scalar) loads.
+// The element statistics of the raw stage (always formed before this map) give the element
+// averages: the OE map keeps each element's mean, the (0, 0) Legendre mode.
 template <int P>
 __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ Ust, double* __restrict__ Uout,
                                                      const double* __restrict__ stats, const double* __restrict__ lines,
@@ -308,36 +314,34 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
                                                      const int* __restrict__ flag, const HydroTab* __restrict__ T,
                                                      MeshP mp, double tau, double sH, int do_oe, int do_pp) {
   using C = Cfg<P>;
-  constexpr int NP = C::NP, NN = C::NN, EB = C::EB;
+  constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NL = 5 * NP;
   __shared__ double su[5][EB * NN];
   __shared__ double st[10][EB * NN];
-  __shared__ double ssig[EB][2][NP];
-  __shared__ double sD[EB][NP], samp[EB][2][5], ssg[EB][5][NP];
+  __shared__ double ssig0[EB][NP], ssg[EB][2][5][NP];
+  __shared__ double sD[EB][NP], samp[EB][2][5], srow[EB][3][NP];
   __shared__ int scst[EB][5];
-  __shared__ double tD0[NP][NP], tDp[NP][NP], tTf[NP][NP], tV[NP][NP], tw[NP], tfr[NP];
   if (flag && *flag) return;
   const int tid = threadIdx.x;
-  for (int t = tid; t < NP * NP; t += 256) {
-    const int a = t / NP, b = t - a * NP;
-    tD0[a][b] = T->Dr0[a][b]; tDp[a][b] = T->Drp[a][b]; tTf[a][b] = T->Tf[a][b]; tV[a][b] = T->V[a][b];
-  }
-  if (tid < NP) { tw[tid] = T->w[tid]; tfr[tid] = T->fr[tid]; }
   const int el = tid / NN, q = tid - el * NN;
-  const int i = q % NP, j = q / NP;
   const long e = xcd_block() * EB + el;
   const bool act = tid < C::NT && e < mp.K;
   const long KN = mp.K * NN;
   const double g = mp.gamma;
-  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
-  double U[5];
+  long ex, ey;
+  elem_xy(mp, act ? e : 0, ex, ey);
+  // grid line ln of direction D (D = 0: row, index along x; D = 1: column), position k on it
+  auto nodeof = [](int D, int ln, int k) { return D == 0 ? ln * NP + k : k * NP + ln; };
+  double U[5], a[5];
   if (act) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) { U[c] = Ust[c * KN + e * NN + q]; su[c][tid] = U[c]; }
+#pragma unroll
+    for (int c = 0; c < 5; ++c) a[c] = 0.25 * stats[(e * 5 + c) * 3];
   }
+  double rmin = act ? stats[(e * 5) * 3 + 1] : DBL_MAX;  // raw-stage density minimum (no OE)
   __syncthreads();
   if (do_oe) {
-    // global and cross-line amplitudes (eq. euler-oe-amplitude), shared over components: each
-    // component's amplitudes are formed once per element (task c) and combined from LDS below
+    // global and cross-line amplitudes (eq. euler-oe-amplitude), one task per component
     for (int c = q; act && c < 5; c += NN) {
       const double gs = glob[c * 3 + 0], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
       const double gm = gs / (4.0 * (double)mp.K);
@@ -363,37 +367,44 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
           st[5 + c][tid] = Ust[c * KN + ep * NN + q];
         }
       }
-      __syncthreads();
-      // normal-jump contributions (eq. euler-oe-jump): thread (r, line)
-      const int r = D == 0 ? i : j, line = D == 0 ? j : i;
-      double jmp[10];
-      if (act) {
-        const double wl = 0.5 * tw[line];
+      if (D == 1 && act && q < NP) {  // direction-0 sigma: maximum over the components
+        double sg = 0.0;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-          double a = 0.0, d = 0.0, b = 0.0, cc = 0.0;
+        for (int c = 0; c < 5; ++c) sg = fmax(sg, ssg[el][0][c][q]);
+        ssig0[el][q] = sg;
+      }
+      __syncthreads();
+      // normal-jump contributions (eq. euler-oe-jump) of line ln of component c: the r-th
+      // derivatives at both faces of the element and of its neighbours.  The squared, weighted
+      // jumps of derivative order r overwrite the task's own staged slots (position r on the line)
+      for (int t = q; act && t < NL; t += NN) {
+        const int c = t / NP, ln = t - c * NP;
+        double own[NP], mn[NP], pl[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+          const int n = el * NN + nodeof(D, ln, k);
+          own[k] = su[c][n]; mn[k] = st[c][n]; pl[k] = st[5 + c][n];
+        }
+        const double wl = 0.5 * T->w[ln];
+#pragma unroll
+        for (int r = 0; r < NP; ++r) {
+          double ja = 0.0, jd = 0.0, jb = 0.0, jc = 0.0;
 #pragma unroll
           for (int k = 0; k < NP; ++k) {
-            const int nk = el * NN + (D == 0 ? line * NP + k : k * NP + line);
-            const double own = su[c][nk];
-            a += tD0[r][k] * own;
-            d += tDp[r][k] * own;
-            b += tDp[r][k] * st[c][nk];
-            cc += tD0[r][k] * st[5 + c][nk];
+            const double d0 = T->Dr0[r][k], dp = T->Drp[r][k];
+            ja += d0 * own[k];
+            jd += dp * own[k];
+            jb += dp * mn[k];
+            jc += d0 * pl[k];
           }
-          const double jm = a - b, jp = cc - d;
-          jmp[2 * c] = wl * jm * jm;
-          jmp[2 * c + 1] = wl * jp * jp;
+          const double jm = ja - jb, jp = jc - jd;
+          const int n = el * NN + nodeof(D, ln, r);
+          st[c][n] = wl * jm * jm;
+          st[5 + c][n] = wl * jp * jp;
         }
       }
       __syncthreads();
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < 10; ++c) st[c][tid] = jmp[c];
-      }
-      __syncthreads();
-      // sigma (eq. euler-oe-sigma): the (r, component) terms are spread over the element's
-      // threads, then the maximum over components is taken per r
+      // sigma (eq. euler-oe-sigma): task (r, c) sums its squared jumps over the lines
       {
         double Dsh = 0.0;
 #pragma unroll
@@ -404,114 +415,104 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
           if (Dsh > 0.0 && !scst[el][c]) {
             double sm = 0.0, spp = 0.0;
             for (int l = 0; l < NP; ++l) {
-              const int nk = D == 0 ? l * NP + rr : rr * NP + l;
-              sm += st[2 * c][el * NN + nk];
-              spp += st[2 * c + 1][el * NN + nk];
+              const int n = el * NN + nodeof(D, l, rr);
+              sm += st[c][n];
+              spp += st[5 + c][n];
             }
-            v = tfr[rr] * (sqrt(sm) + sqrt(spp)) / Dsh;
+            v = T->fr[rr] * (sqrt(sm) + sqrt(spp)) / Dsh;
           }
-          ssg[el][c][rr] = v;
+          ssg[el][D][c][rr] = v;
         }
       }
       __syncthreads();
-      if (act && q < NP) {
-        double sig = 0.0;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) sig = fmax(sig, ssg[el][c][q]);
-        ssig[el][D][q] = sig;
-      }
-      __syncthreads();
     }
+    // shell damping factors (eq. euler-oe-map): D_l = exp(-s tau (lx sum_{r<=l} sigma_x,r + ...))
     if (act && q <= P) {
       if (q == 0) {
         sD[el][0] = 1.0;
       } else {
-        double a[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) a[c] = 0.25 * stats[(e * 5 + c) * 3];
         const double ck = sqrt(g * pres(a, g) / a[0]);
         const double lx = (2.0 * P + 1.0) * (fabs(a[1] / a[0]) + ck) / mp.hx;
         const double ly = (2.0 * P + 1.0) * (fabs(a[2] / a[0]) + ck) / mp.hy;
         double sx = 0.0, sy = 0.0;
-        for (int r = 0; r <= q; ++r) { sx += ssig[el][0][r]; sy += ssig[el][1][r]; }
+        for (int r = 0; r <= q; ++r) {
+          double s1 = 0.0;
+#pragma unroll
+          for (int c = 0; c < 5; ++c) s1 = fmax(s1, ssg[el][1][c][r]);
+          sx += ssig0[el][r];
+          sy += s1;
+        }
         sD[el][q] = exp(-sH * tau * (lx * sx + ly * sy));
       }
     }
     __syncthreads();
-    // modal damping: forward transform in x, then y; damp shell max(a,b); back-transform
-    if (act) {
+    // modal damping with line tasks: x transform of each row, then per column the y transform,
+    // the shell factors and the inverse y transform, then the inverse x transform of each row
+    for (int t = q; act && t < NL; t += NN) {
+      const int c = t / NP, ln = t - c * NP;
+      double v[NP];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
+      for (int k = 0; k < NP; ++k) v[k] = su[c][el * NN + ln * NP + k];
+#pragma unroll
+      for (int aa = 0; aa < NP; ++aa) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) s += tTf[i][k] * su[c][el * NN + j * NP + k];
-        st[c][tid] = s;  // [j][a=i]
+        for (int k = 0; k < NP; ++k) s += T->Tf[aa][k] * v[k];
+        st[c][el * NN + ln * NP + aa] = s;  // [row][x mode]
       }
     }
     __syncthreads();
-    if (act) {
-      const double dmp = sD[el][i > j ? i : j];
+    for (int t = q; act && t < NL; t += NN) {
+      const int c = t / NP, aa = t - c * NP;
+      double v[NP], cb[NP];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
+      for (int k = 0; k < NP; ++k) v[k] = st[c][el * NN + k * NP + aa];
+#pragma unroll
+      for (int b = 0; b < NP; ++b) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) s += tTf[j][k] * st[c][el * NN + k * NP + i];
-        st[5 + c][tid] = dmp * s;  // coefficient [b=j][a=i]
+        for (int k = 0; k < NP; ++k) s += T->Tf[b][k] * v[k];
+        cb[b] = sD[el][aa > b ? aa : b] * s;  // coefficient (x mode aa, y mode b), damped
+      }
+#pragma unroll
+      for (int jj = 0; jj < NP; ++jj) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) s += T->V[jj][b] * cb[b];
+        st[c][el * NN + jj * NP + aa] = s;  // [row][x mode]
       }
     }
     __syncthreads();
-    if (act) {
+    for (int t = q; act && t < NL; t += NN) {
+      const int c = t / NP, ln = t - c * NP;
+      double v[NP];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
+      for (int k = 0; k < NP; ++k) v[k] = st[c][el * NN + ln * NP + k];
+      double mn = DBL_MAX;
+#pragma unroll
+      for (int ii = 0; ii < NP; ++ii) {
         double s = 0.0;
 #pragma unroll
-        for (int a = 0; a < NP; ++a) s += tV[i][a] * st[5 + c][el * NN + j * NP + a];
-        su[c][tid] = s;  // [b=j][i]
+        for (int k = 0; k < NP; ++k) s += T->V[ii][k] * v[k];
+        su[c][el * NN + ln * NP + ii] = s;
+        mn = fmin(mn, s);
       }
+      if (c == 0) srow[el][0][ln] = mn;  // row minimum of the damped density
     }
     __syncthreads();
     if (act) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        double s = 0.0;
+      for (int c = 0; c < 5; ++c) U[c] = su[c][tid];
+      rmin = DBL_MAX;
 #pragma unroll
-        for (int b = 0; b < NP; ++b) s += tV[j][b] * su[c][el * NN + b * NP + i];
-        U[c] = s;
-      }
+      for (int l = 0; l < NP; ++l) rmin = fmin(rmin, srow[el][0][l]);
     }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-      for (int c = 0; c < 5; ++c) su[c][tid] = U[c];
-    }
-    __syncthreads();
   }
   uint8_t f = 0;
   if (do_pp) {
-    // positivity scaling: element reductions are taken once per element (six tasks for the
-    // averages and the density minimum, thread 0 for S_p and the pressure minimum) and broadcast
-    // through LDS; st rows 0..2 are free after the modal damping, rows 3..4 hold the results
+    // positivity scaling: the S_p and pressure extrema are reduced per row (NP tasks per
+    // element), then over the rows by every thread
     const double eps_r = 64.0 * EPSM;
-    double* red = &st[3][0] + el * 8;  // [0..4] averages, [5] min rho, [6] S, [7] min p
-    for (int t = q; act && t < 6; t += NN) {  // NN < 6 only for p = 1
-      if (t < 5) {
-        double s = 0.0;
-        for (int k = 0; k < NN; ++k) s += (tw[k % NP] * tw[k / NP]) * su[t][el * NN + k];
-        red[t] = 0.25 * s;
-      } else {
-        double rmin = DBL_MAX;
-        for (int k = 0; k < NN; ++k) rmin = fmin(rmin, su[0][el * NN + k]);
-        red[5] = rmin;
-      }
-    }
-    __syncthreads();
-    double a[5] = {0, 0, 0, 0, 0};
-    double rmin = DBL_MAX;
-    if (act) {
-#pragma unroll
-      for (int c = 0; c < 5; ++c) a[c] = red[c];
-      rmin = red[5];
-    }
     const bool collapse_r = !(a[0] > eps_r);
     double thr = 1.0;
     if (act && !collapse_r && rmin < eps_r) {
@@ -524,14 +525,21 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
       st[1][tid] = pres(U, g);
     }
     __syncthreads();
-    if (act && q == 0) {
-      double S = Sp(a, eps_r), pmin = DBL_MAX;
-      for (int k = 0; k < NN; ++k) { S = fmax(S, st[0][el * NN + k]); pmin = fmin(pmin, st[1][el * NN + k]); }
-      red[6] = S; red[7] = pmin;
+    for (int t = q; act && t < NP; t += NN) {
+      double S = 0.0, pm = DBL_MAX;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        S = fmax(S, st[0][el * NN + t * NP + k]);
+        pm = fmin(pm, st[1][el * NN + t * NP + k]);
+      }
+      srow[el][1][t] = S;
+      srow[el][2][t] = pm;
     }
     __syncthreads();
     if (act && !collapse_r) {
-      const double S = red[6], pmin = red[7];
+      double S = Sp(a, eps_r), pmin = DBL_MAX;
+#pragma unroll
+      for (int l = 0; l < NP; ++l) { S = fmax(S, srow[el][1][l]); pmin = fmin(pmin, srow[el][2][l]); }
       const double eps_p = fmax(64.0 * EPSM, 8192.0 * EPSM * S);
       const double pb = pres(a, g);
       if (pb <= eps_p) {

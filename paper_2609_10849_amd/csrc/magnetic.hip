@@ -61,7 +61,8 @@ __global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, 
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
   const long e = xcd_block() * EB + el;
   const bool act = el < EB && e < mp.K;
-  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  long ex, ey;
+  elem_xy(mp, act ? e : 0, ex, ey);
   for (int k = tid; k < A * A; k += 256) {
     tWQ[k / A][k % A] = T->I_W_Q[k / A][k % A];
     tDWQ[k / A][k % A] = T->D_W_Q[k / A][k % A];
@@ -171,7 +172,8 @@ __global__ __launch_bounds__(256) void k_E_loads(const double* __restrict__ u, c
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
   const long e = xcd_block() * EB + el;
   const bool act = el < EB && e < mp.K;
-  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  long ex, ey;
+  elem_xy(mp, act ? e : 0, ex, ey);
   const long KN = mp.K * NN;
   const double et = (act && eta) ? eta[e] : 0.0;
   for (int k = tid; k < NP * B; k += 256) tGP[k / B][k % B] = T->I_G_P[k / B][k % B];
@@ -324,7 +326,8 @@ __global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __re
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
   const long e = xcd_block() * EB + el;
   const bool act = el < EB && e < mp.K;
-  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  long ex, ey;
+  elem_xy(mp, act ? e : 0, ex, ey);
   const long KN = mp.K * NN;
   for (int k = tid; k < B * A; k += 256) tDWG[k / A][k % A] = T->D_W_G[k / A][k % A];
   for (int k = tid; k < B * A; k += 256) tDWV[k / A][k % A] = T->D_W_V[k / A][k % A];
@@ -711,7 +714,8 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
   const int qi = q % NP, qj = q / NP;
   const long e = xcd_block() * EB + el;
   const bool act = el < EB && e < mp.K;
-  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  long ex, ey;
+  elem_xy(mp, act ? e : 0, ex, ey);
   const long KN = mp.K * NN;
   for (int t = tid; t < NP * NP; t += 256) {
     tD0[t / NP][t % NP] = H->Dr0[t / NP][t % NP];
@@ -975,7 +979,9 @@ __global__ __launch_bounds__(256) void k_ar_traces(const double* __restrict__ rh
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN, qi = q % NP, qj = q / NP;
   const long e = (long)blockIdx.x * EB + el;
   const bool act = el < EB && e < mp.K;
-  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0, KN = mp.K * NN;
+  long ex, ey;
+  elem_xy(mp, act ? e : 0, ex, ey);
+  const long KN = mp.K * NN;
   for (int t = tid; t < NP * A; t += 256) tWP[t / A][t % A] = T->I_W_P[t / A][t % A];
   for (int t = tid; t < NP * B; t += 256) {
     tGP[t / B][t % B] = T->I_G_P[t / B][t % B];
@@ -1055,7 +1061,8 @@ __global__ __launch_bounds__(256) void k_ar_eta(const double* __restrict__ tr, c
   constexpr int A = M + 2, NT = 8 * A + 2;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= mp.K) return;
-  const long ex = e % mp.nx, ey = e / mp.nx;
+  long ex, ey;
+  elem_xy(mp, e, ex, ey);
   double dOm[3];
   bool cf[3];
   const double area = (double)mp.K * mp.hx * mp.hy;
@@ -1106,7 +1113,8 @@ __global__ __launch_bounds__(256) void k_B_stats(const double* __restrict__ Bx, 
   constexpr int A = M + 2, B = M + 1;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= mp.K) return;
-  const long ex = e % mp.nx, ey = e / mp.nx;
+  long ex, ey;
+  elem_xy(mp, e, ex, ey);
   double s[3] = {0, 0, 0}, mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
   for (int j = 0; j < B; ++j)
     for (int i = 0; i < A; ++i) {
@@ -1145,7 +1153,7 @@ __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ Lx, c
   const long NX = (long)mp.nx * B, G = NX * mp.ny * B;
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
-  const long gy = g / NX, gx = g - gy * NX;
+  const long gy = row_of(mp, g / B), gx = g - gy * NX;  // g / (nx B) = (g / B) / nx
   const long ex = gx / B, ey = gy / B;
   const int i = gx - ex * B, j = gy - ey * B;
   const long e = ey * mp.nx + ex;
@@ -1196,7 +1204,7 @@ __global__ void k_B_from_potential(const double* __restrict__ Az, double* __rest
   const long NX = (long)mp.nx * B, G = NX * mp.ny * B;
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
-  const long gy = g / NX, gx = g - gy * NX;
+  const long gy = row_of(mp, g / B), gx = g - gy * NX;  // g / (nx B) = (g / B) / nx
   const long ex = gx / B, ey = gy / B;
   const int i = gx - ex * B, j = gy - ey * B;
   double bx = 0.0, by = 0.0;

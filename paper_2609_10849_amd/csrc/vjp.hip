@@ -212,7 +212,8 @@ __device__ __forceinline__ void vjp_dir(const Pr& me, const double U[5], const d
       for (int c = 0; c < 5; ++c) sbl[(pos * ND + (d - 1)) * 5 + c] = bo[c];
     }
     if (pos == 0 || pos == P) {
-      const long ex = e % mp.nx, ey = e / mp.nx;
+      long ex, ey;
+      elem_xy(mp, e, ex, ey);
       long en;
       if (D == 0) en = ey * mp.nx + wrap(ex + (pos == 0 ? -1 : 1), mp.nx);
       else en = wrap(ey + (pos == 0 ? -1 : 1), mp.ny) * mp.nx + ex;
@@ -321,7 +322,8 @@ __global__ __launch_bounds__(256) void k_vjp_update(const double* __restrict__ r
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
   const long e = (long)blockIdx.x * EB + el;
   const bool act = el < EB && e < mp.K;
-  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  long ex, ey;
+  elem_xy(mp, act ? e : 0, ex, ey);
   const long KN = mp.K * NN;
   const double et = (act && eta) ? eta[e] : 0.0;
   const double* Jx = JE; const double* Jy = JE + G; const double* Jz = JE + 2 * G;
@@ -509,7 +511,8 @@ __global__ __launch_bounds__(256) void k_vjp_E(const double* __restrict__ u, con
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
   const long e = (long)blockIdx.x * EB + el;
   const bool act = el < EB && e < mp.K;
-  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  long ex, ey;
+  elem_xy(mp, act ? e : 0, ex, ey);
   const long KN = mp.K * NN;
   const double et = (act && eta) ? eta[e] : 0.0;
   const double* Exb = Ebar; const double* Eyb = Ebar + G; const double* Ezb = Ebar + 2 * G;
@@ -686,7 +689,8 @@ __global__ __launch_bounds__(256) void k_vjp_J(const double* __restrict__ Jbar, 
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
   const long e = (long)blockIdx.x * EB + el;
   const bool act = el < EB && e < mp.K;
-  const long ex = act ? e % mp.nx : 0, ey = act ? e / mp.nx : 0;
+  long ex, ey;
+  elem_xy(mp, act ? e : 0, ex, ey);
   const double* Jxb = Jbar; const double* Jyb = Jbar + G; const double* Jzb = Jbar + 2 * G;
   if (act) {
     for (int k = t; k < AA; k += NT) {
@@ -768,7 +772,7 @@ __global__ __launch_bounds__(256) void k_gather_sum(const double* __restrict__ L
   const long NX = (long)mp.nx * B, G = NX * mp.ny * B;
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
-  const long gy = g / NX, gx = g - gy * NX;
+  const long gy = row_of(mp, g / B), gx = g - gy * NX;  // g / (nx B) = (g / B) / nx
   const long ex = gx / B, ey = gy / B;
   const int i = gx - ex * B, j = gy - ey * B;
   auto wr = [](long a, long n) { return a < 0 ? a + n : a; };
@@ -801,7 +805,7 @@ __global__ void k_scatter_bz(const double* __restrict__ BL, long stride, long of
   const long NX = (long)mp.nx * B, G = NX * mp.ny * B;
   const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
-  const long gy = g / NX, gx = g - gy * NX;
+  const long gy = row_of(mp, g / B), gx = g - gy * NX;  // g / (nx B) = (g / B) / nx
   const long ex = gx / B, ey = gy / B;
   const int i = gx - ex * B, j = gy - ey * B;
   Oz[g] = BL[(ey * mp.nx + ex) * stride + off + j * B + i];
