@@ -53,6 +53,8 @@ struct MeshP {
   int nx, ny;
   long K;
   double hx, hy, J, gamma;
+  double rhx, rhy;         // 1 / hx, 1 / hy
+  double r4K, r4nx, r4ny;  // 1 / (4 K), 1 / (4 nx), 1 / (4 ny): element-average sums to means
   unsigned nx_mul;  // element row of e: (e * nx_mul) >> nx_sh, see elem_xy
   int nx_sh;
 };

@@ -78,13 +78,14 @@ __device__ __forceinline__ void ecflux(const Prim& L, const Prim& R, double gk, 
   F[4] = f0 * (ibl * gk - 0.5 * u2a + (uxa * uxa + uya * uya + uza * uza)) + ph * ud;
 }
 
-template <int D>
-__device__ __forceinline__ void physflux(const double U[5], double g, double F[5], double& ud, double& c) {
+// physical flux in direction D (0: x, 1: y, a run-time value so that x and y faces can share one
+// code path), with the normal velocity and the sound speed
+__device__ __forceinline__ void physflux(const double U[5], double g, int D, double F[5], double& ud, double& c) {
   const double ir = 1.0 / U[0];
   const double ux = U[1] * ir, uy = U[2] * ir, uz = U[3] * ir;
   const double p = (g - 1.0) * (U[4] - 0.5 * (U[1] * ux + U[2] * uy + U[3] * uz));
   ud = D == 0 ? ux : uy;
-  F[0] = U[1 + D];
+  F[0] = D == 0 ? U[1] : U[2];
   F[1] = U[1] * ud + (D == 0 ? p : 0.0);
   F[2] = U[2] * ud + (D == 1 ? p : 0.0);
   F[3] = U[3] * ud;
@@ -92,36 +93,38 @@ __device__ __forceinline__ void physflux(const double U[5], double g, double F[5
   c = sqrt(g * p * ir);
 }
 
-// numerical interface flux: LLF (eq. euler-lf-flux) or, for tests, the EC flux
-template <int D>
-__device__ __forceinline__ void iflux(const double UL[5], const double UR[5], double g, int iface, double F[5]) {
+// numerical interface flux in direction D between the element's own face value uo and the
+// neighbour's un: LLF (eq. euler-lf-flux) or, for tests, the EC flux.  Both are symmetric in their
+// two states except for the LLF jump U_R - U_L = sgn (un - uo) (sgn = +1 when the neighbour is the
+// plus side), so no left/right copies are formed.
+__device__ __forceinline__ void face_flux(const double uo[5], const double un[5], double sgn, double g, int D,
+                                          int iface, double F[5]) {
   if (iface == 1) {
-    Prim a = make_prim(UL, g), b = make_prim(UR, g);
-    ecflux<D>(a, b, 0.5 / (g - 1.0), F);
+    Prim a = make_prim(uo, g), b = make_prim(un, g);
+    if (D == 0) ecflux<0>(a, b, 0.5 / (g - 1.0), F);
+    else ecflux<1>(a, b, 0.5 / (g - 1.0), F);
     return;
   }
-  double FL[5], FR[5], udL, cL, udR, cR;
-  physflux<D>(UL, g, FL, udL, cL);
-  physflux<D>(UR, g, FR, udR, cR);
-  const double lam = fmax(fabs(udL) + cL, fabs(udR) + cR);
+  double Fo[5], Fn[5], udo, co, udn, cn;
+  physflux(uo, g, D, Fo, udo, co);
+  physflux(un, g, D, Fn, udn, cn);
+  const double lam = fmax(fabs(udo) + co, fabs(udn) + cn);
 #pragma unroll
-  for (int c = 0; c < 5; ++c) F[c] = 0.5 * (FL[c] + FR[c]) - 0.5 * lam * (UR[c] - UL[c]);
+  for (int c = 0; c < 5; ++c) F[c] = 0.5 * (Fo[c] + Fn[c]) - 0.5 * lam * (sgn * (un[c] - uo[c]));
 }
 
 __device__ __forceinline__ long wrap(long a, long n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-// One direction of L_E for the thread's node: owned pairs, interface flux, incoming halves.
+// One direction of the volume part of L_E for the thread's node: owned pairs, incoming halves.
 template <int P, int D, int BS>
-__device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], double acc[5], bool act, int el, int i,
-                                           int j, long e, const double* __restrict__ Us, long KN,
+__device__ __forceinline__ void volume_dir(const Prim& me, double acc[5], bool act, int el, int i, int j,
                                            double (*sp)[Cfg<P, BS>::EB * Cfg<P, BS>::NN], double* sb,
-                                           const double* tS, const HydroTab* __restrict__ T, const MeshP& mp,
-                                           int iface) {
+                                           const double* tS, const MeshP& mp) {
   using C = Cfg<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, ND = C::ND;
   const int pos = D == 0 ? i : j, line = D == 0 ? j : i;
   const double sc = D == 0 ? 2.0 / mp.hx : 2.0 / mp.hy;
-  const double g = mp.gamma, gk = 0.5 / (g - 1.0);
+  const double gk = 0.5 / (mp.gamma - 1.0);
   // sb layout: [el][line][owner pos][dslot][5]
   double* sbl = sb + ((long)(el * NP + line) * NP) * ND * 5;
   if (act) {
@@ -143,27 +146,6 @@ __device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], do
         sbl[(pos * ND + (d - 1)) * 5 + c] = cr * F[c];
       }
     }
-    if (pos == 0 || pos == P) {
-      long ex, ey;
-      elem_xy(mp, e, ex, ey);
-      long en;
-      if (D == 0) en = ey * mp.nx + wrap(ex + (pos == 0 ? -1 : 1), mp.nx);
-      else en = wrap(ey + (pos == 0 ? -1 : 1), mp.ny) * mp.nx + ex;
-      const int qn = D == 0 ? line * NP + (pos == 0 ? P : 0) : (pos == 0 ? P : 0) * NP + line;
-      // one interface flux per thread: the face's minus side is the neighbour at pos == 0
-      const bool lo = pos == 0;
-      double UL[5], UR[5], F[5];
-#pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        const double un = Us[c * KN + en * NN + qn];
-        UL[c] = lo ? un : U[c];
-        UR[c] = lo ? U[c] : un;
-      }
-      iflux<D>(UL, UR, g, iface, F);
-      const double s = lo ? sc / T->w[0] : -(sc / T->w[P]);
-#pragma unroll
-      for (int c = 0; c < 5; ++c) acc[c] += s * F[c];
-    }
   }
   __syncthreads();
   if (act) {
@@ -179,25 +161,101 @@ __device__ __forceinline__ void volume_dir(const Prim& me, const double U[5], do
   __syncthreads();
 }
 
+// Surface part of L_E: the element's 4 (p+1) interface fluxes as tasks f = (direction, side, line)
+// with the direction a run-time value (x and y faces share one code path, so a wave runs the flux
+// once), stored in sf = scr + el * 20 (p+1); then added at the face nodes.  The minus side of a face
+// is the neighbour for side 0.  Every thread of the block must call this.
+template <int P, int BS>
+__device__ __forceinline__ void surface_terms(double acc[5], bool act, int el, int q, int i, int j, long e,
+                                              const double* __restrict__ Us, long KN, double* scr,
+                                              double (*sp)[Cfg<P, BS>::EB * Cfg<P, BS>::NN],
+                                              const HydroTab* __restrict__ T, const MeshP& mp, int iface) {
+  using C = Cfg<P, BS>;
+  constexpr int NP = C::NP, NN = C::NN;
+  double* sf = scr + el * 20 * NP;  // [f][5]
+  const int tid = el * NN + q;
+  if (act) {
+    // the volume accumulators wait in the (now free) primitive rows, to keep registers for the fluxes
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sp[c][tid] = acc[c];
+    long ex, ey;
+    elem_xy(mp, e, ex, ey);
+    for (int f = q; f < 4 * NP; f += NN) {
+      const int D = f / (2 * NP), side = (f / NP) & 1, line = f % NP;
+      const int pos = side ? P : 0;
+      const int qo = D == 0 ? line * NP + pos : pos * NP + line;
+      const int qn = D == 0 ? line * NP + (P - pos) : (P - pos) * NP + line;
+      const long en = D == 0 ? ey * mp.nx + wrap(ex + (side ? 1 : -1), mp.nx)
+                             : wrap(ey + (side ? 1 : -1), mp.ny) * mp.nx + ex;
+      double uo[5], un[5], F[5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) { uo[c] = Us[c * KN + e * NN + qo]; un[c] = Us[c * KN + en * NN + qn]; }
+      face_flux(uo, un, side ? 1.0 : -1.0, mp.gamma, D, iface, F);
+      const double sc = D == 0 ? 2.0 / mp.hx : 2.0 / mp.hy;
+      const double s = side ? -(sc / T->w[P]) : sc / T->w[0];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) sf[f * 5 + c] = s * F[c];
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) acc[c] = sp[c][tid];
+    // face f = (D * 2 + side) * NP + line; x faces carry line j, y faces line i
+    if (i == 0) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) acc[c] += sf[(0 * NP + j) * 5 + c];
+    }
+    if (i == P) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) acc[c] += sf[(1 * NP + j) * 5 + c];
+    }
+    if (j == 0) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) acc[c] += sf[(2 * NP + i) * 5 + c];
+    }
+    if (j == P) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) acc[c] += sf[(3 * NP + i) * 5 + c];
+    }
+  }
+}
+
 // Per-element sums (GLL weights, without |J_K|), minima and maxima of 5 fields held in LDS rows
-// 0..4 of svf, plus the raw-average admissibility test (NaN-safe) from the five sums.  Rows 5..6
-// (at least 5 values per element) take the sums; every thread of the block must call this.
+// 0..4 of svf, plus the raw-average admissibility test (NaN-safe) from the five sums.  Two fixed-
+// order levels: task (component, grid row) reduces its row into rs = sst + el * 15 NP (at least
+// 15 (p+1) values per element, free LDS), then task (component, kind) combines the rows.  Rows
+// 5..6 of svf (at least 5 values per element) take the sums; every thread of the block must call
+// this.
 template <class C>
-__device__ __forceinline__ void element_stats(double* svf, bool act, int el, int q, long e,
+__device__ __forceinline__ void element_stats(double* svf, double* sst, bool act, int el, int q, long e,
                                               double* __restrict__ stats, int* __restrict__ flag,
                                               const HydroTab* __restrict__ T, double g) {
   constexpr int NP = C::NP, NN = C::NN, S = C::EB * C::NN;
-  auto sv = [&](int c, int k) { return svf[c * S + k]; };
+  double* rs = sst + el * 15 * NP;  // [component][kind][row]
+  for (int t = q; act && t < 5 * NP; t += NN) {
+    const int c = t / NP, r = t - c * NP;
+    const double wr = T->w[r];
+    double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const double v = svf[c * S + el * NN + r * NP + i];
+      s += (T->w[i] * wr) * v;
+      mn = fmin(mn, v); mx = fmax(mx, v);
+    }
+    rs[(c * 3 + 0) * NP + r] = s;
+    rs[(c * 3 + 1) * NP + r] = mn;
+    rs[(c * 3 + 2) * NP + r] = mx;
+  }
+  __syncthreads();
   double* ssum = svf + 5 * S + el * 5;
   for (int t = q; act && t < 15; t += NN) {
     const int c = t / 3, kind = t - 3 * c;
-    double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
-    for (int k = 0; k < NN; ++k) {
-      const double v = sv(c, el * NN + k);
-      s += (T->w[k % NP] * T->w[k / NP]) * v;
-      mn = fmin(mn, v); mx = fmax(mx, v);
-    }
-    stats[(e * 5 + c) * 3 + kind] = kind == 0 ? s : (kind == 1 ? mn : mx);
+    const double* v = rs + t * NP;
+    double s = kind == 0 ? 0.0 : v[0];
+#pragma unroll
+    for (int r = kind == 0 ? 0 : 1; r < NP; ++r) s = kind == 0 ? s + v[r] : (kind == 1 ? fmin(s, v[r]) : fmax(s, v[r]));
+    stats[(e * 5 + c) * 3 + kind] = s;
     if (kind == 0) ssum[c] = s;
   }
   if (!flag) return;
@@ -222,6 +280,10 @@ __global__ __launch_bounds__(BS) void k_hydro_stage(const double* __restrict__ U
   __shared__ double sp[7][EB * NN];
   __shared__ double sb[EB * NP * NP * (ND > 0 ? ND : 1) * 5];
   __shared__ double tS[NP * NP];
+  // scratch for the interface fluxes and the statistics' row partials (20 (p+1) values per
+  // element): the flux hand-off buffer sb when it is large enough, else an array of its own
+  constexpr bool SB_BIG = NP * (ND > 0 ? ND : 1) >= 4;
+  __shared__ double sxt[SB_BIG ? 1 : EB * 20 * NP];
   __shared__ int sflag;
   const int tid = threadIdx.x;
   if (tid < NP * NP) tS[tid] = T->Shat[tid / NP][tid % NP];
@@ -251,10 +313,18 @@ __global__ __launch_bounds__(BS) void k_hydro_stage(const double* __restrict__ U
     me = make_prim(U, mp.gamma);
     sp[0][tid] = me.r; sp[1][tid] = me.ux; sp[2][tid] = me.uy; sp[3][tid] = me.uz;
     sp[4][tid] = me.b; sp[5][tid] = me.lr; sp[6][tid] = me.lb;
+    // the SSP combine ca U^n + cb (U_s + tau L) is carried as (ca U^n + cb U_s) + cb tau L, so
+    // that one state instead of two stays live through the flux phases
+    if (MODE == 1) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) U[c] = ca * UNo[c] + cb * U[c];
+    }
   }
   __syncthreads();
-  volume_dir<P, 0, BS>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, tS, T, mp, iface);
-  volume_dir<P, 1, BS>(me, U, acc, act, el, i, j, e, Us, KN, sp, sb, tS, T, mp, iface);
+  volume_dir<P, 0, BS>(me, acc, act, el, i, j, sp, sb, tS, mp);
+  volume_dir<P, 1, BS>(me, acc, act, el, i, j, sp, sb, tS, mp);
+  double* scr = SB_BIG ? sb : sxt;
+  surface_terms<P, BS>(acc, act, el, q, i, j, e, Us, KN, scr, sp, T, mp, iface);
   if (MODE == 0) {
     if (act) {
 #pragma unroll
@@ -266,13 +336,13 @@ __global__ __launch_bounds__(BS) void k_hydro_stage(const double* __restrict__ U
   if (act) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
-      Y[c] = ca * UNo[c] + cb * (U[c] + tau * acc[c]);
+      Y[c] = U[c] + (cb * tau) * acc[c];
       out[c * KN + e * NN + q] = Y[c];
       sp[c][tid] = Y[c];
     }
   }
   __syncthreads();
-  element_stats<C>(&sp[0][0], act, el, q, e, stats, flag, T, mp.gamma);
+  element_stats<C>(&sp[0][0], scr, act, el, q, e, stats, flag, T, mp.gamma);
 }
 
 template <int P>
@@ -281,6 +351,7 @@ __global__ __launch_bounds__(256) void k_elem_stats(const double* __restrict__ U
   using C = Cfg<P>;
   constexpr int NN = C::NN, EB = C::EB;
   __shared__ double sv[7][EB * NN];
+  __shared__ double sst[EB * 15 * C::NP];
   const int tid = threadIdx.x;
   const int el = tid / NN, q = tid - el * NN;
   const long e = (long)blockIdx.x * EB + el;
@@ -289,7 +360,7 @@ __global__ __launch_bounds__(256) void k_elem_stats(const double* __restrict__ U
   if (act)
     for (int c = 0; c < 5; ++c) sv[c][tid] = Uin[c * KN + e * NN + q];
   __syncthreads();
-  element_stats<Cfg<P>>(&sv[0][0], act, el, q, e, stats, flag, T, mp.gamma);
+  element_stats<Cfg<P>>(&sv[0][0], sst, act, el, q, e, stats, flag, T, mp.gamma);
 }
 
 // Element-average pressure helper
@@ -306,18 +377,18 @@ __device__ __forceinline__ double Sp(const double* a, double eps_r) {
 // per pass instead of once per output node; the 1D tables are read with uniform (scalar) loads.
 // The element statistics of the raw stage (always formed before this map) give the element
 // averages: the OE map keeps each element's mean, the (0, 0) Legendre mode.
-template <int P>
-__global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ Ust, double* __restrict__ Uout,
+template <int P, int BS>
+__global__ __launch_bounds__(BS) void k_hydro_oe_pp(const double* __restrict__ Ust, double* __restrict__ Uout,
                                                      const double* __restrict__ stats, const double* __restrict__ lines,
                                                      const double* __restrict__ glob, uint8_t* __restrict__ flags,
                                                      unsigned long long* __restrict__ counts,
                                                      const int* __restrict__ flag, const HydroTab* __restrict__ T,
                                                      MeshP mp, double tau, double sH, int do_oe, int do_pp) {
-  using C = Cfg<P>;
+  using C = Cfg<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NL = 5 * NP;
   __shared__ double su[5][EB * NN];
   __shared__ double st[10][EB * NN];
-  __shared__ double ssig0[EB][NP], ssg[EB][2][5][NP];
+  __shared__ double ssig0[EB][NP], ssig1[EB][NP], ssg[EB][5][NP];
   __shared__ double sD[EB][NP], samp[EB][2][5], srow[EB][3][NP];
   __shared__ int scst[EB][5];
   if (flag && *flag) return;
@@ -344,12 +415,12 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
     // global and cross-line amplitudes (eq. euler-oe-amplitude), one task per component
     for (int c = q; act && c < 5; c += NN) {
       const double gs = glob[c * 3 + 0], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
-      const double gm = gs / (4.0 * (double)mp.K);
+      const double gm = gs * mp.r4K;
       const double dOm = fmax(gmx - gm, gm - gmn);
       scst[el][c] = dOm <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn)) ? 1 : 0;
       const double* rl = lines + (ey * 5 + c) * 3;
       const double* cl = lines + ((mp.ny + ex) * 5 + c) * 3;
-      const double rm = rl[0] / (4.0 * mp.nx), cm = cl[0] / (4.0 * mp.ny);
+      const double rm = rl[0] * mp.r4nx, cm = cl[0] * mp.r4ny;
       samp[el][0][c] = fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm);
       samp[el][1][c] = fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm);
     }
@@ -370,7 +441,7 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
       if (D == 1 && act && q < NP) {  // direction-0 sigma: maximum over the components
         double sg = 0.0;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) sg = fmax(sg, ssg[el][0][c][q]);
+        for (int c = 0; c < 5; ++c) sg = fmax(sg, ssg[el][c][q]);
         ssig0[el][q] = sg;
       }
       __syncthreads();
@@ -421,31 +492,11 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
             }
             v = T->fr[rr] * (sqrt(sm) + sqrt(spp)) / Dsh;
           }
-          ssg[el][D][c][rr] = v;
+          ssg[el][c][rr] = v;  // direction 0's values are reduced before direction 1 writes
         }
       }
       __syncthreads();
     }
-    // shell damping factors (eq. euler-oe-map): D_l = exp(-s tau (lx sum_{r<=l} sigma_x,r + ...))
-    if (act && q <= P) {
-      if (q == 0) {
-        sD[el][0] = 1.0;
-      } else {
-        const double ck = sqrt(g * pres(a, g) / a[0]);
-        const double lx = (2.0 * P + 1.0) * (fabs(a[1] / a[0]) + ck) / mp.hx;
-        const double ly = (2.0 * P + 1.0) * (fabs(a[2] / a[0]) + ck) / mp.hy;
-        double sx = 0.0, sy = 0.0;
-        for (int r = 0; r <= q; ++r) {
-          double s1 = 0.0;
-#pragma unroll
-          for (int c = 0; c < 5; ++c) s1 = fmax(s1, ssg[el][1][c][r]);
-          sx += ssig0[el][r];
-          sy += s1;
-        }
-        sD[el][q] = exp(-sH * tau * (lx * sx + ly * sy));
-      }
-    }
-    __syncthreads();
     // modal damping with line tasks: x transform of each row, then per column the y transform,
     // the shell factors and the inverse y transform, then the inverse x transform of each row
     for (int t = q; act && t < NL; t += NN) {
@@ -459,6 +510,29 @@ __global__ __launch_bounds__(256) void k_hydro_oe_pp(const double* __restrict__ 
 #pragma unroll
         for (int k = 0; k < NP; ++k) s += T->Tf[aa][k] * v[k];
         st[c][el * NN + ln * NP + aa] = s;  // [row][x mode]
+      }
+    }
+    if (act && q < NP) {  // direction-1 sigma: maximum over the components
+      double sg = 0.0;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) sg = fmax(sg, ssg[el][c][q]);
+      ssig1[el][q] = sg;
+    }
+    __syncthreads();
+    // shell damping factors (eq. euler-oe-map): D_l = exp(-s tau (lx sum_{r<=l} sigma_x,r + ...)),
+    // with one reciprocal of the mean density
+    if (act && q <= P) {
+      if (q == 0) {
+        sD[el][0] = 1.0;
+      } else {
+        const double ir0 = 1.0 / a[0];
+        const double pa = (g - 1.0) * (a[4] - 0.5 * (a[1] * a[1] + a[2] * a[2] + a[3] * a[3]) * ir0);
+        const double ck = sqrt(g * pa * ir0);
+        const double lx = (2.0 * P + 1.0) * (fabs(a[1] * ir0) + ck) * mp.rhx;
+        const double ly = (2.0 * P + 1.0) * (fabs(a[2] * ir0) + ck) * mp.rhy;
+        double sx = 0.0, sy = 0.0;
+        for (int r = 0; r <= q; ++r) { sx += ssig0[el][r]; sy += ssig1[el][r]; }
+        sD[el][q] = exp(-sH * tau * (lx * sx + ly * sy));
       }
     }
     __syncthreads();
@@ -735,9 +809,18 @@ int hydro_stats_only(mhd25_ctx* c, const double* U, int* flag) {
   return check(c, hipGetLastError(), "stats launch");
 }
 
+// threads per block of the OE/PP map: its LDS use (about 35 KB at N = 4 with 256 threads) caps a CU
+// at 4 such blocks, 4 waves per SIMD; with 128 threads the registers allow 5 waves per SIMD, which
+// measured 10 % faster on the 1024^2, N = 4 workload
+#ifndef MHD_OE_BS
+#define MHD_OE_BS 128
+#endif
+
 int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, const int* flag) {
-  const long blocks = (c->mp.K + eb_of(c->p) - 1) / eb_of(c->p);
-#define LB(P) hipLaunchKernelGGL((k_hydro_oe_pp<P>), dim3(blocks), dim3(256), 0, c->stream, Ust, Uout, c->stats, \
+  constexpr int BS = MHD_OE_BS;
+  const int eb = BS / ((c->p + 1) * (c->p + 1));
+  const long blocks = (c->mp.K + eb - 1) / eb;
+#define LB(P) hipLaunchKernelGGL((k_hydro_oe_pp<P, BS>), dim3(blocks), dim3(BS), 0, c->stream, Ust, Uout, c->stats, \
                                  c->lines, c->glob, c->d_flags, c->d_counts, flag, c->d_ht, c->mp, tau, c->opt.s_H, \
                                  c->opt.oe_hydro, c->opt.pp)
   DISPATCH_P(c->p, LB);

@@ -590,31 +590,51 @@ __host__ __device__ constexpr int shell_of(int k) {
   return l;
 }
 
+// shell-ordered tensor Legendre mode k -> (a, b): shell l = max(a, b) holds modes l^2 .. (l+1)^2 - 1,
+// (a, l) for a < l first, then (l, b) for b = 0..l (the order of the basis tables)
+__host__ __device__ constexpr int mode_a(int k) {
+  const int l = shell_of(k), r = k - l * l;
+  return r < l ? r : l;
+}
+__host__ __device__ constexpr int mode_b(int k) {
+  const int l = shell_of(k), r = k - l * l;
+  return r < l ? l : r - l;
+}
+
+// 1 / sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// y <- y (3/2 - x y^2 / 2), each of which squares the relative error, to within rounding of FP64.
+__device__ __forceinline__ double rsqrt_refined(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = y * (1.5 - h * y * y);
+  y = y * (1.5 - h * y * y);
+  return y;
+}
+
 template <int P>
 struct VP {
   static constexpr int NP = P + 1, NN = NP * NP, EB = 64 / NN > 0 ? 64 / NN : 1;
 };
 
-// One wave per block (EB elements).  Thread q holds row q of the element's Gram matrix in
-// registers; the right-looking Cholesky broadcasts the pivot and column k through LDS at step k
-// (two barriers per step).  The trailing update is masked arithmetic, not branches: entries right
-// of the diagonal take garbage updates that are never read.  L is kept packed in LDS for the
-// forward substitution Psi = Phi L^{-T}.
+// One wave per block (EB elements).  The Gram matrix is formed by sum factorisation and packed in
+// LDS; a left-looking Cholesky (thread q owns row q, one barrier per column) overwrites it with L,
+// and row q of Psi = Phi L^{-T} follows by forward substitution with L read from LDS.  Mode indices
+// are compile-time constants in the unrolled loops, and masked arithmetic replaces branches, so
+// the steps stay branch-free; the Cholesky dot products run on two accumulators to halve their FMA
+// chains (a second accumulator in the substitution as well would cost 50 more VGPRs).
 template <int P>
 __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho, double* __restrict__ Psi,
                                                  const HydroTab* __restrict__ H, MeshP mp) {
   constexpr int NP = P + 1, NN = NP * NP, EB = VP<P>::EB, NL = NN * (NN + 1) / 2;
-  __shared__ double sw[EB][NN], sL[EB][NL], scol[EB][NN], srd[EB][NN], sdg[EB], sdum[64];
+  __shared__ double sw[EB][NN], sL[EB][NL], srd[EB][NN], sdum[64];
   __shared__ double sH[EB][NP][NP * NP];  // Gram staging
   __shared__ double sV[NP][NP];
-  __shared__ int ska[NN], skb[NN];
   const int tid = threadIdx.x, el0 = tid / NN;
   const bool act0 = el0 < EB && (long)blockIdx.x * EB + el0 < mp.K;
   const int el = act0 ? el0 : 0, q = act0 ? tid - el0 * NN : 0;  // idle lanes shadow lane 0
   const int qi = q % NP, qj = q / NP;
   const long e = (long)blockIdx.x * EB + el;
   for (int t = tid; t < NP * NP; t += 64) sV[t / NP][t % NP] = H->V[t / NP][t % NP];
-  for (int t = tid; t < NN; t += 64) { ska[t] = H->ka[t]; skb[t] = H->kb[t]; }
   if (act0) sw[el][q] = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
   __syncthreads();
   // sum factorisation: Hm[qj][a][a'] = sum_qi W[qj][qi] V[qi][a] V[qi][a']
@@ -627,52 +647,65 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
       sH[el][jj][aa] = s;
     }
   __syncthreads();
-  // Gram row q (shell order): G[q][k'] = sum_qj V[qj][b] V[qj][b'] Hm[qj][a][a'], k' <= q (packed)
-  if (act0) {
-    const int ka = ska[q], kb = skb[q];
-    for (int k2 = 0; k2 <= q; ++k2) {
-      const int a2 = ska[k2], b2 = skb[k2];
+  // (LDS stores below go through address selects, not branches: a lane that must not write
+  // targets its own dummy slot)
+  // Gram row q (shell order): G[q][k'] = sum_qj V[qj][b'] (V[qj][b] Hm[qj][a][a']), k' <= q,
+  // packed; row q starts at rq = q (q + 1) / 2, so rq + k <= NL - 1 for every q, k < NN
+  const int rq = q * (q + 1) / 2;
+  {
+    const int ka = mode_a(q), kb = mode_b(q);
+    double w[NP][NP];
+#pragma unroll
+    for (int jj = 0; jj < NP; ++jj)
+#pragma unroll
+      for (int a2 = 0; a2 < NP; ++a2) w[jj][a2] = sV[jj][kb] * sH[el][jj][ka * NP + a2];
+#pragma unroll
+    for (int k2 = 0; k2 < NN; ++k2) {
       double s = 0.0;
 #pragma unroll
-      for (int jj = 0; jj < NP; ++jj) s += sV[jj][kb] * sV[jj][b2] * sH[el][jj][ka * NP + a2];
-      sL[el][q * (q + 1) / 2 + k2] = s;
+      for (int jj = 0; jj < NP; ++jj) s += sV[jj][mode_b(k2)] * w[jj][mode_a(k2)];
+      *((act0 && k2 <= q) ? &sL[el][rq + k2] : &sdum[tid]) = s;
     }
   }
   __syncthreads();
-  // (LDS stores below go through address selects, not branches: a lane that must not write
-  // targets its own dummy slot; this keeps the unrolled steps branch-free)
-  double g[NN];
-#pragma unroll
-  for (int k2 = 0; k2 < NN; ++k2) {
-    const double v = sL[el][(q * (q + 1) / 2 + k2) % NL];  // in bounds; used only for k2 <= q
-    g[k2] = k2 <= q ? v : 0.0;
-  }
-  // Cholesky G = L L^T; after step k, g[k] = L[q][k] (q >= k), srd[k] = 1 / L[k][k].  The pivot
-  // goes through sdg, the column through scol: a column is only rewritten after the next step's
-  // first barrier, which every thread reaches after its updates of this step.
-#pragma unroll
-  for (int k = 0; k < NN; ++k) {
-    *((act0 && q == k) ? &sdg[el] : &sdum[tid]) = g[k];
-    __syncthreads();
-    const double rk = 1.0 / sqrt(sdg[el]);
-    g[k] = q >= k ? g[k] * rk : g[k];
-    *(act0 ? &scol[el][q] : &sdum[tid]) = g[k];  // entries q <= k are not read at this step
-    *((act0 && q == k) ? &srd[el][k] : &sdum[tid]) = rk;
-    __syncthreads();
-    const double f = q > k ? g[k] : 0.0;
-#pragma unroll
-    for (int jj = k + 1; jj < NN; ++jj) g[jj] -= f * scol[el][jj];
+  // Left-looking Cholesky G = L L^T, one column per step, L written in place over the packed Gram
+  // matrix.  Thread q keeps its row of L in registers.  At step k the threads q > k form
+  // L[q][k] = (G[q][k] - sum_{m<k} L[q][m] L[k][m]) / L[k][k] with row k read from LDS, and the
+  // thread of row k + 1, whose row is then complete up to the diagonal, forms its pivot from its
+  // running G[q][q] - sum_m L[q][m]^2.  srd[k] = 1 / L[k][k].
+  double Lr[NN];
+  double piv = sL[el][rq + q];  // G[q][q]
+  {
+    const double rk = rsqrt_refined(piv);  // used by row 0 only
+    *((act0 && q == 0) ? &sL[el][0] : &sdum[tid]) = piv * rk;
+    *((act0 && q == 0) ? &srd[el][0] : &sdum[tid]) = rk;
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < NN; ++k) *((act0 && k <= q) ? &sL[el][q * (q + 1) / 2 + k] : &sdum[tid]) = g[k];
-  __syncthreads();
+  for (int k = 0; k + 1 < NN; ++k) {
+    double s0 = sL[el][rq + k], s1 = 0.0;  // G[q][k] (used only for q > k)
+#pragma unroll
+    for (int m = 0; m < k; ++m) {
+      if (m & 1) s1 -= Lr[m] * sL[el][k * (k + 1) / 2 + m];
+      else s0 -= Lr[m] * sL[el][k * (k + 1) / 2 + m];
+    }
+    Lr[k] = (s0 + s1) * srd[el][k];  // L[q][k] on the rows q > k; never read on the others
+    *((act0 && q > k) ? &sL[el][rq + k] : &sdum[tid]) = Lr[k];
+    piv -= Lr[k] * Lr[k];
+    const double rk = rsqrt_refined(piv);  // pivot of row k + 1 (used by that row only)
+    *((act0 && q == k + 1) ? &sL[el][rq + q] : &sdum[tid]) = piv * rk;
+    *((act0 && q == k + 1) ? &srd[el][k + 1] : &sdum[tid]) = rk;
+    __syncthreads();
+  }
   // row q of Psi = Phi L^{-T}: forward substitution over the modes with the row in registers
-  // (L is read from LDS as broadcasts)
+  // (L is read from LDS as broadcasts); Phi[q][k] = V[qi][a_k] V[qj][b_k]
+  double vi[NP], vj[NP];
+#pragma unroll
+  for (int a = 0; a < NP; ++a) { vi[a] = sV[qi][a]; vj[a] = sV[qj][a]; }
   double psi[NN];
 #pragma unroll
   for (int k = 0; k < NN; ++k) {
-    double s = sV[qi][ska[k]] * sV[qj][skb[k]];
+    double s = vi[mode_a(k)] * vj[mode_b(k)];
 #pragma unroll
     for (int k2 = 0; k2 < k; ++k2) s -= sL[el][k * (k + 1) / 2 + k2] * psi[k2];
     psi[k] = s * srd[el][k];
@@ -707,6 +740,7 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
   using C = VS<P, M>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, A = C::A, B = C::B, AB = C::AB;
   __shared__ double su[EB][3][NN], sx[EB][6][NN], sva[EB][2][NN], ssig[EB][2][NP], samp[EB][2][3], ssg[EB][3][NP];
+  __shared__ double srow[EB][2][NP];
   __shared__ int scst[EB][3];
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][C::BB];
   __shared__ double tD0[NP][NP], tDp[NP][NP], tWP[NP][A], tGP[NP][B], tVP[NP][B], tw[NP], tfr[NP];
@@ -742,12 +776,12 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
   // shared amplitudes: each component's global and cross-line spreads formed once per element
   for (int c = q; act && c < 3; c += NN) {
     const double gs = glob[c * 3], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
-    const double gm = gs / (4.0 * (double)mp.K);
+    const double gm = gs * mp.r4K;
     const double dOm = fmax(gmx - gm, gm - gmn);
     scst[el][c] = dOm <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn)) ? 1 : 0;
     const double* rl = lines + (ey * 3 + c) * 3;
     const double* cl = lines + ((mp.ny + ex) * 3 + c) * 3;
-    const double rm = rl[0] / (4.0 * mp.nx), cm = cl[0] / (4.0 * mp.ny);
+    const double rm = rl[0] * mp.r4nx, cm = cl[0] * mp.r4ny;
     samp[el][0][c] = fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm);
     samp[el][1][c] = fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm);
   }
@@ -838,6 +872,14 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
         }
         ssg[el][c][rr] = v;
       }
+      if (D == 0)  // row maxima of the node wave speeds, combined over the rows at the end
+        for (int t = q; act && t < NP; t += NN) {
+          double ax = 0.0, ay = 0.0;
+#pragma unroll
+          for (int k = 0; k < NP; ++k) { ax = fmax(ax, sva[el][0][t * NP + k]); ay = fmax(ay, sva[el][1][t * NP + k]); }
+          srow[el][0][t] = ax;
+          srow[el][1][t] = ay;
+        }
     }
     __syncthreads();
     if (act && q < NP) {
@@ -852,8 +894,9 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
     double Dl = 1.0;
     if (q > 0) {
       double ax = 0.0, ay = 0.0;
-      for (int k = 0; k < NN; ++k) { ax = fmax(ax, sva[el][0][k]); ay = fmax(ay, sva[el][1][k]); }
-      const double lx = (2.0 * P + 1.0) / mp.hx * ax, ly = (2.0 * P + 1.0) / mp.hy * ay;
+#pragma unroll
+      for (int l = 0; l < NP; ++l) { ax = fmax(ax, srow[el][0][l]); ay = fmax(ay, srow[el][1][l]); }
+      const double lx = (2.0 * P + 1.0) * mp.rhx * ax, ly = (2.0 * P + 1.0) * mp.rhy * ay;
       double sx_ = 0.0, sy_ = 0.0;
       for (int r = 0; r <= q; ++r) { sx_ += ssig[el][0][r]; sy_ += ssig[el][1][r]; }
       Dl = exp(-sM * tau * (lx * sx_ + ly * sy_));

@@ -24,6 +24,7 @@
 #define __launch_bounds__(...)
 #define __shared__ static
 #define HIP_SYMBOL(x) (&x)
+#define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt(x))  // hardware 1/sqrt estimate
 
 struct dim3 {
   unsigned x, y, z;
