@@ -12,6 +12,7 @@
 
 #include "common.h"
 #include "xcd.h"
+#include "ec_log.h"
 
 namespace {
 
@@ -33,7 +34,7 @@ __device__ __forceinline__ Prim make_prim(const double U[5], double g) {
   q.ux = U[1] * ir; q.uy = U[2] * ir; q.uz = U[3] * ir;
   const double p = (g - 1.0) * (U[4] - 0.5 * (U[1] * q.ux + U[2] * q.uy + U[3] * q.uz));
   q.b = 0.5 * q.r / p;
-  q.lr = log(q.r); q.lb = log(q.b);
+  q.lr = log_ec(q.r); q.lb = log_ec(q.b);
   return q;
 }
 

@@ -9,16 +9,17 @@
 
 #include "common.h"
 #include "xcd.h"
+#include "rsqrt.h"
 
 namespace {
 
 constexpr double EPSM = 2.220446049250313e-16;
 
-template <int P, int M>
+template <int P, int M, int BS = 256>
 struct MC {
   static constexpr int NP = P + 1, NN = NP * NP, A = M + 2, B = M + 1, AA = A * A, AB = A * B, BB = B * B;
   static constexpr int NT = NN > AA ? NN : AA;
-  static constexpr int EB = 256 / NT;
+  static constexpr int EB = BS / NT;
 };
 
 __device__ __forceinline__ long wrapl(long a, long n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
@@ -48,12 +49,12 @@ __device__ __forceinline__ void load_B(double* bx, double* by, double* bz, const
 // Current loads (eq. mag-current-proj): W part int B_x d_y phi - B_y d_x phi with the (m+2)-point
 // Gauss rule; N parts int B_z (-d_y psi) and int B_z d_x psi with the (m+1)-point rule.
 // ---------------------------------------------------------------------------------------------
-template <int P, int M>
-__global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, const double* __restrict__ By,
+template <int P, int M, int BS>
+__global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, const double* __restrict__ By,
                                                  const double* __restrict__ Bz, double* __restrict__ Lx,
                                                  double* __restrict__ Ly, double* __restrict__ Lz,
                                                  const MagTab* __restrict__ T, MeshP mp) {
-  using C = MC<P, M>;
+  using C = MC<P, M, BS>;
   constexpr int A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB, NT = C::NT;
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB], swx[EB][AA], swy[EB][AA], szg[EB][BB];
   __shared__ double sh[EB][2][AA];  // first half of the sum factorisation of the W loads
@@ -63,13 +64,13 @@ __global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, 
   const bool act = el < EB && e < mp.K;
   long ex, ey;
   elem_xy(mp, act ? e : 0, ex, ey);
-  for (int k = tid; k < A * A; k += 256) {
+  for (int k = tid; k < A * A; k += BS) {
     tWQ[k / A][k % A] = T->I_W_Q[k / A][k % A];
     tDWQ[k / A][k % A] = T->D_W_Q[k / A][k % A];
   }
-  for (int k = tid; k < A * B; k += 256) tGQ[k / B][k % B] = T->I_G_Q[k / B][k % B];
-  for (int k = tid; k < B * B; k += 256) tVG[k / B][k % B] = T->I_V_G[k / B][k % B];
-  for (int k = tid; k < B * A; k += 256) tDWG[k / A][k % A] = T->D_W_G[k / A][k % A];
+  for (int k = tid; k < A * B; k += BS) tGQ[k / B][k % B] = T->I_G_Q[k / B][k % B];
+  for (int k = tid; k < B * B; k += BS) tVG[k / B][k % B] = T->I_V_G[k / B][k % B];
+  for (int k = tid; k < B * A; k += BS) tDWG[k / A][k % A] = T->D_W_G[k / A][k % A];
   if (tid < A) twq[tid] = T->wq[tid];
   if (tid < B) twg[tid] = T->wg[tid];
   if (act) load_B<P, M>(sbx[el], sby[el], sbz[el], Bx, By, Bz, mp, ex, ey, t);
@@ -154,14 +155,14 @@ __global__ __launch_bounds__(256) void k_J_loads(const double* __restrict__ Bx, 
 // Electric-field loads (eq. mag-electric-proj): w_a (-u x B)|_K at the element's own auxiliary
 // nodes, plus eta_K sum_q M_q J(x_q) . phi_a(x_q) by the degree-p GLL rule.
 // ---------------------------------------------------------------------------------------------
-template <int P, int M>
-__global__ __launch_bounds__(256) void k_E_loads(const double* __restrict__ u, const double* __restrict__ Bx,
+template <int P, int M, int BS>
+__global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, const double* __restrict__ Bx,
                                                  const double* __restrict__ By, const double* __restrict__ Bz,
                                                  const double* __restrict__ Jx, const double* __restrict__ Jy,
                                                  const double* __restrict__ Jz, const double* __restrict__ eta,
                                                  double* __restrict__ Lx, double* __restrict__ Ly,
                                                  double* __restrict__ Lz, const MagTab* __restrict__ T, MeshP mp) {
-  using C = MC<P, M>;
+  using C = MC<P, M, BS>;
   constexpr int NP = C::NP, NN = C::NN, A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB,
                 NT = C::NT;
   __shared__ double su[EB][3][NN], sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
@@ -176,17 +177,17 @@ __global__ __launch_bounds__(256) void k_E_loads(const double* __restrict__ u, c
   elem_xy(mp, act ? e : 0, ex, ey);
   const long KN = mp.K * NN;
   const double et = (act && eta) ? eta[e] : 0.0;
-  for (int k = tid; k < NP * B; k += 256) tGP[k / B][k % B] = T->I_G_P[k / B][k % B];
-  for (int k = tid; k < NP * A; k += 256) {
+  for (int k = tid; k < NP * B; k += BS) tGP[k / B][k % B] = T->I_G_P[k / B][k % B];
+  for (int k = tid; k < NP * A; k += BS) {
     tWP[k / A][k % A] = T->I_W_P[k / A][k % A];
     tPW[k / NP][k % NP] = T->I_P_W[k / NP][k % NP];
   }
-  for (int k = tid; k < B * NP; k += 256) tPG[k / NP][k % NP] = T->I_P_G[k / NP][k % NP];
-  for (int k = tid; k < A * B; k += 256) {
+  for (int k = tid; k < B * NP; k += BS) tPG[k / NP][k % NP] = T->I_P_G[k / NP][k % NP];
+  for (int k = tid; k < A * B; k += BS) {
     tGW[k / B][k % B] = T->I_G_W[k / B][k % B];
     tVW[k / B][k % B] = T->I_V_W[k / B][k % B];
   }
-  for (int k = tid; k < B * B; k += 256) tVG[k / B][k % B] = T->I_V_G[k / B][k % B];
+  for (int k = tid; k < B * B; k += BS) tVG[k / B][k % B] = T->I_V_G[k / B][k % B];
   if (tid < NP) twp[tid] = T->wp[tid];
   if (tid < A) tww[tid] = T->ww[tid];
   if (tid < B) twg[tid] = T->wg[tid];
@@ -312,9 +313,9 @@ __global__ __launch_bounds__(256) void k_E_loads(const double* __restrict__ u, c
 // MODE 0: write L_M.  MODE 1: write the SSP stage ca*Y^n + cb*(Y_s + tau*L_M(Y_s)).
 // ---------------------------------------------------------------------------------------------
 
-template <int P, int M, int MODE>
-__global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __restrict__ T, MeshP mp) {
-  using C = MC<P, M>;
+template <int P, int M, int MODE, int BS>
+__global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __restrict__ T, MeshP mp) {
+  using C = MC<P, M, BS>;
   constexpr int NP = C::NP, NN = C::NN, A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB,
                 NT = C::NT;
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
@@ -329,16 +330,16 @@ __global__ __launch_bounds__(256) void k_mag_update(MagIO io, const MagTab* __re
   long ex, ey;
   elem_xy(mp, act ? e : 0, ex, ey);
   const long KN = mp.K * NN;
-  for (int k = tid; k < B * A; k += 256) tDWG[k / A][k % A] = T->D_W_G[k / A][k % A];
-  for (int k = tid; k < B * A; k += 256) tDWV[k / A][k % A] = T->D_W_V[k / A][k % A];
-  for (int k = tid; k < B * B; k += 256) tIGV[k / B][k % B] = T->I_G_V[k / B][k % B];
-  for (int k = tid; k < A * B; k += 256) tIGW[k / B][k % B] = T->I_G_W[k / B][k % B];
-  for (int k = tid; k < B * B; k += 256) tIVG[k / B][k % B] = T->I_V_G[k / B][k % B];
-  for (int k = tid; k < A * B; k += 256) tIVW[k / B][k % B] = T->I_V_W[k / B][k % B];
-  for (int k = tid; k < A * NP; k += 256) tIPW[k / NP][k % NP] = T->I_P_W[k / NP][k % NP];
-  for (int k = tid; k < B * NP; k += 256) tIPG[k / NP][k % NP] = T->I_P_G[k / NP][k % NP];
-  for (int k = tid; k < NP * B; k += 256) tIGP[k / B][k % B] = T->I_G_P[k / B][k % B];
-  for (int k = tid; k < NP * A; k += 256) tIWP[k / A][k % A] = T->I_W_P[k / A][k % A];
+  for (int k = tid; k < B * A; k += BS) tDWG[k / A][k % A] = T->D_W_G[k / A][k % A];
+  for (int k = tid; k < B * A; k += BS) tDWV[k / A][k % A] = T->D_W_V[k / A][k % A];
+  for (int k = tid; k < B * B; k += BS) tIGV[k / B][k % B] = T->I_G_V[k / B][k % B];
+  for (int k = tid; k < A * B; k += BS) tIGW[k / B][k % B] = T->I_G_W[k / B][k % B];
+  for (int k = tid; k < B * B; k += BS) tIVG[k / B][k % B] = T->I_V_G[k / B][k % B];
+  for (int k = tid; k < A * B; k += BS) tIVW[k / B][k % B] = T->I_V_W[k / B][k % B];
+  for (int k = tid; k < A * NP; k += BS) tIPW[k / NP][k % NP] = T->I_P_W[k / NP][k % NP];
+  for (int k = tid; k < B * NP; k += BS) tIPG[k / NP][k % NP] = T->I_P_G[k / NP][k % NP];
+  for (int k = tid; k < NP * B; k += BS) tIGP[k / B][k % B] = T->I_G_P[k / B][k % B];
+  for (int k = tid; k < NP * A; k += BS) tIWP[k / A][k % A] = T->I_W_P[k / A][k % A];
   if (tid < A) tww[tid] = T->ww[tid];
   if (tid < B) twg[tid] = T->wg[tid];
   if (tid < NP) twp[tid] = T->wp[tid];
@@ -599,16 +600,6 @@ __host__ __device__ constexpr int mode_a(int k) {
 __host__ __device__ constexpr int mode_b(int k) {
   const int l = shell_of(k), r = k - l * l;
   return r < l ? l : r - l;
-}
-
-// 1 / sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
-// y <- y (3/2 - x y^2 / 2), each of which squares the relative error, to within rounding of FP64.
-__device__ __forceinline__ double rsqrt_refined(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  y = y * (1.5 - h * y * y);
-  y = y * (1.5 - h * y * y);
-  return y;
 }
 
 template <int P>
@@ -1284,11 +1275,24 @@ static int chk(mhd25_ctx* c, const char* what) {
   switch (m) { case 0: F(0); break; case 1: F(1); break; case 2: F(2); break; case 3: F(3); break; \
                case 4: F(4); break; case 5: F(5); break; case 6: F(6); break; default: return -4; }
 
-static long mblocks(int p, int m, long K) {
+static long mblocks(int p, int m, long K, int bs = 256) {
   const int nn = (p + 1) * (p + 1), aa = (m + 2) * (m + 2);
-  const int eb = 256 / (nn > aa ? nn : aa);
+  const int eb = bs / (nn > aa ? nn : aa);
   return (K + eb - 1) / eb;
 }
+
+// threads per block of the element-load and update kernels (measured on the 1024^2, N = 4, k = 3
+// workload: 128-thread blocks make the E loads 6 % faster, being limited by their LDS use at 256;
+// the J loads and the update run slightly slower with 128)
+#ifndef MHD_JL_BS
+#define MHD_JL_BS 256
+#endif
+#ifndef MHD_EL_BS
+#define MHD_EL_BS 128
+#endif
+#ifndef MHD_MU_BS
+#define MHD_MU_BS 256
+#endif
 
 int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
                        const double* eta, double* JE) {
@@ -1297,16 +1301,17 @@ int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const do
   double* Lx = c->loads;
   double* Ly = Lx + K * a * b;
   double* Lz = Ly + K * a * b;
-  const long nb = mblocks(c->p, c->m, K);
+  const long nbj = mblocks(c->p, c->m, K, MHD_JL_BS), nbe = mblocks(c->p, c->m, K, MHD_EL_BS);
   const long gb = (G + 255) / 256;
-#define LJ(P, M) hipLaunchKernelGGL((k_J_loads<P, M>), dim3(nb), dim3(256), 0, c->stream, Bx, By, Bz, Lx, Ly, Lz, c->d_mt, c->mp)
+#define LJ(P, M) hipLaunchKernelGGL((k_J_loads<P, M, MHD_JL_BS>), dim3(nbj), dim3(MHD_JL_BS), 0, c->stream, Bx, By, Bz, \
+                                    Lx, Ly, Lz, c->d_mt, c->mp)
   DISPATCH_PM(c->p, c->m, LJ);
 #undef LJ
 #define GJ(M) hipLaunchKernelGGL((k_gather<M>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE, JE + G, JE + 2 * G, c->d_mt, c->mp)
   DISPATCH_M(c->m, GJ);
 #undef GJ
-#define LE(P, M) hipLaunchKernelGGL((k_E_loads<P, M>), dim3(nb), dim3(256), 0, c->stream, u, Bx, By, Bz, JE, JE + G, \
-                                    JE + 2 * G, eta, Lx, Ly, Lz, c->d_mt, c->mp)
+#define LE(P, M) hipLaunchKernelGGL((k_E_loads<P, M, MHD_EL_BS>), dim3(nbe), dim3(MHD_EL_BS), 0, c->stream, u, Bx, By, \
+                                    Bz, JE, JE + G, JE + 2 * G, eta, Lx, Ly, Lz, c->d_mt, c->mp)
   DISPATCH_PM(c->p, c->m, LE);
 #undef LE
 #define GE(M) hipLaunchKernelGGL((k_gather<M>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE + 3 * G, JE + 4 * G, \
@@ -1317,13 +1322,15 @@ int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const do
 }
 
 int mag_update(mhd25_ctx* c, const MagIO& io, int mode) {
-  const long nb = mblocks(c->p, c->m, c->mp.K);
+  const long nb = mblocks(c->p, c->m, c->mp.K, MHD_MU_BS);
   if (mode == 0) {
-#define U0(P, M) hipLaunchKernelGGL((k_mag_update<P, M, 0>), dim3(nb), dim3(256), 0, c->stream, io, c->d_mt, c->mp)
+#define U0(P, M) hipLaunchKernelGGL((k_mag_update<P, M, 0, MHD_MU_BS>), dim3(nb), dim3(MHD_MU_BS), 0, c->stream, io, \
+                                    c->d_mt, c->mp)
     DISPATCH_PM(c->p, c->m, U0);
 #undef U0
   } else {
-#define U1(P, M) hipLaunchKernelGGL((k_mag_update<P, M, 1>), dim3(nb), dim3(256), 0, c->stream, io, c->d_mt, c->mp)
+#define U1(P, M) hipLaunchKernelGGL((k_mag_update<P, M, 1, MHD_MU_BS>), dim3(nb), dim3(MHD_MU_BS), 0, c->stream, io, \
+                                    c->d_mt, c->mp)
     DISPATCH_PM(c->p, c->m, U1);
 #undef U1
   }

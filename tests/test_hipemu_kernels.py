@@ -216,3 +216,42 @@ int main() {
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout
     assert int(r.stdout.split()[-2]) > 10 ** 6
+
+
+def test_ec_log_within_two_ulp(tmp_path):
+    """The EC flux's logarithm (a frexp reduction and an atanh series) against the C library: at
+    most 2 ulp over random arguments spanning the double range, near 1 and at powers of two, and
+    the library's special values."""
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    src = tmp_path / "ec_log.cpp"
+    src.write_text(r'''
+#include "ec_log.h"
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <random>
+static double ulps(double a, double b) {
+  int64_t ia, ib; std::memcpy(&ia, &a, 8); std::memcpy(&ib, &b, 8);
+  if (ia < 0) ia = INT64_MIN - ia;
+  if (ib < 0) ib = INT64_MIN - ib;
+  return std::fabs((double)(ia - ib));
+}
+int main() {
+  std::mt19937_64 rng(11);
+  std::uniform_real_distribution<double> E(-744.0, 709.0), M(0.5, 2.0), D(-1e-7, 1e-7);
+  double worst = 0.0; long n = 0;
+  auto chk = [&](double x) { worst = std::fmax(worst, ulps(log_ec(x), std::log(x))); ++n; };
+  for (int i = 0; i < 400000; ++i) { chk(std::exp(E(rng))); chk(M(rng)); chk(1.0 + D(rng)); }
+  for (int k = -1074; k < 1024; ++k) { chk(std::ldexp(1.0, k)); chk(std::ldexp(std::sqrt(0.5), k)); }
+  chk(std::nextafter(1.0, 2.0)); chk(std::nextafter(1.0, 0.0)); chk(1.7976931348623157e308);
+  const bool special = std::isinf(log_ec(0.0)) && log_ec(0.0) < 0 && std::isnan(log_ec(-1.0)) &&
+                       std::isinf(log_ec(HUGE_VAL)) && std::isnan(log_ec(std::nan("")));
+  std::printf("%ld %.0f %d\n", n, worst, (int)special);
+  return !(worst <= 2.0 && special);
+}
+''')
+    exe = tmp_path / "ec_log"
+    subprocess.check_call(["g++", "-std=c++20", "-O2", "-I", os.path.join(HERE, "hipemu"), "-I", SRC, str(src), "-o", str(exe)])
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout
