@@ -181,6 +181,48 @@ def orszag_tang_scaled(nx=256, ny=256, p=4, m=3, gamma=GAMMA):
     return L, U, Bx, By, Bz
 
 
+def orszag_tang(nx=256, ny=256, p=2, m=2, gamma=GAMMA):
+    """Orszag-Tang vortex on [0, 2 pi]^2 as in section "Orszag--Tang vortex": rho = gamma^2,
+    p = gamma, u = (-sin y, sin x, 0), B = (-sin y, sin 2x, 0), with B from the potential
+    A = -cos y - cos(2x)/2, B = (-d_y A, d_x A)."""
+    L = Layout(nx, ny, p, m, 0.0, 2 * math.pi, 0.0, 2 * math.pi, gamma=gamma)
+    X, Y = L.u_nodes()
+    rho = np.full_like(X, gamma * gamma)
+    pr = np.full_like(X, gamma)
+    U = conservative(rho, -np.sin(Y), np.sin(X), np.zeros_like(X), pr, gamma)
+    wX, wY = L.w_nodes()
+    Bx, By = L.curl_of_potential(-np.cos(wY) - 0.5 * np.cos(2.0 * wX))
+    return L, U, Bx, By, np.zeros_like(Bx)
+
+
+def field_loop(nx=256, ny=128, p=2, m=2, A0=1e-3, R=0.3, gamma=GAMMA):
+    """Magnetic-field loop advected across [-1, 1] x [-1/2, 1/2] (section "Advection of a
+    magnetic-field loop"): rho = p = 1, u = (2, 1, 0), B = curl(A_z e_z) = (d_y A_z, -d_x A_z)
+    with A_z = A0 max(R - r, 0)."""
+    L = Layout(nx, ny, p, m, -1.0, 1.0, -0.5, 0.5, gamma=gamma)
+    X, Y = L.u_nodes()
+    one = np.ones_like(X)
+    U = conservative(one, 2.0 * one, one, 0.0 * one, one, gamma)
+    wX, wY = L.w_nodes()
+    Az = A0 * np.maximum(R - np.sqrt(wX * wX + wY * wY), 0.0)
+    Bx, By = L.curl_of_potential(-Az)  # (-d_y(-A_z), d_x(-A_z))
+    return L, U, Bx, By, np.zeros_like(Bx)
+
+
+def oblique_blast(nx=256, ny=256, p=2, m=2, p_in=10.0, p_out=0.1, radius=0.1, gamma=GAMMA):
+    """Oblique MHD blast wave on the periodic unit square (section "Oblique MHD blast wave"):
+    rho = 1, u = 0, B = (cos(pi/4), sin(pi/4), 0), p = p_in at nodes within radius of (1/2, 1/2)
+    (strict point test), p_out elsewhere."""
+    L = Layout(nx, ny, p, m, 0.0, 1.0, 0.0, 1.0, gamma=gamma)
+    X, Y = L.u_nodes()
+    r = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2)
+    z = np.zeros_like(X)
+    U = conservative(np.ones_like(X), z, z, z, np.where(r < radius, p_in, p_out), gamma)
+    Bx = np.full((ny * L.M1, nx * L.M1), math.cos(math.pi / 4))
+    By = np.full_like(Bx, math.sin(math.pi / 4))
+    return L, U, Bx, By, np.zeros_like(Bx)
+
+
 def noisy_vortex(nx=128, ny=128, p=3, m=2, seed=0, amp=1e-3, gamma=GAMMA):
     """C1-type vortex plus seeded N(0,1)*amp noise on the conservative nodal values; the
     in-plane field gets noise through a periodic potential so it stays divergence-free."""

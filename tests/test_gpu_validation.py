@@ -4,9 +4,10 @@
 Spatial table (tests/golden/vortex_table2.json): L2(Omega_e) errors at t_f = 1 with dt = 1e-4
 (10 000 Strang steps per run).  Velocity and magnetic-field errors are required within 5 % of the
 printed values and their refinement rates within 0.1.  Density and pressure are required within
-40 % and 0.35, since the paper does not state how rho_h and p_h are formed from the conservative
-nodal state (here: nodal values, then the nodal interpolant), which matters most on the coarsest
-meshes where the density error is mostly aliasing.
+40 % and 0.35 only: for the identical (2,2) unstabilized runs the paper's stabilized-vortex table
+prints other density and pressure errors than this table (9.863e-3 against 8.185e-3 at N = 16),
+and this path reproduces that other table's values to 4 digits (test_vortex_stabilized_table4),
+so the paper's two tables evaluate rho and p differently and the looser bound covers that.
 
 Temporal table (tests/golden/vortex_table3.json and tests/golden/vortex_table3_oracle.json):
 Cauchy differences of the density and velocity for dt = 1e-2 * 2^-l, l = 0..3; they must equal
@@ -85,3 +86,187 @@ def test_vortex_temporal_table():
     for f in ("rho", "u"):
         for i in range(len(d) - 1):
             assert abs(math.log2(d[i][f] / d[i + 1][f]) - 2.0) < 0.05
+
+
+def run_alfven_gpu(p, m, n, dt, tf=1.0):
+    """Magnetic substeps alone on the reduced Alfven wave (OE, PP, A.R. off), as the paper's
+    magnetic-stage study; errors of u, B, E, J at t_f by the oracle-side L2 norms."""
+    import paper_2609_10849_amd as pk
+    from tests.test_oracle_magnetic import l2_errors, mesh_of
+    L, U, Bx, By, Bz, fields = W.alfven_wave(n, n, p, m)
+    S = pk.Solver.from_layout(L, pk.Options.make())
+    rho, e, u = S.to_primitive(dev(U))
+    g = [dev(a) for a in (Bx, By, Bz)]
+    for _ in range(int(round(tf / dt))):
+        S.step_magnetic(rho, e, u, *g, dt)
+    JE = S.reconstruct_JE(u, *g)
+    out = [host(a) for a in (u, *g, JE)]
+    S.close()
+    _, _, _, _, _, f_end = W.alfven_wave(n, n, p, m, t=tf)
+    f_end.t = tf
+    return l2_errors(L, mesh_of(L), *out, f_end)
+
+
+def test_alfven_table1():
+    """The paper's reduced-Alfven-wave table at its own step dt = 1e-4 (10 000 magnetic substeps
+    per run): (2,2) errors of u, B, E, J within 25 % of the printed values at N = 16 and 32, and
+    the (3,2) primary-field rates between N = 16 and 32 at 3.0 +- 0.3 (its magnitudes are not
+    pinned: the initial projection and the L2 quadrature are unstated, and nodal interpolation
+    alone already exceeds the printed (3,2) B and J errors)."""
+    gold = json.load(open(os.path.join(HERE, "golden", "alfven_table1.json")))["rows"]
+    for n in (16, 32):
+        announce("alfven table 1 p=2 m=2 N=%d" % n)
+        errs = run_alfven_gpu(2, 2, n, 1e-4)
+        row = gold["2,2,%d" % n]
+        for got, ref in zip(errs, (row["e_u"], row["e_B"], row["e_E"], row["e_J"])):
+            assert 0.75 * ref < got < 1.25 * ref, (n, errs, row)
+    announce("alfven table 1 p=3 m=2 N=16, 32")
+    e16 = run_alfven_gpu(3, 2, 16, 1e-4)
+    e32 = run_alfven_gpu(3, 2, 32, 1e-4)
+    for a, b in zip(e16[:3], e32[:3]):
+        assert 2.7 < math.log2(a / b) < 3.3, (e16, e32)
+
+
+def run_vortex_opts(n, opts, dt=1e-4, tf=1.0):
+    import paper_2609_10849_amd as pk
+    L, U, Bx, By, Bz = W.balsara_vortex(n, n, 2, 2)
+    S = pk.Solver.from_layout(L, opts)
+    g = [dev(a) for a in (U, Bx, By, Bz)]
+    eta = 0.0
+    for _ in range(int(round(tf / dt))):
+        r, rep = S.strang_step(*g, dt)
+        assert r == 0
+        eta = rep["eta_max"]
+    out = [host(a) for a in g]
+    S.close()
+    return L, out, eta
+
+
+def test_vortex_stabilized_table4():
+    """The paper's stabilized-vortex table, (p,m) = (2,2), dt = 1e-4, t_f = 1, N = 16, 32, 64:
+    without stabilization, with OE and positivity limiting (s_H = s_M = 0.02), and with OE plus
+    A.R. (C_eta = 0.2, C_s = 5).  Errors of rho, u, B within 2 % and of p within 3 % of the
+    printed values; the final-step maximum A.R. coefficient within 5 % at N = 16 and decaying
+    with rates above 2.5.  (The unstabilized rows here are the paper's; its separate spatial
+    table prints other rho and p errors for the same configuration.)"""
+    import paper_2609_10849_amd as pk
+    gold = json.load(open(os.path.join(HERE, "golden", "vortex_table4.json")))
+    configs = {"none": pk.Options.make(), "oe": pk.Options.make(1, 1, 1, 0),
+               "oe_ar": pk.Options.make(1, 1, 1, 1, C_eta=0.2, C_s=5.0)}
+    etas = []
+    for name, opts in configs.items():
+        for n in (16, 32, 64):
+            announce("vortex table 4 %s N=%d" % (name, n))
+            L, st, eta = run_vortex_opts(n, opts)
+            e = vortex_errors(L, *st, 1.0)
+            row = gold["rows"]["%s,%d" % (name, n)]
+            for f, tol in (("rho", 0.02), ("u", 0.02), ("B", 0.02), ("p", 0.03)):
+                assert abs(e[f] / row["e_" + f] - 1.0) < tol, (name, n, f, e[f], row["e_" + f])
+            if name == "oe_ar":
+                etas.append(eta)
+    assert abs(etas[0] / gold["eta_max_final"]["16"] - 1.0) < 0.05, etas
+    assert all(math.log2(a / b) > 2.5 for a, b in zip(etas[:-1], etas[1:])), etas
+
+
+def run_to(L, U, Bx, By, Bz, opts, tf, cfl):
+    """Strang steps with the CFL step (reading: dt = cfl / max (2p+1)(|u_d| + c_f)/h_d summed over
+    x and y, taken at each step start) up to t_f exactly."""
+    import paper_2609_10849_amd as pk
+    S = pk.Solver.from_layout(L, opts)
+    g = [dev(a) for a in (U, Bx, By, Bz)]
+    d0 = S.diagnostics(*g)
+    t, eta = 0.0, 0.0
+    while t < tf - 1e-14:
+        dt = min(S.cfl_dt(*g, cfl), tf - t)
+        r, rep = S.strang_step(*g, dt)
+        assert r == 0
+        eta, t = rep["eta_max"], t + dt
+    d1 = S.diagnostics(*g)
+    out = [host(a) for a in g]
+    S.close()
+    return out, d0, d1, eta
+
+
+def stab(ar):
+    import paper_2609_10849_amd as pk
+    return pk.Options.make(1, 1, 1, ar, C_eta=0.2, C_s=5.0)
+
+
+def test_orszag_tang_paper_scalars():
+    """Orszag-Tang, p = m = 2, 256^2, t = 3, OE and positivity on, without and with A.R.
+    (readings: s_H = s_M = 0.02 as in the stabilized vortex runs, CFL 0.3, extrema at the
+    velocity nodes).  Density maxima within 0.2 % of the printed ones; the extremes of rho, p_m
+    and Mach number over both runs within 1 %, 2 % and 2 % of the common contour ranges; the
+    divergence norm stays at its initial round-off level, below 3x the printed value."""
+    from tests._fe_fields import B_at, primitives
+    from paper_2609_10849_amd.workloads import gll_nodes
+    gold = json.load(open(os.path.join(HERE, "golden", "nonsmooth_scalars.json")))["orszag_tang"]
+    rho_lo, rho_hi, pm_hi, mach_hi = [], [], [], []
+    for ar in (0, 1):
+        announce("orszag-tang ar=%d" % ar)
+        L, U, Bx, By, Bz = W.orszag_tang(256, 256, 2, 2)
+        (Uf, Bxf, Byf, Bzf), d0, d1, _ = run_to(L, U, Bx, By, Bz, stab(ar), 3.0, 0.3)
+        rho, u, p = primitives(L, Uf)
+        Bn = B_at(L, Bxf, Byf, Bzf, np.array(gll_nodes(2))).reshape(3, *rho.shape)
+        assert abs(rho.max() / gold["rho_max"][ar] - 1.0) < 2e-3, (ar, rho.max())
+        rho_lo.append(rho.min()); rho_hi.append(rho.max())
+        pm_hi.append(0.5 * (Bn ** 2).sum(0).max())
+        mach_hi.append((np.sqrt((u ** 2).sum(0)) / np.sqrt(L.gamma * p / rho)).max())
+        assert d1["divB_L2"] < 3 * gold["divB"] and d1["divB_L2"] < 1.5 * d0["divB_L2"], (d0, d1)
+    assert abs(min(rho_lo) / gold["rho_levels"][0] - 1.0) < 0.01, rho_lo
+    assert abs(max(rho_hi) / gold["rho_levels"][1] - 1.0) < 0.01, rho_hi
+    assert abs(max(pm_hi) / gold["pm_levels"][1] - 1.0) < 0.02, pm_hi
+    assert abs(max(mach_hi) / gold["mach_levels"][1] - 1.0) < 0.02, mach_hi
+
+
+def test_oblique_blast_paper_scalars():
+    """Oblique blast, 256^2, t = 0.2 (readings: p = m = 2, CFL 0.3, OE and positivity on, maxima
+    at the velocity nodes): magnetic-pressure maxima within 3 % of 2.25 (no A.R.) and 1.77
+    (A.R.), the final-step A.R. maximum within 5 % of 3.18e-4, divergence norm below 3x the
+    printed one."""
+    from tests._fe_fields import B_at
+    from paper_2609_10849_amd.workloads import gll_nodes
+    gold = json.load(open(os.path.join(HERE, "golden", "nonsmooth_scalars.json")))["oblique_blast"]
+    for ar in (0, 1):
+        announce("oblique blast ar=%d" % ar)
+        L, U, Bx, By, Bz = W.oblique_blast(256, 256, 2, 2)
+        (Uf, Bxf, Byf, Bzf), _, d1, eta = run_to(L, U, Bx, By, Bz, stab(ar), 0.2, 0.3)
+        pm = 0.5 * (B_at(L, Bxf, Byf, Bzf, np.array(gll_nodes(2))) ** 2).sum(0).max()
+        assert abs(pm / gold["pm_max"][ar] - 1.0) < 0.03, (ar, pm)
+        if ar:
+            assert abs(eta / gold["eta_max_final"] - 1.0) < 0.05, eta
+        assert d1["divB_L2"] < 3 * gold["divB"], d1
+
+
+def test_field_loop_paper_scalars():
+    """Field loop, 256 x 128, CFL 0.8, t = 1 (reading: p = m = 2, OE and positivity on, the
+    maximum at the velocity nodes, e_B^tr by an 8-point Gauss rule per direction against the
+    analytic loop).  With A.R.: maximum |B| within 1 %, retained magnetic energy within 0.5 %,
+    e_B^tr within 2 % of the printed values.  Without A.R.: maximum |B| within 2 %, energy within
+    0.5 %, e_B^tr within 10 % (the grid-scale oscillations of that run make its error the most
+    sensitive to the unstated step rule).  Divergence norm below 1e-14 in both."""
+    from tests._fe_fields import B_at, points
+    from paper_2609_10849_amd.workloads import gll_nodes
+    gold = json.load(open(os.path.join(HERE, "golden", "nonsmooth_scalars.json")))["field_loop"]
+    A0, R = 1e-3, 0.3
+    for ar in (0, 1):
+        announce("field loop ar=%d" % ar)
+        L, U, Bx, By, Bz = W.field_loop(256, 128, 2, 2, A0=A0, R=R)
+        (Uf, Bxf, Byf, Bzf), d0, d1, _ = run_to(L, U, Bx, By, Bz, stab(ar), 1.0, 0.8)
+        Bn = B_at(L, Bxf, Byf, Bzf, np.array(gll_nodes(2)))
+        bmax = np.sqrt((Bn ** 2).sum(0)).max() / A0
+        zq, wq = np.polynomial.legendre.leggauss(8)
+        Bq = B_at(L, Bxf, Byf, Bzf, zq)
+        X, Y = points(L, zq)
+        r = np.sqrt(X * X + Y * Y)
+        ins = r < R
+        bex = np.where(ins, -A0 * Y / np.maximum(r, 1e-300), 0.0)
+        bey = np.where(ins, A0 * X / np.maximum(r, 1e-300), 0.0)
+        W2 = np.outer(wq, wq) * L.hx * L.hy / 4.0
+        etr = math.sqrt((W2 * ((Bq[0] - bex) ** 2 + (Bq[1] - bey) ** 2 + Bq[2] ** 2)).sum()
+                        / (W2 * (bex ** 2 + bey ** 2)).sum())
+        keep = d1["E_mag"] / d0["E_mag"]
+        assert abs(bmax / gold["B_max_over_A0"][ar] - 1.0) < (0.01 if ar else 0.02), (ar, bmax)
+        assert abs(keep / gold["energy_retained"][ar] - 1.0) < 0.005, (ar, keep)
+        assert abs(etr / gold["eB_tr"][ar] - 1.0) < (0.02 if ar else 0.10), (ar, etr)
+        assert d1["divB_L2"] < 1e-14, d1
