@@ -33,8 +33,17 @@ def stage_bytes(K, nn):
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the source the hydro stage kernel is built from: hydro.hip up to the end of that
+    kernel (its device helpers and element statistics), its launcher, and the headers it
+    includes.  Edits elsewhere (the OE/PP map, other launchers) leave the counters valid."""
+    src = open(KERNEL_SRC, encoding="utf-8").read()
+    end = src.index("template <int P>\n__global__ __launch_bounds__(256) void k_elem_stats(")
+    a = src.index("int hydro_stage_a(")
+    b = src.index("int line_global_reduce(", a)
+    h = hashlib.sha256((src[:end] + src[a:b]).encode())
+    for name in ("common.h", "xcd.h", "ec_log.h"):
+        h.update(open(os.path.join(os.path.dirname(KERNEL_SRC), name), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_per_launch():

@@ -24,7 +24,8 @@
 #include "common.h"
 
 int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust, double ca, double cb, double tau);
-int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, const int* flag);
+int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, const int* flag, double* rho_o,
+                  double* e_o, double* u_o);
 int reset_attempt(mhd25_ctx* c);
 int dcopy(mhd25_ctx* c, const double* a, double* b, long n);
 int mag_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u);
@@ -78,11 +79,11 @@ static int attempt_deferred(mhd25_ctx* c, double* U, double tau, int* fail, long
   BTRY(reset_attempt(c));
   BTRY(dcopy(c, U, c->Un, n5));
   BTRY(hydro_stage_a(c, c->Un, c->Un, c->Ust, 0.0, 1.0, tau));
-  BTRY(hydro_stage_b(c, c->Ust, c->S1, tau, c->d_flag));
+  BTRY(hydro_stage_b(c, c->Ust, c->S1, tau, c->d_flag, nullptr, nullptr, nullptr));
   BTRY(hydro_stage_a(c, c->S1, c->Un, c->Ust, 0.75, 0.25, tau));
-  BTRY(hydro_stage_b(c, c->Ust, c->S2, tau, c->d_flag));
+  BTRY(hydro_stage_b(c, c->Ust, c->S2, tau, c->d_flag, nullptr, nullptr, nullptr));
   BTRY(hydro_stage_a(c, c->S2, c->Un, c->Ust, 1.0 / 3.0, 2.0 / 3.0, tau));
-  BTRY(hydro_stage_b(c, c->Ust, U, tau, c->d_flag));
+  BTRY(hydro_stage_b(c, c->Ust, U, tau, c->d_flag, nullptr, nullptr, nullptr));
   hipLaunchKernelGGL(k_batch_fold, dim3(1), dim3(64), 0, c->stream, c->d_flag, c->d_counts, fail, acc);
   return hipGetLastError() == hipSuccess ? 0 : -2;
 }

@@ -13,7 +13,8 @@
 int hydro_rhs(mhd25_ctx* c, const double* U, double* dU);
 int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust, double ca, double cb, double tau);
 int hydro_stats_only(mhd25_ctx* c, const double* U, int* flag);
-int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, const int* flag);
+int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, const int* flag, double* rho_o,
+                  double* e_o, double* u_o);
 int reset_attempt(mhd25_ctx* c);
 int dcopy(mhd25_ctx* c, const double* a, double* b, long n);
 int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
@@ -189,22 +190,25 @@ int mhd25_hydro_stage_map(mhd25_ctx* c, double* U, double tau, uint8_t* flags) {
   const long n5 = 5 * c->mp.K * c->nn;
   TRY(dcopy(c, U, c->Ust, n5));
   TRY(hydro_stats_only(c, c->Ust, nullptr));
-  TRY(hydro_stage_b(c, c->Ust, U, tau, nullptr));
+  TRY(hydro_stage_b(c, c->Ust, U, tau, nullptr, nullptr, nullptr, nullptr));
   if (flags) HIPCHK(c, hipMemcpyAsync(flags, c->d_flags, c->mp.K, hipMemcpyDeviceToDevice, c->stream));
   return 0;
 }
 
 // one attempt of the SSP-RK(3,3) hydro substep; returns 1 accepted, 0 rejected, <0 error
-static int hydro_attempt(mhd25_ctx* c, double* U, double tau, long long* counts) {
+// with_prim: the last stage also writes the primitive copy (c->rho, c->e, c->u) of the new state
+static int hydro_attempt(mhd25_ctx* c, double* U, double tau, long long* counts, bool with_prim) {
   // U itself serves as U^n: it is written only by the last stage's map, which every thread
   // does for its own nodes after all reads of U^n, and which is skipped when the attempt is rejected
   TRY(reset_attempt(c));
   TRY(hydro_stage_a(c, U, U, c->Ust, 0.0, 1.0, tau));
-  TRY(hydro_stage_b(c, c->Ust, c->S1, tau, c->d_flag));
+  TRY(hydro_stage_b(c, c->Ust, c->S1, tau, c->d_flag, nullptr, nullptr, nullptr));
   TRY(hydro_stage_a(c, c->S1, U, c->Ust, 0.75, 0.25, tau));
-  TRY(hydro_stage_b(c, c->Ust, c->S2, tau, c->d_flag));
+  TRY(hydro_stage_b(c, c->Ust, c->S2, tau, c->d_flag, nullptr, nullptr, nullptr));
   TRY(hydro_stage_a(c, c->S2, U, c->Ust, 1.0 / 3.0, 2.0 / 3.0, tau));
-  TRY(hydro_stage_b(c, c->Ust, U, tau, c->d_flag));  // skipped (U untouched) when rejected
+  // skipped (U untouched) when rejected
+  TRY(hydro_stage_b(c, c->Ust, U, tau, c->d_flag, with_prim ? c->rho : nullptr, with_prim ? c->e : nullptr,
+                    with_prim ? c->u : nullptr));
   int* hf = (int*)c->h_pinned;
   unsigned long long* hc = (unsigned long long*)(c->h_pinned + 8);
   HIPCHK(c, hipMemcpyAsync(hf, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
@@ -215,11 +219,14 @@ static int hydro_attempt(mhd25_ctx* c, double* U, double tau, long long* counts)
   return 1;
 }
 
-static int hydro_substep_rec(mhd25_ctx* c, double* U, double tau, int depth, mhd25_report* rep) {
+// with_prim: every accepted attempt also writes the primitive copy of its result, so after an
+// accepted substep it holds the final state (the last accepted attempt writes last)
+static int hydro_substep_rec(mhd25_ctx* c, double* U, double tau, int depth, mhd25_report* rep,
+                             bool with_prim = false) {
   rep->substeps_attempted++;
   rep->max_depth = std::max(rep->max_depth, depth);
   long long cnt[3] = {0, 0, 0};
-  int ok = hydro_attempt(c, U, tau, cnt);
+  int ok = hydro_attempt(c, U, tau, cnt, with_prim);
   if (ok < 0) return ok;
   if (ok) {
     rep->substeps_accepted++;
@@ -230,8 +237,8 @@ static int hydro_substep_rec(mhd25_ctx* c, double* U, double tau, int depth, mhd
     c->err = "hydro substep not accepted within max_halvings";
     return 1;
   }
-  TRY(hydro_substep_rec(c, U, 0.5 * tau, depth + 1, rep));
-  return hydro_substep_rec(c, U, 0.5 * tau, depth + 1, rep);
+  TRY(hydro_substep_rec(c, U, 0.5 * tau, depth + 1, rep, with_prim));
+  return hydro_substep_rec(c, U, 0.5 * tau, depth + 1, rep, with_prim);
 }
 
 int mhd25_hydro_substep(mhd25_ctx* c, double* U, double tau, mhd25_report* rep) {
@@ -359,9 +366,8 @@ int mhd25_strang_step(mhd25_ctx* c, double* U, double* Bx, double* By, double* B
   };
   mhd25_report h1, m, h2;
   std::memset(&h1, 0, sizeof(h1)); std::memset(&m, 0, sizeof(m)); std::memset(&h2, 0, sizeof(h2));
-  int s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h1);
+  int s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h1, true);  // also leaves (rho, e, u) of U
   if (s != 0) return restore(s);
-  TRY(mag_to_primitive(c, U, c->rho, c->e, c->u));
   TRY(mhd25_step_magnetic(c, c->rho, c->e, c->u, Bx, By, Bz, dt, &m));
   TRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
   s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h2);

@@ -384,7 +384,9 @@ __global__ __launch_bounds__(BS) void k_hydro_oe_pp(const double* __restrict__ U
                                                      const double* __restrict__ glob, uint8_t* __restrict__ flags,
                                                      unsigned long long* __restrict__ counts,
                                                      const int* __restrict__ flag, const HydroTab* __restrict__ T,
-                                                     MeshP mp, double tau, double sH, int do_oe, int do_pp) {
+                                                     MeshP mp, double tau, double sH, int do_oe, int do_pp,
+                                                     double* __restrict__ rho_o, double* __restrict__ e_o,
+                                                     double* __restrict__ u_o) {
   using C = Cfg<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NL = 5 * NP;
   __shared__ double su[5][EB * NN];
@@ -636,6 +638,12 @@ __global__ __launch_bounds__(BS) void k_hydro_oe_pp(const double* __restrict__ U
   if (act) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) Uout[c * KN + e * NN + q] = U[c];
+    if (rho_o) {  // primitive copy for the magnetic substep (the conversion's arithmetic)
+      const long n = e * NN + q;
+      const double r = U[0], ux = U[1] / r, uy = U[2] / r, uz = U[3] / r;
+      rho_o[n] = r; u_o[n] = ux; u_o[KN + n] = uy; u_o[2 * KN + n] = uz;
+      e_o[n] = (U[4] - 0.5 * r * (ux * ux + uy * uy + uz * uz)) / r;
+    }
     if (q == 0) {
       if (flags) flags[e] = f;
       if (counts && f) {
@@ -817,13 +825,15 @@ int hydro_stats_only(mhd25_ctx* c, const double* U, int* flag) {
 #define MHD_OE_BS 128
 #endif
 
-int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, const int* flag) {
+// rho_o, e_o, u_o: optional primitive outputs (all null or all set)
+int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, const int* flag, double* rho_o,
+                  double* e_o, double* u_o) {
   constexpr int BS = MHD_OE_BS;
   const int eb = BS / ((c->p + 1) * (c->p + 1));
   const long blocks = (c->mp.K + eb - 1) / eb;
 #define LB(P) hipLaunchKernelGGL((k_hydro_oe_pp<P, BS>), dim3(blocks), dim3(BS), 0, c->stream, Ust, Uout, c->stats, \
                                  c->lines, c->glob, c->d_flags, c->d_counts, flag, c->d_ht, c->mp, tau, c->opt.s_H, \
-                                 c->opt.oe_hydro, c->opt.pp)
+                                 c->opt.oe_hydro, c->opt.pp, rho_o, e_o, u_o)
   DISPATCH_P(c->p, LB);
 #undef LB
   return check(c, hipGetLastError(), "stage map launch");

@@ -897,22 +897,22 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
 }
 
 // Velocity-OE map (eq. magnetic-oe-map) with the prepared basis: one thread per node, EB elements
-// per 128-thread block.  The block's basis tables are copied to LDS first (all of a thread's
+// per block.  The block's basis tables are copied to LDS first (all of a thread's
 // 16-byte loads are issued before the first store; rows keep an odd LDS stride), so the basis is
 // read from HBM once; then the coefficients c_k = (u_d, psi_k)_rho (thread = mode) and the shell
 // increments at the nodes (thread = node) are formed, and u and e are updated in place.
-template <int P>
+template <int P, int BS>
 struct VPJ {
-  static constexpr int NP = P + 1, NN = NP * NP, EB = 128 / NN, NNP = NN | 1;
+  static constexpr int NP = P + 1, NN = NP * NP, EB = BS / NN, NNP = NN | 1;
   static constexpr long PS = psi_stride(NN), RS = psi_row(NN);
 };
 
-template <int P>
-__global__ __launch_bounds__(128) void k_vel_proj(const double* __restrict__ rho, double* __restrict__ u,
+template <int P, int BS>
+__global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho, double* __restrict__ u,
                                                   double* __restrict__ en, const double* __restrict__ Psi,
                                                   const double* __restrict__ Dfac, const HydroTab* __restrict__ H,
                                                   MeshP mp) {
-  using C = VPJ<P>;
+  using C = VPJ<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NNP = C::NNP;
   constexpr long PS = C::PS, RS = C::RS;
   __shared__ double sP[EB * NN * NNP];
@@ -923,19 +923,19 @@ __global__ __launch_bounds__(128) void k_vel_proj(const double* __restrict__ rho
   const bool act = el < EB && e < mp.K;
   const long KN = mp.K * NN;
   {
-    constexpr int NL = (int)((EB * PS / 2 + 127) / 128);
+    constexpr int NL = (int)((EB * PS / 2 + BS - 1) / BS);
     const long nel = mp.K - e0 < EB ? mp.K - e0 : EB;
     const long n2 = nel * PS / 2;
     const double2* src = reinterpret_cast<const double2*>(Psi + e0 * PS);
     double2 v[NL];
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-      const long t = tid + 128L * k;
+      const long t = tid + (long)BS * k;
       v[k] = t < n2 ? src[t] : double2{0.0, 0.0};
     }
 #pragma unroll
     for (int k = 0; k < NL; ++k) {
-      const long t = tid + 128L * k;
+      const long t = tid + (long)BS * k;
       if (t < n2) {
         // RS even: both values lie in one row (ee, r), columns c0 and c0 + 1 (padding skipped)
         const int ee = (int)((2 * t) / PS), rem = (int)(2 * t - ee * PS), r = rem / (int)RS, c0 = rem % (int)RS;
@@ -1293,6 +1293,11 @@ static long mblocks(int p, int m, long K, int bs = 256) {
 #ifndef MHD_MU_BS
 #define MHD_MU_BS 256
 #endif
+// threads per block of the velocity-OE projection (its per-element basis tile in LDS sets how
+// many blocks share a CU)
+#ifndef MHD_VP_BS
+#define MHD_VP_BS 128
+#endif
 
 int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
                        const double* eta, double* JE) {
@@ -1354,7 +1359,7 @@ int mag_velocity_prep(mhd25_ctx* c, const double* rho) {
 int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
                        const double* By, const double* Bz, bool stats_ready) {
   const long K = c->mp.K;
-  const int nn = (c->p + 1) * (c->p + 1), eb = 256 / nn, eb2 = 128 / nn;
+  const int nn = (c->p + 1) * (c->p + 1), eb = 256 / nn, eb2 = MHD_VP_BS / nn;
   const long nb = (K + eb - 1) / eb, nb2 = (K + eb2 - 1) / eb2;
   if (!stats_ready) {
 #define FS(P) hipLaunchKernelGGL((k_field_stats<P, 3>), dim3(nb), dim3(256), 0, c->stream, u, c->stats, c->d_mt, c->mp)
@@ -1367,7 +1372,8 @@ int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, d
                                      c->glob, c->dfac, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M)
   DISPATCH_PM(c->p, c->m, VSN);
 #undef VSN
-#define VPR(P) hipLaunchKernelGGL((k_vel_proj<P>), dim3(nb2), dim3(128), 0, c->stream, rho, u, e, c->psi, c->dfac, c->d_ht, c->mp)
+#define VPR(P) hipLaunchKernelGGL((k_vel_proj<P, MHD_VP_BS>), dim3(nb2), dim3(MHD_VP_BS), 0, c->stream, rho, u, e, c->psi, \
+                                  c->dfac, c->d_ht, c->mp)
   switch (c->p) { case 1: VPR(1); break; case 2: VPR(2); break; case 3: VPR(3); break; case 4: VPR(4); break;
                   case 5: VPR(5); break; case 6: VPR(6); break; default: return -4; }
 #undef VPR
