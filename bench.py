@@ -170,6 +170,37 @@ def batched_speedup(steps=50):
             "steps": steps, "nodes": nodes}
 
 
+def reduced_2d2v(S, g, steps=10, warm=2):
+    """The same workload and state through the 2D2V reduced system (u_z = B_z = 0; the paper
+    solves that system for such states): steps timed like the main run.  The headline value
+    above is the general path's."""
+    import torch
+    S.set_options(S_options(reduced_2d2v=1))
+    try:
+        for _ in range(warm):
+            dt = S.cfl_dt(*g, 0.3)
+            S.strang_step(*g, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            dt = S.cfl_dt(*g, 0.3)
+            r, rep = S.strang_step(*g, dt)
+            if r != 0:
+                raise RuntimeError("strang step failed: %r" % (rep,))
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+    finally:
+        S.set_options(S_options(reduced_2d2v=0))
+    K, nn = S.K, (S.p + 1) ** 2
+    return {"value": K * nn * 9 / t, "ms_per_step": 1e3 * t, "steps": steps,
+            "note": "same workload through the 2D2V reduced system (u_z, B_z and the in-plane E, J skipped)"}
+
+
+def S_options(reduced_2d2v):
+    import paper_2609_10849_amd as pk
+    return pk.Options.full(reduced_2d2v=reduced_2d2v)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +209,8 @@ def main():
     ap.add_argument("--n", type=int, default=1024, help="elements per direction")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint-ratio and ensemble measurements")
+    ap.add_argument("--reduced-2d2v", action="store_true",
+                    help="time the 2D2V reduced system instead of the general path (for profiling it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
@@ -192,7 +225,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     n, N, k = args.n, 4, 3
     L, U, Bx, By, Bz = W.blast(n, n, N, k)
-    S = pk.Solver.from_layout(L, pk.Options.full())
+    S = pk.Solver.from_layout(L, pk.Options.full(reduced_2d2v=int(args.reduced_2d2v)))
     g = [torch.from_numpy(a).to("cuda") for a in (U, Bx, By, Bz)]
     del U, Bx, By, Bz
     K = L.K
@@ -241,13 +274,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "blast-like stress state, [-0.5,0.5]^2 periodic, %dx%d elements, N=%d, k=%d, "
                                "p_in/p_out=1e4, full stabilisation (OE, PP, velocity OE, A.R.), CFL 0.3" % (n, n, N, k),
-                   "elements": K, "N": N, "k": k, "dofs": K * nn},
+                   "elements": K, "N": N, "k": k, "dofs": K * nn,
+                   "system": "2D2V reduced" if args.reduced_2d2v else "general"},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "traffic": tr, "kernel": "k_hydro_stage<4,1> (L_E + SSP combine + element statistics)",
                      "avg_ms": avg_ms, "launches": launches},
         "accepted_substep_rate": accepted / max(attempted, 1),
     }
-    if not args.no_extras:
+    if not args.no_extras and not args.reduced_2d2v:
+        out["reduced_2d2v"] = reduced_2d2v(S, g, steps=min(args.steps, 10))
         out["adjoint_cost_ratio"] = adjoint_ratio()
         # the captured-graph ensemble path is held off the GPU until the cause of a host
         # segmentation fault seen in one build of it is shown (last measured speedup: 1.63)

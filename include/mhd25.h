@@ -55,6 +55,10 @@ typedef struct {
   double C_s, C_eta;        /* A.R. sensor response and maximum (paper: 5, 0.2)      */
   int32_t iface_flux;       /* 0: local Lax-Friedrichs (the scheme), 1: the EC flux  */
   int32_t max_halvings;     /* reject-and-halve depth budget (default 10)            */
+  int32_t reduced_2d2v;     /* 2D2V reduced system (section "Numerical experiments"): the
+                             * caller guarantees u_z = 0 and B_z = 0; the magnetic substep then
+                             * neither reads nor writes u_z and B_z and skips the identically
+                             * zero in-plane E and J (results equal the general path's). Default 0 */
 } mhd25_options;
 
 typedef struct {

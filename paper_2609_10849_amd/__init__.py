@@ -28,16 +28,16 @@ class Options(ctypes.Structure):
     _fields_ = [("oe_hydro", ctypes.c_int32), ("oe_mag", ctypes.c_int32), ("pp", ctypes.c_int32),
                 ("ar", ctypes.c_int32), ("s_H", ctypes.c_double), ("s_M", ctypes.c_double),
                 ("C_s", ctypes.c_double), ("C_eta", ctypes.c_double), ("iface_flux", ctypes.c_int32),
-                ("max_halvings", ctypes.c_int32)]
+                ("max_halvings", ctypes.c_int32), ("reduced_2d2v", ctypes.c_int32)]
 
     @staticmethod
     def make(oe_hydro=0, oe_mag=0, pp=0, ar=0, iface_flux=0, max_halvings=10, s_H=0.02, s_M=0.02, C_s=5.0,
-             C_eta=0.2):
-        return Options(oe_hydro, oe_mag, pp, ar, s_H, s_M, C_s, C_eta, iface_flux, max_halvings)
+             C_eta=0.2, reduced_2d2v=0):
+        return Options(oe_hydro, oe_mag, pp, ar, s_H, s_M, C_s, C_eta, iface_flux, max_halvings, reduced_2d2v)
 
     @staticmethod
-    def full():
-        return Options.make(1, 1, 1, 1)
+    def full(reduced_2d2v=0):
+        return Options.make(1, 1, 1, 1, reduced_2d2v=reduced_2d2v)
 
 
 class Report(ctypes.Structure):

@@ -18,7 +18,7 @@ int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, con
 int reset_attempt(mhd25_ctx* c);
 int dcopy(mhd25_ctx* c, const double* a, double* b, long n);
 int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
-                       const double* eta, double* JE);
+                       const double* eta, double* JE, bool r2);
 int mag_update(mhd25_ctx* c, const MagIO& io, int mode);
 int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
                     const double* By, const double* Bz);
@@ -88,7 +88,8 @@ const char* mhd25_last_error(const mhd25_ctx* c) { return c ? c->err.c_str() : "
 int mhd25_set_options(mhd25_ctx* c, const mhd25_options* opt) {
   if (!c || !opt) return -1;
   if (opt->max_halvings < 0 || opt->max_halvings > 60 || opt->s_H < 0 || opt->s_M < 0 || opt->C_s < 0 ||
-      opt->C_eta < 0 || (opt->iface_flux != 0 && opt->iface_flux != 1))
+      opt->C_eta < 0 || (opt->iface_flux != 0 && opt->iface_flux != 1) ||
+      (opt->reduced_2d2v != 0 && opt->reduced_2d2v != 1))
     return fail(c, -1, "invalid options");
   c->opt = *opt;
   return 0;
@@ -259,7 +260,7 @@ int mhd25_hydro_substep(mhd25_ctx* c, double* U, double tau, mhd25_report* rep) 
 int mhd25_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
                          const double* eta, double* JE6) {
   if (!c || !u || !Bx || !By || !Bz || !JE6) return -1;
-  return mag_reconstruct_JE(c, u, Bx, By, Bz, eta, JE6);
+  return mag_reconstruct_JE(c, u, Bx, By, Bz, eta, JE6, false);  // all six grids are returned
 }
 
 int mhd25_rhs_magnetic(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,
@@ -267,7 +268,7 @@ int mhd25_rhs_magnetic(mhd25_ctx* c, const double* rho, const double* u, const d
                        double* dBz) {
   if (!c || !rho || !u || !Bx || !By || !Bz || !de || !du || !dBx || !dBy || !dBz) return -1;
   const long G = c->G;
-  TRY(mag_reconstruct_JE(c, u, Bx, By, Bz, eta, c->JE));
+  TRY(mag_reconstruct_JE(c, u, Bx, By, Bz, eta, c->JE, c->opt.reduced_2d2v != 0));
   MagIO io{};
   io.rho = rho; io.us = u; io.bxs = Bx; io.bys = By; io.bzs = Bz;
   io.jx = c->JE; io.jy = c->JE + G; io.jz = c->JE + 2 * G;
@@ -314,7 +315,7 @@ int mhd25_step_magnetic(mhd25_ctx* c, const double* rho, double* e, double* u, d
     double *oe, *ou, *ox, *oy, *oz;
     if (s < 2) parts(s == 0 ? c->Y1 : c->Y2, &oe, &ou, &ox, &oy, &oz);
     else { oe = e; ou = u; ox = Bx; oy = By; oz = Bz; }
-    TRY(mag_reconstruct_JE(c, su, sx, sy, sz, eta, c->JE));
+    TRY(mag_reconstruct_JE(c, su, sx, sy, sz, eta, c->JE, c->opt.reduced_2d2v != 0));
     MagIO io{};
     io.rho = rho; io.us = su; io.es = se; io.bxs = sx; io.bys = sy; io.bzs = sz;
     io.un = u; io.en = e; io.bxn = Bx; io.byn = By; io.bzn = Bz;

@@ -33,7 +33,8 @@ __device__ __forceinline__ long gix(const MeshP& mp, int B, long ex, long ey, in
   return gy * NX + gx;
 }
 
-template <int P, int M>
+// R2: the 2D2V reduced system (u_z = B_z = 0, in-plane E and J identically zero); B_z is not read
+template <int P, int M, bool R2 = false>
 __device__ __forceinline__ void load_B(double* bx, double* by, double* bz, const double* __restrict__ Bx,
                                        const double* __restrict__ By, const double* __restrict__ Bz, const MeshP& mp,
                                        long ex, long ey, int t) {
@@ -42,14 +43,15 @@ __device__ __forceinline__ void load_B(double* bx, double* by, double* bz, const
     bx[k] = Bx[gix(mp, C::B, ex, ey, k % C::A, k / C::A)];  // [j<B][i<A]
     by[k] = By[gix(mp, C::B, ex, ey, k % C::B, k / C::B)];  // [j<A][i<B]
   }
-  for (int k = t; k < C::BB; k += C::NT) bz[k] = Bz[gix(mp, C::B, ex, ey, k % C::B, k / C::B)];
+  if constexpr (!R2)
+    for (int k = t; k < C::BB; k += C::NT) bz[k] = Bz[gix(mp, C::B, ex, ey, k % C::B, k / C::B)];
 }
 
 // ---------------------------------------------------------------------------------------------
 // Current loads (eq. mag-current-proj): W part int B_x d_y phi - B_y d_x phi with the (m+2)-point
 // Gauss rule; N parts int B_z (-d_y psi) and int B_z d_x psi with the (m+1)-point rule.
 // ---------------------------------------------------------------------------------------------
-template <int P, int M, int BS>
+template <int P, int M, int BS, bool R2>
 __global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, const double* __restrict__ By,
                                                  const double* __restrict__ Bz, double* __restrict__ Lx,
                                                  double* __restrict__ Ly, double* __restrict__ Lz,
@@ -73,7 +75,7 @@ __global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, c
   for (int k = tid; k < B * A; k += BS) tDWG[k / A][k % A] = T->D_W_G[k / A][k % A];
   if (tid < A) twq[tid] = T->wq[tid];
   if (tid < B) twg[tid] = T->wg[tid];
-  if (act) load_B<P, M>(sbx[el], sby[el], sbz[el], Bx, By, Bz, mp, ex, ey, t);
+  if (act) load_B<P, M, R2>(sbx[el], sby[el], sbz[el], Bx, By, Bz, mp, ex, ey, t);
   __syncthreads();
   if (act && t < AA) {
     const int qx = t % A, qy = t / A;
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, c
     swx[el][t] = wgt * bxq;
     swy[el][t] = wgt * byq;
   }
-  if (act && t < BB) {
+  if (!R2 && act && t < BB) {  // B_z at the Gauss nodes (the N loads; none in the 2D2V system)
     const int gx = t % B, gy = t / B;
     double v = 0.0;
 #pragma unroll
@@ -133,7 +135,7 @@ __global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, c
     }
     Lz[e * AA + t] = (2.0 / mp.hy) * sx - (2.0 / mp.hx) * sy;
   }
-  if (t < AB) {
+  if (!R2 && t < AB) {
     {  // N_x node: i Gauss (B), j GLL (A); index j*B + i
       const int i = t % B, j = t / B;
       double s = 0.0;
@@ -155,7 +157,7 @@ __global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, c
 // Electric-field loads (eq. mag-electric-proj): w_a (-u x B)|_K at the element's own auxiliary
 // nodes, plus eta_K sum_q M_q J(x_q) . phi_a(x_q) by the degree-p GLL rule.
 // ---------------------------------------------------------------------------------------------
-template <int P, int M, int BS>
+template <int P, int M, int BS, bool R2>
 __global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, const double* __restrict__ Bx,
                                                  const double* __restrict__ By, const double* __restrict__ Bz,
                                                  const double* __restrict__ Jx, const double* __restrict__ Jy,
@@ -191,23 +193,27 @@ __global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, co
   if (tid < NP) twp[tid] = T->wp[tid];
   if (tid < A) tww[tid] = T->ww[tid];
   if (tid < B) twg[tid] = T->wg[tid];
+  constexpr int NU = R2 ? 2 : 3;  // velocity components carried (u_z = 0 in the 2D2V system)
   if (act) {
     for (int k = t; k < NN; k += NT)
-      for (int d = 0; d < 3; ++d) su[el][d][k] = u[d * KN + e * NN + k];
-    load_B<P, M>(sbx[el], sby[el], sbz[el], Bx, By, Bz, mp, ex, ey, t);
+      for (int d = 0; d < NU; ++d) su[el][d][k] = u[d * KN + e * NN + k];
+    load_B<P, M, R2>(sbx[el], sby[el], sbz[el], Bx, By, Bz, mp, ex, ey, t);
     if (et != 0.0) {
-      for (int k = t; k < AB; k += NT) {
-        sjx[el][k] = Jx[gix(mp, B, ex, ey, k % B, k / B)];
-        sjy[el][k] = Jy[gix(mp, B, ex, ey, k % A, k / A)];
-      }
+      if constexpr (!R2)
+        for (int k = t; k < AB; k += NT) {
+          sjx[el][k] = Jx[gix(mp, B, ex, ey, k % B, k / B)];
+          sjy[el][k] = Jy[gix(mp, B, ex, ey, k % A, k / A)];
+        }
       for (int k = t; k < AA; k += NT) sjz[el][k] = Jz[gix(mp, B, ex, ey, k % A, k / A)];
     }
   }
   __syncthreads();
   if (act) {
     // first half of the sum factorisation of u at the auxiliary nodes: interpolate in x
-    for (int tk = t; tk < 3 * NP * (A + B); tk += NT) {
-      const int d = tk / (NP * (A + B)), rem = tk - d * NP * (A + B), qj = rem / (A + B), x = rem - qj * (A + B);
+    // (the 2D2V system needs u_x, u_y at the W nodes only: x < A)
+    constexpr int NX = R2 ? A : A + B;
+    for (int tk = t; tk < NU * NP * NX; tk += NT) {
+      const int d = tk / (NP * NX), rem = tk - d * NP * NX, qj = rem / NX, x = rem - qj * NX;
       const double* I = x < A ? tPW[x] : tPG[x - A];
       double v = 0.0;
 #pragma unroll
@@ -218,19 +224,21 @@ __global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, co
   if (act && et != 0.0 && t < NN) {
     const int qi = t % NP, qj = t / NP;
     double jx = 0.0, jy = 0.0, jz = 0.0;
+    if constexpr (!R2) {
 #pragma unroll
-    for (int j = 0; j < A; ++j) {
-      double s = 0.0;
+      for (int j = 0; j < A; ++j) {
+        double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += tGP[qi][i] * sjx[el][j * B + i];
-      jx += tWP[qj][j] * s;
-    }
+        for (int i = 0; i < B; ++i) s += tGP[qi][i] * sjx[el][j * B + i];
+        jx += tWP[qj][j] * s;
+      }
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      double s = 0.0;
+      for (int j = 0; j < B; ++j) {
+        double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sjy[el][j * A + i];
-      jy += tGP[qj][j] * s;
+        for (int i = 0; i < A; ++i) s += tWP[qi][i] * sjy[el][j * A + i];
+        jy += tGP[qj][j] * s;
+      }
     }
 #pragma unroll
     for (int j = 0; j < A; ++j) {
@@ -272,7 +280,7 @@ __global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, co
     if (et != 0.0) s += eta_term(2, T->I_W_P, i, T->I_W_P, j);
     Lz[e * AA + t] = s;
   }
-  if (t < AB) {
+  if (!R2 && t < AB) {
     {  // N_x node (xg[i], xw[j]): x-component; B_y lives on these nodes
       const int i = t % B, j = t / B;
       const double uy = u_at(1, tPW[j], A + i), uz = u_at(2, tPW[j], A + i);
@@ -313,7 +321,7 @@ __global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, co
 // MODE 0: write L_M.  MODE 1: write the SSP stage ca*Y^n + cb*(Y_s + tau*L_M(Y_s)).
 // ---------------------------------------------------------------------------------------------
 
-template <int P, int M, int MODE, int BS>
+template <int P, int M, int MODE, int BS, bool R2>
 __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __restrict__ T, MeshP mp) {
   using C = MC<P, M, BS>;
   constexpr int NP = C::NP, NN = C::NN, A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB,
@@ -352,20 +360,21 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
     et = io.eta ? io.eta[e] : 0.0;
     if (MODE == 1) {
 #pragma unroll
-      for (int d = 0; d < 3; ++d) { yn[d] = io.un[d * KN + n]; ys[d] = io.us[d * KN + n]; }
+      for (int d = 0; d < (R2 ? 2 : 3); ++d) { yn[d] = io.un[d * KN + n]; ys[d] = io.us[d * KN + n]; }
       yn[3] = io.en[n]; ys[3] = io.es[n];
     }
   }
   if (act && t < BB) {
     gown = gix(mp, B, ex, ey, t % B, t / B);
     if (MODE == 1) {
-      bn[0] = io.bxn[gown]; bn[1] = io.byn[gown]; bn[2] = io.bzn[gown];
-      bs[0] = io.bxs[gown]; bs[1] = io.bys[gown]; bs[2] = io.bzs[gown];
+      bn[0] = io.bxn[gown]; bn[1] = io.byn[gown];
+      bs[0] = io.bxs[gown]; bs[1] = io.bys[gown];
+      if (!R2) { bn[2] = io.bzn[gown]; bs[2] = io.bzs[gown]; }
     }
   }
   if (act) {
-    load_B<P, M>(sbx[el], sby[el], sbz[el], io.bxs, io.bys, io.bzs, mp, ex, ey, t);
-    for (int k = t; k < AB; k += NT) {
+    load_B<P, M, R2>(sbx[el], sby[el], sbz[el], io.bxs, io.bys, io.bzs, mp, ex, ey, t);
+    for (int k = t; !R2 && k < AB; k += NT) {  // in-plane E and J (none in the 2D2V system)
       const long gN_x = gix(mp, B, ex, ey, k % B, k / B), gN_y = gix(mp, B, ex, ey, k % A, k / A);
       sex[el][k] = io.ex[gN_x]; sjx[el][k] = io.jx[gN_x];
       sey[el][k] = io.ey[gN_y]; sjy[el][k] = io.jy[gN_y];
@@ -388,6 +397,7 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
     dbx *= -(2.0 / mp.hy);
     dby *= (2.0 / mp.hx);
     double dxey = 0.0, dyex = 0.0;
+    if constexpr (!R2) {
 #pragma unroll
     for (int l = 0; l < B; ++l) {
       double s = 0.0;
@@ -402,13 +412,14 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
       for (int k = 0; k < B; ++k) s += tIGV[i][k] * sex[el][l * B + k];
       dyex += tDWV[j][l] * s;
     }
-    const double dbz = -((2.0 / mp.hx) * dxey - (2.0 / mp.hy) * dyex);
+    }
+    const double dbz = R2 ? 0.0 : -((2.0 / mp.hx) * dxey - (2.0 / mp.hy) * dyex);
     if (MODE == 0) {
       io.obx[g] = dbx; io.oby[g] = dby; io.obz[g] = dbz;
     } else {
       io.obx[g] = io.ca * bn[0] + io.cb * (bs[0] + io.tau * dbx);
       io.oby[g] = io.ca * bn[1] + io.cb * (bs[1] + io.tau * dby);
-      io.obz[g] = io.ca * bn[2] + io.cb * (bs[2] + io.tau * dbz);
+      io.obz[g] = R2 ? 0.0 : io.ca * bn[2] + io.cb * (bs[2] + io.tau * dbz);
     }
   }
   // weighted Lorentz loads f_a at the auxiliary nodes (transpose of the coupling form)
@@ -424,7 +435,7 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
     fz[el][0][t] = -byv * w;  // x
     fz[el][1][t] = bxv * w;   // y
   }
-  if (act && t < AB) {
+  if (!R2 && act && t < AB) {
     {
       const int i = t % B, j = t / B;  // N_x node: (0, -B_z J_x, B_y J_x)
       double bzv = 0.0;
@@ -469,11 +480,13 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
         s0 += I * fz[el][0][j * A + i];
         s1 += I * fz[el][1][j * A + i];
       }
+      if constexpr (!R2) {
 #pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const double I = tIPG[i][qi];
-        t1 += I * fx[el][0][j * B + i];
-        t2 += I * fx[el][1][j * B + i];
+        for (int i = 0; i < B; ++i) {
+          const double I = tIPG[i][qi];
+          t1 += I * fx[el][0][j * B + i];
+          t2 += I * fx[el][1][j * B + i];
+        }
       }
       const double Iy = tIPW[j][qj];
       du[0] += Iy * s0;
@@ -481,7 +494,7 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
       du[2] += Iy * t2;
     }
 #pragma unroll 1
-    for (int j = 0; j < B; ++j) {
+    for (int j = 0; !R2 && j < B; ++j) {
       double s0 = 0.0, s2 = 0.0;
 #pragma unroll
       for (int i = 0; i < A; ++i) {
@@ -498,19 +511,21 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
     double de = 0.0;
     if (et != 0.0) {
       double jx = 0.0, jy = 0.0, jz = 0.0;
+      if constexpr (!R2) {
 #pragma unroll
-      for (int j = 0; j < A; ++j) {
-        double s = 0.0;
+        for (int j = 0; j < A; ++j) {
+          double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < B; ++i) s += tIGP[qi][i] * sjx[el][j * B + i];
-        jx += tIWP[qj][j] * s;
-      }
+          for (int i = 0; i < B; ++i) s += tIGP[qi][i] * sjx[el][j * B + i];
+          jx += tIWP[qj][j] * s;
+        }
 #pragma unroll
-      for (int j = 0; j < B; ++j) {
-        double s = 0.0;
+        for (int j = 0; j < B; ++j) {
+          double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < A; ++i) s += tIWP[qi][i] * sjy[el][j * A + i];
-        jy += tIGP[qj][j] * s;
+          for (int i = 0; i < A; ++i) s += tIWP[qi][i] * sjy[el][j * A + i];
+          jy += tIGP[qj][j] * s;
+        }
       }
 #pragma unroll
       for (int j = 0; j < A; ++j) {
@@ -521,13 +536,14 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
       }
       de = et * (jx * jx + jy * jy + jz * jz) / rq;
     }
+    // (the 2D2V system writes u_z = 0, so that no stage buffer carries a stale value)
     if (MODE == 0) {
-      for (int d = 0; d < 3; ++d) io.ou[d * KN + n] = du[d] / (rq * Mq);
+      for (int d = 0; d < 3; ++d) io.ou[d * KN + n] = (R2 && d == 2) ? 0.0 : du[d] / (rq * Mq);
       io.oe[n] = de;
     } else {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double v = io.ca * yn[d] + io.cb * (ys[d] + io.tau * (du[d] / (rq * Mq)));
+        const double v = (R2 && d == 2) ? 0.0 : io.ca * yn[d] + io.cb * (ys[d] + io.tau * (du[d] / (rq * Mq)));
         io.ou[d * KN + n] = v;
         snew[el][d][t] = v;
       }
@@ -538,7 +554,8 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
     // element statistics of the new velocity (GLL-weighted sum, min, max), as the velocity-OE
     // sensor needs them
     __syncthreads();
-    for (int tk = t; act && tk < 9; tk += NT) {
+    constexpr int NU = R2 ? 2 : 3;  // statistics [K][NU][3] of the carried components
+    for (int tk = t; act && tk < 3 * NU; tk += NT) {
       const int c = tk / 3, kind = tk - 3 * c;
       double sm = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
       for (int k = 0; k < NN; ++k) {
@@ -546,7 +563,7 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
         sm += (twp[k % NP] * twp[k / NP]) * v;
         mn = fmin(mn, v); mx = fmax(mx, v);
       }
-      io.ustats[(e * 3 + c) * 3 + kind] = kind == 0 ? sm : (kind == 1 ? mn : mx);
+      io.ustats[(e * NU + c) * 3 + kind] = kind == 0 ? sm : (kind == 1 ? mn : mx);
     }
   }
 }
@@ -721,7 +738,7 @@ struct VS {
 // thread per GLL_p node, EB elements per block; writes the element's damping factors D_l
 // (l = 0..p) to Dfac[K][p+1].  Neighbour velocities are staged per direction in LDS with coalesced
 // loads.  u is only read here (the projection kernel that updates it runs afterwards).
-template <int P, int M>
+template <int P, int M, bool R2>
 __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ rho, const double* __restrict__ u,
                                                     const double* __restrict__ Bx, const double* __restrict__ By,
                                                     const double* __restrict__ Bz, const double* __restrict__ lines,
@@ -735,6 +752,7 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
   __shared__ int scst[EB][3];
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][C::BB];
   __shared__ double tD0[NP][NP], tDp[NP][NP], tWP[NP][A], tGP[NP][B], tVP[NP][B], tw[NP], tfr[NP];
+  constexpr int NU = R2 ? 2 : 3;  // velocity components (u_z = 0 in the 2D2V system)
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
   const int qi = q % NP, qj = q / NP;
   const long e = xcd_block() * EB + el;
@@ -755,23 +773,23 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
   double uu[3] = {0.0, 0.0, 0.0}, rq = 1.0;
   if (act) {
 #pragma unroll
-    for (int d = 0; d < 3; ++d) { uu[d] = u[d * KN + e * NN + q]; su[el][d][q] = uu[d]; }
+    for (int d = 0; d < NU; ++d) { uu[d] = u[d * KN + e * NN + q]; su[el][d][q] = uu[d]; }
     rq = rho[e * NN + q];
     for (int k = q; k < AB; k += NN) {
       sbx[el][k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];
       sby[el][k] = By[gix(mp, B, ex, ey, k % B, k / B)];
     }
-    for (int k = q; k < C::BB; k += NN) sbz[el][k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
+    for (int k = q; !R2 && k < C::BB; k += NN) sbz[el][k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
   }
   __syncthreads();
   // shared amplitudes: each component's global and cross-line spreads formed once per element
-  for (int c = q; act && c < 3; c += NN) {
+  for (int c = q; act && c < NU; c += NN) {
     const double gs = glob[c * 3], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
     const double gm = gs * mp.r4K;
     const double dOm = fmax(gmx - gm, gm - gmn);
     scst[el][c] = dOm <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn)) ? 1 : 0;
-    const double* rl = lines + (ey * 3 + c) * 3;
-    const double* cl = lines + ((mp.ny + ex) * 3 + c) * 3;
+    const double* rl = lines + (ey * NU + c) * 3;
+    const double* cl = lines + ((mp.ny + ex) * NU + c) * 3;
     const double rm = rl[0] * mp.r4nx, cm = cl[0] * mp.r4ny;
     samp[el][0][c] = fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm);
     samp[el][1][c] = fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm);
@@ -793,7 +811,7 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
       byv += tWP[qj][j] * s;
     }
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
+    for (int j = 0; !R2 && j < B; ++j) {
       double s = 0.0;
 #pragma unroll
       for (int i = 0; i < B; ++i) s += tVP[qi][i] * sbz[el][j * B + i];
@@ -811,7 +829,7 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
       if (D == 0) { em = ey * mp.nx + wrapl(ex - 1, mp.nx); ep = ey * mp.nx + wrapl(ex + 1, mp.nx); }
       else { em = wrapl(ey - 1, mp.ny) * mp.nx + ex; ep = wrapl(ey + 1, mp.ny) * mp.nx + ex; }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < NU; ++c) {
         sx[el][c][q] = u[c * KN + em * NN + q];
         sx[el][3 + c][q] = u[c * KN + ep * NN + q];
       }
@@ -822,7 +840,7 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
     if (act) {
       const double wl = 0.5 * tw[line];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < NU; ++c) {
         double a = 0.0, d = 0.0, b = 0.0, cc = 0.0;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
@@ -841,15 +859,15 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
     __syncthreads();
     if (act) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) sx[el][c][q] = jmp[c];
+      for (int c = 0; c < 2 * NU; ++c) sx[el][c][q] = jmp[c];
     }
     __syncthreads();
     // sigma^u: the (r, component) terms spread over the element's threads, then max over components
     {
       double Dsh = 0.0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) Dsh = act ? fmax(Dsh, samp[el][D][c]) : 0.0;
-      for (int tk = q; act && tk < 3 * NP; tk += NN) {
+      for (int c = 0; c < NU; ++c) Dsh = act ? fmax(Dsh, samp[el][D][c]) : 0.0;
+      for (int tk = q; act && tk < NU * NP; tk += NN) {
         const int rr = tk % NP, c = tk / NP;
         double v = 0.0;
         if (Dsh > 0.0 && !scst[el][c]) {
@@ -876,7 +894,7 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
     if (act && q < NP) {
       double sig = 0.0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) sig = fmax(sig, ssg[el][c][q]);
+      for (int c = 0; c < NU; ++c) sig = fmax(sig, ssg[el][c][q]);
       ssig[el][D][q] = sig;
     }
     __syncthreads();
@@ -907,7 +925,7 @@ struct VPJ {
   static constexpr long PS = psi_stride(NN), RS = psi_row(NN);
 };
 
-template <int P, int BS>
+template <int P, int BS, bool R2>
 __global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho, double* __restrict__ u,
                                                   double* __restrict__ en, const double* __restrict__ Psi,
                                                   const double* __restrict__ Dfac, const HydroTab* __restrict__ H,
@@ -948,7 +966,7 @@ __global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho,
   if (act) {
     const double wq = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) sv[el][d][q] = wq * u[d * KN + e * NN + q];
+    for (int d = 0; d < (R2 ? 2 : 3); ++d) sv[el][d][q] = wq * u[d * KN + e * NN + q];  // u_z = 0 in 2D2V
     if (q < NP) sD[el][q] = Dfac[e * NP + q];
   }
   __syncthreads();
@@ -960,7 +978,7 @@ __global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho,
       const double pn = Pe[n * NNP + q];
       s0 += sv[el][0][n] * pn;
       s1 += sv[el][1][n] * pn;
-      s2 += sv[el][2][n] * pn;
+      if (!R2) s2 += sv[el][2][n] * pn;
     }
     sc[el][0][q] = s0; sc[el][1][q] = s1; sc[el][2][q] = s2;
   }
@@ -976,11 +994,11 @@ __global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho,
     const double pk = Pe[q * NNP + k];
     wl[0][shell_of(k)] += sc[el][0][k] * pk;
     wl[1][shell_of(k)] += sc[el][1][k] * pk;
-    wl[2][shell_of(k)] += sc[el][2][k] * pk;
+    if (!R2) wl[2][shell_of(k)] += sc[el][2][k] * pk;
   }
   double heat = 0.0;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
+  for (int d = 0; d < (R2 ? 2 : 3); ++d) {
     double v = wl[d][0];
 #pragma unroll
     for (int l = 1; l < NP; ++l) {
@@ -1178,7 +1196,7 @@ __global__ __launch_bounds__(256) void k_B_stats(const double* __restrict__ Bx, 
 }  // namespace
 
 // gather of per-element loads at shared nodes and division by the lumped weights
-template <int M>
+template <int M, bool R2>
 __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ Lx, const double* __restrict__ Ly,
                                                 const double* __restrict__ Lz, double* __restrict__ Ox,
                                                 double* __restrict__ Oy, double* __restrict__ Oz,
@@ -1200,6 +1218,7 @@ __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ Lx, c
     if (i == 0 && j == 0) { s += Lz[eLD * AA + (A - 1) * A + (A - 1)]; w += T->ww[A - 1] * T->ww[A - 1]; }
     Oz[g] = s / (mp.J * w);
   }
+  if (R2) return;  // the 2D2V system has no in-plane J or E
   {  // N_x node: Gauss in x (i), GLL in y (j); local index j*B + i
     double s = Lx[e * AB + j * B + i], w = T->wg[i] * T->ww[j];
     if (j == 0) { s += Lx[eD * AB + (A - 1) * B + i]; w += T->wg[i] * T->ww[A - 1]; }
@@ -1299,8 +1318,9 @@ static long mblocks(int p, int m, long K, int bs = 256) {
 #define MHD_VP_BS 128
 #endif
 
+// r2: the 2D2V reduced system (only J_z and E_z are formed; the in-plane grids are not written)
 int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
-                       const double* eta, double* JE) {
+                       const double* eta, double* JE, bool r2) {
   const long K = c->mp.K, G = c->G;
   const int a = c->m + 2, b = c->m + 1;
   double* Lx = c->loads;
@@ -1308,19 +1328,32 @@ int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const do
   double* Lz = Ly + K * a * b;
   const long nbj = mblocks(c->p, c->m, K, MHD_JL_BS), nbe = mblocks(c->p, c->m, K, MHD_EL_BS);
   const long gb = (G + 255) / 256;
-#define LJ(P, M) hipLaunchKernelGGL((k_J_loads<P, M, MHD_JL_BS>), dim3(nbj), dim3(MHD_JL_BS), 0, c->stream, Bx, By, Bz, \
-                                    Lx, Ly, Lz, c->d_mt, c->mp)
+#define LJ(P, M)                                                                                                    \
+  if (r2) hipLaunchKernelGGL((k_J_loads<P, M, MHD_JL_BS, true>), dim3(nbj), dim3(MHD_JL_BS), 0, c->stream, Bx, By, \
+                             Bz, Lx, Ly, Lz, c->d_mt, c->mp);                                                       \
+  else hipLaunchKernelGGL((k_J_loads<P, M, MHD_JL_BS, false>), dim3(nbj), dim3(MHD_JL_BS), 0, c->stream, Bx, By, Bz, \
+                          Lx, Ly, Lz, c->d_mt, c->mp)
   DISPATCH_PM(c->p, c->m, LJ);
 #undef LJ
-#define GJ(M) hipLaunchKernelGGL((k_gather<M>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE, JE + G, JE + 2 * G, c->d_mt, c->mp)
+#define GJ(M)                                                                                                       \
+  if (r2) hipLaunchKernelGGL((k_gather<M, true>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE, JE + G,       \
+                             JE + 2 * G, c->d_mt, c->mp);                                                           \
+  else hipLaunchKernelGGL((k_gather<M, false>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE, JE + G,         \
+                          JE + 2 * G, c->d_mt, c->mp)
   DISPATCH_M(c->m, GJ);
 #undef GJ
-#define LE(P, M) hipLaunchKernelGGL((k_E_loads<P, M, MHD_EL_BS>), dim3(nbe), dim3(MHD_EL_BS), 0, c->stream, u, Bx, By, \
-                                    Bz, JE, JE + G, JE + 2 * G, eta, Lx, Ly, Lz, c->d_mt, c->mp)
+#define LE(P, M)                                                                                                    \
+  if (r2) hipLaunchKernelGGL((k_E_loads<P, M, MHD_EL_BS, true>), dim3(nbe), dim3(MHD_EL_BS), 0, c->stream, u, Bx,  \
+                             By, Bz, JE, JE + G, JE + 2 * G, eta, Lx, Ly, Lz, c->d_mt, c->mp);                      \
+  else hipLaunchKernelGGL((k_E_loads<P, M, MHD_EL_BS, false>), dim3(nbe), dim3(MHD_EL_BS), 0, c->stream, u, Bx, By, \
+                          Bz, JE, JE + G, JE + 2 * G, eta, Lx, Ly, Lz, c->d_mt, c->mp)
   DISPATCH_PM(c->p, c->m, LE);
 #undef LE
-#define GE(M) hipLaunchKernelGGL((k_gather<M>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE + 3 * G, JE + 4 * G, \
-                                 JE + 5 * G, c->d_mt, c->mp)
+#define GE(M)                                                                                                       \
+  if (r2) hipLaunchKernelGGL((k_gather<M, true>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE + 3 * G,       \
+                             JE + 4 * G, JE + 5 * G, c->d_mt, c->mp);                                               \
+  else hipLaunchKernelGGL((k_gather<M, false>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE + 3 * G,         \
+                          JE + 4 * G, JE + 5 * G, c->d_mt, c->mp)
   DISPATCH_M(c->m, GE);
 #undef GE
   return chk(c, "reconstruct launch");
@@ -1328,17 +1361,24 @@ int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const do
 
 int mag_update(mhd25_ctx* c, const MagIO& io, int mode) {
   const long nb = mblocks(c->p, c->m, c->mp.K, MHD_MU_BS);
+  const bool r2 = c->opt.reduced_2d2v != 0;
+#define U0(P, M)                                                                                                    \
+  if (r2) hipLaunchKernelGGL((k_mag_update<P, M, 0, MHD_MU_BS, true>), dim3(nb), dim3(MHD_MU_BS), 0, c->stream, io, \
+                             c->d_mt, c->mp);                                                                        \
+  else hipLaunchKernelGGL((k_mag_update<P, M, 0, MHD_MU_BS, false>), dim3(nb), dim3(MHD_MU_BS), 0, c->stream, io,   \
+                          c->d_mt, c->mp)
+#define U1(P, M)                                                                                                    \
+  if (r2) hipLaunchKernelGGL((k_mag_update<P, M, 1, MHD_MU_BS, true>), dim3(nb), dim3(MHD_MU_BS), 0, c->stream, io, \
+                             c->d_mt, c->mp);                                                                        \
+  else hipLaunchKernelGGL((k_mag_update<P, M, 1, MHD_MU_BS, false>), dim3(nb), dim3(MHD_MU_BS), 0, c->stream, io,   \
+                          c->d_mt, c->mp)
   if (mode == 0) {
-#define U0(P, M) hipLaunchKernelGGL((k_mag_update<P, M, 0, MHD_MU_BS>), dim3(nb), dim3(MHD_MU_BS), 0, c->stream, io, \
-                                    c->d_mt, c->mp)
     DISPATCH_PM(c->p, c->m, U0);
-#undef U0
   } else {
-#define U1(P, M) hipLaunchKernelGGL((k_mag_update<P, M, 1, MHD_MU_BS>), dim3(nb), dim3(MHD_MU_BS), 0, c->stream, io, \
-                                    c->d_mt, c->mp)
     DISPATCH_PM(c->p, c->m, U1);
-#undef U1
   }
+#undef U0
+#undef U1
   return chk(c, "magnetic update launch");
 }
 
@@ -1355,25 +1395,34 @@ int mag_velocity_prep(mhd25_ctx* c, const double* rho) {
   return chk(c, "velocity OE prep launch");
 }
 
-// apply with the basis prepared for the current rho: line statistics of u, sensor, projection
 int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
                        const double* By, const double* Bz, bool stats_ready) {
   const long K = c->mp.K;
   const int nn = (c->p + 1) * (c->p + 1), eb = 256 / nn, eb2 = MHD_VP_BS / nn;
   const long nb = (K + eb - 1) / eb, nb2 = (K + eb2 - 1) / eb2;
+  const bool r2 = c->opt.reduced_2d2v != 0;
+  const int nu = r2 ? 2 : 3;  // velocity components carried
   if (!stats_ready) {
-#define FS(P) hipLaunchKernelGGL((k_field_stats<P, 3>), dim3(nb), dim3(256), 0, c->stream, u, c->stats, c->d_mt, c->mp)
+#define FS(P)                                                                                                       \
+  if (r2) hipLaunchKernelGGL((k_field_stats<P, 2>), dim3(nb), dim3(256), 0, c->stream, u, c->stats, c->d_mt, c->mp); \
+  else hipLaunchKernelGGL((k_field_stats<P, 3>), dim3(nb), dim3(256), 0, c->stream, u, c->stats, c->d_mt, c->mp)
     switch (c->p) { case 1: FS(1); break; case 2: FS(2); break; case 3: FS(3); break; case 4: FS(4); break;
                     case 5: FS(5); break; case 6: FS(6); break; default: return -4; }
 #undef FS
   }
-  line_global_reduce(c, c->stats, 3, nullptr);
-#define VSN(P, M) hipLaunchKernelGGL((k_vel_sensor<P, M>), dim3(nb), dim3(256), 0, c->stream, rho, u, Bx, By, Bz, c->lines, \
-                                     c->glob, c->dfac, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M)
+  line_global_reduce(c, c->stats, nu, nullptr);
+#define VSN(P, M)                                                                                                   \
+  if (r2) hipLaunchKernelGGL((k_vel_sensor<P, M, true>), dim3(nb), dim3(256), 0, c->stream, rho, u, Bx, By, Bz,    \
+                             c->lines, c->glob, c->dfac, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M);                 \
+  else hipLaunchKernelGGL((k_vel_sensor<P, M, false>), dim3(nb), dim3(256), 0, c->stream, rho, u, Bx, By, Bz,      \
+                          c->lines, c->glob, c->dfac, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M)
   DISPATCH_PM(c->p, c->m, VSN);
 #undef VSN
-#define VPR(P) hipLaunchKernelGGL((k_vel_proj<P, MHD_VP_BS>), dim3(nb2), dim3(MHD_VP_BS), 0, c->stream, rho, u, e, c->psi, \
-                                  c->dfac, c->d_ht, c->mp)
+#define VPR(P)                                                                                                      \
+  if (r2) hipLaunchKernelGGL((k_vel_proj<P, MHD_VP_BS, true>), dim3(nb2), dim3(MHD_VP_BS), 0, c->stream, rho, u, e, \
+                             c->psi, c->dfac, c->d_ht, c->mp);                                                        \
+  else hipLaunchKernelGGL((k_vel_proj<P, MHD_VP_BS, false>), dim3(nb2), dim3(MHD_VP_BS), 0, c->stream, rho, u, e,   \
+                          c->psi, c->dfac, c->d_ht, c->mp)
   switch (c->p) { case 1: VPR(1); break; case 2: VPR(2); break; case 3: VPR(3); break; case 4: VPR(4); break;
                   case 5: VPR(5); break; case 6: VPR(6); break; default: return -4; }
 #undef VPR

@@ -830,7 +830,7 @@ __global__ void k_scatter_bz(const double* __restrict__ BL, long stride, long of
                case 4: F(4); break; case 5: F(5); break; case 6: F(6); break; default: return -4; }
 
 int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
-                       const double* eta, double* JE);
+                       const double* eta, double* JE, bool r2);
 
 static int vchk(mhd25_ctx* c, const char* what) {
   hipError_t e = hipGetLastError();
@@ -869,7 +869,7 @@ extern "C" int mhd25_rhs_magnetic_vjp(mhd25_ctx* c, const double* rho, const dou
   double* Ebar = BL + K * bloc;  // 3G
   double* Jbar = Ebar + 3 * G;   // 3G
   // forward recomputation of J and E
-  int r = mag_reconstruct_JE(c, u, Bx, By, Bz, eta, c->JE);
+  int r = mag_reconstruct_JE(c, u, Bx, By, Bz, eta, c->JE, false);  // the VJP reads every grid
   if (r) return r;
   int nn = (c->p + 1) * (c->p + 1), aa = a * a;
   const int eb = 256 / (nn > aa ? nn : aa);

@@ -193,9 +193,8 @@ def stab(ar):
 
 
 def test_orszag_tang_paper_scalars():
-    """Orszag-Tang, p = m = 2, 256^2, t = 3, OE and positivity on, without and with A.R.
-    (readings: s_H = s_M = 0.02 as in the stabilized vortex runs, CFL 0.3, extrema at the
-    velocity nodes).  Density maxima within 0.2 % of the printed ones; the extremes of rho, p_m
+    """Orszag-Tang, p = m = 2, 256^2, t = 3, OE (s_H = s_M = 0.02) and positivity on, without and
+    with A.R. (readings: CFL 0.3, extrema at the velocity nodes).  Density maxima within 0.2 % of the printed ones; the extremes of rho, p_m
     and Mach number over both runs within 1 %, 2 % and 2 % of the common contour ranges; the
     divergence norm stays at its initial round-off level, below 3x the printed value."""
     from tests._fe_fields import B_at, primitives
@@ -220,7 +219,7 @@ def test_orszag_tang_paper_scalars():
 
 
 def test_oblique_blast_paper_scalars():
-    """Oblique blast, 256^2, t = 0.2 (readings: p = m = 2, CFL 0.3, OE and positivity on, maxima
+    """Oblique blast, p = m = 2, 256^2, t = 0.2, OE and positivity on (readings: CFL 0.3, maxima
     at the velocity nodes): magnetic-pressure maxima within 3 % of 2.25 (no A.R.) and 1.77
     (A.R.), the final-step A.R. maximum within 5 % of 3.18e-4, divergence norm below 3x the
     printed one."""
@@ -239,7 +238,7 @@ def test_oblique_blast_paper_scalars():
 
 
 def test_field_loop_paper_scalars():
-    """Field loop, 256 x 128, CFL 0.8, t = 1 (reading: p = m = 2, OE and positivity on, the
+    """Field loop, p = m = 2, 256 x 128, CFL 0.8, t = 1, OE and positivity on (readings: the
     maximum at the velocity nodes, e_B^tr by an 8-point Gauss rule per direction against the
     analytic loop).  With A.R.: maximum |B| within 1 %, retained magnetic energy within 0.5 %,
     e_B^tr within 2 % of the printed values.  Without A.R.: maximum |B| within 2 %, energy within
