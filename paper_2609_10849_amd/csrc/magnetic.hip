@@ -318,18 +318,26 @@ __global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, co
 
 // ---------------------------------------------------------------------------------------------
 // Curl update, Lorentz transpose and Ohmic heating (eq. magnetic-dae with J, E eliminated).
-// MODE 0: write L_M.  MODE 1: write the SSP stage ca*Y^n + cb*(Y_s + tau*L_M(Y_s)).
+// MODE 0: write L_M.  MODE 1: write the SSP stage (ca*Y^n + cb*Y_s) + cb*tau*L_M(Y_s).
 // ---------------------------------------------------------------------------------------------
 
+// (the 2D2V variants up to N = 4 fit 72 VGPRs, i.e. 7 waves per SIMD, without spills; the bound
+// keeps the compiler there)
 template <int P, int M, int MODE, int BS, bool R2>
-__global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __restrict__ T, MeshP mp) {
+__global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update(MagIO io, const MagTab* __restrict__ T, MeshP mp) {
   using C = MC<P, M, BS>;
   constexpr int NP = C::NP, NN = C::NN, A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB,
                 NT = C::NT;
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
   __shared__ double sex[EB][AB], sey[EB][AB], sez[EB][AA];
   __shared__ double sjx[EB][AB], sjy[EB][AB], sjz[EB][AA];
-  __shared__ double fz[EB][2][AA], fx[EB][2][AB], fy[EB][2][AB], snew[EB][3][NN];
+  // Lorentz loads at the auxiliary nodes, one buffer per element: fz (W nodes, x and y parts), fx
+  // (N_x nodes, y and z parts), fy (N_y nodes, x and z parts).  After a barrier the new velocities
+  // for the closing element statistics reuse it, which keeps the block's LDS within five blocks
+  // per CU at N = 4.
+  constexpr int NF = 2 * AA + 4 * AB;
+  static_assert(3 * NN <= NF, "the velocity buffer must fit in the Lorentz-load buffer");
+  __shared__ double sf[EB][NF];
   __shared__ double tDWG[B][A], tDWV[B][A], tIGV[B][B], tIGW[A][B], tIVG[B][B], tIVW[A][B], tIPW[A][NP], tIPG[B][NP], tIGP[NP][B], tIWP[NP][A];
   __shared__ double tww[A], twg[B], twp[NP];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
@@ -338,6 +346,9 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
   long ex, ey;
   elem_xy(mp, act ? e : 0, ex, ey);
   const long KN = mp.K * NN;
+  double* const fz = sf[act ? el : 0];
+  double* const fx = fz + 2 * AA;
+  double* const fy = fx + 2 * AB;
   for (int k = tid; k < B * A; k += BS) tDWG[k / A][k % A] = T->D_W_G[k / A][k % A];
   for (int k = tid; k < B * A; k += BS) tDWV[k / A][k % A] = T->D_W_V[k / A][k % A];
   for (int k = tid; k < B * B; k += BS) tIGV[k / B][k % B] = T->I_G_V[k / B][k % B];
@@ -352,7 +363,9 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
   if (tid < B) twg[tid] = T->wg[tid];
   if (tid < NP) twp[tid] = T->wp[tid];
   // values used only at the end are loaded first, so that their latency overlaps the work
-  double rq = 1.0, et = 0.0, yn[5] = {0, 0, 0, 0, 0}, ys[5] = {0, 0, 0, 0, 0}, bn[3] = {0, 0, 0}, bs[3] = {0, 0, 0};
+  // (MODE 1 keeps only y0 = ca*Y^n + cb*Y_s of every value and adds cb*tau*L_M at the end, so
+  // that one register pair per value stays live across the kernel instead of two)
+  double rq = 1.0, et = 0.0, y0[4] = {0, 0, 0, 0}, b0[3] = {0, 0, 0};
   long gown = 0;
   if (act && t < NN) {
     const long n = e * NN + t;
@@ -360,16 +373,16 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
     et = io.eta ? io.eta[e] : 0.0;
     if (MODE == 1) {
 #pragma unroll
-      for (int d = 0; d < (R2 ? 2 : 3); ++d) { yn[d] = io.un[d * KN + n]; ys[d] = io.us[d * KN + n]; }
-      yn[3] = io.en[n]; ys[3] = io.es[n];
+      for (int d = 0; d < (R2 ? 2 : 3); ++d) y0[d] = io.ca * io.un[d * KN + n] + io.cb * io.us[d * KN + n];
+      y0[3] = io.ca * io.en[n] + io.cb * io.es[n];
     }
   }
   if (act && t < BB) {
     gown = gix(mp, B, ex, ey, t % B, t / B);
     if (MODE == 1) {
-      bn[0] = io.bxn[gown]; bn[1] = io.byn[gown];
-      bs[0] = io.bxs[gown]; bs[1] = io.bys[gown];
-      if (!R2) { bn[2] = io.bzn[gown]; bs[2] = io.bzs[gown]; }
+      b0[0] = io.ca * io.bxn[gown] + io.cb * io.bxs[gown];
+      b0[1] = io.ca * io.byn[gown] + io.cb * io.bys[gown];
+      if (!R2) b0[2] = io.ca * io.bzn[gown] + io.cb * io.bzs[gown];
     }
   }
   if (act) {
@@ -417,9 +430,10 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
     if (MODE == 0) {
       io.obx[g] = dbx; io.oby[g] = dby; io.obz[g] = dbz;
     } else {
-      io.obx[g] = io.ca * bn[0] + io.cb * (bs[0] + io.tau * dbx);
-      io.oby[g] = io.ca * bn[1] + io.cb * (bs[1] + io.tau * dby);
-      io.obz[g] = R2 ? 0.0 : io.ca * bn[2] + io.cb * (bs[2] + io.tau * dbz);
+      const double ct = io.cb * io.tau;
+      io.obx[g] = b0[0] + ct * dbx;
+      io.oby[g] = b0[1] + ct * dby;
+      io.obz[g] = R2 ? 0.0 : b0[2] + ct * dbz;
     }
   }
   // weighted Lorentz loads f_a at the auxiliary nodes (transpose of the coupling form)
@@ -432,8 +446,8 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
       byv += tIGW[i][k] * sby[el][j * B + k];
     }
     const double w = mp.J * tww[i] * tww[j] * sjz[el][t];
-    fz[el][0][t] = -byv * w;  // x
-    fz[el][1][t] = bxv * w;   // y
+    fz[t] = -byv * w;      // x
+    fz[AA + t] = bxv * w;  // y
   }
   if (!R2 && act && t < AB) {
     {
@@ -447,8 +461,8 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
         bzv += tIVW[j][jj] * s;
       }
       const double w = mp.J * twg[i] * tww[j] * sjx[el][t];
-      fx[el][0][t] = -bzv * w;          // y
-      fx[el][1][t] = sby[el][t] * w;    // z
+      fx[t] = -bzv * w;             // y
+      fx[AB + t] = sby[el][t] * w;  // z
     }
     {
       const int i = t % A, j = t / A;  // N_y node: (B_z J_y, 0, -B_x J_y)
@@ -461,12 +475,13 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
         bzv += tIVG[j][jj] * s;
       }
       const double w = mp.J * tww[i] * twg[j] * sjy[el][t];
-      fy[el][0][t] = bzv * w;           // x
-      fy[el][1][t] = -sbx[el][t] * w;   // z
+      fy[t] = bzv * w;               // x
+      fy[AB + t] = -sbx[el][t] * w;  // z
     }
   }
   __syncthreads();
   const bool node = act && t < NN;
+  double vnew[3] = {0.0, 0.0, 0.0};
   if (node) {
     const int qi = t % NP, qj = t / NP;
     // transpose of the interpolation to the auxiliary nodes, factorised over the two directions
@@ -477,15 +492,15 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
 #pragma unroll
       for (int i = 0; i < A; ++i) {
         const double I = tIPW[i][qi];
-        s0 += I * fz[el][0][j * A + i];
-        s1 += I * fz[el][1][j * A + i];
+        s0 += I * fz[j * A + i];
+        s1 += I * fz[AA + j * A + i];
       }
       if constexpr (!R2) {
 #pragma unroll
         for (int i = 0; i < B; ++i) {
           const double I = tIPG[i][qi];
-          t1 += I * fx[el][0][j * B + i];
-          t2 += I * fx[el][1][j * B + i];
+          t1 += I * fx[j * B + i];
+          t2 += I * fx[AB + j * B + i];
         }
       }
       const double Iy = tIPW[j][qj];
@@ -499,8 +514,8 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
 #pragma unroll
       for (int i = 0; i < A; ++i) {
         const double I = tIPW[i][qi];
-        s0 += I * fy[el][0][j * A + i];
-        s2 += I * fy[el][1][j * A + i];
+        s0 += I * fy[j * A + i];
+        s2 += I * fy[AB + j * A + i];
       }
       const double Iy = tIPG[j][qj];
       du[0] += Iy * s0;
@@ -543,23 +558,27 @@ __global__ __launch_bounds__(BS) void k_mag_update(MagIO io, const MagTab* __res
     } else {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double v = (R2 && d == 2) ? 0.0 : io.ca * yn[d] + io.cb * (ys[d] + io.tau * (du[d] / (rq * Mq)));
+        const double v = (R2 && d == 2) ? 0.0 : y0[d] + (io.cb * io.tau) * (du[d] / (rq * Mq));
         io.ou[d * KN + n] = v;
-        snew[el][d][t] = v;
+        vnew[d] = v;
       }
-      io.oe[n] = io.ca * yn[3] + io.cb * (ys[3] + io.tau * de);
+      io.oe[n] = y0[3] + (io.cb * io.tau) * de;
     }
   }
   if (MODE == 1 && io.ustats) {
     // element statistics of the new velocity (GLL-weighted sum, min, max), as the velocity-OE
     // sensor needs them
+    __syncthreads();  // every lane has finished reading the Lorentz loads
+    if (node)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) fz[d * NN + t] = vnew[d];
     __syncthreads();
     constexpr int NU = R2 ? 2 : 3;  // statistics [K][NU][3] of the carried components
     for (int tk = t; act && tk < 3 * NU; tk += NT) {
       const int c = tk / 3, kind = tk - 3 * c;
       double sm = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
       for (int k = 0; k < NN; ++k) {
-        const double v = snew[el][c][k];
+        const double v = fz[c * NN + k];
         sm += (twp[k % NP] * twp[k / NP]) * v;
         mn = fmin(mn, v); mx = fmax(mx, v);
       }
@@ -634,7 +653,11 @@ template <int P>
 __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho, double* __restrict__ Psi,
                                                  const HydroTab* __restrict__ H, MeshP mp) {
   constexpr int NP = P + 1, NN = NP * NP, EB = VP<P>::EB, NL = NN * (NN + 1) / 2;
-  __shared__ double sw[EB][NN], sL[EB][NL], srd[EB][NN], sdum[64];
+  // srd (pivot reciprocals) reuses sw, whose last reads come before the barrier that precedes the
+  // Gram rows; masked lanes store to one of eight dummy slots.  At N = 4 these two savings keep the
+  // block under 8 KB of LDS, so that 20 blocks fit on a CU.
+  __shared__ double sw[EB][NN], sL[EB][NL], sdum[8];
+  double(*const srd)[NN] = sw;
   __shared__ double sH[EB][NP][NP * NP];  // Gram staging
   __shared__ double sV[NP][NP];
   const int tid = threadIdx.x, el0 = tid / NN;
@@ -672,7 +695,7 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
       double s = 0.0;
 #pragma unroll
       for (int jj = 0; jj < NP; ++jj) s += sV[jj][mode_b(k2)] * w[jj][mode_a(k2)];
-      *((act0 && k2 <= q) ? &sL[el][rq + k2] : &sdum[tid]) = s;
+      *((act0 && k2 <= q) ? &sL[el][rq + k2] : &sdum[tid & 7]) = s;
     }
   }
   __syncthreads();
@@ -685,8 +708,8 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
   double piv = sL[el][rq + q];  // G[q][q]
   {
     const double rk = rsqrt_refined(piv);  // used by row 0 only
-    *((act0 && q == 0) ? &sL[el][0] : &sdum[tid]) = piv * rk;
-    *((act0 && q == 0) ? &srd[el][0] : &sdum[tid]) = rk;
+    *((act0 && q == 0) ? &sL[el][0] : &sdum[tid & 7]) = piv * rk;
+    *((act0 && q == 0) ? &srd[el][0] : &sdum[tid & 7]) = rk;
   }
   __syncthreads();
 #pragma unroll
@@ -698,11 +721,11 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
       else s0 -= Lr[m] * sL[el][k * (k + 1) / 2 + m];
     }
     Lr[k] = (s0 + s1) * srd[el][k];  // L[q][k] on the rows q > k; never read on the others
-    *((act0 && q > k) ? &sL[el][rq + k] : &sdum[tid]) = Lr[k];
+    *((act0 && q > k) ? &sL[el][rq + k] : &sdum[tid & 7]) = Lr[k];
     piv -= Lr[k] * Lr[k];
     const double rk = rsqrt_refined(piv);  // pivot of row k + 1 (used by that row only)
-    *((act0 && q == k + 1) ? &sL[el][rq + q] : &sdum[tid]) = piv * rk;
-    *((act0 && q == k + 1) ? &srd[el][k + 1] : &sdum[tid]) = rk;
+    *((act0 && q == k + 1) ? &sL[el][rq + q] : &sdum[tid & 7]) = piv * rk;
+    *((act0 && q == k + 1) ? &srd[el][k + 1] : &sdum[tid & 7]) = rk;
     __syncthreads();
   }
   // row q of Psi = Phi L^{-T}: forward substitution over the modes with the row in registers
