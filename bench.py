@@ -6,8 +6,9 @@ B = (1, 1, 0)/sqrt(2); full Strang step with hydro OE, positivity scaling, veloc
 artificial resistivity; dt from the positivity CFL rule at CFL 0.3 before every step.
 One Strang step = 6 hydro + 3 magnetic stages; value = K (N+1)^2 * 9 / t_step.
 
-Prints one JSON line.  The roofline object describes the dominant kernel (the hydro stage:
-L_E + SSP combine + element statistics), timed with HIP events on the library's stream.
+Prints one JSON line.  The roofline object describes the hydro stage kernel (L_E + SSP combine
++ element statistics), roofline_oe_pp the hydro stage map (OE + PP), which takes about as long per
+launch; both are timed with HIP events on the library's stream.
 """
 import argparse
 import hashlib
@@ -20,7 +21,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hydro_stage_traffic.json")
+TRAFFIC_FILES = {"stage": os.path.join(ROOT, "profiles", "hydro_stage_traffic.json"),
+                 "oe_pp": os.path.join(ROOT, "profiles", "hydro_oe_pp_traffic.json")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2609_10849_amd", "csrc", "hydro.hip")
 
 
@@ -32,28 +34,46 @@ def stage_bytes(K, nn):
     return (2 * u + 3 * u + 3 * u) / 3.0 + K * 15 * 8
 
 
-def kernel_sha():
-    """Hash of the source the hydro stage kernel is built from: hydro.hip up to the end of that
-    kernel (its device helpers and element statistics), its launcher, and the headers it
-    includes.  Edits elsewhere (the OE/PP map, other launchers) leave the counters valid."""
+def oe_pp_bytes(K, nn):
+    """Algorithmic HBM bytes of one stage-map launch, averaged over the six launches of a Strang
+    step: the raw stage read and the limited stage written (one U each), the six element
+    statistics it uses read and its decision flag written; the last launch of the first hydro
+    half-step also writes the primitive copy (rho, e, u) for the magnetic substep."""
+    u = 5 * K * nn * 8
+    return 2 * u + u / 6.0 + K * (6 * 8 + 1)
+
+
+def kernel_sha(kind="stage"):
+    """Hash of the source a hydro kernel is built from.  "stage": hydro.hip up to the end of the
+    stage kernel (its device helpers and element statistics), its launcher, and the headers it
+    includes; edits elsewhere (the OE/PP map, other launchers) leave its counters valid.
+    "oe_pp": hydro.hip up to the end of the stage map (so the stage kernel's source as well), its
+    launcher, and the same headers."""
     src = open(KERNEL_SRC, encoding="utf-8").read()
-    end = src.index("template <int P>\n__global__ __launch_bounds__(256) void k_elem_stats(")
-    a = src.index("int hydro_stage_a(")
-    b = src.index("int line_global_reduce(", a)
+    if kind == "stage":
+        end = src.index("template <int P>\n__global__ __launch_bounds__(256) void k_elem_stats(")
+        a = src.index("int hydro_stage_a(")
+        b = src.index("int line_global_reduce(", a)
+    elif kind == "oe_pp":
+        end = src.index("}  // namespace\n", src.index("void k_hydro_oe_pp("))
+        a = src.index("int hydro_stage_b(")
+        b = src.index("int reset_attempt(", a)
+    else:
+        raise ValueError(kind)
     h = hashlib.sha256((src[:end] + src[a:b]).encode())
     for name in ("common.h", "xcd.h", "ec_log.h"):
         h.update(open(os.path.join(os.path.dirname(KERNEL_SRC), name), "rb").read())
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch():
-    """HBM bytes per hydro-stage launch from the committed rocprofv3 counter runs, or None
+def traffic_per_launch(kind="stage"):
+    """HBM bytes per launch of a hydro kernel from the committed rocprofv3 counter runs, or None
     when they are missing or were taken on a different kernel source."""
     try:
-        d = json.load(open(TRAFFIC_FILE))
+        d = json.load(open(TRAFFIC_FILES[kind]))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_src_sha") != kernel_sha():
+    if d.get("kernel_src_sha") != kernel_sha(kind):
         return None
     return d.get("bytes_per_launch")
 
@@ -253,12 +273,15 @@ def main():
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     S.timing(False)
-    launches, kms = S.timing_read()
+    launches, kms = S.timing_read(0)
+    launches_b, kms_b = S.timing_read(1)
     ms_per_step = 1e3 * t / args.steps
     value = K * nn * 9 / (t / args.steps)
     avg_ms = kms / max(launches, 1)
     ach = stage_bytes(K, nn) / (avg_ms * 1e-3) / 1e9
-    tr = traffic_per_launch()
+    tr = traffic_per_launch("stage")
+    avg_b = kms_b / max(launches_b, 1)
+    ach_b = oe_pp_bytes(K, nn) / (avg_b * 1e-3) / 1e9
     out = {
         "metric": "DOF-stage updates/s (FP64) per Strang step",
         "value": value,
@@ -279,6 +302,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "traffic": tr, "kernel": "k_hydro_stage<4,1> (L_E + SSP combine + element statistics)",
                      "avg_ms": avg_ms, "launches": launches},
+        "roofline_oe_pp": {"bound": "hbm", "achieved": ach_b, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": ach_b / HBM_PEAK_GBS, "traffic": traffic_per_launch("oe_pp"),
+                           "kernel": "k_hydro_oe_pp<4,128> (hydro OE + PP map)", "avg_ms": avg_b,
+                           "launches": launches_b},
         "accepted_substep_rate": accepted / max(attempted, 1),
     }
     if not args.no_extras and not args.reduced_2d2v:

@@ -169,8 +169,10 @@ int mhd25_rhs_magnetic_vjp(mhd25_ctx* ctx, const double* rho, const double* u, c
                            const double* dBz_cot, double* u_bar, double* Bx_bar, double* By_bar,
                            double* Bz_bar);
 
-/* Kernel timing on the context stream with HIP events (off by default).  kernel id 0 is the
- * hydro stage kernel (L_E + SSP combine + statistics).  Returns launches and summed ms. */
+/* Kernel timing on the context stream with HIP events (off by default).  Kernel id 0 is the
+ * hydro stage kernel (L_E + SSP combine + statistics), id 1 the hydro stage map (OE + PP).
+ * mhd25_timing_read returns the launches and summed ms of one kernel since its last read and
+ * resets them; another id or a NULL pointer returns -1. */
 int mhd25_timing_enable(mhd25_ctx* ctx, int32_t on);
 int mhd25_timing_read(mhd25_ctx* ctx, int32_t kernel_id, int64_t* launches, double* total_ms);
 

@@ -35,23 +35,32 @@ int extra_cfl(mhd25_ctx* c, const double* U, const double* Bx, const double* By,
 int extra_diagnostics(mhd25_ctx* c, const double* U, const double* Bx, const double* By, const double* Bz,
                       double* out6);
 
-hipEvent_t* timing_slot(mhd25_ctx* c) {
+// fold the recorded (start, stop) pairs into the per-kernel totals
+static hipError_t timing_fold(mhd25_ctx* c) {
+  if (c->ev_used == 0) return hipSuccess;
+  const hipError_t e = hipEventSynchronize(c->ev_pool[c->ev_used - 1]);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k + 1 < c->ev_used; k += 2) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]);
+    const int kid = c->ev_kid[k / 2];
+    c->t_launch[kid]++; c->t_ms[kid] += ms;
+  }
+  c->ev_used = 0;
+  return hipSuccess;
+}
+
+// next free (start, stop) event pair for a launch of kernel kid; a full pool is folded first
+hipEvent_t* timing_slot(mhd25_ctx* c, int kid) {
   if ((size_t)(c->ev_used + 2) > c->ev_pool.size()) {
-    // pool full: fold the recorded pairs into the totals and reuse
-    if (!c->ev_pool.empty()) {
-      hipEventSynchronize(c->ev_pool[c->ev_used - 1]);
-      for (int k = 0; k + 1 < c->ev_used; k += 2) {
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]);
-        c->t_launch[0]++; c->t_ms[0] += ms;
-      }
-      c->ev_used = 0;
-    }
+    (void)timing_fold(c);
     if (c->ev_pool.empty()) {
       c->ev_pool.resize(2048);
+      c->ev_kid.assign(1024, 0);
       for (auto& ev : c->ev_pool) hipEventCreate(&ev);
     }
   }
+  c->ev_kid[c->ev_used / 2] = kid;
   hipEvent_t* s = &c->ev_pool[c->ev_used];
   c->ev_used += 2;
   return s;
@@ -418,19 +427,11 @@ int mhd25_timing_enable(mhd25_ctx* c, int32_t on) {
 }
 
 int mhd25_timing_read(mhd25_ctx* c, int32_t kid, int64_t* launches, double* total_ms) {
-  if (!c || kid != 0 || !launches || !total_ms) return -1;
-  if (c->ev_used > 0) {
-    HIPCHK(c, hipEventSynchronize(c->ev_pool[c->ev_used - 1]));
-    for (int k = 0; k + 1 < c->ev_used; k += 2) {
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]);
-      c->t_launch[0]++; c->t_ms[0] += ms;
-    }
-    c->ev_used = 0;
-  }
-  *launches = c->t_launch[0];
-  *total_ms = c->t_ms[0];
-  c->t_launch[0] = 0; c->t_ms[0] = 0.0;
+  if (!c || kid < 0 || kid > 1 || !launches || !total_ms) return -1;
+  HIPCHK(c, timing_fold(c));
+  *launches = c->t_launch[kid];
+  *total_ms = c->t_ms[kid];
+  c->t_launch[kid] = 0; c->t_ms[kid] = 0.0;
   return 0;
 }
 

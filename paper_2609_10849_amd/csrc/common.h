@@ -126,7 +126,8 @@ struct mhd25_ctx {
   // timing
   int timing;
   int hydro_bs;  // threads per block of the hydro stage kernel (128 or 256; tuned)
-  std::vector<hipEvent_t> ev_pool;  // pairs (start, stop) of timed hydro-stage launches
+  std::vector<hipEvent_t> ev_pool;  // pairs (start, stop) of timed launches
+  std::vector<int> ev_kid;          // kernel id of each pair (0 hydro stage, 1 stage map)
   int ev_used;
   long long t_launch[4];
   double t_ms[4];

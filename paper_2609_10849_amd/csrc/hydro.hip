@@ -755,7 +755,7 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, lon
   switch (p) { case 1: F(1); break; case 2: F(2); break; case 3: F(3); break; \
                case 4: F(4); break; case 5: F(5); break; case 6: F(6); break; default: return -4; }
 
-hipEvent_t* timing_slot(mhd25_ctx* c);
+hipEvent_t* timing_slot(mhd25_ctx* c, int kid);
 static int eb_of(int p) { return 256 / ((p + 1) * (p + 1)); }
 
 static int check(mhd25_ctx* c, hipError_t e, const char* what) {
@@ -782,7 +782,7 @@ int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust,
   const int bs = c->hydro_bs == 128 ? 128 : 256;
   const int eb = bs / ((c->p + 1) * (c->p + 1));
   const long blocks = (c->mp.K + eb - 1) / eb;
-  hipEvent_t* ev = c->timing ? timing_slot(c) : nullptr;
+  hipEvent_t* ev = c->timing ? timing_slot(c, 0) : nullptr;
   if (ev) hipEventRecord(ev[0], c->stream);
 #define L1(P)                                                                                                      \
   if (bs == 128) hipLaunchKernelGGL((k_hydro_stage<P, 1, 128>), dim3(blocks), dim3(128), 0, c->stream, Us, Un, Ust, \
@@ -831,11 +831,14 @@ int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, con
   constexpr int BS = MHD_OE_BS;
   const int eb = BS / ((c->p + 1) * (c->p + 1));
   const long blocks = (c->mp.K + eb - 1) / eb;
+  hipEvent_t* ev = c->timing ? timing_slot(c, 1) : nullptr;
+  if (ev) hipEventRecord(ev[0], c->stream);
 #define LB(P) hipLaunchKernelGGL((k_hydro_oe_pp<P, BS>), dim3(blocks), dim3(BS), 0, c->stream, Ust, Uout, c->stats, \
                                  c->lines, c->glob, c->d_flags, c->d_counts, flag, c->d_ht, c->mp, tau, c->opt.s_H, \
                                  c->opt.oe_hydro, c->opt.pp, rho_o, e_o, u_o)
   DISPATCH_P(c->p, LB);
 #undef LB
+  if (ev) hipEventRecord(ev[1], c->stream);
   return check(c, hipGetLastError(), "stage map launch");
 }
 

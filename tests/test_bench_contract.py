@@ -1,5 +1,5 @@
 """bench.py's contract on the CPU: more than one GPU is refused with a message, and the roofline
-bytes of the hydro stage kernel follow from the state sizes."""
+bytes of the hydro stage kernel and of the stage map follow from the state sizes."""
 import os
 import subprocess
 import sys
@@ -25,7 +25,17 @@ def test_stage_bytes():
     assert abs(bench.stage_bytes(K, nn) - 2.922e9) < 1e6
 
 
-def test_kernel_hash_covers_only_the_stage_kernel():
+def test_oe_pp_bytes():
     import bench
-    h = bench.kernel_sha()
-    assert len(h) == 16 and int(h, 16) >= 0
+    K, nn = 1024 * 1024, 25
+    u = 5 * K * nn * 8
+    # U* read and U^(s) written on every launch, the primitive copy on one launch in six
+    assert bench.oe_pp_bytes(K, nn) == 2 * u + u / 6.0 + K * 49
+    assert abs(bench.oe_pp_bytes(K, nn) - 2.3233e9) < 1e6
+
+
+def test_kernel_hashes():
+    import bench
+    h, g = bench.kernel_sha("stage"), bench.kernel_sha("oe_pp")
+    assert len(h) == 16 and int(h, 16) >= 0 and len(g) == 16 and g != h
+    assert bench.kernel_sha() == h
