@@ -158,7 +158,7 @@ __global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, c
 // nodes, plus eta_K sum_q M_q J(x_q) . phi_a(x_q) by the degree-p GLL rule.
 // ---------------------------------------------------------------------------------------------
 template <int P, int M, int BS, bool R2>
-__global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, const double* __restrict__ Bx,
+__global__ __launch_bounds__(BS, (!R2 && P <= 5) ? 5 : 1) void k_E_loads(const double* __restrict__ u, const double* __restrict__ Bx,
                                                  const double* __restrict__ By, const double* __restrict__ Bz,
                                                  const double* __restrict__ Jx, const double* __restrict__ Jy,
                                                  const double* __restrict__ Jz, const double* __restrict__ eta,
@@ -168,7 +168,10 @@ __global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, co
   constexpr int NP = C::NP, NN = C::NN, A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB,
                 NT = C::NT;
   __shared__ double su[EB][3][NN], sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
-  __shared__ double sjx[EB][AB], sjy[EB][AB], sjz[EB][AA], swj[EB][3][NN];
+  __shared__ double sjx[EB][AB], sjy[EB][AB], sjz[EB][AA];
+  // the eta-weighted J values at the GLL_p nodes reuse su once the x interpolation has read it
+  // (with 96 VGPRs and 14.6 KB of LDS per 128-thread block at N = 4: 5 waves per SIMD)
+  double(*const swj)[3][NN] = su;
   __shared__ double sux[EB][3][NP][A + B];  // velocity interpolated in x: [d][qj][W nodes | Gauss nodes]
   __shared__ double tGP[NP][B], tWP[NP][A], tPW[A][NP], tPG[B][NP], tGW[A][B], tVG[B][B], tVW[A][B];
   __shared__ double twp[NP], tww[A], twg[B];
@@ -221,7 +224,9 @@ __global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, co
       sux[el][d][qj][x] = v;
     }
   }
-  if (act && et != 0.0 && t < NN) {
+  const bool jnode = act && et != 0.0 && t < NN;
+  double jw[3] = {0.0, 0.0, 0.0};
+  if (jnode) {
     const int qi = t % NP, qj = t / NP;
     double jx = 0.0, jy = 0.0, jz = 0.0;
     if constexpr (!R2) {
@@ -248,8 +253,10 @@ __global__ __launch_bounds__(BS) void k_E_loads(const double* __restrict__ u, co
       jz += tWP[qj][j] * s;
     }
     const double w = et * mp.J * twp[qi] * twp[qj];
-    swj[el][0][t] = w * jx; swj[el][1][t] = w * jy; swj[el][2][t] = w * jz;
+    jw[0] = w * jx; jw[1] = w * jy; jw[2] = w * jz;
   }
+  __syncthreads();  // every lane has finished reading su
+  if (jnode) { swj[el][0][t] = jw[0]; swj[el][1][t] = jw[1]; swj[el][2][t] = jw[2]; }
   __syncthreads();
   if (!act) return;
   // second half: interpolate in y (Iy = I_P_W or I_P_G row aj; x column xc of sux)
@@ -761,8 +768,9 @@ struct VS {
 // thread per GLL_p node, EB elements per block; writes the element's damping factors D_l
 // (l = 0..p) to Dfac[K][p+1].  Neighbour velocities are staged per direction in LDS with coalesced
 // loads.  u is only read here (the projection kernel that updates it runs afterwards).
+// (at N = 4, k = 3 the kernel fits 80 VGPRs and 27 KB of LDS without spills: 6 waves per SIMD)
 template <int P, int M, bool R2>
-__global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ rho, const double* __restrict__ u,
+__global__ __launch_bounds__(256, (P == 4 && M == 3) ? 6 : 1) void k_vel_sensor(const double* __restrict__ rho, const double* __restrict__ u,
                                                     const double* __restrict__ Bx, const double* __restrict__ By,
                                                     const double* __restrict__ Bz, const double* __restrict__ lines,
                                                     const double* __restrict__ glob, double* __restrict__ Dfac,
@@ -770,10 +778,14 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
                                                     MeshP mp, double tau, double sM) {
   using C = VS<P, M>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, A = C::A, B = C::B, AB = C::AB;
-  __shared__ double su[EB][3][NN], sx[EB][6][NN], sva[EB][2][NN], ssig[EB][2][NP], samp[EB][2][3], ssg[EB][3][NP];
+  // sbb holds an element's B coefficients (B_x, B_y, B_z at offsets 0, AB, 2 AB) and, once they
+  // have been interpolated, its node wave speeds |u_x| + c_A and |u_y| + c_A (offsets 0 and NN);
+  // sharing the buffer keeps the block at about 27 KB of LDS at N = 4 (6 blocks per CU)
+  constexpr int NSB = 2 * AB + C::BB > 2 * NN ? 2 * AB + C::BB : 2 * NN;
+  __shared__ double su[EB][3][NN], sx[EB][6][NN], ssig[EB][2][NP], samp[EB][2][3], ssg[EB][3][NP];
   __shared__ double srow[EB][2][NP];
   __shared__ int scst[EB][3];
-  __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][C::BB];
+  __shared__ double sbb[EB][NSB];
   __shared__ double tD0[NP][NP], tDp[NP][NP], tWP[NP][A], tGP[NP][B], tVP[NP][B], tw[NP], tfr[NP];
   constexpr int NU = R2 ? 2 : 3;  // velocity components (u_z = 0 in the 2D2V system)
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
@@ -799,10 +811,10 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
     for (int d = 0; d < NU; ++d) { uu[d] = u[d * KN + e * NN + q]; su[el][d][q] = uu[d]; }
     rq = rho[e * NN + q];
     for (int k = q; k < AB; k += NN) {
-      sbx[el][k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];
-      sby[el][k] = By[gix(mp, B, ex, ey, k % B, k / B)];
+      sbb[el][k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];
+      sbb[el][AB + k] = By[gix(mp, B, ex, ey, k % B, k / B)];
     }
-    for (int k = q; !R2 && k < C::BB; k += NN) sbz[el][k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
+    for (int k = q; !R2 && k < C::BB; k += NN) sbb[el][2 * AB + k] = Bz[gix(mp, B, ex, ey, k % B, k / B)];
   }
   __syncthreads();
   // shared amplitudes: each component's global and cross-line spreads formed once per element
@@ -817,33 +829,36 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
     samp[el][0][c] = fmax(fmax(rl[2] - rm, rm - rl[1]), 1e-6 * dOm);
     samp[el][1][c] = fmax(fmax(cl[2] - cm, cm - cl[1]), 1e-6 * dOm);
   }
+  double wsx = 0.0, wsy = 0.0;  // node wave speeds
   if (act) {
     double bxv = 0.0, byv = 0.0, bzv = 0.0;
 #pragma unroll
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sbx[el][j * A + i];
+      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sbb[el][j * A + i];
       bxv += tGP[qj][j] * s;
     }
 #pragma unroll
     for (int j = 0; j < A; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += tGP[qi][i] * sby[el][j * B + i];
+      for (int i = 0; i < B; ++i) s += tGP[qi][i] * sbb[el][AB + j * B + i];
       byv += tWP[qj][j] * s;
     }
 #pragma unroll
     for (int j = 0; !R2 && j < B; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < B; ++i) s += tVP[qi][i] * sbz[el][j * B + i];
+      for (int i = 0; i < B; ++i) s += tVP[qi][i] * sbb[el][2 * AB + j * B + i];
       bzv += tVP[qj][j] * s;
     }
     const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) / sqrt(rq);
-    sva[el][0][q] = fabs(uu[0]) + va;
-    sva[el][1][q] = fabs(uu[1]) + va;
+    wsx = fabs(uu[0]) + va;
+    wsy = fabs(uu[1]) + va;
   }
+  __syncthreads();  // every lane has read the B coefficients
+  if (act) { sbb[el][q] = wsx; sbb[el][NN + q] = wsy; }
 #pragma unroll
   for (int D = 0; D < 2; ++D) {
     // neighbours across the faces normal to D: sx rows 0..2 minus side, 3..5 plus side
@@ -908,7 +923,7 @@ __global__ __launch_bounds__(256) void k_vel_sensor(const double* __restrict__ r
         for (int t = q; act && t < NP; t += NN) {
           double ax = 0.0, ay = 0.0;
 #pragma unroll
-          for (int k = 0; k < NP; ++k) { ax = fmax(ax, sva[el][0][t * NP + k]); ay = fmax(ay, sva[el][1][t * NP + k]); }
+          for (int k = 0; k < NP; ++k) { ax = fmax(ax, sbb[el][t * NP + k]); ay = fmax(ay, sbb[el][NN + t * NP + k]); }
           srow[el][0][t] = ax;
           srow[el][1][t] = ay;
         }
