@@ -216,6 +216,33 @@ def reduced_2d2v(S, g, steps=10, warm=2):
             "note": "same workload through the 2D2V reduced system (u_z, B_z and the in-plane E, J skipped)"}
 
 
+def hydro_only(S, g, steps=10, warm=2):
+    """The hydro part of a Strang step alone: two half-step substeps (six SSP stages with their
+    OE/PP maps and reject checks) on a copy of the state, at the step's dt; rate K (N+1)^2 6 / t.
+    Rejected attempts would show as attempted > accepted."""
+    import torch
+    U = g[0].clone()
+    dt = S.cfl_dt(*g, 0.3)
+    for _ in range(warm):
+        S.hydro_substep(U, 0.5 * dt)
+    torch.cuda.synchronize()
+    attempted = accepted = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for _ in range(2):
+            r, rep = S.hydro_substep(U, 0.5 * dt)
+            if r != 0:
+                raise RuntimeError("hydro substep failed: %r" % (rep,))
+            attempted += rep["substeps_attempted"]
+            accepted += rep["substeps_accepted"]
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    K, nn = S.K, (S.p + 1) ** 2
+    return {"value": K * nn * 6 / t, "unit": "DOF-stage updates/s", "ms_per_step": 1e3 * t, "steps": steps,
+            "substeps_attempted": attempted, "substeps_accepted": accepted,
+            "note": "the two hydro half-steps of a Strang step alone (6 stages), same state and dt"}
+
+
 def S_options(reduced_2d2v):
     import paper_2609_10849_amd as pk
     return pk.Options.full(reduced_2d2v=reduced_2d2v)
@@ -309,6 +336,7 @@ def main():
         "accepted_substep_rate": accepted / max(attempted, 1),
     }
     if not args.no_extras and not args.reduced_2d2v:
+        out["hydro_only"] = hydro_only(S, g, steps=min(args.steps, 10))
         out["reduced_2d2v"] = reduced_2d2v(S, g, steps=min(args.steps, 10))
         out["adjoint_cost_ratio"] = adjoint_ratio()
         # the captured-graph ensemble path is held off the GPU until the cause of a host

@@ -740,13 +740,17 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
   double vi[NP], vj[NP];
 #pragma unroll
   for (int a = 0; a < NP; ++a) { vi[a] = sV[qi][a]; vj[a] = sV[qj][a]; }
+  // Right-looking order: once psi[k] is final, L[j][k] psi[k] is subtracted from every later
+  // entry j.  Each entry receives the same subtractions in the same order as in the row-by-row
+  // form (so the results are identical), but the 25 entries are independent chains.
   double psi[NN];
 #pragma unroll
-  for (int k = 0; k < NN; ++k) {
-    double s = vi[mode_a(k)] * vj[mode_b(k)];
+  for (int k = 0; k < NN; ++k) psi[k] = vi[mode_a(k)] * vj[mode_b(k)];
 #pragma unroll
-    for (int k2 = 0; k2 < k; ++k2) s -= sL[el][k * (k + 1) / 2 + k2] * psi[k2];
-    psi[k] = s * srd[el][k];
+  for (int k = 0; k < NN; ++k) {
+    psi[k] *= srd[el][k];
+#pragma unroll
+    for (int j = k + 1; j < NN; ++j) psi[j] -= sL[el][j * (j + 1) / 2 + k] * psi[k];
   }
   // row q of the element's table, stored directly (rows are 16-byte aligned: psi_row is even)
   if (act0) {
