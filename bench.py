@@ -21,6 +21,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+VALU_FILE = os.path.join(ROOT, "profiles", "hydro_valu_flops.json")
 TRAFFIC_FILES = {"stage": os.path.join(ROOT, "profiles", "hydro_stage_traffic.json"),
                  "oe_pp": os.path.join(ROOT, "profiles", "hydro_oe_pp_traffic.json")}
 KERNEL_SRC = os.path.join(ROOT, "paper_2609_10849_amd", "csrc", "hydro.hip")
@@ -32,6 +34,54 @@ def stage_bytes(K, nn):
     (one U is 5 fields x K x nn doubles) and 15 statistics per element."""
     u = 5 * K * nn * 8
     return (2 * u + 3 * u + 3 * u) / 3.0 + K * 15 * 8
+
+
+def stage_flops(K, NP):
+    """Algorithmic FP64 flops of one hydro-stage launch (+, -, *, / and log, exp, sqrt count 1,
+    FMA 2), per element: node primitives 20 per node; EC flux differencing 74 per node pair
+    (flux, six divisions, two-sided accumulation) over (N+1)^2 N pairs; the LLF flux, 50 per
+    face point, over the element's 2(N+1) own face points; the lift, 15 per face point over
+    4(N+1); inverse mass and SSP combine 25 per node; statistics 20 per node."""
+    nn = NP * NP
+    return K * (20 * nn + 74 * nn * (NP - 1) + 50 * 2 * NP + 15 * 4 * NP + 25 * nn + 20 * nn)
+
+
+def oe_pp_flops(K, NP):
+    """Algorithmic FP64 flops of one stage-map launch, per element: the derivative traces of
+    both sides of one face per direction, line and component (2 (N+1) dot products of length
+    N+1) with the weighted squared jumps (3 per order); the per-order sums and sigma terms; the
+    forward and inverse two-dimensional Legendre transforms (two passes each, 2 (N+1)^3 flops
+    per pass and component); the shell damping; the positivity scaling, 30 per node."""
+    nn = NP * NP
+    jumps = 10 * NP * (4 * NP * NP + 3 * NP)
+    sigma = 10 * NP * (NP + 4)
+    return K * (jumps + sigma + 40 * NP ** 3 + 5 * nn + 4 * NP + 30 * nn)
+
+
+def valu_per_launch(kind):
+    """Executed FP64 flops per launch of a hydro kernel from the committed SQ counter run
+    (SQ_INSTS_VALU_FLOPS_FP64 counts 2 FMA + ADD + MUL + TRANS instructions per wave; times
+    the active lanes), or None when missing or taken on a different kernel source."""
+    try:
+        d = json.load(open(VALU_FILE))[kind]
+    except (OSError, ValueError, KeyError):
+        return None
+    if d.get("kernel_src_sha") != kernel_sha(kind):
+        return None
+    return d.get("flops_per_launch")
+
+
+def valu_object(flops_alg, flops_ctr, avg_ms):
+    """FP64 VALU view of a kernel: algorithmic and counter-measured TFLOP/s against the FP64
+    vector peak."""
+    t = avg_ms * 1e-3
+    out = {"peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+           "algorithmic": flops_alg / t / 1e12, "algorithmic_frac": flops_alg / t / 1e12 / FP64_PEAK_TFS,
+           "counter": None, "counter_frac": None}
+    if flops_ctr is not None:
+        out["counter"] = flops_ctr / t / 1e12
+        out["counter_frac"] = flops_ctr / t / 1e12 / FP64_PEAK_TFS
+    return out
 
 
 def oe_pp_bytes(K, nn):
@@ -328,11 +378,13 @@ def main():
                    "system": "2D2V reduced" if args.reduced_2d2v else "general"},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "traffic": tr, "kernel": "k_hydro_stage<4,1> (L_E + SSP combine + element statistics)",
-                     "avg_ms": avg_ms, "launches": launches},
+                     "avg_ms": avg_ms, "launches": launches,
+                     "valu": valu_object(stage_flops(K, N + 1), valu_per_launch("stage"), avg_ms)},
         "roofline_oe_pp": {"bound": "hbm", "achieved": ach_b, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach_b / HBM_PEAK_GBS, "traffic": traffic_per_launch("oe_pp"),
                            "kernel": "k_hydro_oe_pp<4,128> (hydro OE + PP map)", "avg_ms": avg_b,
-                           "launches": launches_b},
+                           "launches": launches_b,
+                           "valu": valu_object(oe_pp_flops(K, N + 1), valu_per_launch("oe_pp"), avg_b)},
         "accepted_substep_rate": accepted / max(attempted, 1),
     }
     if not args.no_extras and not args.reduced_2d2v:

@@ -34,6 +34,17 @@ def test_oe_pp_bytes():
     assert abs(bench.oe_pp_bytes(K, nn) - 2.3233e9) < 1e6
 
 
+def test_algorithmic_flop_counts():
+    import bench
+    K = 1024 * 1024
+    # N = 4: 25 nodes, 100 EC pairs, 10 own and 20 lifted face points per element
+    assert bench.stage_flops(K, 5) == K * (20 * 25 + 74 * 100 + 50 * 10 + 15 * 20 + 25 * 25 + 20 * 25)
+    assert bench.stage_flops(K, 5) / K == 9825
+    assert bench.oe_pp_flops(K, 5) / K == 12095
+    v = bench.valu_object(bench.stage_flops(K, 5), None, 1.0)
+    assert abs(v["algorithmic"] - 9825 * K / 1e-3 / 1e12) < 1e-9 and v["counter"] is None
+
+
 def test_kernel_hashes():
     import bench
     h, g = bench.kernel_sha("stage"), bench.kernel_sha("oe_pp")
