@@ -660,13 +660,17 @@ template <int P>
 __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho, double* __restrict__ Psi,
                                                  const HydroTab* __restrict__ H, MeshP mp) {
   constexpr int NP = P + 1, NN = NP * NP, EB = VP<P>::EB, NL = NN * (NN + 1) / 2;
-  // srd (pivot reciprocals) reuses sw, whose last reads come before the barrier that precedes the
-  // Gram rows; masked lanes store to one of eight dummy slots.  At N = 4 these two savings keep the
-  // block under 8 KB of LDS, so that 20 blocks fit on a CU.
-  __shared__ double sw[EB][NN], sL[EB][NL], sdum[8];
-  double(*const srd)[NN] = sw;
-  __shared__ double sH[EB][NP][NP * NP];  // Gram staging
-  __shared__ double sV[NP][NP];
+  constexpr int NPS = NP * (NP + 1) / 2;  // pairs a <= a'
+  // LDS, sized so that 24 one-wave blocks fit on a CU at N = 4 (6 waves per SIMD):
+  // - sL holds the packed Gram matrix and then L.  Until the Gram rows are written, its first
+  //   EB NN entries hold the node weights sw, whose last reads come before the barrier that
+  //   precedes the Gram rows.
+  // - sH holds the line partials Hm[qj][a][a'] for a <= a', and then the pivot reciprocals srd,
+  //   which are first written after the barrier that follows the last reads of the partials.
+  // - Masked lanes store to one of eight dummy slots.
+  __shared__ double sL[EB][NL], sH[EB][NP][NPS], sV[NP][NP], sdum[8];
+  double(*const sw)[NN] = reinterpret_cast<double(*)[NN]>(&sL[0][0]);
+  double(*const srd)[NN] = reinterpret_cast<double(*)[NN]>(&sH[0][0][0]);
   const int tid = threadIdx.x, el0 = tid / NN;
   const bool act0 = el0 < EB && (long)blockIdx.x * EB + el0 < mp.K;
   const int el = act0 ? el0 : 0, q = act0 ? tid - el0 * NN : 0;  // idle lanes shadow lane 0
@@ -675,14 +679,18 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
   for (int t = tid; t < NP * NP; t += 64) sV[t / NP][t % NP] = H->V[t / NP][t % NP];
   if (act0) sw[el][q] = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
   __syncthreads();
-  // sum factorisation: Hm[qj][a][a'] = sum_qi W[qj][qi] V[qi][a] V[qi][a']
+  // sum factorisation: Hm[qj][a][a'] = sum_qi W[qj][qi] V[qi][a] V[qi][a'], symmetric in (a, a'),
+  // kept for a <= a' (entry p of a line runs over (0, 0..NP-1), (1, 1..NP-1), ...)
   if (act0)
-    for (int t = q; t < NP * NP * NP; t += NN) {
-      const int jj = t / (NP * NP), aa = t - jj * NP * NP, a = aa / NP, a2 = aa - a * NP;
+    for (int t = q; t < NP * NPS; t += NN) {
+      const int jj = t / NPS;
+      int p = t - jj * NPS, a = 0;
+      while (p >= NP - a) { p -= NP - a; ++a; }
+      const int a2 = a + p;
       double s = 0.0;
 #pragma unroll
       for (int ii = 0; ii < NP; ++ii) s += sw[el][jj * NP + ii] * sV[ii][a] * sV[ii][a2];
-      sH[el][jj][aa] = s;
+      sH[el][jj][t - jj * NPS] = s;
     }
   __syncthreads();
   // (LDS stores below go through address selects, not branches: a lane that must not write
@@ -692,11 +700,17 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
   const int rq = q * (q + 1) / 2;
   {
     const int ka = mode_a(q), kb = mode_b(q);
+    int hx[NP];  // position of the pair (min(a_q, a'), max(a_q, a')) in a line of sH
+#pragma unroll
+    for (int a2 = 0; a2 < NP; ++a2) {
+      const int lo = ka < a2 ? ka : a2, hi = ka < a2 ? a2 : ka;
+      hx[a2] = lo * NP - lo * (lo - 1) / 2 + (hi - lo);
+    }
     double w[NP][NP];
 #pragma unroll
     for (int jj = 0; jj < NP; ++jj)
 #pragma unroll
-      for (int a2 = 0; a2 < NP; ++a2) w[jj][a2] = sV[jj][kb] * sH[el][jj][ka * NP + a2];
+      for (int a2 = 0; a2 < NP; ++a2) w[jj][a2] = sV[jj][kb] * sH[el][jj][hx[a2]];
 #pragma unroll
     for (int k2 = 0; k2 < NN; ++k2) {
       double s = 0.0;
