@@ -95,14 +95,14 @@ def oe_pp_bytes(K, nn):
 
 def kernel_sha(kind="stage"):
     """Hash of the source a hydro kernel is built from.  "stage": hydro.hip up to the end of the
-    stage kernel (its device helpers and element statistics), its launcher, and the headers it
-    includes; edits elsewhere (the OE/PP map, other launchers) leave its counters valid.
+    stage kernel (its device helpers and element statistics), its launch helpers and launcher, and
+    the headers it includes; edits elsewhere (the OE/PP map) leave its counters valid.
     "oe_pp": hydro.hip up to the end of the stage map (so the stage kernel's source as well), its
     launcher, and the same headers."""
     src = open(KERNEL_SRC, encoding="utf-8").read()
     if kind == "stage":
         end = src.index("template <int P>\n__global__ __launch_bounds__(256) void k_elem_stats(")
-        a = src.index("int hydro_stage_a(")
+        a = src.index("static int eb_of(")  # launch helpers (block size choice) and the launcher
         b = src.index("int line_global_reduce(", a)
     elif kind == "oe_pp":
         end = src.index("}  // namespace\n", src.index("void k_hydro_oe_pp("))
@@ -111,7 +111,7 @@ def kernel_sha(kind="stage"):
     else:
         raise ValueError(kind)
     h = hashlib.sha256((src[:end] + src[a:b]).encode())
-    for name in ("common.h", "xcd.h", "ec_log.h"):
+    for name in ("common.h", "xcd.h", "ec_log.h", "rsqrt.h"):
         h.update(open(os.path.join(os.path.dirname(KERNEL_SRC), name), "rb").read())
     return h.hexdigest()[:16]
 

@@ -136,6 +136,7 @@ int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stre
   c->mp.hx = (d.x1 - d.x0) / d.nx; c->mp.hy = (d.y1 - d.y0) / d.ny;
   c->mp.J = c->mp.hx * c->mp.hy / 4.0; c->mp.gamma = d.gamma;
   c->mp.rhx = 1.0 / c->mp.hx; c->mp.rhy = 1.0 / c->mp.hy;
+  c->mp.gk = 0.5 / (c->mp.gamma - 1.0);
   c->mp.r4K = 1.0 / (4.0 * (double)c->mp.K); c->mp.r4nx = 1.0 / (4.0 * d.nx); c->mp.r4ny = 1.0 / (4.0 * d.ny);
   c->G = (long)d.nx * d.ny * c->M1 * c->M1;
   build_hydro_tables(c->p, &c->h_ht);

@@ -54,6 +54,7 @@ struct MeshP {
   long K;
   double hx, hy, J, gamma;
   double rhx, rhy;         // 1 / hx, 1 / hy
+  double gk;               // 1 / (2 (gamma - 1)), the energy coefficient of the EC flux
   double r4K, r4nx, r4ny;  // 1 / (4 K), 1 / (4 nx), 1 / (4 ny): element-average sums to means
   unsigned nx_mul;  // element row of e: (e * nx_mul) >> nx_sh, see elem_xy
   int nx_sh;

@@ -13,6 +13,7 @@
 #include "common.h"
 #include "xcd.h"
 #include "ec_log.h"
+#include "rsqrt.h"
 
 namespace {
 
@@ -30,10 +31,10 @@ struct Prim {
 __device__ __forceinline__ Prim make_prim(const double U[5], double g) {
   Prim q;
   q.r = U[0];
-  const double ir = 1.0 / U[0];
+  const double ir = rcp_refined(U[0]);  // rho > 0 on admissible states
   q.ux = U[1] * ir; q.uy = U[2] * ir; q.uz = U[3] * ir;
   const double p = (g - 1.0) * (U[4] - 0.5 * (U[1] * q.ux + U[2] * q.uy + U[3] * q.uz));
-  q.b = 0.5 * q.r / p;
+  q.b = 0.5 * q.r * rcp_refined(p);  // p > 0 on admissible states
   q.lr = log_ec(q.r); q.lb = log_ec(q.b);
   return q;
 }
@@ -64,7 +65,7 @@ __device__ __forceinline__ void ecflux(const Prim& L, const Prim& R, double gk, 
   const Frac fb = lmean_frac(L.b, R.b, L.lb, R.lb);
   const double sb = L.b + R.b;
   const double t1 = fr.d * fb.n;
-  const double Q = 1.0 / (t1 * sb);
+  const double Q = rcp_refined(t1 * sb);  // nonzero: each factor is a positive sum or a nonzero difference
   const double rl = fr.n * fb.n * sb * Q;
   const double ibl = fb.d * fr.d * sb * Q;
   const double ph = 0.5 * (L.r + R.r) * t1 * Q;
@@ -82,7 +83,7 @@ __device__ __forceinline__ void ecflux(const Prim& L, const Prim& R, double gk, 
 // physical flux in direction D (0: x, 1: y, a run-time value so that x and y faces can share one
 // code path), with the normal velocity and the sound speed
 __device__ __forceinline__ void physflux(const double U[5], double g, int D, double F[5], double& ud, double& c) {
-  const double ir = 1.0 / U[0];
+  const double ir = rcp_refined(U[0]);
   const double ux = U[1] * ir, uy = U[2] * ir, uz = U[3] * ir;
   const double p = (g - 1.0) * (U[4] - 0.5 * (U[1] * ux + U[2] * uy + U[3] * uz));
   ud = D == 0 ? ux : uy;
@@ -98,12 +99,12 @@ __device__ __forceinline__ void physflux(const double U[5], double g, int D, dou
 // neighbour's un: LLF (eq. euler-lf-flux) or, for tests, the EC flux.  Both are symmetric in their
 // two states except for the LLF jump U_R - U_L = sgn (un - uo) (sgn = +1 when the neighbour is the
 // plus side), so no left/right copies are formed.
-__device__ __forceinline__ void face_flux(const double uo[5], const double un[5], double sgn, double g, int D,
-                                          int iface, double F[5]) {
+__device__ __forceinline__ void face_flux(const double uo[5], const double un[5], double sgn, double g, double gk,
+                                          int D, int iface, double F[5]) {
   if (iface == 1) {
     Prim a = make_prim(uo, g), b = make_prim(un, g);
-    if (D == 0) ecflux<0>(a, b, 0.5 / (g - 1.0), F);
-    else ecflux<1>(a, b, 0.5 / (g - 1.0), F);
+    if (D == 0) ecflux<0>(a, b, gk, F);
+    else ecflux<1>(a, b, gk, F);
     return;
   }
   double Fo[5], Fn[5], udo, co, udn, cn;
@@ -124,8 +125,8 @@ __device__ __forceinline__ void volume_dir(const Prim& me, double acc[5], bool a
   using C = Cfg<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, ND = C::ND;
   const int pos = D == 0 ? i : j, line = D == 0 ? j : i;
-  const double sc = D == 0 ? 2.0 / mp.hx : 2.0 / mp.hy;
-  const double gk = 0.5 / (mp.gamma - 1.0);
+  const double sc = 2.0 * (D == 0 ? mp.rhx : mp.rhy);
+  const double gk = mp.gk;
   // sb layout: [el][line][owner pos][dslot][5]
   double* sbl = sb + ((long)(el * NP + line) * NP) * ND * 5;
   if (act) {
@@ -191,9 +192,9 @@ __device__ __forceinline__ void surface_terms(double acc[5], bool act, int el, i
       double uo[5], un[5], F[5];
 #pragma unroll
       for (int c = 0; c < 5; ++c) { uo[c] = Us[c * KN + e * NN + qo]; un[c] = Us[c * KN + en * NN + qn]; }
-      face_flux(uo, un, side ? 1.0 : -1.0, mp.gamma, D, iface, F);
-      const double sc = D == 0 ? 2.0 / mp.hx : 2.0 / mp.hy;
-      const double s = side ? -(sc / T->w[P]) : sc / T->w[0];
+      face_flux(uo, un, side ? 1.0 : -1.0, mp.gamma, mp.gk, D, iface, F);
+      const double sc = 2.0 * (D == 0 ? mp.rhx : mp.rhy);
+      const double s = side ? -(sc * rcp_refined(T->w[P])) : sc * rcp_refined(T->w[0]);
 #pragma unroll
       for (int c = 0; c < 5; ++c) sf[f * 5 + c] = s * F[c];
     }
@@ -272,7 +273,7 @@ __device__ __forceinline__ void element_stats(double* svf, double* sst, bool act
 
 // MODE 0: out = L_E(Us).  MODE 1: out = ca*Un + cb*(Us + tau*L_E(Us)) plus element statistics.
 template <int P, int MODE, int BS>
-__global__ __launch_bounds__(BS) void k_hydro_stage(const double* __restrict__ Us, const double* __restrict__ Un,
+__global__ __launch_bounds__(BS, P == 4 ? 4 : 1) void k_hydro_stage(const double* __restrict__ Us, const double* __restrict__ Un,
                                                     double* __restrict__ out, double* __restrict__ stats,
                                                     int* __restrict__ flag, const HydroTab* __restrict__ T, MeshP mp,
                                                     double ca, double cb, double tau, int iface) {
@@ -757,6 +758,13 @@ __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, lon
 
 hipEvent_t* timing_slot(mhd25_ctx* c, int kid);
 static int eb_of(int p) { return 256 / ((p + 1) * (p + 1)); }
+// threads per block of the hydro stage kernel: the tuned value if set, else 128 up to N = 4 (all
+// lanes but three carry nodes, and the kernel fits 128 VGPRs without spills) and 256 above (fewer
+// idle lanes for (N+1)^2 = 36, 49)
+static int stage_block(const mhd25_ctx* c) {
+  if (c->hydro_bs == 128 || c->hydro_bs == 256) return c->hydro_bs;
+  return c->p <= 4 ? 128 : 256;
+}
 
 static int check(mhd25_ctx* c, hipError_t e, const char* what) {
   if (e != hipSuccess) { c->err = std::string(what) + ": " + hipGetErrorString(e); return -2; }
@@ -764,7 +772,7 @@ static int check(mhd25_ctx* c, hipError_t e, const char* what) {
 }
 
 int hydro_rhs(mhd25_ctx* c, const double* U, double* dU) {
-  const int bs = c->hydro_bs == 128 ? 128 : 256;
+  const int bs = stage_block(c);
   const int eb = bs / ((c->p + 1) * (c->p + 1));
   const long blocks = (c->mp.K + eb - 1) / eb;
 #define L0(P)                                                                                                      \
@@ -779,7 +787,7 @@ int hydro_rhs(mhd25_ctx* c, const double* U, double* dU) {
 
 // raw stage + statistics + line/global reductions
 int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust, double ca, double cb, double tau) {
-  const int bs = c->hydro_bs == 128 ? 128 : 256;
+  const int bs = stage_block(c);
   const int eb = bs / ((c->p + 1) * (c->p + 1));
   const long blocks = (c->mp.K + eb - 1) / eb;
   hipEvent_t* ev = c->timing ? timing_slot(c, 0) : nullptr;

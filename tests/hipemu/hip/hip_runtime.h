@@ -25,6 +25,7 @@
 #define __shared__ static
 #define HIP_SYMBOL(x) (&x)
 #define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt(x))  // hardware 1/sqrt estimate
+#define __builtin_amdgcn_rcp(x) (1.0 / (x))  // hardware 1/x estimate
 
 struct dim3 {
   unsigned x, y, z;
