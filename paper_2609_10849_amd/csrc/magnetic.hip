@@ -133,7 +133,7 @@ __global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, c
       sx += tDWQ[qy][j] * sh[el][0][qy * A + i];
       sy += tWQ[qy][j] * sh[el][1][qy * A + i];
     }
-    Lz[e * AA + t] = (2.0 / mp.hy) * sx - (2.0 / mp.hx) * sy;
+    Lz[e * AA + t] = (2.0 * mp.rhy) * sx - (2.0 * mp.rhx) * sy;
   }
   if (!R2 && t < AB) {
     {  // N_x node: i Gauss (B), j GLL (A); index j*B + i
@@ -141,14 +141,14 @@ __global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, c
       double s = 0.0;
 #pragma unroll
       for (int qy = 0; qy < B; ++qy) s += twg[qy] * szg[el][qy * B + i] * tDWG[qy][j];
-      Lx[e * AB + t] = -(2.0 / mp.hy) * mp.J * twg[i] * s;
+      Lx[e * AB + t] = -(2.0 * mp.rhy) * mp.J * twg[i] * s;
     }
     {  // N_y node: i GLL (A), j Gauss (B); index j*A + i
       const int i = t % A, j = t / A;
       double s = 0.0;
 #pragma unroll
       for (int qx = 0; qx < B; ++qx) s += twg[qx] * szg[el][j * B + qx] * tDWG[qx][i];
-      Ly[e * AB + t] = (2.0 / mp.hx) * mp.J * twg[j] * s;
+      Ly[e * AB + t] = (2.0 * mp.rhx) * mp.J * twg[j] * s;
     }
   }
 }
@@ -414,8 +414,8 @@ __global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update(MagIO
       dbx += tDWG[j][k] * sez[el][k * A + i];
       dby += tDWG[i][k] * sez[el][j * A + k];
     }
-    dbx *= -(2.0 / mp.hy);
-    dby *= (2.0 / mp.hx);
+    dbx *= -(2.0 * mp.rhy);
+    dby *= (2.0 * mp.rhx);
     double dxey = 0.0, dyex = 0.0;
     if constexpr (!R2) {
 #pragma unroll
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update(MagIO
       dyex += tDWV[j][l] * s;
     }
     }
-    const double dbz = R2 ? 0.0 : -((2.0 / mp.hx) * dxey - (2.0 / mp.hy) * dyex);
+    const double dbz = R2 ? 0.0 : -((2.0 * mp.rhx) * dxey - (2.0 * mp.rhy) * dyex);
     if (MODE == 0) {
       io.obx[g] = dbx; io.oby[g] = dby; io.obz[g] = dbz;
     } else {
@@ -556,16 +556,17 @@ __global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update(MagIO
         for (int i = 0; i < A; ++i) s += tIWP[qi][i] * sjz[el][j * A + i];
         jz += tIWP[qj][j] * s;
       }
-      de = et * (jx * jx + jy * jy + jz * jz) / rq;
+      de = et * (jx * jx + jy * jy + jz * jz) * rcp_refined(rq);  // rho > 0
     }
     // (the 2D2V system writes u_z = 0, so that no stage buffer carries a stale value)
+    const double irm = rcp_refined(rq * Mq);  // 1 / (rho M), both positive
     if (MODE == 0) {
-      for (int d = 0; d < 3; ++d) io.ou[d * KN + n] = (R2 && d == 2) ? 0.0 : du[d] / (rq * Mq);
+      for (int d = 0; d < 3; ++d) io.ou[d * KN + n] = (R2 && d == 2) ? 0.0 : du[d] * irm;
       io.oe[n] = de;
     } else {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const double v = (R2 && d == 2) ? 0.0 : y0[d] + (io.cb * io.tau) * (du[d] / (rq * Mq));
+        const double v = (R2 && d == 2) ? 0.0 : y0[d] + (io.cb * io.tau) * (du[d] * irm);
         io.ou[d * KN + n] = v;
         vnew[d] = v;
       }
@@ -871,7 +872,7 @@ __global__ __launch_bounds__(256, (P == 4 && M == 3) ? 6 : 1) void k_vel_sensor(
       for (int i = 0; i < B; ++i) s += tVP[qi][i] * sbb[el][2 * AB + j * B + i];
       bzv += tVP[qj][j] * s;
     }
-    const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) / sqrt(rq);
+    const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) * rsqrt_refined(rq);  // rho > 0
     wsx = fabs(uu[0]) + va;
     wsy = fabs(uu[1]) + va;
   }
@@ -1133,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_ar_traces(const double* __restrict__ rh
       for (int i = 0; i < B; ++i) s += tVP[qi][i] * sbz[el][j * B + i];
       bzv += tVP[qj][j] * s;
     }
-    const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) / sqrt(rho[e * NN + q]);
+    const double va = sqrt(bxv * bxv + byv * byv + bzv * bzv) * rsqrt_refined(rho[e * NN + q]);  // rho > 0
     sv[el][0][q] = fabs(u[e * NN + q]) + va;
     sv[el][1][q] = fabs(u[KN + e * NN + q]) + va;
     for (int t = q; t < 8 * A; t += NN) {
