@@ -666,8 +666,10 @@ __global__ __launch_bounds__(BS) void k_hydro_oe_pp(const double* __restrict__ U
 // by a fixed tree.
 constexpr int LRC = 8, LRP = 256 / LRC;
 
+template <int NC>
 __global__ __launch_bounds__(256) void k_line_reduce(const double* __restrict__ stats, double* __restrict__ lines,
-                                                     int nx, int ny, int nc, const int* __restrict__ flag) {
+                                                     int nx, int ny, const int* __restrict__ flag) {
+  constexpr int nc = NC;  // components per element record (compile-time, so that no load waits on a branch)
   __shared__ double red[15][256];
   if (flag && *flag) return;
   const int b = blockIdx.x, t = threadIdx.x;
@@ -685,11 +687,15 @@ __global__ __launch_bounds__(256) void k_line_reduce(const double* __restrict__ 
         v[3 * c + 2] = fmax(v[3 * c + 2], st[3 * c + 2]);
       }
   };
+  // (unrolled by 4 so that four records' loads are in flight at once; the accumulation order, and so
+  // every result bit, is that of the plain loop)
   if (b < ny) {
+#pragma unroll 4
     for (int k = t; k < nx; k += 256) take((long)b * nx + k);
   } else {
     const int col = (b - ny) * LRC + t % LRC, ph = t / LRC;
     if (col < nx)
+#pragma unroll 4
       for (int r = ph; r < ny; r += LRP) take((long)r * nx + col);
   }
 #pragma unroll
@@ -771,6 +777,17 @@ static int check(mhd25_ctx* c, hipError_t e, const char* what) {
   return 0;
 }
 
+// row and column reductions of nc-component element records (nc = 1..5)
+static int launch_line_reduce(mhd25_ctx* c, const double* stats, int nc, const int* flag) {
+  const dim3 grid(c->mp.ny + (c->mp.nx + LRC - 1) / LRC);
+#define LR(NC) hipLaunchKernelGGL((k_line_reduce<NC>), grid, dim3(256), 0, c->stream, stats, c->lines, c->mp.nx, \
+                                   c->mp.ny, flag)
+  switch (nc) { case 1: LR(1); break; case 2: LR(2); break; case 3: LR(3); break; case 4: LR(4); break;
+                case 5: LR(5); break; default: c->err = "line reduction: unsupported component count"; return -2; }
+#undef LR
+  return 0;
+}
+
 int hydro_rhs(mhd25_ctx* c, const double* U, double* dU) {
   const int bs = stage_block(c);
   const int eb = bs / ((c->p + 1) * (c->p + 1));
@@ -802,15 +819,13 @@ int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust,
   if (ev) hipEventRecord(ev[1], c->stream);
   int r = check(c, hipGetLastError(), "hydro stage launch");
   if (r) return r;
-  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.ny + (c->mp.nx + LRC - 1) / LRC), dim3(256), 0, c->stream, c->stats, c->lines,
-                     c->mp.nx, c->mp.ny, 5, c->d_flag);
+  if (const int rl = launch_line_reduce(c, c->stats, 5, c->d_flag)) return rl;
   hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, 5, c->d_flag);
   return check(c, hipGetLastError(), "reduce launch");
 }
 
 int line_global_reduce(mhd25_ctx* c, const double* stats, int nc, const int* flag) {
-  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.ny + (c->mp.nx + LRC - 1) / LRC), dim3(256), 0, c->stream, stats, c->lines,
-                     c->mp.nx, c->mp.ny, nc, flag);
+  if (const int r = launch_line_reduce(c, stats, nc, flag)) return r;
   hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, nc, flag);
   return check(c, hipGetLastError(), "reduce launch");
 }
@@ -820,8 +835,7 @@ int hydro_stats_only(mhd25_ctx* c, const double* U, int* flag) {
 #define LS(P) hipLaunchKernelGGL((k_elem_stats<P>), dim3(blocks), dim3(256), 0, c->stream, U, c->stats, flag, c->d_ht, c->mp)
   DISPATCH_P(c->p, LS);
 #undef LS
-  hipLaunchKernelGGL(k_line_reduce, dim3(c->mp.ny + (c->mp.nx + LRC - 1) / LRC), dim3(256), 0, c->stream, c->stats, c->lines,
-                     c->mp.nx, c->mp.ny, 5, nullptr);
+  if (const int rl = launch_line_reduce(c, c->stats, 5, nullptr)) return rl;
   hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, 5, nullptr);
   return check(c, hipGetLastError(), "stats launch");
 }
