@@ -84,6 +84,15 @@ def valu_object(flops_alg, flops_ctr, avg_ms):
     return out
 
 
+def traffic_rate(traffic, avg_ms):
+    """Counter-measured HBM bytes per launch over the launch time: GB/s and the fraction of the
+    HBM peak, or None when the counters are not valid for this kernel source."""
+    if traffic is None:
+        return None, None
+    r = traffic / (avg_ms * 1e-3) / 1e9
+    return r, r / HBM_PEAK_GBS
+
+
 def oe_pp_bytes(K, nn):
     """Algorithmic HBM bytes of one stage-map launch, averaged over the six launches of a Strang
     step: the raw stage read and the limited stage written (one U each), the six element
@@ -358,6 +367,7 @@ def main():
     ach = stage_bytes(K, nn) / (avg_ms * 1e-3) / 1e9
     tr = traffic_per_launch("stage")
     avg_b = kms_b / max(launches_b, 1)
+    tr_b = traffic_per_launch("oe_pp")
     ach_b = oe_pp_bytes(K, nn) / (avg_b * 1e-3) / 1e9
     out = {
         "metric": "DOF-stage updates/s (FP64) per Strang step",
@@ -379,11 +389,14 @@ def main():
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                      "traffic": tr, "kernel": "k_hydro_stage<4,1> (L_E + SSP combine + element statistics)",
                      "avg_ms": avg_ms, "launches": launches,
+                     "traffic_achieved": traffic_rate(tr, avg_ms)[0], "traffic_frac": traffic_rate(tr, avg_ms)[1],
                      "valu": valu_object(stage_flops(K, N + 1), valu_per_launch("stage"), avg_ms)},
         "roofline_oe_pp": {"bound": "hbm", "achieved": ach_b, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach_b / HBM_PEAK_GBS, "traffic": traffic_per_launch("oe_pp"),
+                           "frac": ach_b / HBM_PEAK_GBS, "traffic": tr_b,
                            "kernel": "k_hydro_oe_pp<4,128> (hydro OE + PP map)", "avg_ms": avg_b,
                            "launches": launches_b,
+                           "traffic_achieved": traffic_rate(tr_b, avg_b)[0],
+                           "traffic_frac": traffic_rate(tr_b, avg_b)[1],
                            "valu": valu_object(oe_pp_flops(K, N + 1), valu_per_launch("oe_pp"), avg_b)},
         "accepted_substep_rate": accepted / max(attempted, 1),
     }

@@ -45,6 +45,13 @@ def test_algorithmic_flop_counts():
     assert abs(v["algorithmic"] - 9825 * K / 1e-3 / 1e12) < 1e-9 and v["counter"] is None
 
 
+def test_traffic_rate():
+    import bench
+    assert bench.traffic_rate(None, 1.0) == (None, None)
+    r, f = bench.traffic_rate(4e9, 1.0)  # 4 GB in 1 ms
+    assert abs(r - 4000.0) < 1e-9 and abs(f - 0.5) < 1e-12
+
+
 def test_kernel_hashes():
     import bench
     h, g = bench.kernel_sha("stage"), bench.kernel_sha("oe_pp")
