@@ -58,15 +58,15 @@ def oe_pp_flops(K, NP):
     return K * (jumps + sigma + 40 * NP ** 3 + 5 * nn + 4 * NP + 30 * nn)
 
 
-def valu_per_launch(kind):
+def valu_per_launch(kind, K=1048576, N=4):
     """Executed FP64 flops per launch of a hydro kernel from the committed SQ counter run
     (SQ_INSTS_VALU_FLOPS_FP64 counts 2 FMA + ADD + MUL + TRANS instructions per wave; times
-    the active lanes), or None when missing or taken on a different kernel source."""
+    the active lanes), or None when missing or taken on a different kernel source or workload."""
     try:
         d = json.load(open(VALU_FILE))[kind]
     except (OSError, ValueError, KeyError):
         return None
-    if d.get("kernel_src_sha") != kernel_sha(kind):
+    if d.get("kernel_src_sha") != kernel_sha(kind) or d.get("elements") != K or d.get("N") != N:
         return None
     return d.get("flops_per_launch")
 
@@ -125,14 +125,14 @@ def kernel_sha(kind="stage"):
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch(kind="stage"):
+def traffic_per_launch(kind="stage", K=1048576, N=4):
     """HBM bytes per launch of a hydro kernel from the committed rocprofv3 counter runs, or None
-    when they are missing or were taken on a different kernel source."""
+    when they are missing or were taken on a different kernel source or workload (K, N)."""
     try:
         d = json.load(open(TRAFFIC_FILES[kind]))
     except (OSError, ValueError):
         return None
-    if d.get("kernel_src_sha") != kernel_sha(kind):
+    if d.get("kernel_src_sha") != kernel_sha(kind) or d.get("elements") != K or d.get("N") != N:
         return None
     return d.get("bytes_per_launch")
 
@@ -365,9 +365,9 @@ def main():
     value = K * nn * 9 / (t / args.steps)
     avg_ms = kms / max(launches, 1)
     ach = stage_bytes(K, nn) / (avg_ms * 1e-3) / 1e9
-    tr = traffic_per_launch("stage")
+    tr = traffic_per_launch("stage", K, N)
     avg_b = kms_b / max(launches_b, 1)
-    tr_b = traffic_per_launch("oe_pp")
+    tr_b = traffic_per_launch("oe_pp", K, N)
     ach_b = oe_pp_bytes(K, nn) / (avg_b * 1e-3) / 1e9
     out = {
         "metric": "DOF-stage updates/s (FP64) per Strang step",
@@ -390,14 +390,14 @@ def main():
                      "traffic": tr, "kernel": "k_hydro_stage<4,1> (L_E + SSP combine + element statistics)",
                      "avg_ms": avg_ms, "launches": launches,
                      "traffic_achieved": traffic_rate(tr, avg_ms)[0], "traffic_frac": traffic_rate(tr, avg_ms)[1],
-                     "valu": valu_object(stage_flops(K, N + 1), valu_per_launch("stage"), avg_ms)},
+                     "valu": valu_object(stage_flops(K, N + 1), valu_per_launch("stage", K, N), avg_ms)},
         "roofline_oe_pp": {"bound": "hbm", "achieved": ach_b, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": ach_b / HBM_PEAK_GBS, "traffic": tr_b,
                            "kernel": "k_hydro_oe_pp<4,128> (hydro OE + PP map)", "avg_ms": avg_b,
                            "launches": launches_b,
                            "traffic_achieved": traffic_rate(tr_b, avg_b)[0],
                            "traffic_frac": traffic_rate(tr_b, avg_b)[1],
-                           "valu": valu_object(oe_pp_flops(K, N + 1), valu_per_launch("oe_pp"), avg_b)},
+                           "valu": valu_object(oe_pp_flops(K, N + 1), valu_per_launch("oe_pp", K, N), avg_b)},
         "accepted_substep_rate": accepted / max(attempted, 1),
     }
     if not args.no_extras and not args.reduced_2d2v:

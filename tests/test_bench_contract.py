@@ -52,6 +52,15 @@ def test_traffic_rate():
     assert abs(r - 4000.0) < 1e-9 and abs(f - 0.5) < 1e-12
 
 
+def test_counter_records_apply_only_to_their_workload():
+    import bench
+    for kind in ("stage", "oe_pp"):
+        # a record is never attached to another mesh size or degree
+        assert bench.traffic_per_launch(kind, 64 * 64, 4) is None
+        assert bench.traffic_per_launch(kind, 1024 * 1024, 3) is None
+        assert bench.valu_per_launch(kind, 64 * 64, 4) is None
+
+
 def test_kernel_hashes():
     import bench
     h, g = bench.kernel_sha("stage"), bench.kernel_sha("oe_pp")
