@@ -206,10 +206,12 @@ def adjoint_ratio():
             "workload": "noisy isentropic vortex, 128x128 elements, N=3, k=2"}
 
 
-def batched_speedup(steps=50):
+def batched_speedup(steps=50, streams=False):
     """Ensemble of 64 uneven runs (n in {32..192}, N in {2,3,4}, k = N-1, vortex amplitude and
     field drawn from PCG64 seed 0; full stabilisation; per-run dt from CFL 0.3 at the start):
-    time per Strang step of all runs, sequential plain launches vs the captured multi-branch graph."""
+    time per Strang step of all runs, sequential plain launches vs the batch step: the captured
+    multi-branch graph, or with streams=True the same deferred steps launched directly on the
+    concurrent branch streams."""
     import numpy as np
     import torch
 
@@ -233,11 +235,11 @@ def batched_speedup(steps=50):
     def run(sequential, nsteps):
         g = [[dev(a) for a in st] for st in states]
         args = [[x[i] for x in g] for i in range(4)]
-        B.strang_step(*args, dts, sequential=sequential)  # warm-up (and capture)
+        B.strang_step(*args, dts, sequential=sequential, streams=streams)  # warm-up (and capture)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(nsteps):
-            r, _ = B.strang_step(*args, dts, sequential=sequential)
+            r, _ = B.strang_step(*args, dts, sequential=sequential, streams=streams)
         torch.cuda.synchronize()
         return 1e3 * (time.perf_counter() - t0) / nsteps
 
@@ -246,7 +248,7 @@ def batched_speedup(steps=50):
     B.close()
     nodes = sum(L.K * (L.p + 1) ** 2 for L in layouts)
     return {"value": ts / tb, "sequential_ms_per_step": ts, "batched_ms_per_step": tb, "runs": 64,
-            "steps": steps, "nodes": nodes}
+            "steps": steps, "nodes": nodes, "path": "branch streams, no graph" if streams else "captured graph"}
 
 
 def reduced_2d2v(S, g, steps=10, warm=2):
@@ -407,6 +409,7 @@ def main():
         # the captured-graph ensemble path is held off the GPU until the cause of a host
         # segmentation fault seen in one build of it is shown (last measured speedup: 1.63)
         out["batched_speedup"] = None
+        out["batched_streams_speedup"] = batched_speedup(steps=min(args.steps, 20), streams=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

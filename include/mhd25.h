@@ -187,6 +187,12 @@ void mhd25_batch_destroy(mhd25_batch* b);
  * halving are re-done individually.  Returns 0, or the first nonzero run status. */
 int mhd25_batch_strang_step(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
                             double* const* Bz, const double* dt, mhd25_report* rep);
+/* The same step without a graph: each run's deferred step (no host read inside) is launched
+ * directly on its branch stream, between a fork event on the context stream and join events that
+ * the context stream waits on; then, as above, runs that need a halving are re-done individually.
+ * Same arguments, layouts, results and return codes as mhd25_batch_strang_step. */
+int mhd25_batch_strang_step_streams(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
+                                    double* const* Bz, const double* dt, mhd25_report* rep);
 /* Sequential reference: the same step run by run with the plain per-run kernels. */
 int mhd25_batch_strang_step_sequential(mhd25_batch* b, double* const* U, double* const* Bx,
                                        double* const* By, double* const* Bz, const double* dt,

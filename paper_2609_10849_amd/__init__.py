@@ -82,6 +82,7 @@ _SIGS = {
     "mhd25_batch_destroy": (None, [_dp]),
     "mhd25_batch_strang_step": (ctypes.c_int, [_dp] * 6 + [ctypes.POINTER(Report)]),
     "mhd25_batch_strang_step_sequential": (ctypes.c_int, [_dp] * 6 + [ctypes.POINTER(Report)]),
+    "mhd25_batch_strang_step_streams": (ctypes.c_int, [_dp] * 6 + [ctypes.POINTER(Report)]),
     "mhd25_batch_set_tuning": (ctypes.c_int, [_dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
     "mhd25_batch_autotune": (ctypes.c_int, [_dp] * 6 + [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
 }
@@ -327,9 +328,16 @@ class Batch:
             _ptr(t)
         return (self._ptrs(U), self._ptrs(Bx), self._ptrs(By), self._ptrs(Bz), (ctypes.c_double * self.n)(*dt))
 
-    def strang_step(self, U, Bx, By, Bz, dt, sequential=False):
+    def strang_step(self, U, Bx, By, Bz, dt, sequential=False, streams=False):
+        """One Strang step of every run: replayed from the captured graph (default), launched
+        directly on the branch streams (streams=True), or run by run (sequential=True)."""
         reps = (Report * self.n)()
-        fn = self.lib.mhd25_batch_strang_step_sequential if sequential else self.lib.mhd25_batch_strang_step
+        if sequential:
+            fn = self.lib.mhd25_batch_strang_step_sequential
+        elif streams:
+            fn = self.lib.mhd25_batch_strang_step_streams
+        else:
+            fn = self.lib.mhd25_batch_strang_step
         a = self._args(U, Bx, By, Bz, dt)
         r = fn(self.h, *a, reps)
         if r < 0:

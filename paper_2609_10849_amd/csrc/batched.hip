@@ -183,6 +183,33 @@ static int capture(mhd25_batch* b, double* const* U, double* const* Bx, double* 
   return 0;
 }
 
+// The same deferred steps launched directly on the branch streams, without a graph: a fork event
+// on the caller's stream, every branch waits on it, each run is issued on its branch, and the
+// caller's stream waits on every branch's join event.  The joins are recorded even when a launch
+// fails, so the caller's stream never runs ahead of work already issued.
+static int launch_streams(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
+                          double* const* Bz, const double* dt) {
+  std::vector<int> br = assign(b);
+  if (hipEventRecord(b->ev_fork, b->main) != hipSuccess) { b->err = "fork event"; return -2; }
+  for (int s = 0; s < b->nbranch; ++s)
+    if (hipStreamWaitEvent(b->br[s], b->ev_fork, 0) != hipSuccess) { b->err = "fork wait"; return -2; }
+  int rc = 0;
+  for (int r = 0; r < b->nruns && !rc; ++r) {
+    mhd25_ctx* c = b->ctx[r];
+    c->stream = b->br[br[r]];
+    rc = strang_deferred(c, U[r], Bx[r], By[r], Bz[r], dt[r], b->d_fail + r, b->d_acc + 3 * r, b->d_eta + r);
+  }
+  for (int r = 0; r < b->nruns; ++r) b->ctx[r]->stream = b->main;
+  for (int s = 0; s < b->nbranch; ++s) {
+    if (hipEventRecord(b->ev_join[s], b->br[s]) != hipSuccess ||
+        hipStreamWaitEvent(b->main, b->ev_join[s], 0) != hipSuccess) {
+      b->err = "join";
+      if (!rc) rc = -2;
+    }
+  }
+  return rc;
+}
+
 static bool same_capture(const mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
                          double* const* Bz, const double* dt) {
   if (!b->captured) return false;
@@ -247,16 +274,21 @@ void mhd25_batch_destroy(mhd25_batch* b) {
   delete b;
 }
 
-int mhd25_batch_strang_step(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
-                            double* const* Bz, const double* dt, mhd25_report* rep) {
-  if (!b || !U || !Bx || !By || !Bz || !dt) return -1;
+}  // extern "C"
+
+static bool batch_args_ok(const mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
+                          double* const* Bz, const double* dt) {
+  if (!b || !U || !Bx || !By || !Bz || !dt) return false;
   for (int r = 0; r < b->nruns; ++r)
-    if (!U[r] || !Bx[r] || !By[r] || !Bz[r] || !(dt[r] > 0.0)) return -1;
-  if (!same_capture(b, U, Bx, By, Bz, dt)) {
-    if (hipStreamSynchronize(b->main) != hipSuccess) { b->err = "sync"; return -2; }
-    BTRY(capture(b, U, Bx, By, Bz, dt));
-  }
-  if (hipGraphLaunch(b->exec, b->main) != hipSuccess) { b->err = "graph launch"; return -2; }
+    if (!U[r] || !Bx[r] || !By[r] || !Bz[r] || !(dt[r] > 0.0)) return false;
+  return true;
+}
+
+// After the runs' deferred steps are on the caller's stream: one small copy returns every run's
+// failure word, limiter counters and A.R. maximum; a run that needed a halving is restored from
+// its entry snapshot and re-done with the ordinary reject-and-halve step.
+static int finish_step(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
+                       double* const* Bz, const double* dt, mhd25_report* rep) {
   hipMemcpyAsync(b->h_fail, b->d_fail, b->nruns * sizeof(int), hipMemcpyDeviceToHost, b->main);
   hipMemcpyAsync(b->h_acc, b->d_acc, 3 * b->nruns * sizeof(long long), hipMemcpyDeviceToHost, b->main);
   hipMemcpyAsync(b->h_eta, b->d_eta, b->nruns * sizeof(double), hipMemcpyDeviceToHost, b->main);
@@ -283,6 +315,26 @@ int mhd25_batch_strang_step(mhd25_batch* b, double* const* U, double* const* Bx,
     if (rep) rep[r] = one;
   }
   return status;
+}
+
+extern "C" {
+
+int mhd25_batch_strang_step(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
+                            double* const* Bz, const double* dt, mhd25_report* rep) {
+  if (!batch_args_ok(b, U, Bx, By, Bz, dt)) return -1;
+  if (!same_capture(b, U, Bx, By, Bz, dt)) {
+    if (hipStreamSynchronize(b->main) != hipSuccess) { b->err = "sync"; return -2; }
+    BTRY(capture(b, U, Bx, By, Bz, dt));
+  }
+  if (hipGraphLaunch(b->exec, b->main) != hipSuccess) { b->err = "graph launch"; return -2; }
+  return finish_step(b, U, Bx, By, Bz, dt, rep);
+}
+
+int mhd25_batch_strang_step_streams(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
+                                    double* const* Bz, const double* dt, mhd25_report* rep) {
+  if (!batch_args_ok(b, U, Bx, By, Bz, dt)) return -1;
+  BTRY(launch_streams(b, U, Bx, By, Bz, dt));
+  return finish_step(b, U, Bx, By, Bz, dt, rep);
 }
 
 int mhd25_batch_strang_step_sequential(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
