@@ -231,6 +231,10 @@ def batched_speedup(steps=50, streams=False):
         dts.append(S.cfl_dt(*[dev(a) for a in st], 0.3))
         S.close()
     B = pk.Batch(layouts, pk.Options.full())
+    if streams:  # tile and branch choice by the event-timed autotuner (on scratch copies; untimed)
+        g0 = [[dev(a) for a in st] for st in states]
+        B.autotune(*[[x[i] for x in g0] for i in range(4)], dts)
+        del g0
 
     def run(sequential, nsteps):
         g = [[dev(a) for a in st] for st in states]
@@ -248,7 +252,8 @@ def batched_speedup(steps=50, streams=False):
     B.close()
     nodes = sum(L.K * (L.p + 1) ** 2 for L in layouts)
     return {"value": ts / tb, "sequential_ms_per_step": ts, "batched_ms_per_step": tb, "runs": 64,
-            "steps": steps, "nodes": nodes, "path": "branch streams, no graph" if streams else "captured graph"}
+            "steps": steps, "nodes": nodes,
+            "path": "branch streams, no graph, autotuned tiles" if streams else "captured graph"}
 
 
 def reduced_2d2v(S, g, steps=10, warm=2):

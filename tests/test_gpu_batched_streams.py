@@ -1,7 +1,10 @@
 """Batched ensemble without a graph: one Strang step of uneven runs launched directly on the
 batch's concurrent branch streams must equal, bit for bit, each run stepped alone with the plain
 entry point (same kernels); one member is checked against the oracle; a member that needs a
-halving takes the individual fallback."""
+halving takes the individual fallback.  The event-timed autotuner (plain launches, no graph)
+writes and reuses its cache."""
+import json
+
 import numpy as np
 import pytest
 
@@ -69,3 +72,24 @@ def test_streams_batch_rejection_fallback():
         for a, b in zip(bat[k], g):
             assert (host(a) == host(b)).all(), k
     B.close()
+
+
+def test_batch_autotune_event_timed(tmp_path):
+    """Tile choice timed with plain launches (no graph capture while tuning), cache written and
+    reused, states untouched."""
+    import paper_2609_10849_amd as pk
+    announce("batch autotune (event-timed tiles)")
+    runs = runs_small()
+    B = pk.Batch([r[0] for r in runs], pk.Options.full())
+    bat = [to_dev(r) for r in runs]
+    before = [host(a).copy() for b in bat for a in b]
+    cache = str(tmp_path / "tune.jsonl")
+    dts = [1e-3] * len(runs)
+    S1 = B.autotune([b[0] for b in bat], [b[1] for b in bat], [b[2] for b in bat], [b[3] for b in bat], dts, cache)
+    assert 2 <= S1 <= 8
+    after = [host(a) for b in bat for a in b]
+    assert all((x == y).all() for x, y in zip(before, after))  # tuning works on scratch copies
+    line = json.loads(open(cache).read().strip().splitlines()[-1])
+    assert line["branches"] == S1
+    S2 = B.autotune([b[0] for b in bat], [b[1] for b in bat], [b[2] for b in bat], [b[3] for b in bat], dts, cache)
+    assert S2 == S1
