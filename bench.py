@@ -324,6 +324,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the adjoint-ratio and ensemble measurements")
     ap.add_argument("--reduced-2d2v", action="store_true",
                     help="time the 2D2V reduced system instead of the general path (for profiling it)")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="time only the 64-run ensemble (streams batch step against sequential launches), for "
+                         "profiling it; prints its own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
@@ -336,6 +339,9 @@ def main():
     from paper_2609_10849_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.ensemble_only:
+        print(json.dumps({"batched_streams_speedup": batched_speedup(steps=args.steps, streams=True)}), flush=True)
+        return
     n, N, k = args.n, 4, 3
     L, U, Bx, By, Bz = W.blast(n, n, N, k)
     S = pk.Solver.from_layout(L, pk.Options.full(reduced_2d2v=int(args.reduced_2d2v)))
