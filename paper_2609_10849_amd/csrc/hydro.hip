@@ -720,31 +720,41 @@ __global__ __launch_bounds__(256) void k_line_reduce(const double* __restrict__ 
   }
 }
 
-// Global reduction of the first `n` line results (the rows) into glob[nc][3].
+// Global reduction of the first `n` line results (the rows) into glob[nc][3]: all NC components in
+// one tree (each component's accumulation order is that of its own tree), so the block passes
+// eight barriers instead of eight per component.
+template <int NC>
 __global__ __launch_bounds__(256) void k_global_reduce(const double* __restrict__ lines, double* __restrict__ glob,
-                                                       int n, int nc, const int* __restrict__ flag) {
-  __shared__ double red[3][256];
+                                                       int n, const int* __restrict__ flag) {
+  __shared__ double red[3 * NC][256];
   if (flag && *flag) return;
   const int t = threadIdx.x;
-  for (int c = 0; c < nc; ++c) {
-    double s = 0.0, mn = DBL_MAX, mx = -DBL_MAX;
-    for (int k = t; k < n; k += 256) {
-      const double* st = lines + ((long)k * nc + c) * 3;
-      s += st[0]; mn = fmin(mn, st[1]); mx = fmax(mx, st[2]);
+  double v[3 * NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) { v[3 * c] = 0.0; v[3 * c + 1] = DBL_MAX; v[3 * c + 2] = -DBL_MAX; }
+  for (int k = t; k < n; k += 256) {
+    const double* st = lines + (long)k * NC * 3;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      v[3 * c] += st[3 * c];
+      v[3 * c + 1] = fmin(v[3 * c + 1], st[3 * c + 1]);
+      v[3 * c + 2] = fmax(v[3 * c + 2], st[3 * c + 2]);
     }
-    red[0][t] = s; red[1][t] = mn; red[2][t] = mx;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (t < w) {
-        red[0][t] += red[0][t + w];
-        red[1][t] = fmin(red[1][t], red[1][t + w]);
-        red[2][t] = fmax(red[2][t], red[2][t + w]);
+  }
+#pragma unroll
+  for (int x = 0; x < 3 * NC; ++x) red[x][t] = v[x];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        red[3 * c][t] += red[3 * c][t + w];
+        red[3 * c + 1][t] = fmin(red[3 * c + 1][t], red[3 * c + 1][t + w]);
+        red[3 * c + 2][t] = fmax(red[3 * c + 2][t], red[3 * c + 2][t + w]);
       }
-      __syncthreads();
-    }
-    if (t == 0) { glob[c * 3] = red[0][0]; glob[c * 3 + 1] = red[1][0]; glob[c * 3 + 2] = red[2][0]; }
     __syncthreads();
   }
+  if (t < 3 * NC) glob[t] = red[t][0];
 }
 
 __global__ void k_reset_attempt(int* flag, unsigned long long* counts) {
@@ -777,11 +787,13 @@ static int check(mhd25_ctx* c, hipError_t e, const char* what) {
   return 0;
 }
 
-// row and column reductions of nc-component element records (nc = 1..5)
-static int launch_line_reduce(mhd25_ctx* c, const double* stats, int nc, const int* flag) {
+// row and column reductions of nc-component element records (nc = 1..5), then the global one
+static int launch_reductions(mhd25_ctx* c, const double* stats, int nc, const int* flag) {
   const dim3 grid(c->mp.ny + (c->mp.nx + LRC - 1) / LRC);
-#define LR(NC) hipLaunchKernelGGL((k_line_reduce<NC>), grid, dim3(256), 0, c->stream, stats, c->lines, c->mp.nx, \
-                                   c->mp.ny, flag)
+#define LR(NC)                                                                                                    \
+  hipLaunchKernelGGL((k_line_reduce<NC>), grid, dim3(256), 0, c->stream, stats, c->lines, c->mp.nx, c->mp.ny,    \
+                     flag);                                                                                       \
+  hipLaunchKernelGGL((k_global_reduce<NC>), dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, flag)
   switch (nc) { case 1: LR(1); break; case 2: LR(2); break; case 3: LR(3); break; case 4: LR(4); break;
                 case 5: LR(5); break; default: c->err = "line reduction: unsupported component count"; return -2; }
 #undef LR
@@ -819,14 +831,12 @@ int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust,
   if (ev) hipEventRecord(ev[1], c->stream);
   int r = check(c, hipGetLastError(), "hydro stage launch");
   if (r) return r;
-  if (const int rl = launch_line_reduce(c, c->stats, 5, c->d_flag)) return rl;
-  hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, 5, c->d_flag);
+  if (const int rl = launch_reductions(c, c->stats, 5, c->d_flag)) return rl;
   return check(c, hipGetLastError(), "reduce launch");
 }
 
 int line_global_reduce(mhd25_ctx* c, const double* stats, int nc, const int* flag) {
-  if (const int r = launch_line_reduce(c, stats, nc, flag)) return r;
-  hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, nc, flag);
+  if (const int r = launch_reductions(c, stats, nc, flag)) return r;
   return check(c, hipGetLastError(), "reduce launch");
 }
 
@@ -835,8 +845,7 @@ int hydro_stats_only(mhd25_ctx* c, const double* U, int* flag) {
 #define LS(P) hipLaunchKernelGGL((k_elem_stats<P>), dim3(blocks), dim3(256), 0, c->stream, U, c->stats, flag, c->d_ht, c->mp)
   DISPATCH_P(c->p, LS);
 #undef LS
-  if (const int rl = launch_line_reduce(c, c->stats, 5, nullptr)) return rl;
-  hipLaunchKernelGGL(k_global_reduce, dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, 5, nullptr);
+  if (const int rl = launch_reductions(c, c->stats, 5, nullptr)) return rl;
   return check(c, hipGetLastError(), "stats launch");
 }
 
