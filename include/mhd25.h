@@ -23,9 +23,12 @@
  *    decision synchronise that stream.  One context belongs to one stream; concurrent
  *    calls on one context are not allowed.
  *  - Return codes: 0 ok; negative = caller or system error (-1 invalid argument, -2 HIP
- *    error, -3 out of device memory, -4 unsupported degree); positive = numerical outcome
- *    with the state left at its value on entry (1: substep not accepted within
- *    max_halvings).  The library never aborts; mhd25_last_error() describes the failure.
+ *    error, -3 out of device memory, -4 unsupported degree (p outside 1..6 or m not in
+ *    {p-1, p})); positive = numerical outcome with the state left at its value on entry
+ *    (1: a hydro substep was not accepted within max_halvings; 2: the input is outside the
+ *    admissible set of section "Conservative ideal MHD": a non-finite value, or a non-positive
+ *    nodal density or pressure).  The library never aborts; mhd25_last_error() describes
+ *    the failure.
  */
 #ifndef MHD25_H
 #define MHD25_H
@@ -100,7 +103,8 @@ int mhd25_hydro_stage_map(mhd25_ctx* ctx, double* U, double tau, uint8_t* flags)
 /* Algorithm "Hydrodynamic Euler substep": SSP-RK(3,3) (eq. euler-ssprk33) with P after every
  * raw stage; a raw stage whose element average is inadmissible rejects the attempt, which
  * is replaced by two attempts of tau/2 (recursively, depth <= max_halvings).  U in place.
- * `rep` (host, may be NULL) is filled.  Returns 0, 1 (not accepted; U unchanged) or <0. */
+ * `rep` (host, may be NULL) is filled.  Returns 0, 1 (not accepted; U unchanged), 2 (U has a
+ * non-finite value or a non-positive nodal rho or p; U unchanged, nothing attempted) or <0. */
 int mhd25_hydro_substep(mhd25_ctx* ctx, double* U, double tau, mhd25_report* rep);
 
 /* L_M: mass-inverted magnetic-velocity operator with J and E eliminated (eq. magnetic-dae):
@@ -128,7 +132,9 @@ int mhd25_velocity_oe(mhd25_ctx* ctx, double tau, const double* rho, double* u, 
                       const double* Bx, const double* By, const double* Bz);
 
 /* Algorithm "Magnetic-velocity substep": eta frozen at entry (when ar is on), SSP-RK(3,3)
- * (eq. magnetic-ssprk33) with the velocity OE after every raw stage.  e, u, B in place. */
+ * (eq. magnetic-ssprk33) with the velocity OE after every raw stage.  e, u, B in place.
+ * Returns 0, 2 (a non-finite value, or a non-positive nodal rho or e, in the input; nothing is
+ * modified) or <0.  The entry test synchronises the stream once. */
 int mhd25_step_magnetic(mhd25_ctx* ctx, const double* rho, double* e, double* u, double* Bx,
                         double* By, double* Bz, double tau, mhd25_report* rep);
 
@@ -137,12 +143,15 @@ int mhd25_to_primitive(mhd25_ctx* ctx, const double* U, double* rho, double* e, 
 int mhd25_to_conservative(mhd25_ctx* ctx, const double* rho, const double* e, const double* u, double* U);
 
 /* Algorithm "Strang split MHD step": H(dt/2) -> exchange -> M(dt) -> exchange -> H(dt/2).
- * U and B in place.  On a positive return both are restored to their entry values. */
+ * U and B in place.  Returns 0, 1 (a hydro substep not accepted within max_halvings), 2 (U or B
+ * has a non-finite value, or U a non-positive nodal rho or p) or <0; on a positive return U and
+ * B are restored to their entry values.  The entry test is folded into the entry snapshot. */
 int mhd25_strang_step(mhd25_ctx* ctx, double* U, double* Bx, double* By, double* Bz, double dt,
                       mhd25_report* rep);
 
 /* Time step from the positivity CFL: dt = cfl / max_{K,q} (2p+1)[(|u_x|+c_f)/hx + (|u_y|+c_f)/hy],
- * c_f = sqrt((gamma p + |B|^2)/rho) with B at the GLL_p nodes.  dt written to *dt (host). */
+ * c_f = sqrt((gamma p + |B|^2)/rho) with B at the GLL_p nodes.  dt written to *dt (host).
+ * Returns 2 when the maximum is not a positive finite number (an inadmissible state). */
 int mhd25_cfl_dt(mhd25_ctx* ctx, const double* U, const double* Bx, const double* By, const double* Bz,
                  double cfl, double* dt);
 
@@ -154,6 +163,29 @@ int mhd25_B_from_potential(mhd25_ctx* ctx, const double* A, double* Bx, double* 
  * magnetic energy (B,B)_B / 2, ||div B||_{L2}, min nodal rho, min nodal p. */
 int mhd25_diagnostics(mhd25_ctx* ctx, const double* U, const double* Bx, const double* By,
                       const double* Bz, double* out6);
+
+/* Physical coordinates (x, y) of the nodes of one node set (section "Spatial preparation";
+ * element map x = x_K + (xi + 1) h / 2 per direction).  space 0: the GLL_p element nodes,
+ * x and y [K][p+1][p+1]; 1: B_x grid (GLL_{m+1} x Gauss_m); 2: B_y grid (Gauss_m x GLL_{m+1});
+ * 3: B_z grid (GLL_m x GLL_m); 4: W grid of E_z, J_z (GLL_{m+1}^2); 5: N_x grid of E_x, J_x
+ * (Gauss_m x GLL_{m+1}); 6: N_y grid of E_y, J_y (GLL_{m+1} x Gauss_m); grids [ny(m+1)][nx(m+1)].
+ * Grid node (gy, gx) is local node (gx mod (m+1), gy mod (m+1)) of element (gx/(m+1), gy/(m+1));
+ * a node shared by two elements is the first local node of the right / upper one.  x, y: device
+ * FP64 arrays, overwritten.  Returns 0 or -1 (null pointer, space outside 0..6). */
+int mhd25_node_coords(mhd25_ctx* ctx, int32_t space, double* x, double* y);
+
+/* Connectivity of the conforming periodic mesh (section "Spatial preparation") as used by the
+ * kernels.  elem_nbr: device int32 [K][4], the neighbour across the left, right, bottom and top
+ * face.  dof_maps (device int32, may be NULL), concatenated:
+ *   face map [K][4][p+1]: for face f (left, right, bottom, top) and face node k (k indexes y on
+ *     the left / right faces, x on the bottom / top faces) the index e' (p+1)^2 + q' (q' = j (p+1) + i)
+ *     of the neighbour's node at the same point;
+ *   then [K][n_s] local-to-global grid indices of the six magnetic node sets B_x ((m+2)(m+1)),
+ *     B_y ((m+1)(m+2)), B_z ((m+1)^2), W ((m+2)^2), N_x ((m+1)(m+2)), N_y ((m+2)(m+1)), each in
+ *     local order [j][i], i fastest, i in x.
+ * Total length K (4(p+1) + 4(m+1)(m+2) + (m+1)^2 + (m+2)^2).  Returns 0, -1 (null pointer, or an
+ * index beyond the int32 range). */
+int mhd25_get_maps(mhd25_ctx* ctx, int32_t* elem_nbr, int32_t* dof_maps);
 
 /* Per-element decision flags of the last stage map applied (device [K] uint8 copied to the
  * host buffer `host_flags` of length n >= K).  Bit-exact comparisons use these. */
@@ -182,15 +214,18 @@ typedef struct mhd25_batch mhd25_batch;
 int mhd25_batch_create(const mhd25_mesh_desc* runs, int32_t nruns, const mhd25_options* opt,
                        void* hip_stream, mhd25_batch** out);
 void mhd25_batch_destroy(mhd25_batch* b);
-/* One Strang step of every run.  U, Bx, By, Bz: host arrays of nruns device pointers;
- * dt: host [nruns]; rep: host [nruns] (may be NULL).  Runs whose hydro substep needs a
- * halving are re-done individually.  Returns 0, or the first nonzero run status. */
+const char* mhd25_batch_last_error(const mhd25_batch* b);
+/* One Strang step of every run from a captured multi-branch HIP graph.  DISABLED: returns -2
+ * (see mhd25_batch_last_error) because its first GPU run ended in a host segmentation fault
+ * whose cause has not been shown.  Arguments as mhd25_batch_strang_step_streams. */
 int mhd25_batch_strang_step(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
                             double* const* Bz, const double* dt, mhd25_report* rep);
-/* The same step without a graph: each run's deferred step (no host read inside) is launched
- * directly on its branch stream, between a fork event on the context stream and join events that
- * the context stream waits on; then, as above, runs that need a halving are re-done individually.
- * Same arguments, layouts, results and return codes as mhd25_batch_strang_step. */
+/* One Strang step of every run without a graph: each run's deferred step (no host read inside)
+ * is launched directly on its branch stream, between a fork event on the context stream and join
+ * events that the context stream waits on.  U, Bx, By, Bz: host arrays of nruns device pointers;
+ * dt: host [nruns]; rep: host [nruns] (may be NULL).  Runs whose hydro substep needs a halving, or
+ * whose input is inadmissible, are re-done individually with mhd25_strang_step.  Returns 0, or
+ * the first nonzero run status (1, 2 or <0). */
 int mhd25_batch_strang_step_streams(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
                                     double* const* Bz, const double* dt, mhd25_report* rep);
 /* Sequential reference: the same step run by run with the plain per-run kernels. */

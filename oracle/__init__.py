@@ -295,3 +295,33 @@ def eval_B(mesh, Bx, By, Bz, e, X, Y):
     out = np.zeros((len(X), 3))
     lib().or_eval_B(mesh._i, mesh._dd, _d(Bx), _d(By), _d(Bz), ctypes.c_long(e), len(X), _d(X), _d(Y), _d(out))
     return out
+
+
+def node_count(mesh, space):
+    """Number of nodes of a node set (0: GLL_p element nodes; 1..6: magnetic grids)."""
+    return mesh.K * mesh.np1 * mesh.np1 if space == 0 else mesh.G
+
+
+def node_coords(mesh, space):
+    """Physical (x, y) of the nodes of node set `space` (0: GLL_p element nodes [K][p+1][p+1];
+    1: B_x, 2: B_y, 3: B_z, 4: W (E_z, J_z), 5: N_x (E_x, J_x), 6: N_y (E_y, J_y) grids)."""
+    n = node_count(mesh, space)
+    x = np.zeros(n); y = np.zeros(n)
+    r = lib().or_node_coords(mesh._i, mesh._dd, int(space), _d(x), _d(y))
+    if r:
+        raise ValueError("unknown node set %r" % (space,))
+    return x, y
+
+
+def maps_size(mesh):
+    """Length of the concatenated face and DOF maps of `get_maps`."""
+    A, B = mesh.m + 2, mesh.m + 1
+    return mesh.K * (4 * mesh.np1 + 4 * A * B + B * B + A * A)
+
+
+def get_maps(mesh):
+    """(nbr [K][4] int32, dof maps int32) of the periodic mesh (see or_get_maps)."""
+    nbr = np.zeros((mesh.K, 4), np.int32)
+    dof = np.zeros(maps_size(mesh), np.int32)
+    lib().or_get_maps(mesh._i, mesh._dd, nbr.ctypes.data_as(_ip), dof.ctypes.data_as(_ip))
+    return nbr, dof

@@ -633,6 +633,38 @@ static void hydro_stage_map(const Mesh& M, const Opts& o, double tau, double* U,
 }
 
 // ---------------------------------------------------------------------------
+// Admissibility of an input state: the admissible set of section "Conservative ideal MHD"
+// (positive density and pressure) at every node, with every value finite.  An input outside
+// it is refused with status 2 before anything is modified.
+// ---------------------------------------------------------------------------
+static bool all_finite(const double* a, long n) {
+  for (long k = 0; k < n; ++k)
+    if (!std::isfinite(a[k])) return false;
+  return true;
+}
+
+static bool state_admissible(const Mesh& M, const double* U) {
+  for (long e = 0; e < M.K; ++e)
+    for (int j = 0; j < M.np; ++j)
+      for (int i = 0; i < M.np; ++i) {
+        St<double> s = load_state(M, U, e, i, j);
+        const double v[5] = {s.r, s.mx, s.my, s.mz, s.E};
+        if (!all_finite(v, 5)) return false;
+        if (!(s.r > 0.0) || !(pressure(s, M.gamma) > 0.0)) return false;
+      }
+  return true;
+}
+
+// the magnetic substep's state: rho > 0 and e > 0 (so p = (gamma - 1) rho e > 0), all finite
+static bool primitive_admissible(const Mesh& M, const double* rho, const double* en, const double* u) {
+  const long n = M.K * M.nn;
+  if (!all_finite(u, 3 * n)) return false;
+  for (long q = 0; q < n; ++q)
+    if (!std::isfinite(rho[q]) || !std::isfinite(en[q]) || !(rho[q] > 0.0) || !(en[q] > 0.0)) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
 // Hydrodynamic substep (Algorithm "Hydrodynamic Euler substep", eq. euler-ssprk33)
 // with reject-and-halve (reading R15: a rejected attempt is replaced by two
 // attempts of half the step, recursively).
@@ -1261,6 +1293,7 @@ int or_hydro_substep(const int* im, const double* dm, const int* io, const doubl
   Mesh M = make_mesh(im, dm); Opts o = make_opts(io, dop);
   std::memset(rep, 0, sizeof(Report));
   rep->dt = tau;
+  if (!state_admissible(M, U)) { rep->status = 2; return 2; }
   std::vector<double> save(U, U + 5 * M.K * M.nn);
   int s = hydro_substep_rec(M, o, U, tau, 0, rep, flags, log, log_cap);
   if (s) std::memcpy(U, save.data(), save.size() * sizeof(double));
@@ -1322,6 +1355,11 @@ int or_step_magnetic(const int* im, const double* dm, const int* io, const doubl
                      double* u, double* Bx, double* By, double* Bz, double tau, Report* rep) {
   Mesh M = make_mesh(im, dm); Opts o = make_opts(io, dop);
   if (rep) { std::memset(rep, 0, sizeof(Report)); rep->dt = tau; }
+  const long G = (long)M.nx * M.ny * M.M1 * M.M1;
+  if (!primitive_admissible(M, rho, en, u) || !all_finite(Bx, G) || !all_finite(By, G) || !all_finite(Bz, G)) {
+    if (rep) rep->status = 2;
+    return 2;
+  }
   magnetic_substep(M, o, rho, en, u, Bx, By, Bz, tau, rep);
   return 0;
 }
@@ -1344,6 +1382,10 @@ int or_strang_step(const int* im, const double* dm, const int* io, const double*
   std::memset(rep, 0, sizeof(Report));
   rep->dt = dt;
   const long nn = M.K * M.nn, G = (long)M.nx * M.ny * M.M1 * M.M1;
+  if (!state_admissible(M, U) || !all_finite(Bx, G) || !all_finite(By, G) || !all_finite(Bz, G)) {
+    rep->status = 2;
+    return 2;
+  }
   std::vector<double> save(U, U + 5 * nn), sbx(Bx, Bx + G), sby(By, By + G), sbz(Bz, Bz + G);
   Report r1; std::memset(&r1, 0, sizeof(r1));
   int s = hydro_substep_rec(M, o, U, 0.5 * dt, 0, &r1, flags, nullptr, 0);
@@ -1438,6 +1480,89 @@ int or_eval_B(const int* im, const double* dm, const double* Bx, const double* B
   Mesh M = make_mesh(im, dm);
   LocalB<double> L = local_B(M, e, Bx, By, Bz);
   for (int k = 0; k < npts; ++k) B_at(M, L, X[k], Y[k], out + 3 * k);
+  return 0;
+}
+
+// Physical coordinates of the nodes of one node set (space 0: GLL_p element nodes [K][p+1][p+1];
+// 1: B_x grid; 2: B_y grid; 3: B_z grid; 4: E_z/J_z grid (W); 5: E_x/J_x grid (N_x); 6: E_y/J_y
+// grid (N_y)).  A grid node with global index (gy, gx) belongs to element (gx / (m+1), gy / (m+1))
+// as its local node (gx mod (m+1), gy mod (m+1)); a shared GLL_{m+1} node is its first local node.
+int or_node_coords(const int* im, const double* dm, int space, double* x, double* y) {
+  Mesh M = make_mesh(im, dm);
+  if (space == 0) {
+    for (long e = 0; e < M.K; ++e) {
+      const long ex = e % M.nx, ey = e / M.nx;
+      for (int j = 0; j < M.np; ++j)
+        for (int i = 0; i < M.np; ++i) {
+          x[nid(M, 0, e, i, j)] = M.x0 + M.hx * ex + 0.5 * (M.xi[i] + 1.0) * M.hx;
+          y[nid(M, 0, e, i, j)] = M.y0 + M.hy * ey + 0.5 * (M.xi[j] + 1.0) * M.hy;
+        }
+    }
+    return 0;
+  }
+  if (space < 1 || space > 6) return -1;
+  // 1D node sets per direction: GLL_{m+1} (first m+1 nodes), Gauss_m, GLL_m
+  const std::vector<double>* sx;
+  const std::vector<double>* sy;
+  switch (space) {
+    case 1: sx = &M.xw; sy = &M.zg; break;   // B_x: GLL_{m+1} x Gauss_m
+    case 2: sx = &M.zg; sy = &M.xw; break;   // B_y: Gauss_m x GLL_{m+1}
+    case 3: sx = &M.xv; sy = &M.xv; break;   // B_z: GLL_m x GLL_m
+    case 4: sx = &M.xw; sy = &M.xw; break;   // W: GLL_{m+1} x GLL_{m+1}
+    case 5: sx = &M.zg; sy = &M.xw; break;   // N_x: Gauss_m x GLL_{m+1}
+    default: sx = &M.xw; sy = &M.zg; break;  // N_y: GLL_{m+1} x Gauss_m
+  }
+  for (long ey = 0; ey < M.ny; ++ey)
+    for (long ex = 0; ex < M.nx; ++ex)
+      for (int j = 0; j < M.M1; ++j)
+        for (int i = 0; i < M.M1; ++i) {
+          const long g = gid(M, ex, ey, i, j);
+          x[g] = M.x0 + M.hx * ex + 0.5 * ((*sx)[i] + 1.0) * M.hx;
+          y[g] = M.y0 + M.hy * ey + 0.5 * ((*sy)[j] + 1.0) * M.hy;
+        }
+  return 0;
+}
+
+// Connectivity of the periodic mesh.  nbr[K][4]: the neighbour across the left, right, bottom
+// and top face.  dof (optional), concatenated:
+//   face map [K][4][p+1]: for face f (left, right, bottom, top) and face node k (k indexes y on
+//     x-normal faces, x on y-normal faces), the index e' (p+1)^2 + q' of the neighbour node at the
+//     same point;
+//   local-to-global maps [K][n_s] of the six magnetic node sets in the order B_x (GLL_{m+1} x
+//     Gauss_m), B_y (Gauss_m x GLL_{m+1}), B_z (GLL_m^2), W (GLL_{m+1}^2), N_x (Gauss_m x
+//     GLL_{m+1}), N_y (GLL_{m+1} x Gauss_m), local order [j][i], i fastest.
+int or_get_maps(const int* im, const double* dm, int32_t* nbr, int32_t* dof) {
+  Mesh M = make_mesh(im, dm);
+  for (long e = 0; e < M.K; ++e) {
+    const long ex = e % M.nx, ey = e / M.nx;
+    nbr[4 * e + 0] = (int32_t)elem(M, ex - 1, ey);
+    nbr[4 * e + 1] = (int32_t)elem(M, ex + 1, ey);
+    nbr[4 * e + 2] = (int32_t)elem(M, ex, ey - 1);
+    nbr[4 * e + 3] = (int32_t)elem(M, ex, ey + 1);
+  }
+  if (!dof) return 0;
+  int32_t* o = dof;
+  for (long e = 0; e < M.K; ++e) {
+    const long ex = e % M.nx, ey = e / M.nx;
+    for (int f = 0; f < 4; ++f)
+      for (int k = 0; k < M.np; ++k) {
+        long en;
+        int i, j;  // the neighbour's node at the same point
+        if (f == 0) { en = elem(M, ex - 1, ey); i = M.p; j = k; }
+        else if (f == 1) { en = elem(M, ex + 1, ey); i = 0; j = k; }
+        else if (f == 2) { en = elem(M, ex, ey - 1); i = k; j = M.p; }
+        else { en = elem(M, ex, ey + 1); i = k; j = 0; }
+        *o++ = (int32_t)nid(M, 0, en, i, j);
+      }
+  }
+  const int A = M.m + 2, B = M.m + 1;
+  const int ni[6] = {A, B, B, A, B, A}, nj[6] = {B, A, B, A, A, B};
+  for (int s = 0; s < 6; ++s)
+    for (long e = 0; e < M.K; ++e) {
+      const long ex = e % M.nx, ey = e / M.nx;
+      for (int j = 0; j < nj[s]; ++j)
+        for (int i = 0; i < ni[s]; ++i) *o++ = (int32_t)gid(M, ex, ey, i, j);
+    }
   return 0;
 }
 

@@ -72,6 +72,9 @@ _SIGS = {
     "mhd25_B_from_potential": (ctypes.c_int, [_dp] * 4),
     "mhd25_diagnostics": (ctypes.c_int, [_dp] * 5 + [ctypes.POINTER(ctypes.c_double)]),
     "mhd25_decisions": (ctypes.c_int, [_dp, _dp, ctypes.c_int64]),
+    "mhd25_node_coords": (ctypes.c_int, [_dp, ctypes.c_int32, _dp, _dp]),
+    "mhd25_get_maps": (ctypes.c_int, [_dp, _dp, _dp]),
+    "mhd25_batch_last_error": (ctypes.c_char_p, [_dp]),
     "mhd25_rhs_hydro_vjp": (ctypes.c_int, [_dp] * 4),
     "mhd25_rhs_magnetic_vjp": (ctypes.c_int, [_dp] * 16),
     "mhd25_timing_enable": (ctypes.c_int, [_dp, ctypes.c_int32]),
@@ -224,8 +227,9 @@ class Solver:
 
     def step_magnetic(self, rho, e, u, Bx, By, Bz, tau):
         rep = Report()
-        self._chk(self.lib.mhd25_step_magnetic(self.h, _ptr(rho), _ptr(e), _ptr(u), _ptr(Bx), _ptr(By), _ptr(Bz),
-                                               float(tau), ctypes.byref(rep)), "step_magnetic")
+        r = self._chk(self.lib.mhd25_step_magnetic(self.h, _ptr(rho), _ptr(e), _ptr(u), _ptr(Bx), _ptr(By),
+                                                   _ptr(Bz), float(tau), ctypes.byref(rep)), "step_magnetic")
+        rep.status = r
         return rep.as_dict()
 
     def to_primitive(self, U):
@@ -263,6 +267,28 @@ class Solver:
         keys = ("mass", "E_mech", "E_mag", "divB_L2", "rho_min", "p_min")
         return dict(zip(keys, list(out)))
 
+    def node_coords(self, space):
+        """(x, y) of the nodes of node set `space` (0: GLL_p element nodes [K, p+1, p+1];
+        1..6: the B_x, B_y, B_z, W, N_x, N_y grids [ny(m+1), nx(m+1)])."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+        shape = (self.K, self.p + 1, self.p + 1) if space == 0 else self.gshape()
+        x = torch.empty(shape, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        self._chk(self.lib.mhd25_node_coords(self.h, int(space), _ptr(x), _ptr(y)), "node_coords")
+        return x, y
+
+    def maps_size(self):
+        A, B = self.m + 2, self.m + 1
+        return self.K * (4 * (self.p + 1) + 4 * A * B + B * B + A * A)
+
+    def get_maps(self, with_dofs=True):
+        """(elem_nbr [K, 4], dof maps or None) as int32 device tensors (layout in include/mhd25.h)."""
+        dev = torch.device("cuda", torch.cuda.current_device())
+        nbr = torch.empty((self.K, 4), dtype=torch.int32, device=dev)
+        dof = torch.empty(self.maps_size(), dtype=torch.int32, device=dev) if with_dofs else None
+        self._chk(self.lib.mhd25_get_maps(self.h, _ptr(nbr), _ptr(dof)), "get_maps")
+        return nbr, dof
+
     def decisions(self):
         import numpy as np
         buf = np.zeros(self.K, np.uint8)
@@ -293,7 +319,7 @@ class Solver:
 
 class Batch:
     """Ensemble of independent runs advanced together (wraps an mhd25_batch): one Strang step of
-    every run is replayed from a captured HIP graph with concurrent branches."""
+    every run is launched on concurrent branch streams."""
 
     def __init__(self, layouts, options=None):
         if not torch.cuda.is_available():
@@ -328,9 +354,10 @@ class Batch:
             _ptr(t)
         return (self._ptrs(U), self._ptrs(Bx), self._ptrs(By), self._ptrs(Bz), (ctypes.c_double * self.n)(*dt))
 
-    def strang_step(self, U, Bx, By, Bz, dt, sequential=False, streams=False):
-        """One Strang step of every run: replayed from the captured graph (default), launched
-        directly on the branch streams (streams=True), or run by run (sequential=True)."""
+    def strang_step(self, U, Bx, By, Bz, dt, sequential=False, streams=True):
+        """One Strang step of every run: launched on the branch streams (default), run by run
+        (sequential=True), or from the captured multi-branch graph (streams=False; that entry point
+        is disabled and raises)."""
         reps = (Report * self.n)()
         if sequential:
             fn = self.lib.mhd25_batch_strang_step_sequential
@@ -341,7 +368,7 @@ class Batch:
         a = self._args(U, Bx, By, Bz, dt)
         r = fn(self.h, *a, reps)
         if r < 0:
-            raise MHD25Error("batch strang step failed (%d)" % r)
+            raise MHD25Error("batch strang step failed (%d): %s" % (r, self.lib.mhd25_batch_last_error(self.h).decode()))
         return r, [x.as_dict() for x in reps]
 
     def set_tuning(self, branches=0, p=0, hydro_bs=0):

@@ -31,6 +31,9 @@ int dcopy(mhd25_ctx* c, const double* a, double* b, long n);
 int mag_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u);
 int mag_to_conservative(mhd25_ctx* c, const double* rho, const double* e, const double* u, double* U);
 int extra_max_dev(mhd25_ctx* c, const double* a, long n, double* d_out);
+int entry_snapshot(mhd25_ctx* c, const double* U, double* snapU, const double* const* B, double* saveB);
+int step_magnetic_impl(mhd25_ctx* c, const double* rho, double* e, double* u, double* Bx, double* By, double* Bz,
+                       double tau, mhd25_report* rep);
 
 __global__ void k_batch_zero(int* fail, long long* acc, double* eta) {
   if (threadIdx.x == 0) { *fail = 0; acc[0] = acc[1] = acc[2] = 0; *eta = 0.0; }
@@ -65,6 +68,7 @@ struct mhd25_batch {
   std::vector<double> cap_dt;
   std::vector<const double*> cap_ptr;
   std::string err;
+  bool allow_capture;  // false: the captured step refuses to run (see mhd25_batch_strang_step)
 };
 
 #define BTRY(x)          \
@@ -91,13 +95,14 @@ static int attempt_deferred(mhd25_ctx* c, double* U, double tau, int* fail, long
 // one Strang step of one run, no host synchronisation (graph-capturable)
 static int strang_deferred(mhd25_ctx* c, double* U, double* Bx, double* By, double* Bz, double dt, int* fail,
                            long long* acc, double* eta_out) {
-  const long KN = c->mp.K * c->nn, G = c->G;
   hipLaunchKernelGGL(k_batch_zero, dim3(1), dim3(64), 0, c->stream, fail, acc, eta_out);
-  BTRY(dcopy(c, U, c->snapU, 5 * KN));
-  BTRY(dcopy(c, Bx, c->saveB, G)); BTRY(dcopy(c, By, c->saveB + G, G)); BTRY(dcopy(c, Bz, c->saveB + 2 * G, G));
+  // entry snapshot with the admissibility test: an inadmissible input makes every attempt of the
+  // run fail, so the run is redone individually, which returns status 2
+  const double* Bin[3] = {Bx, By, Bz};
+  BTRY(entry_snapshot(c, U, c->snapU, Bin, c->saveB));
   BTRY(attempt_deferred(c, U, 0.5 * dt, fail, acc));
   BTRY(mag_to_primitive(c, U, c->rho, c->e, c->u));
-  BTRY(mhd25_step_magnetic(c, c->rho, c->e, c->u, Bx, By, Bz, dt, nullptr));
+  BTRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, dt, nullptr));
   if (c->opt.ar && c->opt.C_eta > 0.0) BTRY(extra_max_dev(c, c->eta, c->mp.K, eta_out));
   BTRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
   BTRY(attempt_deferred(c, U, 0.5 * dt, fail, acc));
@@ -233,6 +238,7 @@ int mhd25_batch_create(const mhd25_mesh_desc* runs, int32_t nruns, const mhd25_o
   b->main = (hipStream_t)stream;
   b->nbranch = 0;
   b->captured = false;
+  b->allow_capture = false;
   for (int r = 0; r < nruns; ++r) {
     mhd25_ctx* c = nullptr;
     int rc = mhd25_init(&runs[r], opt, stream, &c);
@@ -255,6 +261,8 @@ int mhd25_batch_create(const mhd25_mesh_desc* runs, int32_t nruns, const mhd25_o
   *out = b;
   return 0;
 }
+
+const char* mhd25_batch_last_error(const mhd25_batch* b) { return b ? b->err.c_str() : "null batch"; }
 
 void mhd25_batch_destroy(mhd25_batch* b) {
   if (!b) return;
@@ -322,6 +330,11 @@ extern "C" {
 int mhd25_batch_strang_step(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
                             double* const* Bz, const double* dt, mhd25_report* rep) {
   if (!batch_args_ok(b, U, Bx, By, Bz, dt)) return -1;
+  if (!b->allow_capture) {
+    b->err = "the captured multi-branch batch step is disabled: its first GPU run ended in a host segmentation "
+             "fault whose cause has not been shown; use mhd25_batch_strang_step_streams";
+    return -2;
+  }
   if (!same_capture(b, U, Bx, By, Bz, dt)) {
     if (hipStreamSynchronize(b->main) != hipSuccess) { b->err = "sync"; return -2; }
     BTRY(capture(b, U, Bx, By, Bz, dt));

@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <climits>
+#include <cstdint>
 #include <new>
 
 #include "common.h"
@@ -34,6 +36,12 @@ int extra_max(mhd25_ctx* c, const double* a, long n, double* host_out);
 int extra_cfl(mhd25_ctx* c, const double* U, const double* Bx, const double* By, const double* Bz, double* host_max);
 int extra_diagnostics(mhd25_ctx* c, const double* U, const double* Bx, const double* By, const double* Bz,
                       double* out6);
+int extra_node_coords(mhd25_ctx* c, int space, double* x, double* y);
+int entry_snapshot(mhd25_ctx* c, const double* U, double* snapU, const double* const* B, double* saveB);
+int mag_check_input(mhd25_ctx* c, const double* rho, const double* e, const double* u, const double* Bx,
+                    const double* By, const double* Bz);
+int hydro_face_map(mhd25_ctx* c, int32_t* nbr, int32_t* fmap);
+int mag_dof_maps(mhd25_ctx* c, int32_t* dof);
 
 // fold the recorded (start, stop) pairs into the per-kernel totals
 static hipError_t timing_fold(mhd25_ctx* c) {
@@ -206,7 +214,8 @@ int mhd25_hydro_stage_map(mhd25_ctx* c, double* U, double tau, uint8_t* flags) {
   return 0;
 }
 
-// one attempt of the SSP-RK(3,3) hydro substep; returns 1 accepted, 0 rejected, <0 error
+// one attempt of the SSP-RK(3,3) hydro substep; returns 1 accepted, 0 rejected, 2 inadmissible
+// input (the entry check's word, see entry_snapshot), <0 error
 // with_prim: the last stage also writes the primitive copy (c->rho, c->e, c->u) of the new state
 static int hydro_attempt(mhd25_ctx* c, double* U, double tau, long long* counts, bool with_prim) {
   // U itself serves as U^n: it is written only by the last stage's map, which every thread
@@ -222,10 +231,11 @@ static int hydro_attempt(mhd25_ctx* c, double* U, double tau, long long* counts,
                     with_prim ? c->u : nullptr));
   int* hf = (int*)c->h_pinned;
   unsigned long long* hc = (unsigned long long*)(c->h_pinned + 8);
-  HIPCHK(c, hipMemcpyAsync(hf, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(hf, c->d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(hc, c->d_counts, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (*hf) return 0;
+  if (hf[1]) return 2;
+  if (hf[0]) return 0;
   counts[0] += (long long)hc[0]; counts[1] += (long long)hc[1]; counts[2] += (long long)hc[2];
   return 1;
 }
@@ -239,6 +249,11 @@ static int hydro_substep_rec(mhd25_ctx* c, double* U, double tau, int depth, mhd
   long long cnt[3] = {0, 0, 0};
   int ok = hydro_attempt(c, U, tau, cnt, with_prim);
   if (ok < 0) return ok;
+  if (ok == 2) {
+    rep->substeps_attempted--;
+    c->err = "inadmissible input: a non-finite value or a non-positive nodal density or pressure";
+    return 2;
+  }
   if (ok) {
     rep->substeps_accepted++;
     rep->n_rho_limited += cnt[0]; rep->n_p_limited += cnt[1]; rep->n_collapsed += cnt[2];
@@ -258,7 +273,7 @@ int mhd25_hydro_substep(mhd25_ctx* c, double* U, double tau, mhd25_report* rep) 
   std::memset(&r, 0, sizeof(r));
   r.dt = tau;
   const long n5 = 5 * c->mp.K * c->nn;
-  TRY(dcopy(c, U, c->saveU, n5));
+  TRY(entry_snapshot(c, U, c->saveU, nullptr, nullptr));
   int s = hydro_substep_rec(c, U, tau, 0, &r);
   if (s > 0) TRY(dcopy(c, c->saveU, U, n5));
   r.status = s;
@@ -300,9 +315,11 @@ int mhd25_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, do
   return mag_velocity_oe(c, tau, rho, u, e, Bx, By, Bz);
 }
 
-int mhd25_step_magnetic(mhd25_ctx* c, const double* rho, double* e, double* u, double* Bx, double* By, double* Bz,
-                        double tau, mhd25_report* rep) {
-  if (!c || !rho || !e || !u || !Bx || !By || !Bz || !(tau > 0.0)) return -1;
+}  // extern "C"
+
+// the magnetic substep without the entry check (the Strang step's own state is admissible)
+int step_magnetic_impl(mhd25_ctx* c, const double* rho, double* e, double* u, double* Bx, double* By, double* Bz,
+                       double tau, mhd25_report* rep) {
   const long KN = c->mp.K * c->nn, G = c->G;
   const double* eta = nullptr;
   double eta_max = 0.0;
@@ -346,6 +363,22 @@ int mhd25_step_magnetic(mhd25_ctx* c, const double* rho, double* e, double* u, d
   return 0;
 }
 
+extern "C" {
+
+int mhd25_step_magnetic(mhd25_ctx* c, const double* rho, double* e, double* u, double* Bx, double* By, double* Bz,
+                        double tau, mhd25_report* rep) {
+  if (!c || !rho || !e || !u || !Bx || !By || !Bz || !(tau > 0.0)) return -1;
+  TRY(mag_check_input(c, rho, e, u, Bx, By, Bz));
+  int* hf = (int*)c->h_pinned;
+  HIPCHK(c, hipMemcpyAsync(hf, c->d_flag + 1, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (*hf) {
+    if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->dt = tau; rep->status = 2; }
+    return fail(c, 2, "inadmissible input: a non-finite value or a non-positive nodal density or internal energy");
+  }
+  return step_magnetic_impl(c, rho, e, u, Bx, By, Bz, tau, rep);
+}
+
 int mhd25_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u) {
   if (!c || !U || !rho || !e || !u) return -1;
   return mag_to_primitive(c, U, rho, e, u);
@@ -362,9 +395,10 @@ int mhd25_strang_step(mhd25_ctx* c, double* U, double* Bx, double* By, double* B
   mhd25_report r;
   std::memset(&r, 0, sizeof(r));
   r.dt = dt;
-  // entry snapshot for the failure path (state restored on a positive return)
-  TRY(dcopy(c, U, c->snapU, 5 * KN));
-  TRY(dcopy(c, Bx, c->saveB, G)); TRY(dcopy(c, By, c->saveB + G, G)); TRY(dcopy(c, Bz, c->saveB + 2 * G, G));
+  // entry snapshot for the failure path (state restored on a positive return), with the input's
+  // admissibility test (status 2 from the first attempt when it fails)
+  const double* Bin[3] = {Bx, By, Bz};
+  TRY(entry_snapshot(c, U, c->snapU, Bin, c->saveB));
   auto restore = [&](int s) {
     if (s > 0) {
       dcopy(c, c->snapU, U, 5 * KN);
@@ -379,7 +413,7 @@ int mhd25_strang_step(mhd25_ctx* c, double* U, double* Bx, double* By, double* B
   std::memset(&h1, 0, sizeof(h1)); std::memset(&m, 0, sizeof(m)); std::memset(&h2, 0, sizeof(h2));
   int s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h1, true);  // also leaves (rho, e, u) of U
   if (s != 0) return restore(s);
-  TRY(mhd25_step_magnetic(c, c->rho, c->e, c->u, Bx, By, Bz, dt, &m));
+  TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, dt, &m));
   TRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
   s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h2);
   r.substeps_attempted = h1.substeps_attempted + h2.substeps_attempted;
@@ -411,6 +445,22 @@ int mhd25_diagnostics(mhd25_ctx* c, const double* U, const double* Bx, const dou
                       double* out6) {
   if (!c || !U || !Bx || !By || !Bz || !out6) return -1;
   return extra_diagnostics(c, U, Bx, By, Bz, out6);
+}
+
+int mhd25_node_coords(mhd25_ctx* c, int32_t space, double* x, double* y) {
+  if (!c || !x || !y || space < 0 || space > 6) return -1;
+  return extra_node_coords(c, space, x, y);
+}
+
+int mhd25_get_maps(mhd25_ctx* c, int32_t* elem_nbr, int32_t* dof_maps) {
+  if (!c || !elem_nbr) return -1;
+  const long A = c->m + 2, B = c->m + 1;
+  if (c->mp.K * c->nn > INT32_MAX || c->G > INT32_MAX ||
+      c->mp.K * (4 * c->np + 4 * A * B + A * A + B * B) > INT32_MAX)
+    return fail(c, -1, "maps exceed the int32 index range");
+  TRY(hydro_face_map(c, elem_nbr, dof_maps));
+  if (dof_maps) TRY(mag_dof_maps(c, dof_maps + 4 * c->mp.K * c->np));
+  return 0;
 }
 
 int mhd25_decisions(const mhd25_ctx* c, uint8_t* host_flags, int64_t n) {

@@ -178,6 +178,35 @@ __global__ __launch_bounds__(128) void k_diag(const double* __restrict__ U, cons
   o[0] = mass; o[1] = Em; o[2] = mag; o[3] = div2; o[4] = rmin; o[5] = pmin;
 }
 
+// Physical coordinates of the nodes of one node set (space 0: GLL_p element nodes [K][p+1][p+1];
+// 1..6: the B_x, B_y, B_z, W, N_x, N_y grids).  Grid node (gy, gx) is local node (gx mod (m+1),
+// gy mod (m+1)) of element (gx / (m+1), gy / (m+1)).  One thread per node.
+__global__ __launch_bounds__(256) void k_node_coords(int space, double* __restrict__ x, double* __restrict__ y,
+                                                     const HydroTab* __restrict__ H, const MagTab* __restrict__ T,
+                                                     MeshP mp, int p, int m, double x0, double y0) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (space == 0) {
+    const int np = p + 1, nn = np * np;
+    if (k >= mp.K * nn) return;
+    const long e = k / nn;
+    const int q = (int)(k - e * nn), i = q % np, j = q / np;
+    long ex, ey;
+    elem_xy(mp, e, ex, ey);
+    x[k] = x0 + mp.hx * ex + 0.5 * (H->xi[i] + 1.0) * mp.hx;
+    y[k] = y0 + mp.hy * ey + 0.5 * (H->xi[j] + 1.0) * mp.hy;
+    return;
+  }
+  const int B = m + 1;
+  const long NX = (long)mp.nx * B;
+  if (k >= NX * mp.ny * B) return;
+  const long gy = k / NX, gx = k - gy * NX, ex = gx / B, ey = gy / B;
+  const int i = (int)(gx - ex * B), j = (int)(gy - ey * B);
+  const double* sx = space == 2 || space == 5 ? T->xg : (space == 3 ? T->xv : T->xw);
+  const double* sy = space == 1 || space == 6 ? T->xg : (space == 3 ? T->xv : T->xw);
+  x[k] = x0 + mp.hx * ex + 0.5 * (sx[i] + 1.0) * mp.hx;
+  y[k] = y0 + mp.hy * ey + 0.5 * (sy[j] + 1.0) * mp.hy;
+}
+
 }  // namespace
 
 #define DISPATCH_PM2(p, m, F)                                                                             \
@@ -244,4 +273,12 @@ int extra_diagnostics(mhd25_ctx* c, const double* U, const double* Bx, const dou
   for (int k = 0; k < 6; ++k) out6[k] = c->h_pinned[k];
   out6[3] = sqrt(out6[3]);
   return r;
+}
+
+int extra_node_coords(mhd25_ctx* c, int space, double* x, double* y) {
+  const long n = space == 0 ? c->mp.K * c->nn : c->G;
+  const long nb = (n + 255) / 256;
+  hipLaunchKernelGGL(k_node_coords, dim3(nb), dim3(256), 0, c->stream, space, x, y, c->d_ht, c->d_mt, c->mp, c->p,
+                     c->m, c->mesh.x0, c->mesh.y0);
+  return ex_chk(c, hipGetLastError(), "node coordinate launch");
 }

@@ -117,6 +117,19 @@ __device__ __forceinline__ void face_flux(const double uo[5], const double un[5]
 
 __device__ __forceinline__ long wrap(long a, long n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
+// Face f = 2 D + side of element (ex, ey) (D 0: the x-normal faces, D 1: the y-normal faces; side 0
+// is the face at -1) and the face node `line` on it: the neighbour element en across the face, the
+// element's own face node qo and the neighbour's node qn at the same point (periodic mesh).
+template <int P>
+__device__ __forceinline__ void face_match(const MeshP& mp, long ex, long ey, int D, int side, int line, long& en,
+                                           int& qo, int& qn) {
+  constexpr int NP = P + 1;
+  const int pos = side ? P : 0;
+  qo = D == 0 ? line * NP + pos : pos * NP + line;
+  qn = D == 0 ? line * NP + (P - pos) : (P - pos) * NP + line;
+  en = D == 0 ? ey * mp.nx + wrap(ex + (side ? 1 : -1), mp.nx) : wrap(ey + (side ? 1 : -1), mp.ny) * mp.nx + ex;
+}
+
 // One direction of the volume part of L_E for the thread's node: owned pairs, incoming halves.
 template <int P, int D, int BS>
 __device__ __forceinline__ void volume_dir(const Prim& me, double acc[5], bool act, int el, int i, int j,
@@ -184,11 +197,9 @@ __device__ __forceinline__ void surface_terms(double acc[5], bool act, int el, i
     elem_xy(mp, e, ex, ey);
     for (int f = q; f < 4 * NP; f += NN) {
       const int D = f / (2 * NP), side = (f / NP) & 1, line = f % NP;
-      const int pos = side ? P : 0;
-      const int qo = D == 0 ? line * NP + pos : pos * NP + line;
-      const int qn = D == 0 ? line * NP + (P - pos) : (P - pos) * NP + line;
-      const long en = D == 0 ? ey * mp.nx + wrap(ex + (side ? 1 : -1), mp.nx)
-                             : wrap(ey + (side ? 1 : -1), mp.ny) * mp.nx + ex;
+      long en;
+      int qo, qn;
+      face_match<P>(mp, ex, ey, D, side, line, en, qo, qn);
       double uo[5], un[5], F[5];
 #pragma unroll
       for (int c = 0; c < 5; ++c) { uo[c] = Us[c * KN + e * NN + qo]; un[c] = Us[c * KN + en * NN + qn]; }
@@ -656,6 +667,56 @@ __global__ __launch_bounds__(BS) void k_hydro_oe_pp(const double* __restrict__ U
   }
 }
 
+// Connectivity export: nbr[K][4] (left, right, bottom, top neighbour) and the face map
+// fmap[K][4][p+1] (the neighbour node e' (p+1)^2 + q' matched to each own face node), formed with the
+// same face_match the stage kernel uses.  One thread per (element, face).
+template <int P>
+__global__ __launch_bounds__(256) void k_face_map(int32_t* __restrict__ nbr, int32_t* __restrict__ fmap, MeshP mp) {
+  constexpr int NP = P + 1, NN = NP * NP;
+  const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 4 * mp.K) return;
+  const long e = t >> 2;
+  const int f = (int)(t & 3), D = f >> 1, side = f & 1;
+  long ex, ey;
+  elem_xy(mp, e, ex, ey);
+  long en = 0;
+  for (int line = 0; line < NP; ++line) {
+    int qo, qn;
+    face_match<P>(mp, ex, ey, D, side, line, en, qo, qn);
+    if (fmap) fmap[t * NP + line] = (int32_t)(en * NN + qn);
+  }
+  nbr[t] = (int32_t)en;
+}
+
+// Entry copy of a conservative state with the admissibility test of every node: all five values
+// finite, rho > 0 and p > 0 (the admissible set of section "Conservative ideal MHD").  A failing node
+// sets bit 1 of flag[1].  One thread per node.
+__global__ __launch_bounds__(256) void k_snap_check_U(const double* __restrict__ U, double* __restrict__ snap, long KN,
+                                                      double g, int* __restrict__ flag) {
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < KN; n += (long)gridDim.x * blockDim.x) {
+    double v[5];
+    bool fin = true;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+      v[c] = U[c * KN + n];
+      snap[c * KN + n] = v[c];
+      fin = fin && fabs(v[c]) <= DBL_MAX;
+    }
+    const double p = (g - 1.0) * (v[4] - (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / (2.0 * v[0]));
+    if (!fin || !(v[0] > 0.0) || !(p > 0.0)) atomicOr(flag + 1, 2);
+  }
+}
+
+// entry copy with a finiteness test (magnetic grids); a non-finite value sets bit 1 of flag[1]
+__global__ __launch_bounds__(256) void k_copy_check(const double* __restrict__ a, double* __restrict__ b, long n,
+                                                    int* __restrict__ flag) {
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    const double v = a[k];
+    b[k] = v;
+    if (!(fabs(v) <= DBL_MAX)) atomicOr(flag + 1, 2);
+  }
+}
+
 }  // namespace
 
 // Row / column reduction of per-element statistics [K][nc][3] (sum, min, max), nc <= 5, fixed
@@ -757,8 +818,16 @@ __global__ __launch_bounds__(256) void k_global_reduce(const double* __restrict_
   if (t < 3 * NC) glob[t] = red[t][0];
 }
 
-__global__ void k_reset_attempt(int* flag, unsigned long long* counts) {
-  if (threadIdx.x == 0) { *flag = 0; counts[0] = 0; counts[1] = 0; counts[2] = 0; }
+// flag[0]: the attempt's reject word (bit 0: an inadmissible raw average), which the stage kernels
+// test to skip the rest of a failed attempt; flag[1]: the entry check's word (bit 1: an inadmissible
+// input), cleared at entry and copied into flag[0] at the start of every attempt so that an attempt
+// on an inadmissible input does no work.
+__global__ void k_reset_attempt(int* flag, unsigned long long* counts, int clear_input) {
+  if (threadIdx.x == 0) {
+    if (clear_input) flag[1] = 0;
+    flag[0] = flag[1];
+    counts[0] = 0; counts[1] = 0; counts[2] = 0;
+  }
 }
 
 __global__ void k_copy(const double* __restrict__ a, double* __restrict__ b, long n) {
@@ -874,8 +943,42 @@ int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, con
 }
 
 int reset_attempt(mhd25_ctx* c) {
-  hipLaunchKernelGGL(k_reset_attempt, dim3(1), dim3(64), 0, c->stream, c->d_flag, c->d_counts);
+  hipLaunchKernelGGL(k_reset_attempt, dim3(1), dim3(64), 0, c->stream, c->d_flag, c->d_counts, 0);
   return check(c, hipGetLastError(), "reset launch");
+}
+
+static long flat_blocks(long n) {
+  long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  return blocks < 1 ? 1 : blocks;
+}
+
+// clears the entry word flag[1] (and the attempt's word and counters)
+int entry_clear(mhd25_ctx* c) {
+  hipLaunchKernelGGL(k_reset_attempt, dim3(1), dim3(64), 0, c->stream, c->d_flag, c->d_counts, 1);
+  return check(c, hipGetLastError(), "entry clear launch");
+}
+
+// entry snapshot of U (and of the magnetic grids when B is set) into snapU / saveB with the
+// admissibility test; clears and then sets the entry word flag[1]
+int entry_snapshot(mhd25_ctx* c, const double* U, double* snapU, const double* const* B, double* saveB) {
+  hipLaunchKernelGGL(k_reset_attempt, dim3(1), dim3(64), 0, c->stream, c->d_flag, c->d_counts, 1);
+  const long KN = c->mp.K * c->nn;
+  hipLaunchKernelGGL(k_snap_check_U, dim3(flat_blocks(KN)), dim3(256), 0, c->stream, U, snapU, KN, c->mp.gamma,
+                     c->d_flag);
+  if (B)
+    for (int k = 0; k < 3; ++k)
+      hipLaunchKernelGGL(k_copy_check, dim3(flat_blocks(c->G)), dim3(256), 0, c->stream, B[k], saveB + k * c->G, c->G,
+                         c->d_flag);
+  return check(c, hipGetLastError(), "entry snapshot launch");
+}
+
+int hydro_face_map(mhd25_ctx* c, int32_t* nbr, int32_t* fmap) {
+  const long blocks = (4 * c->mp.K + 255) / 256;
+#define FM(P) hipLaunchKernelGGL((k_face_map<P>), dim3(blocks), dim3(256), 0, c->stream, nbr, fmap, c->mp)
+  DISPATCH_P(c->p, FM);
+#undef FM
+  return check(c, hipGetLastError(), "face map launch");
 }
 
 int dcopy(mhd25_ctx* c, const double* a, double* b, long n) {

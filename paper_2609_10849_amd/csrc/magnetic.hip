@@ -1288,6 +1288,45 @@ __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ Lx, c
   }
 }
 
+// Local-to-global maps of the six magnetic node sets of each element (B_x, B_y, B_z, W, N_x, N_y;
+// local order [j][i], i fastest), formed with the kernels' own grid index gix.  One thread per element.
+template <int M>
+__global__ __launch_bounds__(256) void k_dof_maps(int32_t* __restrict__ dof, MeshP mp) {
+  constexpr int A = M + 2, B = M + 1;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= mp.K) return;
+  long ex, ey;
+  elem_xy(mp, e, ex, ey);
+  const int ni[6] = {A, B, B, A, B, A}, nj[6] = {B, A, B, A, A, B};
+  long off = 0;
+  for (int s = 0; s < 6; ++s) {
+    const int n = ni[s] * nj[s];
+    int32_t* o = dof + off + e * n;
+    for (int j = 0; j < nj[s]; ++j)
+      for (int i = 0; i < ni[s]; ++i) o[j * ni[s] + i] = (int32_t)gix(mp, B, ex, ey, i, j);
+    off += mp.K * n;
+  }
+}
+
+// Admissibility test of a magnetic-substep input: rho > 0, e > 0 (p = (gamma - 1) rho e > 0) and
+// finite u at every node, finite magnetic grids.  A failure sets bit 1 of flag[1].
+__global__ __launch_bounds__(256) void k_check_mag(const double* __restrict__ rho, const double* __restrict__ e,
+                                                   const double* __restrict__ u, long KN, const double* __restrict__ Bx,
+                                                   const double* __restrict__ By, const double* __restrict__ Bz, long G,
+                                                   int* __restrict__ flag) {
+  const long n = KN > G ? KN : G;
+  bool ok = true;
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    if (k < KN) {
+      const double r = rho[k], en = e[k];
+      ok = ok && r > 0.0 && en > 0.0 && r <= DBL_MAX && en <= DBL_MAX && fabs(u[k]) <= DBL_MAX &&
+           fabs(u[KN + k]) <= DBL_MAX && fabs(u[2 * KN + k]) <= DBL_MAX;
+    }
+    if (k < G) ok = ok && fabs(Bx[k]) <= DBL_MAX && fabs(By[k]) <= DBL_MAX && fabs(Bz[k]) <= DBL_MAX;
+  }
+  if (!ok) atomicOr(flag + 1, 2);
+}
+
 __global__ void k_to_primitive(const double* __restrict__ U, double* __restrict__ rho, double* __restrict__ e,
                                double* __restrict__ u, long n) {
   for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
@@ -1526,6 +1565,26 @@ int mag_to_conservative(mhd25_ctx* c, const double* rho, const double* e, const 
   long nb = (n + 255) / 256; if (nb > 65536) nb = 65536;
   hipLaunchKernelGGL(k_to_conservative, dim3(nb), dim3(256), 0, c->stream, rho, e, u, U, n);
   return chk(c, "exchange launch");
+}
+
+int entry_clear(mhd25_ctx* c);
+
+int mag_dof_maps(mhd25_ctx* c, int32_t* dof) {
+  const long nb = (c->mp.K + 255) / 256;
+#define DM(M) hipLaunchKernelGGL((k_dof_maps<M>), dim3(nb), dim3(256), 0, c->stream, dof, c->mp)
+  DISPATCH_M(c->m, DM);
+#undef DM
+  return chk(c, "dof map launch");
+}
+
+// clears the entry word flag[1], then tests the magnetic-substep input into it
+int mag_check_input(mhd25_ctx* c, const double* rho, const double* e, const double* u, const double* Bx,
+                    const double* By, const double* Bz) {
+  const long KN = c->mp.K * c->nn, n = KN > c->G ? KN : c->G;
+  long nb = (n + 255) / 256; if (nb > 65536) nb = 65536;
+  if (const int r = entry_clear(c)) return r;
+  hipLaunchKernelGGL(k_check_mag, dim3(nb), dim3(256), 0, c->stream, rho, e, u, KN, Bx, By, Bz, c->G, c->d_flag);
+  return chk(c, "input check launch");
 }
 
 int mag_B_from_potential(mhd25_ctx* c, const double* A, double* Bx, double* By) {

@@ -321,3 +321,60 @@ def test_emulated_batch_streams_equals_individual(emu):
         lib.mhd25_destroy(h)
         for a, r in zip(got, st):
             assert (a == r).all()
+
+
+@pytest.mark.parametrize("nx,ny,p,m", [(1, 1, 1, 0), (3, 2, 2, 1), (5, 4, 4, 3), (2, 3, 6, 6)])
+def test_emulated_maps_and_coords(emu, nx, ny, p, m):
+    """The kernels' own connectivity (face matching of the stage kernel, grid indices of the
+    magnetic kernels) equals the oracle's maps bit for bit; node coordinates agree to rounding."""
+    lib, pk = emu
+    L = W.Layout(nx, ny, p, m, -1.0, 2.0, 0.5, 1.25, 5.0 / 3.0)
+    M = omesh(L)
+    onbr, odof = O.get_maps(M)
+    h = context(lib, pk, L, pk.Options.make())
+    nbr = np.zeros((M.K, 4), np.int32)
+    dof = np.zeros(O.maps_size(M), np.int32)
+    assert lib.mhd25_get_maps(h, ptr(nbr), ptr(dof)) == 0
+    assert np.array_equal(nbr, onbr) and np.array_equal(dof, odof)
+    nbr2 = np.zeros((M.K, 4), np.int32)
+    assert lib.mhd25_get_maps(h, ptr(nbr2), None) == 0 and np.array_equal(nbr2, onbr)
+    for space in range(7):
+        ox, oy = O.node_coords(M, space)
+        gx, gy = np.zeros_like(ox), np.zeros_like(oy)
+        assert lib.mhd25_node_coords(h, space, ptr(gx), ptr(gy)) == 0
+        assert np.abs(gx - ox).max() <= 4e-16 * 2.0 and np.abs(gy - oy).max() <= 4e-16 * 1.25, space
+    assert lib.mhd25_node_coords(h, 7, ptr(gx), ptr(gy)) == -1
+    lib.mhd25_destroy(h)
+
+
+def test_emulated_inadmissible_input_status_2(emu):
+    """An input with a non-finite value or a non-positive nodal density or pressure is refused
+    with status 2 and left unmodified, as by the oracle."""
+    lib, pk = emu
+    from tests.test_oracle_maps import bad_states
+    L, U, cases = bad_states()
+    M = omesh(L)
+    h = context(lib, pk, L, pk.Options.full())
+    for name, u, bx, by, bz in cases:
+        st = [np.ascontiguousarray(a.copy()) for a in (u, bx, by, bz)]
+        rep = pk.Report()
+        assert lib.mhd25_strang_step(h, *[ptr(a) for a in st], 1e-3, ctypes.byref(rep)) == 2, name
+        assert rep.status == 2 and rep.substeps_attempted == 0
+        for a, b in zip(st, (u, bx, by, bz)):
+            assert np.array_equal(a, b, equal_nan=True), name
+        assert O.strang_step(M, O.Options.full(), u, bx, by, bz, 1e-3)[-1] == 2
+        if name != "nan Bx":
+            uu = np.ascontiguousarray(u.copy())
+            assert lib.mhd25_hydro_substep(h, ptr(uu), 1e-3, ctypes.byref(rep)) == 2, name
+            assert np.array_equal(uu, u, equal_nan=True)
+    # the admissible state steps normally afterwards (the entry word is cleared at each entry)
+    st = [np.ascontiguousarray(a.copy()) for a in (U,) + tuple(W.isentropic_vortex(4, 3, 2, 1)[2:])]
+    assert lib.mhd25_strang_step(h, *[ptr(a) for a in st], 1e-3, ctypes.byref(rep)) == 0
+    rho, e, uvel = O.to_primitive(M, U)
+    e2 = np.ascontiguousarray(e.copy()); e2[1, 0, 0] = -1.0
+    Bx, By, Bz = [np.ascontiguousarray(a) for a in W.isentropic_vortex(4, 3, 2, 1)[2:]]
+    uv = np.ascontiguousarray(uvel.copy())
+    assert lib.mhd25_step_magnetic(h, ptr(rho), ptr(e2), ptr(uv), ptr(Bx.copy()), ptr(By.copy()), ptr(Bz.copy()),
+                                   1e-3, ctypes.byref(rep)) == 2
+    assert np.array_equal(uv, uvel)
+    lib.mhd25_destroy(h)
