@@ -126,3 +126,68 @@ def test_ssprk3_order_no_stabilization():
         sols.append(U)
     d1 = np.abs(sols[0] - sols[1]).max(); d2 = np.abs(sols[1] - sols[2]).max()
     assert 2.7 < math.log2(d1 / d2) < 3.3, (d1, d2)
+
+
+def _dense_skew_rhs(nx, ny, p, hx, hy, U, iface_flux):
+    """L_E assembled as dense global operators in the skew form M dU/dt = -[(S_x o F_x) 1 +
+    (S_y o F_y) 1 + B-weighted interface fluxes], with S = Q - Q^T = 2Q - B from the SBP property of
+    eq. euler-nodal-index's Q (Q + Q^T = B): the boundary corrections of eq. euler-nodal-index then
+    leave only the numerical flux at the face nodes.  Tables from numpy's Legendre polynomials,
+    matrices over all K (p+1)^2 nodes, fluxes from the oracle's (separately pinned) two-point and
+    interface flux routines."""
+    np1 = p + 1
+    xi = W.gll_nodes(p)
+    Pp = np.polynomial.legendre.Legendre.basis(p)(xi)
+    w = 2.0 / (p * (p + 1) * Pp ** 2)
+    bw = np.array([np.prod([xi[j] - xi[k] for k in range(np1) if k != j]) for j in range(np1)])
+    D = np.zeros((np1, np1))
+    for i in range(np1):
+        for j in range(np1):
+            if i != j:
+                D[i, j] = (1.0 / bw[j]) / (1.0 / bw[i]) / (xi[i] - xi[j])
+        D[i, i] = -D[i].sum()
+    Q = np.diag(w) @ D
+    S = Q - Q.T
+    K = nx * ny
+    N = K * np1 * np1
+    node = lambda e, i, j: e * np1 * np1 + j * np1 + i
+    Sx = np.zeros((N, N)); Sy = np.zeros((N, N)); Mg = np.zeros(N)
+    for e in range(K):
+        for j in range(np1):
+            for i in range(np1):
+                n = node(e, i, j)
+                Mg[n] = hx * hy / 4 * w[i] * w[j]
+                for r in range(np1):
+                    Sx[n, node(e, r, j)] = S[i, r] * w[j] * hy / 2
+                    Sy[n, node(e, i, r)] = w[i] * S[j, r] * hx / 2
+    V = U.reshape(5, N).T
+    R = np.zeros((N, 5))
+    for n in range(N):
+        for n2 in np.nonzero(Sx[n])[0]:
+            R[n] += Sx[n, n2] * O.ec_flux(V[n], V[n2], 0, G)
+        for n2 in np.nonzero(Sy[n])[0]:
+            R[n] += Sy[n, n2] * O.ec_flux(V[n], V[n2], 1, G)
+    fstar = (lambda a, b, d: O.ec_flux(a, b, d, G)) if iface_flux else (lambda a, b, d: O.llf_flux(a, b, d, G))
+    for e in range(K):
+        ex, ey = e % nx, e // nx
+        right, top = ey * nx + (ex + 1) % nx, ((ey + 1) % ny) * nx + ex
+        for k in range(np1):
+            # x-face between e (node i = p) and its right neighbour (node i = 0): minus side is e
+            a, b = node(e, p, k), node(right, 0, k)
+            F = fstar(V[a], V[b], 0) * w[k] * hy / 2
+            R[a] += F; R[b] -= F
+            a, b = node(e, k, p), node(top, k, 0)
+            F = fstar(V[a], V[b], 1) * w[k] * hx / 2
+            R[a] += F; R[b] -= F
+    return (-R / Mg[:, None]).T.reshape(U.shape)
+
+
+@pytest.mark.parametrize("nx,ny,p,flux", [(2, 2, 2, 0), (3, 2, 3, 0), (3, 2, 2, 1), (2, 2, 3, 1)])
+def test_dense_skew_form_equals_literal_sum(nx, ny, p, flux):
+    """Brute force on tiny meshes: the oracle's literal double sum with the boundary corrections of
+    eq. euler-nodal-index equals the dense skew-form assembly to rounding (hx != hy)."""
+    L, U, *_ = W.random_state(nx, ny, p, p - 1, seed=40 + 3 * p + nx, domain=(0, 1.2, 0, 0.5), amp=0.3)
+    M = mesh_of(L)
+    ref = _dense_skew_rhs(nx, ny, p, M.hx, M.hy, U, flux)
+    got = O.rhs_hydro(M, U, iface_flux=flux)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()

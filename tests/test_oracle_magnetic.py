@@ -224,3 +224,73 @@ def test_alfven_wave_rates_slow():
     e32 = run_alfven(3, 2, 32, dt=2e-3)
     for a, b in zip(e16[:3], e32[:3]):
         assert 2.7 < math.log2(a / b) < 3.3, (e16, e32)
+
+
+def test_velocity_oe_factor_hand_computed():
+    """Eqs. magnetic-oe-sensor, magnetic-oe-rate and magnetic-oe-factor by hand on a p = m = 2
+    state whose x-profile is the same in every element of a row: in row ey, u_x = a_ey (xhat +
+    xhat^2), u_z = c a_ey xhat, u_y = 0.3 (constant: contributes zero), with non-uniform nodal rho
+    and |B| (uniform in-plane B, nodal B_z).  With GLL_2 weights (1/3, 4/3, 1/3):
+      x (row): u_x jumps 2 a in value and 8 a / hx in slope at every x-face, u_z 2 c a in value;
+        row amplitudes 5 a / 3 (u_x) and c a (u_z), floored at 1e-6 Delta_Omega; the shared
+        Delta^u_x is their maximum, sigma_x0 = max(2 a, 2 c a) / Delta^u_x, sigma_x1 =
+        (3 hx / 2)(16 a / hx) / Delta^u_x, sigma_x2 = 0;
+      y (column = the whole mesh here): the y-face jumps (a' - a)(xhat + xhat^2) and c (a' - a) xhat
+        give (1/|F|) int [[.]]^2 = 2 (a' - a)^2 / 3 and c^2 (a' - a)^2 / 3; amplitudes are the global
+        ones; no slope jumps;
+      lam_I = 5 / h_I max_q (|u_I| + |B| / sqrt(rho)) over the element's nodes;
+      D_l = exp(-s_M tau sum_I lam_I sum_{r <= l} sigma_{I,r}).
+    A wrong rate (|B| / rho), a per-component amplitude, a dropped order r, or a missing floor in the
+    nearly constant row 2 each move D far outside the tolerance."""
+    p = m = 2
+    nx, hx, hy, tau, sM, c = 3, 0.5, 0.4, 0.1, 0.02, 0.3
+    a = np.array([0.4, 0.1, 4e-8, 0.25])
+    ny = len(a)
+    M = O.Mesh(nx, ny, p, m, 0, nx * hx, 0, ny * hy)
+    xi, w = O.gll(p)
+    X, Y = np.meshgrid(xi, xi)  # [j][i]: X = xhat_i, Y = yhat_j
+    K = M.K
+    ey = np.arange(K) // nx
+    u = np.zeros((3, K, 3, 3))
+    u[0] = a[ey][:, None, None] * (X + X * X)[None]
+    u[1] = 0.3
+    u[2] = c * a[ey][:, None, None] * X[None]
+    rho = np.empty((K, 3, 3))
+    rho[:] = 1.0 + 0.4 * X * Y + 0.2 * Y
+    e = np.full((K, 3, 3), 2.0)
+    G1 = (m + 1)
+    Bx = np.full((ny * G1, nx * G1), 0.3)
+    By = np.full_like(Bx, -0.2)
+    Bz = np.zeros_like(Bx)
+    Bzq = np.empty((K, 3, 3))
+    for k in range(K):
+        ex_, ey_ = k % nx, k // nx
+        Bzq[k] = 0.2 + 0.3 * X + 0.1 * (ey_ + 1) * Y
+        Bz[ey_ * G1:(ey_ + 1) * G1, ex_ * G1:(ex_ + 1) * G1] = Bzq[k]
+    _, _, D = O.velocity_oe(M, O.Options(oe_mag=1, s_M=sM), tau, rho, u, e, Bx, By, Bz)
+
+    # hand computation
+    mean_x, mean_z = a.mean() / 3, 0.0
+    dOm_x = max(max(abs(2 * aa - mean_x), abs(0 - mean_x)) for aa in a)
+    dOm_z = c * a.max()
+    rowx = np.maximum(5 * a / 3, 1e-6 * dOm_x)
+    rowz = np.maximum(c * a, 1e-6 * dOm_z)
+    Dsx = np.maximum(rowx, rowz)
+    sx0 = np.maximum(2 * a, 2 * c * a) / Dsx
+    sx1 = 1.5 * hx * (16 * a / hx) / Dsx
+    Dsy = max(dOm_x, dOm_z)
+    da_lo, da_hi = np.abs(a - np.roll(a, 1)), np.abs(np.roll(a, -1) - a)
+    jyx = math.sqrt(2 / 3) * (da_lo + da_hi)
+    jyz = c / math.sqrt(3) * (da_lo + da_hi)
+    sy0 = 0.5 * np.maximum(jyx, jyz) / Dsy
+    B2 = 0.3 ** 2 + 0.2 ** 2 + Bzq ** 2
+    va = np.sqrt(B2) / np.sqrt(rho)
+    lam_x = 5 / hx * (np.abs(u[0]) + va).reshape(K, -1).max(1)
+    lam_y = 5 / hy * (np.abs(u[1]) + va).reshape(K, -1).max(1)
+    th1 = lam_x * (sx0[ey] + sx1[ey]) + lam_y * sy0[ey]
+    ref = np.exp(-sM * tau * th1)
+    np.testing.assert_allclose(D[:, 1], ref, rtol=1e-10)
+    np.testing.assert_allclose(D[:, 2], ref, rtol=1e-10)  # no second-derivative jumps
+    assert (D[:, 1] < 0.99).all() and (D[:, 1] > 0.05).all()
+    # the floor row's shared amplitude is the floor of u_x, not its own 5 a / 3
+    assert rowx[2] == 1e-6 * dOm_x and Dsx[2] == rowx[2]

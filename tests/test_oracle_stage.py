@@ -186,3 +186,38 @@ def test_reject_equals_two_half_steps():
     Ub, r1, *_ = O.hydro_substep(M, o, U, tau / 2)
     Ub, r2, *_ = O.hydro_substep(M, o, Ub, tau / 2)
     assert (Ua == Ub).all()
+
+
+def test_oe_cross_line_amplitude_by_row_with_floor():
+    """Eq. euler-oe-amplitude with rows of different amplitude.  p = 1, rho = 1, m = 0 and, in
+    element row ey, E = E0 + a_ey * xhat.  Then, by hand:
+      x-direction (the element's row): every x-face value jump is 2 a_ey, so J_0 = 4 a_ey; the row
+        mean is E0, so Delta_x = max(a_ey, 1e-6 Delta_Omega) and sigma_x0 = 2 a_ey / Delta_x;
+      y-direction (the element's column, i.e. all rows): the y-face jump is (a_ey' - a_ey) xhat, so
+        (1/|F|) int [[E]]^2 = (a_ey' - a_ey)^2 and J_0 = |a_ey - a_below| + |a_above - a_ey|; the
+        column mean is E0, so Delta_y = max_ey a_ey = Delta_Omega and sigma_y0 = J_0 / (2 Delta_y);
+      no derivative jumps (sigma_1 = 0); D_1 = exp(-s tau (lam_x sigma_x0 + lam_y sigma_y0)).
+    Row, column and global amplitudes all differ, and row 2 is nearly constant, so its amplitude is
+    the 1e-6 Delta_Omega floor: reading the column for an x-jump, the row for a y-jump, or dropping
+    the floor changes D_1 by far more than the tolerance."""
+    p, hx, hy, tau, sH = 1, 0.25, 0.4, 0.01, 0.02
+    a = np.array([0.5, 0.2, 2.5e-7, 0.35])
+    nx, ny = 3, len(a)
+    L = W.Layout(nx, ny, p, p, 0, nx * hx, 0, ny * hy)
+    xi = W.gll_nodes(p)
+    sh = (L.K, p + 1, p + 1)
+    U = W.conservative(np.ones(sh), np.zeros(sh), np.zeros(sh), np.zeros(sh), np.full(sh, 1.5), G)
+    ey = np.arange(L.K) // nx
+    U[4] += a[ey][:, None, None] * xi[None, None, :]
+    M = O.Mesh(nx, ny, p, p, L.x0, L.x1, L.y0, L.y1)
+    _, _, _, D = O.hydro_stage_map(M, O.Options(oe_hydro=1, s_H=sH), U, tau)
+    dOm = a.max()
+    dx = np.maximum(a, 1e-6 * dOm)
+    sx0 = 2 * a / dx
+    jy = np.abs(a - np.roll(a, 1)) + np.abs(np.roll(a, -1) - a)
+    sy0 = jy / (2 * dOm)
+    c = math.sqrt(G * 1.5)  # element averages: rho = 1, m = 0, p = 1.5
+    lam_x, lam_y = 3 * c / hx, 3 * c / hy
+    ref = np.exp(-sH * tau * (lam_x * sx0 + lam_y * sy0))
+    np.testing.assert_allclose(D[:, 1], ref[ey], rtol=1e-10)
+    assert abs(sx0[2] - 1.0) < 1e-9  # the floor row: 2 a / (1e-6 Delta_Omega) = 1, not 2
