@@ -841,7 +841,8 @@ __global__ __launch_bounds__(256, (P == 4 && M == 3) ? 6 : 1) void k_vel_sensor(
     const double gs = glob[c * 3], gmn = glob[c * 3 + 1], gmx = glob[c * 3 + 2];
     const double gm = gs * mp.r4K;
     const double dOm = fmax(gmx - gm, gm - gmn);
-    scst[el][c] = dOm <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn)) ? 1 : 0;
+    // constant to roundoff: the nodal values agree to 2^10 ulps of the field's size (exact test)
+    scst[el][c] = gmx - gmn <= 1024.0 * EPSM * fmax(fabs(gmx), fabs(gmn)) ? 1 : 0;
     const double* rl = lines + (ey * NU + c) * 3;
     const double* cl = lines + ((mp.ny + ex) * NU + c) * 3;
     const double rm = rl[0] * mp.r4nx, cm = cl[0] * mp.r4ny;
@@ -1179,7 +1180,7 @@ __global__ __launch_bounds__(256) void k_ar_eta(const double* __restrict__ tr, c
   for (int c = 0; c < 3; ++c) {
     const double mean = bglob[c * 3] / area, mn = bglob[c * 3 + 1], mx = bglob[c * 3 + 2];
     dOm[c] = fmax(mx - mean, mean - mn);
-    cf[c] = dOm[c] <= 1024.0 * EPSM * fmax(fabs(mx), fabs(mn));
+    cf[c] = mx - mn <= 1024.0 * EPSM * fmax(fabs(mx), fabs(mn));  // roundoff-level variation (exact test)
   }
   const double* me = tr + e * NT;
   double R[2];
@@ -1415,11 +1416,12 @@ static long mblocks(int p, int m, long K, int bs = 256) {
 #endif
 
 // r2: the 2D2V reduced system (only J_z and E_z are formed; the in-plane grids are not written)
-int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
-                       const double* eta, double* JE, bool r2) {
+// loads: the per-element load workspace, K (2 (m+2)(m+1) + (m+2)^2) doubles
+static int reconstruct_JE_ws(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
+                             const double* eta, double* JE, bool r2, double* loads) {
   const long K = c->mp.K, G = c->G;
   const int a = c->m + 2, b = c->m + 1;
-  double* Lx = c->loads;
+  double* Lx = loads;
   double* Ly = Lx + K * a * b;
   double* Lz = Ly + K * a * b;
   const long nbj = mblocks(c->p, c->m, K, MHD_JL_BS), nbe = mblocks(c->p, c->m, K, MHD_EL_BS);
@@ -1453,6 +1455,11 @@ int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const do
   DISPATCH_M(c->m, GE);
 #undef GE
   return chk(c, "reconstruct launch");
+}
+
+int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const double* By, const double* Bz,
+                       const double* eta, double* JE, bool r2) {
+  return reconstruct_JE_ws(c, u, Bx, By, Bz, eta, JE, r2, c->loads);
 }
 
 int mag_update(mhd25_ctx* c, const MagIO& io, int mode) {

@@ -378,3 +378,4 @@ def test_emulated_inadmissible_input_status_2(emu):
                                    1e-3, ctypes.byref(rep)) == 2
     assert np.array_equal(uv, uvel)
     lib.mhd25_destroy(h)
+

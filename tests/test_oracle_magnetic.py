@@ -294,3 +294,16 @@ def test_velocity_oe_factor_hand_computed():
     assert (D[:, 1] < 0.99).all() and (D[:, 1] > 0.05).all()
     # the floor row's shared amplitude is the floor of u_x, not its own 5 a / 3
     assert rowx[2] == 1e-6 * dOm_x and Dsx[2] == rowx[2]
+
+
+def test_ar_uniform_field_contributes_nothing_on_large_mesh():
+    """A uniform field has only roundoff-level variation, so every direction contributes zero and
+    eta = 0 exactly (eq. magnetic-ar-sensor), however many elements the mean is summed over: the
+    test for roundoff-level variation is the exact nodal spread, not the deviation from a mean
+    whose summation error grows with the mesh (1024 x 32 elements here, as the blast strip)."""
+    L, U, Bx, By, Bz = W.blast(1024, 32, 4, 3)
+    M = mesh_of(L)
+    rho, e, u = O.to_primitive(M, U)
+    u = u + 0.1  # nonzero speeds, so a spurious sensor response would show in eta
+    eta = O.ar_eta(M, O.Options(ar=1), rho, u, Bx, By, Bz)
+    assert (eta == 0.0).all(), eta.max()
