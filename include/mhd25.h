@@ -116,6 +116,22 @@ int mhd25_rhs_magnetic(mhd25_ctx* ctx, const double* rho, const double* u, const
                        const double* By, const double* Bz, const double* eta, double* de, double* du,
                        double* dBx, double* dBy, double* dBz);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mhd25_rhs_magnetic with the same arguments, kernels
+ * and results, whose workspace (the six reconstructed J, E grids and the per-element loads) is a
+ * fixed file-scope device array of 32 MiB per device instead of the context's workspace.  The
+ * call allocates nothing (its address is resolved once per device by mhd25_init).  The mesh must
+ * need at most 32 MiB: 8 (6 G + K (2 (m+2)(m+1) + (m+2)^2)) bytes with G = K (m+1)^2 (up to
+ * 211 x 211 elements at m = 2, 161 x 161 at m = 3); larger meshes return -1 before any device
+ * work.  Every call on a device shares that device's array: calls that overlap on one device
+ * (different streams, threads or contexts) race and must be serialised by the caller.  No
+ * entry of the array needs to start at zero (each is written before it is read).  Returns 0,
+ * -1 (null pointer or mesh above the limit) or -2 (no context was created on the current device,
+ * or a launch failed). */
+int mhd25_rhs_magnetic_noalloc(mhd25_ctx* ctx, const double* rho, const double* u, const double* Bx,
+                               const double* By, const double* Bz, const double* eta, double* de,
+                               double* du, double* dBx, double* dBy, double* dBz);
+
 /* Reconstructed current and electric field (eq. mag-current-proj, eq. mag-electric-proj):
  * J6 = six magnetic grids (J_x, J_y, J_z, E_x, E_y, E_z) in that order, overwritten. */
 int mhd25_reconstruct_JE(mhd25_ctx* ctx, const double* u, const double* Bx, const double* By,

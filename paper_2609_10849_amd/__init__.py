@@ -61,6 +61,7 @@ _SIGS = {
     "mhd25_hydro_stage_map": (ctypes.c_int, [_dp, _dp, ctypes.c_double, _dp]),
     "mhd25_hydro_substep": (ctypes.c_int, [_dp, _dp, ctypes.c_double, ctypes.POINTER(Report)]),
     "mhd25_rhs_magnetic": (ctypes.c_int, [_dp] * 12),
+    "mhd25_rhs_magnetic_noalloc": (ctypes.c_int, [_dp] * 12),
     "mhd25_reconstruct_JE": (ctypes.c_int, [_dp] * 7),
     "mhd25_ar_eta": (ctypes.c_int, [_dp] * 7),
     "mhd25_velocity_oe": (ctypes.c_int, [_dp, ctypes.c_double] + [_dp] * 6),
@@ -213,6 +214,13 @@ class Solver:
         self._chk(self.lib.mhd25_rhs_magnetic(self.h, _ptr(rho), _ptr(u), _ptr(Bx), _ptr(By), _ptr(Bz), _ptr(eta),
                                               _ptr(de), _ptr(du), _ptr(dBx), _ptr(dBy), _ptr(dBz)), "rhs_magnetic")
         return de, du, dBx, dBy, dBz
+
+    def rhs_magnetic_noalloc(self, rho, u, Bx, By, Bz, eta, de, du, dBx, dBy, dBz):
+        """L_M into caller-provided outputs with the library's fixed device workspace (no
+        allocation anywhere in the call)."""
+        return self._chk(self.lib.mhd25_rhs_magnetic_noalloc(self.h, _ptr(rho), _ptr(u), _ptr(Bx), _ptr(By),
+                                                             _ptr(Bz), _ptr(eta), _ptr(de), _ptr(du), _ptr(dBx),
+                                                             _ptr(dBy), _ptr(dBz)), "rhs_magnetic_noalloc")
 
     def ar_eta(self, rho, u, Bx, By, Bz, out=None):
         out = torch.empty(self.K, dtype=rho.dtype, device=rho.device) if out is None else out

@@ -42,6 +42,7 @@ int mag_check_input(mhd25_ctx* c, const double* rho, const double* e, const doub
                     const double* By, const double* Bz);
 int hydro_face_map(mhd25_ctx* c, int32_t* nbr, int32_t* fmap);
 int mag_dof_maps(mhd25_ctx* c, int32_t* dof);
+int noalloc_setup(mhd25_ctx* c);
 
 // fold the recorded (start, stop) pairs into the per-kernel totals
 static hipError_t timing_fold(mhd25_ctx* c) {
@@ -189,6 +190,7 @@ int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stre
   r = r ? r : alloc((void**)&c->artr, (size_t)K * (8 * (c->m + 2) + 2) * 8);
   if (!r && hipHostMalloc((void**)&c->h_pinned, 4096) != hipSuccess) r = fail(c, -3, "hipHostMalloc");
   if (r) { mhd25_destroy(c); return r; }
+  if ((r = noalloc_setup(c)) != 0) { mhd25_destroy(c); return r; }
   if (hipMemcpy(c->d_ht, &c->h_ht, sizeof(HydroTab), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->d_mt, &c->h_mt, sizeof(MagTab), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(c->d_flags, 0, K) != hipSuccess) {

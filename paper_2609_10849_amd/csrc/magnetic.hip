@@ -6,6 +6,8 @@
 // are written per element and summed by a per-node gather in a fixed order (no floating-point
 // atomics), then divided by the lumped weights (eq. quad-hcurl-element, eq. quad-cg-element).
 #include <cfloat>
+#include <mutex>
+#include <string>
 
 #include "common.h"
 #include "xcd.h"
@@ -1600,4 +1602,72 @@ int mag_B_from_potential(mhd25_ctx* c, const double* A, double* Bx, double* By) 
   DISPATCH_M(c->m, BP);
 #undef BP
   return chk(c, "potential launch");
+}
+
+// ---------------------------------------------------------------------------------------------
+// Allocation-free magnetic residual: the same kernels as mhd25_rhs_magnetic, with the
+// reconstructed J, E grids and the per-element loads in a fixed file-scope device array instead
+// of the context's workspace, for callers that cannot allocate device memory.
+// ---------------------------------------------------------------------------------------------
+namespace {
+constexpr long MHD_NOALLOC_DOUBLES = 4L << 20;  // 32 MiB per device
+__device__ __align__(256) double scratch[MHD_NOALLOC_DOUBLES];
+constexpr int MHD_MAX_DEVICES = 64;
+double* g_scratch[MHD_MAX_DEVICES];  // device address of `scratch` on each device (set once)
+std::mutex g_scratch_mu;
+}  // namespace
+
+// Resolves the device address of the scratch array on the current device, once per device (the
+// name `scratch` in host code is only a stand-in, never a device address).  Called by mhd25_init.
+int noalloc_setup(mhd25_ctx* c) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MHD_MAX_DEVICES) {
+    c->err = "no-alloc setup: no current device";
+    return -2;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch[dev]) return 0;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    c->err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return -2;
+  }
+  g_scratch[dev] = (double*)ptr;
+  return 0;
+}
+
+extern "C" int mhd25_rhs_magnetic_noalloc(mhd25_ctx* c, const double* rho, const double* u, const double* Bx,
+                                          const double* By, const double* Bz, const double* eta, double* de,
+                                          double* du, double* dBx, double* dBy, double* dBz) {
+  if (!c || !rho || !u || !Bx || !By || !Bz || !de || !du || !dBx || !dBy || !dBz) return -1;
+  const long K = c->mp.K, G = c->G;
+  const long a = c->m + 2, b = c->m + 1;
+  const long need = 6 * G + K * (2 * a * b + a * a);
+  if (need > MHD_NOALLOC_DOUBLES) {
+    c->err = "rhs_magnetic_noalloc: the mesh needs " + std::to_string(need * 8) + " bytes of scratch, above the " +
+             std::to_string(MHD_NOALLOC_DOUBLES * 8) + "-byte limit";
+    return -1;
+  }
+  int dev = 0;
+  double* ws = nullptr;
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < MHD_MAX_DEVICES) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ws = g_scratch[dev];
+  }
+  if (!ws) {
+    c->err = "rhs_magnetic_noalloc: scratch not set up on the current device (create a context on it first)";
+    return -2;
+  }
+  double* JE = ws;            // six grids: J_x, J_y, J_z, E_x, E_y, E_z
+  double* loads = ws + 6 * G;  // every entry is written by the load kernels before the gathers read it
+  const bool r2 = c->opt.reduced_2d2v != 0;
+  if (const int r = reconstruct_JE_ws(c, u, Bx, By, Bz, eta, JE, r2, loads)) return r;
+  MagIO io{};
+  io.rho = rho; io.us = u; io.bxs = Bx; io.bys = By; io.bzs = Bz;
+  io.jx = JE; io.jy = JE + G; io.jz = JE + 2 * G;
+  io.ex = JE + 3 * G; io.ey = JE + 4 * G; io.ez = JE + 5 * G;
+  io.eta = eta;
+  io.oe = de; io.ou = du; io.obx = dBx; io.oby = dBy; io.obz = dBz;
+  return mag_update(c, io, 0);
 }

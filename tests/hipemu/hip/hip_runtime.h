@@ -24,6 +24,7 @@
 #define __launch_bounds__(...)
 #define __shared__ static
 #define HIP_SYMBOL(x) (&x)
+#define __align__(n) alignas(n)
 #define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt(x))  // hardware 1/sqrt estimate
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))  // hardware 1/x estimate
 
@@ -73,6 +74,9 @@ struct EmuEvent { double t; };
 typedef EmuEvent* hipEvent_t;
 enum hipMemcpyKind { hipMemcpyHostToHost, hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice, hipMemcpyDefault };
 inline hipError_t hipGetLastError() { return hipSuccess; }
+inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+// a device symbol's address is its host address here (device memory is host memory)
+template <class T> inline hipError_t hipGetSymbolAddress(void** p, T* sym) { *p = (void*)sym; return hipSuccess; }
 inline const char* hipGetErrorString(hipError_t) { return "emu error"; }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 inline hipError_t hipMalloc(void** p, size_t n) { *p = std::calloc(1, n ? n : 8); return *p ? hipSuccess : hipErrorOutOfMemory; }

@@ -379,3 +379,30 @@ def test_emulated_inadmissible_input_status_2(emu):
     assert np.array_equal(uv, uvel)
     lib.mhd25_destroy(h)
 
+
+def test_emulated_rhs_magnetic_noalloc(emu):
+    """The allocation-free magnetic residual equals the context-workspace one bit for bit, on two
+    calls in a row (the second on a smaller mesh, over the first call's leftovers), and refuses a
+    mesh above its workspace limit with -1."""
+    lib, pk = emu
+    for nx, ny, p, m, seed in ((9, 7, 3, 2, 1), (4, 3, 4, 3, 2)):
+        L, U, Bx, By, Bz = W.random_state(nx, ny, p, m, seed=seed, domain=(0, 1.5, 0, 1.0), amp=0.3)
+        M = omesh(L)
+        rho, e, u = O.to_primitive(M, U)
+        eta = np.random.default_rng(seed).uniform(0, 0.05, M.K)
+        h = context(lib, pk, L, pk.Options.make())
+        ins = [np.ascontiguousarray(a) for a in (rho, u, Bx, By, Bz)]
+        outs = [[np.zeros_like(a) for a in (e, u, Bx, By, Bz)] for _ in range(2)]
+        assert lib.mhd25_rhs_magnetic(h, *[ptr(a) for a in ins], ptr(eta), *[ptr(a) for a in outs[0]]) == 0
+        assert lib.mhd25_rhs_magnetic_noalloc(h, *[ptr(a) for a in ins], ptr(eta), *[ptr(a) for a in outs[1]]) == 0
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b)
+        lib.mhd25_destroy(h)
+    big = pk.MeshDesc(256, 256, 0.0, 1.0, 0.0, 1.0, 4, 3, 5.0 / 3.0)
+    h = ctypes.c_void_p()
+    assert lib.mhd25_init(ctypes.byref(big), None, None, ctypes.byref(h)) == 0
+    z = np.zeros(8)
+    assert lib.mhd25_rhs_magnetic_noalloc(h, *[ptr(z)] * 6, *[ptr(z)] * 5) == -1
+    assert b"limit" in lib.mhd25_last_error(h)
+    lib.mhd25_destroy(h)
+
