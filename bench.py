@@ -6,9 +6,12 @@ B = (1, 1, 0)/sqrt(2); full Strang step with hydro OE, positivity scaling, veloc
 artificial resistivity; dt from the positivity CFL rule at CFL 0.3 before every step.
 One Strang step = 6 hydro + 3 magnetic stages; value = K (N+1)^2 * 9 / t_step.
 
-Prints one JSON line.  The roofline object describes the hydro stage kernel (L_E + SSP combine
-+ element statistics), roofline_oe_pp the hydro stage map (OE + PP), which takes about as long per
-launch; both are timed with HIP events on the library's stream.
+Prints one JSON line.  Every large kernel of the step is timed with HIP events on the library's
+stream (mhd25_timing_read); "roofline" describes the kernel with the largest share of the step
+time, "roofline_kernels" all of them, each with its algorithmic HBM bytes (and FP64 flops where
+the kernel is arithmetic) per launch against the MI355X peaks, and the counter-measured traffic
+and FP64 flops of profiles/kernel_counters.json when those were taken on the same kernel sources
+and workload (bench.py --ingest writes that record from rocprofv3 counter runs).
 """
 import argparse
 import hashlib
@@ -22,10 +25,132 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
-VALU_FILE = os.path.join(ROOT, "profiles", "hydro_valu_flops.json")
-TRAFFIC_FILES = {"stage": os.path.join(ROOT, "profiles", "hydro_stage_traffic.json"),
-                 "oe_pp": os.path.join(ROOT, "profiles", "hydro_oe_pp_traffic.json")}
-KERNEL_SRC = os.path.join(ROOT, "paper_2609_10849_amd", "csrc", "hydro.hip")
+COUNTER_FILE = os.path.join(ROOT, "profiles", "kernel_counters.json")
+CSRC = os.path.join(ROOT, "paper_2609_10849_amd", "csrc")
+KERNEL_SRC = os.path.join(CSRC, "hydro.hip")
+
+
+def kernel_table(N, k):
+    """The timed kernels of a Strang step: (timing id, name, rocprofv3 name prefix, source file,
+    algorithmic HBM bytes per element and launch, algorithmic FP64 flops per element and launch or
+    None, fraction of a block's lanes that carry work).  Bytes count each array the kernel must
+    touch once (neighbour data counted as cache hits); the stage kernel's and the map's are the
+    averages over the launches of a step (see stage_bytes, oe_pp_bytes)."""
+    NP, nn = N + 1, (N + 1) ** 2
+    A, B = k + 2, k + 1
+    psi = nn * (nn + (nn % 2)) * 8
+    grid3 = 3 * B * B * 8
+    loads = (2 * A * B + A * A) * 8
+    y = 4 * nn * 8 + grid3  # (e, u, B) of one element
+    blk = lambda bs, nt: (bs // nt) * nt / bs
+    nt = max(nn, A * A)
+    return [
+        (0, "hydro stage (L_E + SSP combine + statistics)", "k_hydro_stage<", "hydro.hip",
+         (8.0 / 3.0) * 5 * nn * 8 + 15 * 8, stage_flops(1, NP), blk(128, nn)),
+        (1, "hydro stage map (OE + PP)", "k_hydro_oe_pp<", "hydro.hip",
+         2 * 5 * nn * 8 + 5 * nn * 8 / 6.0 + 49, oe_pp_flops(1, NP), blk(128, nn)),
+        (2, "magnetic update (curl, Lorentz, Ohm, SSP combine)", "k_mag_update<", "magnetic.hip",
+         2 * grid3 + nn * 8 + 8 + y + (2.0 / 3.0) * y + y + 9 * 8, None, blk(256, nt)),
+        (3, "velocity-OE projection", "k_vel_proj<", "magnetic.hip",
+         psi + 3 * nn * 8 + 2 * nn * 8 + NP * 8 + 4 * nn * 8, None, blk(128, nn)),
+        (4, "velocity-OE preparation (Gram, Cholesky, basis)", "k_vel_prep<", "magnetic.hip",
+         nn * 8 + psi, None, blk(64, nn)),
+        (5, "E loads", "k_E_loads<", "magnetic.hip", 3 * nn * 8 + 2 * grid3 + 8 + loads, None, blk(128, nt)),
+        (6, "velocity-OE sensor", "k_vel_sensor<", "magnetic.hip", 4 * nn * 8 + grid3 + NP * 8, None, blk(256, nn)),
+        (7, "J loads", "k_J_loads<", "magnetic.hip", grid3 + loads, None, blk(256, nt)),
+        (8, "gathers of shared DOFs", "k_gather<", "magnetic.hip", loads + grid3, None, 1.0),
+        (9, "A.R. traces", "k_ar_traces<", "magnetic.hip", 4 * nn * 8 + grid3 + (8 * A + 2) * 8, None, blk(256, nn)),
+    ]
+
+
+def source_sha(fname):
+    """Hash of a kernel source file and the headers every kernel file includes."""
+    h = hashlib.sha256(open(os.path.join(CSRC, fname), "rb").read())
+    for name in ("common.h", "xcd.h", "ec_log.h", "rsqrt.h"):
+        h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def counter_record(prefix, fname, K, N):
+    """Counter-measured bytes and FP64 flops per launch of a kernel from profiles/kernel_counters.json,
+    or None when missing or taken on other kernel sources or another workload."""
+    try:
+        d = json.load(open(COUNTER_FILE))
+    except (OSError, ValueError):
+        return None
+    r = d.get("kernels", {}).get(prefix)
+    if not r or r.get("src_sha") != source_sha(fname) or d.get("elements") != K or d.get("N") != N:
+        return None
+    return r
+
+
+def ingest_counters(dirs, K=1048576, N=4, k=3, steps=1):
+    """Write profiles/kernel_counters.json (and a readable summary) from rocprofv3 --pmc runs of
+    `bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-extras`: one directory with FETCH_SIZE, one
+    with WRITE_SIZE and one with the FP64 instruction counters (SQ_INSTS_VALU_FLOPS_FP64, SQ_INSTS_VALU,
+    SQ_WAVES).  FETCH_SIZE and WRITE_SIZE are scaled by what they read for the entry snapshot kernel,
+    which copies the state (5 K (N+1)^2 doubles) once: known bytes over counter value.  FP64 flops per
+    launch are SQ_INSTS_VALU_FLOPS_FP64 (2 FMA + ADD + MUL + TRANS FP64 instructions per wave) times 64
+    lanes times the fraction of a block's lanes that carry work."""
+    import csv
+    import glob
+    vals = {}  # counter -> kernel prefix -> [values per dispatch]
+    cmd = []
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                name, ctr = row["Kernel_Name"], row["Counter_Name"]
+                val = float(row["Counter_Value"])
+                for pre in [t[2] for t in kernel_table(N, k)] + ["k_snap_check_U"]:
+                    if pre in name:
+                        vals.setdefault(ctr, {}).setdefault(pre, []).append(val)
+    known = 5.0 * K * (N + 1) ** 2 * 8
+    fetch_cal = known / vals["FETCH_SIZE"]["k_snap_check_U"][0]
+    write_cal = known / vals["WRITE_SIZE"]["k_snap_check_U"][0]
+    out = {"elements": K, "N": N, "k": k, "workload": "blast-like state %dx%d elements, N=%d, k=%d, one Strang step"
+           % (int(K ** 0.5), int(K ** 0.5), N, k),
+           "calibration": {"kernel": "k_snap_check_U (entry snapshot: copies the state)", "bytes": known,
+                           "fetch_factor": fetch_cal, "write_factor": write_cal},
+           "commands": ["rocprofv3 --pmc %s --output-format csv -d gpurun_out/%s -o %s -- python -u bench.py --steps 1 "
+                        "--warmup 0 --no-cpu-baseline --no-extras" % (c, d, d[-1].lower())
+                        for c, d in (("FETCH_SIZE", "pmcF"), ("WRITE_SIZE", "pmcW"),
+                                     ("SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_FLOPS_FP64", "pmcV"))],
+           "kernels": {}}
+    for kid, name, prefix, fname, bytes_el, flops_el, lanes in kernel_table(N, k):
+        f = vals.get("FETCH_SIZE", {}).get(prefix)
+        w = vals.get("WRITE_SIZE", {}).get(prefix)
+        if not f or not w:
+            continue
+        per = [a * fetch_cal + b * write_cal for a, b in zip(f, w)]
+        r = {"kernel": name, "src_sha": source_sha(fname), "launches": len(per),
+             "fetch_bytes_per_launch": sum(a * fetch_cal for a in f) / len(f),
+             "write_bytes_per_launch": sum(b * write_cal for b in w) / len(w),
+             "bytes_per_launch": sum(per) / len(per), "algorithmic_bytes_per_launch": K * bytes_el}
+        fl = vals.get("SQ_INSTS_VALU_FLOPS_FP64", {}).get(prefix)
+        if fl:
+            r["flops_per_launch"] = sum(fl) / len(fl) * 64 * lanes
+            r["valu_insts_per_launch"] = sum(vals["SQ_INSTS_VALU"][prefix]) / len(fl)
+            r["waves_per_launch"] = sum(vals["SQ_WAVES"][prefix]) / len(fl)
+            if flops_el is not None:
+                r["algorithmic_flops_per_launch"] = K * flops_el
+        out["kernels"][prefix] = r
+    json.dump(out, open(COUNTER_FILE, "w"), indent=1)
+    lines = ["# Per-kernel HBM traffic and FP64 work, blast-like state 1024x1024, N=4, k=3", "",
+             "Counter runs (one Strang step each, on one MI355X):", ""]
+    lines += ["    " + c for c in out["commands"]]
+    lines += ["", "Calibration on the entry snapshot kernel, which copies the state (%d bytes): FETCH_SIZE x %.4f, "
+              "WRITE_SIZE x %.4f." % (known, fetch_cal, write_cal), "",
+              "| kernel | launches | measured GB/launch | algorithmic GB/launch | ratio | FP64 Gflop/launch (counter) |",
+              "|---|---|---|---|---|---|"]
+    for pre, r in out["kernels"].items():
+        lines.append("| `%s` | %d | %.3f | %.3f | %.2f | %s |" % (
+            pre.rstrip("<"), r["launches"], r["bytes_per_launch"] / 1e9, r["algorithmic_bytes_per_launch"] / 1e9,
+            r["bytes_per_launch"] / r["algorithmic_bytes_per_launch"],
+            "%.2f" % (r["flops_per_launch"] / 1e9) if "flops_per_launch" in r else "-"))
+    lines += ["", "Source hashes (bench.source_sha): " + ", ".join(
+        "%s %s" % (f, source_sha(f)) for f in ("hydro.hip", "magnetic.hip")) + "."]
+    open(os.path.join(ROOT, "profiles", "kernel_counters_blast1024_N4.md"), "w").write("\n".join(lines) + "\n")
+    return out
 
 
 def stage_bytes(K, nn):
@@ -58,26 +183,15 @@ def oe_pp_flops(K, NP):
     return K * (jumps + sigma + 40 * NP ** 3 + 5 * nn + 4 * NP + 30 * nn)
 
 
-def valu_per_launch(kind, K=1048576, N=4):
-    """Executed FP64 flops per launch of a hydro kernel from the committed SQ counter run
-    (SQ_INSTS_VALU_FLOPS_FP64 counts 2 FMA + ADD + MUL + TRANS instructions per wave; times
-    the active lanes), or None when missing or taken on a different kernel source or workload."""
-    try:
-        d = json.load(open(VALU_FILE))[kind]
-    except (OSError, ValueError, KeyError):
-        return None
-    if d.get("kernel_src_sha") != kernel_sha(kind) or d.get("elements") != K or d.get("N") != N:
-        return None
-    return d.get("flops_per_launch")
-
-
 def valu_object(flops_alg, flops_ctr, avg_ms):
     """FP64 VALU view of a kernel: algorithmic and counter-measured TFLOP/s against the FP64
-    vector peak."""
+    vector peak (either may be None)."""
     t = avg_ms * 1e-3
-    out = {"peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-           "algorithmic": flops_alg / t / 1e12, "algorithmic_frac": flops_alg / t / 1e12 / FP64_PEAK_TFS,
+    out = {"peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "algorithmic": None, "algorithmic_frac": None,
            "counter": None, "counter_frac": None}
+    if flops_alg is not None:
+        out["algorithmic"] = flops_alg / t / 1e12
+        out["algorithmic_frac"] = flops_alg / t / 1e12 / FP64_PEAK_TFS
     if flops_ctr is not None:
         out["counter"] = flops_ctr / t / 1e12
         out["counter_frac"] = flops_ctr / t / 1e12 / FP64_PEAK_TFS
@@ -102,64 +216,49 @@ def oe_pp_bytes(K, nn):
     return 2 * u + u / 6.0 + K * (6 * 8 + 1)
 
 
-def kernel_sha(kind="stage"):
-    """Hash of the source a hydro kernel is built from.  "stage": hydro.hip up to the end of the
-    stage kernel (its device helpers and element statistics), its launch helpers and launcher, and
-    the headers it includes; edits elsewhere (the OE/PP map) leave its counters valid.
-    "oe_pp": hydro.hip up to the end of the stage map (so the stage kernel's source as well), its
-    launcher, and the same headers."""
-    src = open(KERNEL_SRC, encoding="utf-8").read()
-    if kind == "stage":
-        end = src.index("template <int P>\n__global__ __launch_bounds__(256) void k_elem_stats(")
-        a = src.index("static int eb_of(")  # launch helpers (block size choice) and the launcher
-        b = src.index("int line_global_reduce(", a)
-    elif kind == "oe_pp":
-        end = src.index("}  // namespace\n", src.index("void k_hydro_oe_pp("))
-        a = src.index("int hydro_stage_b(")
-        b = src.index("int reset_attempt(", a)
-    else:
-        raise ValueError(kind)
-    h = hashlib.sha256((src[:end] + src[a:b]).encode())
-    for name in ("common.h", "xcd.h", "ec_log.h", "rsqrt.h"):
-        h.update(open(os.path.join(os.path.dirname(KERNEL_SRC), name), "rb").read())
-    return h.hexdigest()[:16]
-
-
-def traffic_per_launch(kind="stage", K=1048576, N=4):
-    """HBM bytes per launch of a hydro kernel from the committed rocprofv3 counter runs, or None
-    when they are missing or were taken on a different kernel source or workload (K, N)."""
+def cpu_model():
     try:
-        d = json.load(open(TRAFFIC_FILES[kind]))
-    except (OSError, ValueError):
-        return None
-    if d.get("kernel_src_sha") != kernel_sha(kind) or d.get("elements") != K or d.get("N") != N:
-        return None
-    return d.get("bytes_per_launch")
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def cpu_baseline(seconds_hint=20.0):
-    """The plain FP64 oracle, timed on this host: two Strang steps of the same blast workload on
-    a 128 x 128 sub-resolution mesh (same domain, N = 4, k = 3, same options)."""
+def cpu_baseline():
+    """The plain FP64 oracle, timed on this host: Strang steps of the same blast workload (same
+    domain, N = 4, k = 3, full stabilisation) on a 128 x 128 sub-resolution mesh with all host
+    threads, and one step on 32 x 32 with one thread."""
     import numpy as np
 
     import oracle as O
     from paper_2609_10849_amd import workloads as W
 
-    n = 128
-    L, U, Bx, By, Bz = W.blast(n, n, 4, 3)
-    M = O.Mesh(L.nx, L.ny, L.p, L.m, L.x0, L.x1, L.y0, L.y1, L.gamma)
-    threads = O.set_threads(0)
-    dt = 2.0e-5
-    steps = 6
-    t0 = time.perf_counter()
-    st = (U, Bx, By, Bz)
-    for _ in range(steps):
-        st = O.strang_step(M, O.Options.full(), *st, dt)[:4]
-    t = time.perf_counter() - t0
-    rate = M.K * 25 * 9 * steps / t
-    return {"value": rate, "unit": "DOF-stage updates/s", "cores": threads, "kind": "oracle",
-            "sample": "blast workload at 128x128 elements (N=4, k=3, full stabilisation), %d Strang steps, "
-                      "%.1f s on %d OpenMP threads" % (steps, t, threads)}
+    def run(n, steps, threads):
+        L, U, Bx, By, Bz = W.blast(n, n, 4, 3)
+        M = O.Mesh(L.nx, L.ny, L.p, L.m, L.x0, L.x1, L.y0, L.y1, L.gamma)
+        used = O.set_threads(threads)
+        # the positivity-CFL step at CFL 0.3 of the initial state (fast speed sqrt(gamma p_in + |B|^2)
+        # inside the blast, u = 0), as the GPU run takes it
+        cf = (5.0 / 3.0 * 1000.0 + 1.0) ** 0.5
+        dt = 0.3 / (9.0 * 2.0 * cf * n)
+        t0 = time.perf_counter()
+        st = (U, Bx, By, Bz)
+        for _ in range(steps):
+            st = O.strang_step(M, O.Options.full(), *st, dt)[:4]
+        t = time.perf_counter() - t0
+        return M.K * 25 * 9 * steps / t, t, used
+
+    ncpu = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    rate, t, used = run(128, 6, ncpu)
+    rate1, t1, _ = run(32, 1, 1)
+    O.set_threads(ncpu)
+    return {"value": rate, "unit": "DOF-stage updates/s", "cores": used, "kind": "oracle",
+            "sample": "blast workload at 128x128 elements (N=4, k=3, full stabilisation), 6 Strang steps, "
+                      "%.1f s on %d OpenMP threads" % (t, used),
+            "cpu_model": cpu_model(), "host_cpus": ncpu,
+            "one_thread": {"value": rate1, "sample": "blast workload at 32x32 elements, 1 Strang step, %.1f s" % t1}}
 
 
 def _event_ms(fn, reps, warm=3):
@@ -206,12 +305,12 @@ def adjoint_ratio():
             "workload": "noisy isentropic vortex, 128x128 elements, N=3, k=2"}
 
 
-def batched_speedup(steps=50, streams=False):
+def batched_speedup(steps=50, only=None):
     """Ensemble of 64 uneven runs (n in {32..192}, N in {2,3,4}, k = N-1, vortex amplitude and
     field drawn from PCG64 seed 0; full stabilisation; per-run dt from CFL 0.3 at the start):
-    time per Strang step of all runs, sequential plain launches vs the batch step: the captured
-    multi-branch graph, or with streams=True the same deferred steps launched directly on the
-    concurrent branch streams."""
+    time per Strang step of all runs for sequential plain launches, the run-table step (one launch
+    per kernel and degree group over all runs) replayed from its HIP graph, the same launched
+    plainly, and the per-run steps on concurrent branch streams.  value = sequential / graph."""
     import numpy as np
     import torch
 
@@ -231,29 +330,40 @@ def batched_speedup(steps=50, streams=False):
         dts.append(S.cfl_dt(*[dev(a) for a in st], 0.3))
         S.close()
     B = pk.Batch(layouts, pk.Options.full())
-    if streams:  # tile and branch choice by the event-timed autotuner (on scratch copies; untimed)
-        g0 = [[dev(a) for a in st] for st in states]
-        B.autotune(*[[x[i] for x in g0] for i in range(4)], dts)
-        del g0
+    g0 = [[dev(a) for a in st] for st in states]  # tiles and branch count by the event-timed autotuner (untimed)
+    B.autotune(*[[x[i] for x in g0] for i in range(4)], dts)
+    del g0
 
-    def run(sequential, nsteps):
+    def run(nsteps, sequential=False, streams=False, graph=False):
+        B.graph(graph)
         g = [[dev(a) for a in st] for st in states]
         args = [[x[i] for x in g] for i in range(4)]
-        B.strang_step(*args, dts, sequential=sequential, streams=streams)  # warm-up (and capture)
+        B.strang_step(*args, dts, sequential=sequential, streams=streams)  # warm-up (plan, capture)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(nsteps):
             r, _ = B.strang_step(*args, dts, sequential=sequential, streams=streams)
+            if r != 0:
+                raise RuntimeError("batch step failed: %d" % r)
         torch.cuda.synchronize()
+        B.graph(False)
         return 1e3 * (time.perf_counter() - t0) / nsteps
 
-    ts = run(True, steps)
-    tb = run(False, steps)
+    if only == "graph":
+        tg = run(steps, graph=True)
+        B.close()
+        return {"graph_ms_per_step": tg}
+    ts = run(steps, sequential=True)
+    tg = run(steps, graph=True)
+    te = run(steps)
+    tb = run(steps, streams=True)
     B.close()
     nodes = sum(L.K * (L.p + 1) ** 2 for L in layouts)
-    return {"value": ts / tb, "sequential_ms_per_step": ts, "batched_ms_per_step": tb, "runs": 64,
-            "steps": steps, "nodes": nodes,
-            "path": "branch streams, no graph, autotuned tiles" if streams else "captured graph"}
+    return {"value": ts / tg, "sequential_ms_per_step": ts, "graph_ms_per_step": tg, "run_table_ms_per_step": te,
+            "run_table_speedup": ts / te, "streams_ms_per_step": tb, "streams_speedup": ts / tb,
+            "runs": 64, "steps": steps, "nodes": nodes,
+            "path": "run-table launches (one per kernel and degree group over all runs) replayed from a HIP graph; "
+                    "autotuned stage tiles"}
 
 
 def reduced_2d2v(S, g, steps=10, warm=2):
@@ -325,9 +435,17 @@ def main():
     ap.add_argument("--reduced-2d2v", action="store_true",
                     help="time the 2D2V reduced system instead of the general path (for profiling it)")
     ap.add_argument("--ensemble-only", action="store_true",
-                    help="time only the 64-run ensemble (streams batch step against sequential launches), for "
-                         "profiling it; prints its own JSON line")
+                    help="time only the 64-run ensemble (batch steps against sequential launches); prints its own "
+                         "JSON line")
+    ap.add_argument("--ingest", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "VALU_DIR"),
+                    help="write profiles/kernel_counters.json from three rocprofv3 --pmc output directories (no GPU)")
+    ap.add_argument("--ensemble-graph-only", action="store_true",
+                    help="time only the graph-replayed run-table batch step of the 64-run ensemble (for profiling)")
     args = ap.parse_args()
+    if args.ingest:
+        out = ingest_counters(args.ingest)
+        print(json.dumps({k: v["bytes_per_launch"] for k, v in out["kernels"].items()}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
               "'How the path would shard')", file=sys.stderr)
@@ -340,7 +458,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.ensemble_only:
-        print(json.dumps({"batched_streams_speedup": batched_speedup(steps=args.steps, streams=True)}), flush=True)
+        print(json.dumps({"batched_speedup": batched_speedup(steps=args.steps)}), flush=True)
+        return
+    if args.ensemble_graph_only:
+        print(json.dumps({"batched_graph": batched_speedup(steps=args.steps, only="graph")}), flush=True)
         return
     n, N, k = args.n, 4, 3
     L, U, Bx, By, Bz = W.blast(n, n, N, k)
@@ -372,16 +493,29 @@ def main():
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     S.timing(False)
-    launches, kms = S.timing_read(0)
-    launches_b, kms_b = S.timing_read(1)
     ms_per_step = 1e3 * t / args.steps
     value = K * nn * 9 / (t / args.steps)
-    avg_ms = kms / max(launches, 1)
-    ach = stage_bytes(K, nn) / (avg_ms * 1e-3) / 1e9
-    tr = traffic_per_launch("stage", K, N)
-    avg_b = kms_b / max(launches_b, 1)
-    tr_b = traffic_per_launch("oe_pp", K, N)
-    ach_b = oe_pp_bytes(K, nn) / (avg_b * 1e-3) / 1e9
+    kernels = []
+    for kid, name, prefix, fname, bytes_el, flops_el, lanes in kernel_table(N, k):
+        launches, kms = S.timing_read(kid)
+        if launches == 0:
+            continue
+        avg = kms / launches
+        ach = K * bytes_el / (avg * 1e-3) / 1e9
+        rec = counter_record(prefix, fname, K, N)
+        tr = rec.get("bytes_per_launch") if rec else None
+        o = {"kernel": name, "name": prefix.rstrip("<"), "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": tr, "avg_ms": avg,
+             "launches_per_step": launches / args.steps, "ms_per_step": kms / args.steps,
+             "share": kms / args.steps / ms_per_step,
+             "algorithmic_bytes_per_launch": K * bytes_el,
+             "traffic_achieved": traffic_rate(tr, avg)[0], "traffic_frac": traffic_rate(tr, avg)[1]}
+        fl_ctr = rec.get("flops_per_launch") if rec else None
+        if flops_el is not None or fl_ctr is not None:
+            o["valu"] = valu_object(K * flops_el if flops_el is not None else None, fl_ctr, avg)
+        kernels.append(o)
+    kernels.sort(key=lambda o: -o["ms_per_step"])
+    dominant = dict(kernels[0])
     out = {
         "metric": "DOF-stage updates/s (FP64) per Strang step",
         "value": value,
@@ -399,28 +533,16 @@ def main():
                                "p_in/p_out=1e4, full stabilisation (OE, PP, velocity OE, A.R.), CFL 0.3" % (n, n, N, k),
                    "elements": K, "N": N, "k": k, "dofs": K * nn,
                    "system": "2D2V reduced" if args.reduced_2d2v else "general"},
-        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                     "traffic": tr, "kernel": "k_hydro_stage<4,1> (L_E + SSP combine + element statistics)",
-                     "avg_ms": avg_ms, "launches": launches,
-                     "traffic_achieved": traffic_rate(tr, avg_ms)[0], "traffic_frac": traffic_rate(tr, avg_ms)[1],
-                     "valu": valu_object(stage_flops(K, N + 1), valu_per_launch("stage", K, N), avg_ms)},
-        "roofline_oe_pp": {"bound": "hbm", "achieved": ach_b, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach_b / HBM_PEAK_GBS, "traffic": tr_b,
-                           "kernel": "k_hydro_oe_pp<4,128> (hydro OE + PP map)", "avg_ms": avg_b,
-                           "launches": launches_b,
-                           "traffic_achieved": traffic_rate(tr_b, avg_b)[0],
-                           "traffic_frac": traffic_rate(tr_b, avg_b)[1],
-                           "valu": valu_object(oe_pp_flops(K, N + 1), valu_per_launch("oe_pp", K, N), avg_b)},
+        "roofline": dominant,
+        "roofline_kernels": kernels,
+        "timed_kernels_ms_per_step": sum(o["ms_per_step"] for o in kernels),
         "accepted_substep_rate": accepted / max(attempted, 1),
     }
     if not args.no_extras and not args.reduced_2d2v:
         out["hydro_only"] = hydro_only(S, g, steps=min(args.steps, 10))
         out["reduced_2d2v"] = reduced_2d2v(S, g, steps=min(args.steps, 10))
         out["adjoint_cost_ratio"] = adjoint_ratio()
-        # the captured-graph ensemble path is held off the GPU until the cause of a host
-        # segmentation fault seen in one build of it is shown (last measured speedup: 1.63)
-        out["batched_speedup"] = None
-        out["batched_streams_speedup"] = batched_speedup(steps=min(args.steps, 20), streams=True)
+        out["batched_speedup"] = batched_speedup(steps=min(args.steps, 20))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

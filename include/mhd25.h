@@ -62,6 +62,10 @@ typedef struct {
                              * caller guarantees u_z = 0 and B_z = 0; the magnetic substep then
                              * neither reads nor writes u_z and B_z and skips the identically
                              * zero in-plane E and J (results equal the general path's). Default 0 */
+  int32_t strang_order;     /* 0 (default): H(dt/2) M(dt) H(dt/2), the composition the paper states
+                             * (eq. strang-composition, Algorithm "Strang split MHD step");
+                             * 1: M(dt/2) H(dt) M(dt/2), the magnetic-outer composition, whose
+                             * results reproduce the magnitudes of the paper's temporal table */
 } mhd25_options;
 
 typedef struct {
@@ -158,7 +162,8 @@ int mhd25_step_magnetic(mhd25_ctx* ctx, const double* rho, double* e, double* u,
 int mhd25_to_primitive(mhd25_ctx* ctx, const double* U, double* rho, double* e, double* u);
 int mhd25_to_conservative(mhd25_ctx* ctx, const double* rho, const double* e, const double* u, double* U);
 
-/* Algorithm "Strang split MHD step": H(dt/2) -> exchange -> M(dt) -> exchange -> H(dt/2).
+/* Algorithm "Strang split MHD step": H(dt/2) -> exchange -> M(dt) -> exchange -> H(dt/2), or with
+ * strang_order = 1 exchange -> M(dt/2) -> exchange -> H(dt) -> exchange -> M(dt/2) -> exchange.
  * U and B in place.  Returns 0, 1 (a hydro substep not accepted within max_halvings), 2 (U or B
  * has a non-finite value, or U a non-positive nodal rho or p) or <0; on a positive return U and
  * B are restored to their entry values.  The entry test is folded into the entry snapshot. */
@@ -217,10 +222,12 @@ int mhd25_rhs_magnetic_vjp(mhd25_ctx* ctx, const double* rho, const double* u, c
                            const double* dBz_cot, double* u_bar, double* Bx_bar, double* By_bar,
                            double* Bz_bar);
 
-/* Kernel timing on the context stream with HIP events (off by default).  Kernel id 0 is the
- * hydro stage kernel (L_E + SSP combine + statistics), id 1 the hydro stage map (OE + PP).
- * mhd25_timing_read returns the launches and summed ms of one kernel since its last read and
- * resets them; another id or a NULL pointer returns -1. */
+/* Kernel timing on the context stream with HIP events (off by default).  Kernel ids: 0 the hydro
+ * stage kernel (L_E + SSP combine + statistics), 1 the hydro stage map (OE + PP), 2 the magnetic
+ * update, 3 the velocity-OE projection, 4 the velocity-OE preparation, 5 the E loads, 6 the
+ * velocity-OE sensor, 7 the J loads, 8 the gathers, 9 the A.R. traces.  mhd25_timing_read returns
+ * the launches and summed ms of one kernel since its last read and resets them; another id or a
+ * NULL pointer returns -1. */
 int mhd25_timing_enable(mhd25_ctx* ctx, int32_t on);
 int mhd25_timing_read(mhd25_ctx* ctx, int32_t kernel_id, int64_t* launches, double* total_ms);
 
@@ -231,9 +238,15 @@ int mhd25_batch_create(const mhd25_mesh_desc* runs, int32_t nruns, const mhd25_o
                        void* hip_stream, mhd25_batch** out);
 void mhd25_batch_destroy(mhd25_batch* b);
 const char* mhd25_batch_last_error(const mhd25_batch* b);
-/* One Strang step of every run from a captured multi-branch HIP graph.  DISABLED: returns -2
- * (see mhd25_batch_last_error) because its first GPU run ended in a host segmentation fault
- * whose cause has not been shown.  Arguments as mhd25_batch_strang_step_streams. */
+/* One Strang step of every run (extension: batched ensembles) by run-table launches: every launch
+ * of the step covers all runs of one degree group, its blocks split into consecutive per-run
+ * ranges, so one step issues about 150 launches for 64 runs.  The per-run arguments are uploaded
+ * once per set of pointers and steps (a change of either rebuilds the plan: one host-to-device
+ * copy).  With mhd25_batch_graph(b, 1) the step replays a HIP graph of those launches captured on
+ * the batch's stream.  U, Bx, By, Bz: host arrays of nruns device pointers; dt: host [nruns]; rep:
+ * host [nruns] (may be NULL).  Runs whose hydro substep needs a halving, or whose input is
+ * inadmissible, are restored and re-done individually with mhd25_strang_step.  Results equal
+ * mhd25_strang_step of each run bit for bit.  Returns 0, or the first nonzero run status (1, 2, <0). */
 int mhd25_batch_strang_step(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
                             double* const* Bz, const double* dt, mhd25_report* rep);
 /* One Strang step of every run without a graph: each run's deferred step (no host read inside)
@@ -244,14 +257,18 @@ int mhd25_batch_strang_step(mhd25_batch* b, double* const* U, double* const* Bx,
  * the first nonzero run status (1, 2 or <0). */
 int mhd25_batch_strang_step_streams(mhd25_batch* b, double* const* U, double* const* Bx, double* const* By,
                                     double* const* Bz, const double* dt, mhd25_report* rep);
+/* Graph mode of mhd25_batch_strang_step: 1 = capture the run-table step into a HIP graph on the
+ * batch's stream (once per plan) and replay it; 0 = plain launches; -1 = release the graph and use
+ * plain launches.  Returns 0 or -1. */
+int mhd25_batch_graph(mhd25_batch* b, int32_t capture_or_replay);
 /* Sequential reference: the same step run by run with the plain per-run kernels. */
 int mhd25_batch_strang_step_sequential(mhd25_batch* b, double* const* U, double* const* Bx,
                                        double* const* By, double* const* Bz, const double* dt,
                                        mhd25_report* rep);
 
-/* Tuning knobs of the batch: number of concurrent branch streams of the captured step
- * (1..8; <= 0 leaves it) and the hydro-stage tile (128 or 256 threads per block) for runs of
- * degree p (p <= 0: all runs).  Invalidates the captured graph. */
+/* Tuning knobs of the batch: number of concurrent branch streams of the streams step (1..8; <= 0
+ * leaves it) and the hydro-stage tile (128 or 256 threads per block) for runs of degree p (p <= 0:
+ * all runs).  Invalidates the run-table plan and its graph. */
 int mhd25_batch_set_tuning(mhd25_batch* b, int32_t branches, int32_t p, int32_t hydro_bs);
 /* Autotuner: per degree present, times the hydro-stage tiles (128 / 256 threads per block) with
  * plain launches on a scratch copy of the largest run of that degree (the given states are not

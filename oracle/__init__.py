@@ -101,11 +101,13 @@ class Mesh:
 
 
 class Options:
-    """Method switches and constants (paper values: s_H = s_M = 0.02, C_s = 5, C_eta = 0.2)."""
+    """Method switches and constants (paper values: s_H = s_M = 0.02, C_s = 5, C_eta = 0.2);
+    strang_order 0 is the stated composition H(dt/2) M(dt) H(dt/2), 1 the magnetic-outer
+    M(dt/2) H(dt) M(dt/2)."""
 
     def __init__(self, oe_hydro=0, oe_mag=0, pp=0, ar=0, iface_flux=0, max_halvings=10,
-                 s_H=0.02, s_M=0.02, C_s=5.0, C_eta=0.2):
-        self.io = np.array([oe_hydro, oe_mag, pp, ar, iface_flux, max_halvings], dtype=np.int32)
+                 s_H=0.02, s_M=0.02, C_s=5.0, C_eta=0.2, strang_order=0):
+        self.io = np.array([oe_hydro, oe_mag, pp, ar, iface_flux, max_halvings, strang_order], dtype=np.int32)
         self.do = np.array([s_H, s_M, C_s, C_eta], dtype=np.float64)
 
     @property
@@ -117,8 +119,8 @@ class Options:
         return self.do.ctypes.data_as(_dp)
 
     @staticmethod
-    def full():
-        return Options(1, 1, 1, 1)
+    def full(strang_order=0):
+        return Options(1, 1, 1, 1, strang_order=strang_order)
 
 
 def gll(r):

@@ -28,16 +28,17 @@ class Options(ctypes.Structure):
     _fields_ = [("oe_hydro", ctypes.c_int32), ("oe_mag", ctypes.c_int32), ("pp", ctypes.c_int32),
                 ("ar", ctypes.c_int32), ("s_H", ctypes.c_double), ("s_M", ctypes.c_double),
                 ("C_s", ctypes.c_double), ("C_eta", ctypes.c_double), ("iface_flux", ctypes.c_int32),
-                ("max_halvings", ctypes.c_int32), ("reduced_2d2v", ctypes.c_int32)]
+                ("max_halvings", ctypes.c_int32), ("reduced_2d2v", ctypes.c_int32), ("strang_order", ctypes.c_int32)]
 
     @staticmethod
     def make(oe_hydro=0, oe_mag=0, pp=0, ar=0, iface_flux=0, max_halvings=10, s_H=0.02, s_M=0.02, C_s=5.0,
-             C_eta=0.2, reduced_2d2v=0):
-        return Options(oe_hydro, oe_mag, pp, ar, s_H, s_M, C_s, C_eta, iface_flux, max_halvings, reduced_2d2v)
+             C_eta=0.2, reduced_2d2v=0, strang_order=0):
+        return Options(oe_hydro, oe_mag, pp, ar, s_H, s_M, C_s, C_eta, iface_flux, max_halvings, reduced_2d2v,
+                       strang_order)
 
     @staticmethod
-    def full(reduced_2d2v=0):
-        return Options.make(1, 1, 1, 1, reduced_2d2v=reduced_2d2v)
+    def full(reduced_2d2v=0, strang_order=0):
+        return Options.make(1, 1, 1, 1, reduced_2d2v=reduced_2d2v, strang_order=strang_order)
 
 
 class Report(ctypes.Structure):
@@ -76,6 +77,7 @@ _SIGS = {
     "mhd25_node_coords": (ctypes.c_int, [_dp, ctypes.c_int32, _dp, _dp]),
     "mhd25_get_maps": (ctypes.c_int, [_dp, _dp, _dp]),
     "mhd25_batch_last_error": (ctypes.c_char_p, [_dp]),
+    "mhd25_batch_graph": (ctypes.c_int, [_dp, ctypes.c_int32]),
     "mhd25_rhs_hydro_vjp": (ctypes.c_int, [_dp] * 4),
     "mhd25_rhs_magnetic_vjp": (ctypes.c_int, [_dp] * 16),
     "mhd25_timing_enable": (ctypes.c_int, [_dp, ctypes.c_int32]),
@@ -327,7 +329,7 @@ class Solver:
 
 class Batch:
     """Ensemble of independent runs advanced together (wraps an mhd25_batch): one Strang step of
-    every run is launched on concurrent branch streams."""
+    every run by run-table launches that each cover all runs of a degree group."""
 
     def __init__(self, layouts, options=None):
         if not torch.cuda.is_available():
@@ -362,10 +364,10 @@ class Batch:
             _ptr(t)
         return (self._ptrs(U), self._ptrs(Bx), self._ptrs(By), self._ptrs(Bz), (ctypes.c_double * self.n)(*dt))
 
-    def strang_step(self, U, Bx, By, Bz, dt, sequential=False, streams=True):
-        """One Strang step of every run: launched on the branch streams (default), run by run
-        (sequential=True), or from the captured multi-branch graph (streams=False; that entry point
-        is disabled and raises)."""
+    def strang_step(self, U, Bx, By, Bz, dt, sequential=False, streams=False):
+        """One Strang step of every run: run-table launches (default; replayed from a graph after
+        graph(True)), launched run by run on the branch streams (streams=True), or run by run with
+        the plain step (sequential=True)."""
         reps = (Report * self.n)()
         if sequential:
             fn = self.lib.mhd25_batch_strang_step_sequential
@@ -378,6 +380,12 @@ class Batch:
         if r < 0:
             raise MHD25Error("batch strang step failed (%d): %s" % (r, self.lib.mhd25_batch_last_error(self.h).decode()))
         return r, [x.as_dict() for x in reps]
+
+    def graph(self, on):
+        """Replay the run-table step from a captured HIP graph (on=True) or launch it plainly."""
+        r = self.lib.mhd25_batch_graph(self.h, 1 if on else 0)
+        if r:
+            raise MHD25Error("batch graph mode failed (%d)" % r)
 
     def set_tuning(self, branches=0, p=0, hydro_bs=0):
         r = self.lib.mhd25_batch_set_tuning(self.h, branches, p, hydro_bs)

@@ -107,7 +107,7 @@ int mhd25_set_options(mhd25_ctx* c, const mhd25_options* opt) {
   if (!c || !opt) return -1;
   if (opt->max_halvings < 0 || opt->max_halvings > 60 || opt->s_H < 0 || opt->s_M < 0 || opt->C_s < 0 ||
       opt->C_eta < 0 || (opt->iface_flux != 0 && opt->iface_flux != 1) ||
-      (opt->reduced_2d2v != 0 && opt->reduced_2d2v != 1))
+      (opt->reduced_2d2v != 0 && opt->reduced_2d2v != 1) || (opt->strang_order != 0 && opt->strang_order != 1))
     return fail(c, -1, "invalid options");
   c->opt = *opt;
   return 0;
@@ -413,11 +413,23 @@ int mhd25_strang_step(mhd25_ctx* c, double* U, double* Bx, double* By, double* B
   };
   mhd25_report h1, m, h2;
   std::memset(&h1, 0, sizeof(h1)); std::memset(&m, 0, sizeof(m)); std::memset(&h2, 0, sizeof(h2));
-  int s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h1, true);  // also leaves (rho, e, u) of U
-  if (s != 0) return restore(s);
-  TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, dt, &m));
-  TRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
-  s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h2);
+  int s = 0;
+  if (c->opt.strang_order == 0) {
+    s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h1, true);  // also leaves (rho, e, u) of U
+    if (s != 0) return restore(s);
+    TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, dt, &m));
+    TRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
+    s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h2);
+  } else {
+    // magnetic-outer composition (the entry word is read by the hydro attempt in the middle)
+    TRY(mag_to_primitive(c, U, c->rho, c->e, c->u));
+    TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, 0.5 * dt, &m));
+    TRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
+    s = hydro_substep_rec(c, U, dt, 0, &h1, true);  // also leaves (rho, e, u) of U
+    if (s != 0) return restore(s);
+    TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, 0.5 * dt, &m));
+    TRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
+  }
   r.substeps_attempted = h1.substeps_attempted + h2.substeps_attempted;
   r.substeps_accepted = h1.substeps_accepted + h2.substeps_accepted;
   r.max_depth = std::max(h1.max_depth, h2.max_depth);
@@ -480,7 +492,7 @@ int mhd25_timing_enable(mhd25_ctx* c, int32_t on) {
 }
 
 int mhd25_timing_read(mhd25_ctx* c, int32_t kid, int64_t* launches, double* total_ms) {
-  if (!c || kid < 0 || kid > 1 || !launches || !total_ms) return -1;
+  if (!c || kid < 0 || kid > 9 || !launches || !total_ms) return -1;
   HIPCHK(c, timing_fold(c));
   *launches = c->t_launch[kid];
   *total_ms = c->t_ms[kid];

@@ -98,6 +98,21 @@ struct MagIO {
   double ca, cb, tau;
 };
 
+// Run-table plans (batched ensembles): with ctx->rec set, the launch helpers append one record per
+// kernel launch (its kind, template key, block count and the kernel's argument struct for this run)
+// instead of launching; a plan zips the records of all runs into run-table launches.
+enum RtKind {
+  RT_HYDRO_STAGE, RT_OE_PP, RT_LINE_REDUCE, RT_GLOBAL_REDUCE, RT_RESET, RT_COPY, RT_SNAP_U, RT_COPY_CHECK,
+  RT_TO_PRIM, RT_TO_CONS, RT_J_LOADS, RT_E_LOADS, RT_GATHER, RT_MAG_UPDATE, RT_VEL_PREP, RT_VEL_SENSOR,
+  RT_VEL_PROJ, RT_B_STATS, RT_AR_TRACES, RT_AR_ETA, RT_MAX, RT_BATCH_ZERO, RT_BATCH_FOLD, RT_NKIND
+};
+struct RtRecord {
+  int kind;
+  int key;     // template instantiation (kind-specific encoding)
+  long blocks;  // blocks this run needs
+  std::vector<unsigned char> args;  // the kernel's argument struct for this run
+};
+
 struct mhd25_ctx {
   mhd25_mesh_desc mesh;
   mhd25_options opt;
@@ -130,9 +145,18 @@ struct mhd25_ctx {
   std::vector<hipEvent_t> ev_pool;  // pairs (start, stop) of timed launches
   std::vector<int> ev_kid;          // kernel id of each pair (0 hydro stage, 1 stage map)
   int ev_used;
-  long long t_launch[4];
-  double t_ms[4];
+  long long t_launch[16];  // per timed kernel id (see mhd25_timing_read)
+  double t_ms[16];
+  std::vector<RtRecord>* rec;  // non-null: launch helpers record instead of launching
 };
+
+template <class A>
+inline void rt_record(mhd25_ctx* c, int kind, int key, long blocks, const A& a) {
+  RtRecord r;
+  r.kind = kind; r.key = key; r.blocks = blocks;
+  r.args.assign(reinterpret_cast<const unsigned char*>(&a), reinterpret_cast<const unsigned char*>(&a) + sizeof(A));
+  c->rec->push_back(std::move(r));
+}
 
 // host table builders (tables.cpp)
 void build_hydro_tables(int p, HydroTab* t);

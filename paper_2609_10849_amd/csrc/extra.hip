@@ -234,7 +234,38 @@ static void reduce2(mhd25_ctx* c, const double* a, long n, int mode, double* d_o
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, c->stream, part, nb, mode, d_out);
 }
 
+struct max_args {
+  const double* a;
+  long n;
+  double* out;
+};
+
+// run-table maximum: one block per run over its n values (max is exact, so the result equals the
+// two-level reduction's)
+__global__ __launch_bounds__(256) void k_max_rt(const max_args* __restrict__ A, int nr) {
+  __shared__ double red[256];
+  const max_args a = A[blockIdx.x];
+  const int t = threadIdx.x;
+  double v = -DBL_MAX;
+  for (long k = t; k < a.n; k += 256) v = fmax(v, a.a[k]);
+  red[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] = fmax(red[t], red[t + w]);
+    __syncthreads();
+  }
+  if (t == 0) *a.out = red[0];
+}
+
+int extra_rt_launch(const RtRecord& h, const void* dargs, const int* dboff, int nr, long nblocks, hipStream_t s) {
+  (void)dboff; (void)nblocks;
+  if (h.kind != RT_MAX) return 1;
+  hipLaunchKernelGGL(k_max_rt, dim3(nr), dim3(256), 0, s, (const max_args*)dargs, nr);
+  return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 int extra_max_dev(mhd25_ctx* c, const double* a, long n, double* d_out) {
+  if (c->rec) { rt_record(c, RT_MAX, 0, 1, max_args{a, n, d_out}); return 0; }
   reduce2(c, a, n, 0, d_out);
   return ex_chk(c, hipGetLastError(), "reduce");
 }

@@ -284,10 +284,10 @@ __device__ __forceinline__ void element_stats(double* svf, double* sst, bool act
 
 // MODE 0: out = L_E(Us).  MODE 1: out = ca*Un + cb*(Us + tau*L_E(Us)) plus element statistics.
 template <int P, int MODE, int BS>
-__global__ __launch_bounds__(BS, P == 4 ? 4 : 1) void k_hydro_stage(const double* __restrict__ Us, const double* __restrict__ Un,
+__device__ __forceinline__ void hydro_stage_body(const double* __restrict__ Us, const double* __restrict__ Un,
                                                     double* __restrict__ out, double* __restrict__ stats,
                                                     int* __restrict__ flag, const HydroTab* __restrict__ T, MeshP mp,
-                                                    double ca, double cb, double tau, int iface) {
+                                                    double ca, double cb, double tau, int iface, long blk) {
   using C = Cfg<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, ND = C::ND;
   __shared__ double sp[7][EB * NN];
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(BS, P == 4 ? 4 : 1) void k_hydro_stage(const double
   }
   const int el = tid / NN, q = tid - el * NN;
   const int i = q % NP, j = q / NP;
-  const long e = (long)blockIdx.x * EB + el;
+  const long e = blk * EB + el;
   const bool act = tid < C::NT && e < mp.K;
   const long KN = mp.K * NN;
   double U[5], UNo[5], acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -358,6 +358,35 @@ __global__ __launch_bounds__(BS, P == 4 ? 4 : 1) void k_hydro_stage(const double
   element_stats<C>(&sp[0][0], scr, act, el, q, e, stats, flag, T, mp.gamma);
 }
 
+template <int P, int MODE, int BS>
+__global__ __launch_bounds__(BS, P == 4 ? 4 : 1) void k_hydro_stage(const double* __restrict__ Us, const double* __restrict__ Un,
+                                                    double* __restrict__ out, double* __restrict__ stats,
+                                                    int* __restrict__ flag, const HydroTab* __restrict__ T, MeshP mp,
+                                                    double ca, double cb, double tau, int iface) {
+  hydro_stage_body<P, MODE, BS>(Us, Un, out, stats, flag, T, mp, ca, cb, tau, iface, (long)blockIdx.x);
+}
+
+struct hydro_stage_args {
+  const double* Us;
+  const double* Un;
+  double* out;
+  double* stats;
+  int* flag;
+  const HydroTab* T;
+  MeshP mp;
+  double ca;
+  double cb;
+  double tau;
+  int iface;
+};
+
+template <int P, int MODE, int BS>
+__global__ __launch_bounds__(BS, P == 4 ? 4 : 1) void k_hydro_stage_rt(const hydro_stage_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const hydro_stage_args a = A[r];
+  hydro_stage_body<P, MODE, BS>(a.Us, a.Un, a.out, a.stats, a.flag, a.T, a.mp, a.ca, a.cb, a.tau, a.iface, (long)blockIdx.x - boff[r]);
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_elem_stats(const double* __restrict__ Uin, double* __restrict__ stats,
                                                     int* __restrict__ flag, const HydroTab* __restrict__ T, MeshP mp) {
@@ -391,14 +420,14 @@ __device__ __forceinline__ double Sp(const double* a, double eps_r) {
 // The element statistics of the raw stage (always formed before this map) give the element
 // averages: the OE map keeps each element's mean, the (0, 0) Legendre mode.
 template <int P, int BS>
-__global__ __launch_bounds__(BS) void k_hydro_oe_pp(const double* __restrict__ Ust, double* __restrict__ Uout,
+__device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust, double* __restrict__ Uout,
                                                      const double* __restrict__ stats, const double* __restrict__ lines,
                                                      const double* __restrict__ glob, uint8_t* __restrict__ flags,
                                                      unsigned long long* __restrict__ counts,
                                                      const int* __restrict__ flag, const HydroTab* __restrict__ T,
                                                      MeshP mp, double tau, double sH, int do_oe, int do_pp,
                                                      double* __restrict__ rho_o, double* __restrict__ e_o,
-                                                     double* __restrict__ u_o) {
+                                                     double* __restrict__ u_o, long blk) {
   using C = Cfg<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NL = 5 * NP;
   __shared__ double su[5][EB * NN];
@@ -409,7 +438,7 @@ __global__ __launch_bounds__(BS) void k_hydro_oe_pp(const double* __restrict__ U
   if (flag && *flag) return;
   const int tid = threadIdx.x;
   const int el = tid / NN, q = tid - el * NN;
-  const long e = xcd_block() * EB + el;
+  const long e = blk * EB + el;
   const bool act = tid < C::NT && e < mp.K;
   const long KN = mp.K * NN;
   const double g = mp.gamma;
@@ -668,6 +697,45 @@ __global__ __launch_bounds__(BS) void k_hydro_oe_pp(const double* __restrict__ U
   }
 }
 
+template <int P, int BS>
+__global__ __launch_bounds__(BS) void k_hydro_oe_pp(const double* __restrict__ Ust, double* __restrict__ Uout,
+                                                     const double* __restrict__ stats, const double* __restrict__ lines,
+                                                     const double* __restrict__ glob, uint8_t* __restrict__ flags,
+                                                     unsigned long long* __restrict__ counts,
+                                                     const int* __restrict__ flag, const HydroTab* __restrict__ T,
+                                                     MeshP mp, double tau, double sH, int do_oe, int do_pp,
+                                                     double* __restrict__ rho_o, double* __restrict__ e_o,
+                                                     double* __restrict__ u_o) {
+  hydro_oe_pp_body<P, BS>(Ust, Uout, stats, lines, glob, flags, counts, flag, T, mp, tau, sH, do_oe, do_pp, rho_o, e_o, u_o, xcd_block());
+}
+
+struct hydro_oe_pp_args {
+  const double* Ust;
+  double* Uout;
+  const double* stats;
+  const double* lines;
+  const double* glob;
+  uint8_t* flags;
+  unsigned long long* counts;
+  const int* flag;
+  const HydroTab* T;
+  MeshP mp;
+  double tau;
+  double sH;
+  int do_oe;
+  int do_pp;
+  double* rho_o;
+  double* e_o;
+  double* u_o;
+};
+
+template <int P, int BS>
+__global__ __launch_bounds__(BS) void k_hydro_oe_pp_rt(const hydro_oe_pp_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const hydro_oe_pp_args a = A[r];
+  hydro_oe_pp_body<P, BS>(a.Ust, a.Uout, a.stats, a.lines, a.glob, a.flags, a.counts, a.flag, a.T, a.mp, a.tau, a.sH, a.do_oe, a.do_pp, a.rho_o, a.e_o, a.u_o, (long)blockIdx.x - boff[r]);
+}
+
 // Connectivity export: nbr[K][4] (left, right, bottom, top neighbour) and the face map
 // fmap[K][4][p+1] (the neighbour node e' (p+1)^2 + q' matched to each own face node), formed with the
 // same face_match the stage kernel uses.  One thread per (element, face).
@@ -692,20 +760,24 @@ __global__ __launch_bounds__(256) void k_face_map(int32_t* __restrict__ nbr, int
 // Entry copy of a conservative state with the admissibility test of every node: all five values
 // finite, rho > 0 and p > 0 (the admissible set of section "Conservative ideal MHD").  A failing node
 // sets bit 1 of flag[1].  One thread per node.
+__device__ __forceinline__ void snap_check_node(const double* __restrict__ U, double* __restrict__ snap, long KN,
+                                                double g, int* __restrict__ flag, long n) {
+  double v[5];
+  bool fin = true;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    v[c] = U[c * KN + n];
+    snap[c * KN + n] = v[c];
+    fin = fin && fabs(v[c]) <= DBL_MAX;
+  }
+  const double p = (g - 1.0) * (v[4] - (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / (2.0 * v[0]));
+  if (!fin || !(v[0] > 0.0) || !(p > 0.0)) atomicOr(flag + 1, 2);
+}
+
 __global__ __launch_bounds__(256) void k_snap_check_U(const double* __restrict__ U, double* __restrict__ snap, long KN,
                                                       double g, int* __restrict__ flag) {
-  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < KN; n += (long)gridDim.x * blockDim.x) {
-    double v[5];
-    bool fin = true;
-#pragma unroll
-    for (int c = 0; c < 5; ++c) {
-      v[c] = U[c * KN + n];
-      snap[c * KN + n] = v[c];
-      fin = fin && fabs(v[c]) <= DBL_MAX;
-    }
-    const double p = (g - 1.0) * (v[4] - (v[1] * v[1] + v[2] * v[2] + v[3] * v[3]) / (2.0 * v[0]));
-    if (!fin || !(v[0] > 0.0) || !(p > 0.0)) atomicOr(flag + 1, 2);
-  }
+  for (long n = (long)blockIdx.x * blockDim.x + threadIdx.x; n < KN; n += (long)gridDim.x * blockDim.x)
+    snap_check_node(U, snap, KN, g, flag, n);
 }
 
 // entry copy with a finiteness test (magnetic grids); a non-finite value sets bit 1 of flag[1]
@@ -729,12 +801,12 @@ __global__ __launch_bounds__(256) void k_copy_check(const double* __restrict__ a
 constexpr int LRC = 8, LRP = 256 / LRC;
 
 template <int NC>
-__global__ __launch_bounds__(256) void k_line_reduce(const double* __restrict__ stats, double* __restrict__ lines,
-                                                     int nx, int ny, const int* __restrict__ flag) {
+__device__ __forceinline__ void line_reduce_body(const double* __restrict__ stats, double* __restrict__ lines,
+                                                     int nx, int ny, const int* __restrict__ flag, long blk) {
   constexpr int nc = NC;  // components per element record (compile-time, so that no load waits on a branch)
   __shared__ double red[15][256];
   if (flag && *flag) return;
-  const int b = blockIdx.x, t = threadIdx.x;
+  const int b = blk, t = threadIdx.x;
   const int nv = nc * 3;
   double v[15];
 #pragma unroll
@@ -782,12 +854,33 @@ __global__ __launch_bounds__(256) void k_line_reduce(const double* __restrict__ 
   }
 }
 
+template <int NC>
+__global__ __launch_bounds__(256) void k_line_reduce(const double* __restrict__ stats, double* __restrict__ lines,
+                                                     int nx, int ny, const int* __restrict__ flag) {
+  line_reduce_body<NC>(stats, lines, nx, ny, flag, (long)blockIdx.x);
+}
+
+struct line_reduce_args {
+  const double* stats;
+  double* lines;
+  int nx;
+  int ny;
+  const int* flag;
+};
+
+template <int NC>
+__global__ __launch_bounds__(256) void k_line_reduce_rt(const line_reduce_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const line_reduce_args a = A[r];
+  line_reduce_body<NC>(a.stats, a.lines, a.nx, a.ny, a.flag, (long)blockIdx.x - boff[r]);
+}
+
 // Global reduction of the first `n` line results (the rows) into glob[nc][3]: all NC components in
 // one tree (each component's accumulation order is that of its own tree), so the block passes
 // eight barriers instead of eight per component.
 template <int NC>
-__global__ __launch_bounds__(256) void k_global_reduce(const double* __restrict__ lines, double* __restrict__ glob,
-                                                       int n, const int* __restrict__ flag) {
+__device__ __forceinline__ void global_reduce_body(const double* __restrict__ lines, double* __restrict__ glob,
+                                                       int n, const int* __restrict__ flag, long blk) {
   __shared__ double red[3 * NC][256];
   if (flag && *flag) return;
   const int t = threadIdx.x;
@@ -818,6 +911,46 @@ __global__ __launch_bounds__(256) void k_global_reduce(const double* __restrict_
   }
   if (t < 3 * NC) glob[t] = red[t][0];
 }
+
+template <int NC>
+__global__ __launch_bounds__(256) void k_global_reduce(const double* __restrict__ lines, double* __restrict__ glob,
+                                                       int n, const int* __restrict__ flag) {
+  global_reduce_body<NC>(lines, glob, n, flag, (long)blockIdx.x);
+}
+
+struct global_reduce_args {
+  const double* lines;
+  double* glob;
+  int n;
+  const int* flag;
+};
+
+template <int NC>
+__global__ __launch_bounds__(256) void k_global_reduce_rt(const global_reduce_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const global_reduce_args a = A[r];
+  global_reduce_body<NC>(a.lines, a.glob, a.n, a.flag, (long)blockIdx.x - boff[r]);
+}
+
+// argument structs of the small and flat kernels for run-table launches
+struct reset_args {
+  int* flag;
+  unsigned long long* counts;
+  int clear_input;
+};
+struct copy_args {
+  const double* a;
+  double* b;
+  long n;
+  int* flag;  // non-null: finiteness test into flag[1]
+};
+struct snap_args {
+  const double* U;
+  double* snap;
+  long KN;
+  double g;
+  int* flag;
+};
 
 // flag[0]: the attempt's reject word (bit 0: an inadmissible raw average), which the stage kernels
 // test to skip the rest of a failed attempt; flag[1]: the entry check's word (bit 1: an inadmissible
@@ -860,6 +993,11 @@ static int check(mhd25_ctx* c, hipError_t e, const char* what) {
 // row and column reductions of nc-component element records (nc = 1..5), then the global one
 static int launch_reductions(mhd25_ctx* c, const double* stats, int nc, const int* flag) {
   const dim3 grid(c->mp.ny + (c->mp.nx + LRC - 1) / LRC);
+  if (c->rec) {
+    rt_record(c, RT_LINE_REDUCE, nc, grid.x, line_reduce_args{stats, c->lines, c->mp.nx, c->mp.ny, flag});
+    rt_record(c, RT_GLOBAL_REDUCE, nc, 1, global_reduce_args{c->lines, c->glob, c->mp.ny, flag});
+    return 0;
+  }
 #define LR(NC)                                                                                                    \
   hipLaunchKernelGGL((k_line_reduce<NC>), grid, dim3(256), 0, c->stream, stats, c->lines, c->mp.nx, c->mp.ny,    \
                      flag);                                                                                       \
@@ -889,6 +1027,11 @@ int hydro_stage_a(mhd25_ctx* c, const double* Us, const double* Un, double* Ust,
   const int bs = stage_block(c);
   const int eb = bs / ((c->p + 1) * (c->p + 1));
   const long blocks = (c->mp.K + eb - 1) / eb;
+  if (c->rec) {
+    rt_record(c, RT_HYDRO_STAGE, c->p * 1000 + bs, blocks,
+              hydro_stage_args{Us, Un, Ust, c->stats, c->d_flag, c->d_ht, c->mp, ca, cb, tau, c->opt.iface_flux});
+    return launch_reductions(c, c->stats, 5, c->d_flag);
+  }
   hipEvent_t* ev = c->timing ? timing_slot(c, 0) : nullptr;
   if (ev) hipEventRecord(ev[0], c->stream);
 #define L1(P)                                                                                                      \
@@ -932,6 +1075,12 @@ int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, con
   constexpr int BS = MHD_OE_BS;
   const int eb = BS / ((c->p + 1) * (c->p + 1));
   const long blocks = (c->mp.K + eb - 1) / eb;
+  if (c->rec) {
+    rt_record(c, RT_OE_PP, c->p, blocks,
+              hydro_oe_pp_args{Ust, Uout, c->stats, c->lines, c->glob, c->d_flags, c->d_counts, flag, c->d_ht, c->mp,
+                               tau, c->opt.s_H, c->opt.oe_hydro, c->opt.pp, rho_o, e_o, u_o});
+    return 0;
+  }
   hipEvent_t* ev = c->timing ? timing_slot(c, 1) : nullptr;
   if (ev) hipEventRecord(ev[0], c->stream);
 #define LB(P) hipLaunchKernelGGL((k_hydro_oe_pp<P, BS>), dim3(blocks), dim3(BS), 0, c->stream, Ust, Uout, c->stats, \
@@ -944,6 +1093,7 @@ int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, con
 }
 
 int reset_attempt(mhd25_ctx* c) {
+  if (c->rec) { rt_record(c, RT_RESET, 0, 1, reset_args{c->d_flag, c->d_counts, 0}); return 0; }
   hipLaunchKernelGGL(k_reset_attempt, dim3(1), dim3(64), 0, c->stream, c->d_flag, c->d_counts, 0);
   return check(c, hipGetLastError(), "reset launch");
 }
@@ -963,8 +1113,16 @@ int entry_clear(mhd25_ctx* c) {
 // entry snapshot of U (and of the magnetic grids when B is set) into snapU / saveB with the
 // admissibility test; clears and then sets the entry word flag[1]
 int entry_snapshot(mhd25_ctx* c, const double* U, double* snapU, const double* const* B, double* saveB) {
-  hipLaunchKernelGGL(k_reset_attempt, dim3(1), dim3(64), 0, c->stream, c->d_flag, c->d_counts, 1);
   const long KN = c->mp.K * c->nn;
+  if (c->rec) {
+    rt_record(c, RT_RESET, 0, 1, reset_args{c->d_flag, c->d_counts, 1});
+    rt_record(c, RT_SNAP_U, 0, flat_blocks(KN), snap_args{U, snapU, KN, c->mp.gamma, c->d_flag});
+    if (B)
+      for (int k = 0; k < 3; ++k)
+        rt_record(c, RT_COPY_CHECK, 0, flat_blocks(c->G), copy_args{B[k], saveB + k * c->G, c->G, c->d_flag});
+    return 0;
+  }
+  hipLaunchKernelGGL(k_reset_attempt, dim3(1), dim3(64), 0, c->stream, c->d_flag, c->d_counts, 1);
   hipLaunchKernelGGL(k_snap_check_U, dim3(flat_blocks(KN)), dim3(256), 0, c->stream, U, snapU, KN, c->mp.gamma,
                      c->d_flag);
   if (B)
@@ -986,6 +1144,93 @@ int dcopy(mhd25_ctx* c, const double* a, double* b, long n) {
   long blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
+  if (c->rec) { rt_record(c, RT_COPY, 0, blocks, copy_args{a, b, n, nullptr}); return 0; }
   hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, c->stream, a, b, n);
   return check(c, hipGetLastError(), "copy launch");
+}
+
+// ---------------------------------------------------------------------------------------------
+// Run-table kernels of the small and flat kernels (argument structs per run) and the dispatcher of
+// this file's run-table launches.
+// ---------------------------------------------------------------------------------------------
+__global__ void k_reset_rt(const reset_args* __restrict__ A, int nr) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nr) return;
+  const reset_args a = A[r];
+  if (a.clear_input) a.flag[1] = 0;
+  a.flag[0] = a.flag[1];
+  a.counts[0] = 0; a.counts[1] = 0; a.counts[2] = 0;
+}
+
+// flat kernels: run r owns blocks boff[r] .. boff[r+1) and strides over its n entries with them
+__global__ __launch_bounds__(256) void k_copy_rt(const copy_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const copy_args a = A[r];
+  const long stride = (long)(boff[r + 1] - boff[r]) * blockDim.x;
+  for (long k = (long)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x; k < a.n; k += stride) {
+    const double v = a.a[k];
+    a.b[k] = v;
+    if (a.flag && !(fabs(v) <= DBL_MAX)) atomicOr(a.flag + 1, 2);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_snap_check_U_rt(const snap_args* __restrict__ A, const int* __restrict__ boff,
+                                                         int nr) {
+  const int r = rt_run(boff, nr);
+  const snap_args a = A[r];
+  const long stride = (long)(boff[r + 1] - boff[r]) * blockDim.x;
+  for (long n = (long)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x; n < a.KN; n += stride)
+    snap_check_node(a.U, a.snap, a.KN, a.g, a.flag, n);
+}
+
+int hydro_rt_launch(const RtRecord& h, const void* dargs, const int* dboff, int nr, long nblocks, hipStream_t s) {
+  const dim3 g((unsigned)nblocks);
+  switch (h.kind) {
+    case RT_HYDRO_STAGE: {
+      const int P = h.key / 1000, bs = h.key % 1000;
+      const hydro_stage_args* A = (const hydro_stage_args*)dargs;
+#define RS(P_)                                                                                                       \
+  if (bs == 128) hipLaunchKernelGGL((k_hydro_stage_rt<P_, 1, 128>), g, dim3(128), 0, s, A, dboff, nr);              \
+  else hipLaunchKernelGGL((k_hydro_stage_rt<P_, 1, 256>), g, dim3(256), 0, s, A, dboff, nr)
+      DISPATCH_P(P, RS);
+#undef RS
+      break;
+    }
+    case RT_OE_PP: {
+      const hydro_oe_pp_args* A = (const hydro_oe_pp_args*)dargs;
+#define RO(P_) hipLaunchKernelGGL((k_hydro_oe_pp_rt<P_, MHD_OE_BS>), g, dim3(MHD_OE_BS), 0, s, A, dboff, nr)
+      DISPATCH_P(h.key, RO);
+#undef RO
+      break;
+    }
+    case RT_LINE_REDUCE: {
+      const line_reduce_args* A = (const line_reduce_args*)dargs;
+#define RL(NC) hipLaunchKernelGGL((k_line_reduce_rt<NC>), g, dim3(256), 0, s, A, dboff, nr)
+      switch (h.key) { case 1: RL(1); break; case 2: RL(2); break; case 3: RL(3); break; case 4: RL(4); break;
+                       case 5: RL(5); break; default: return -2; }
+#undef RL
+      break;
+    }
+    case RT_GLOBAL_REDUCE: {
+      const global_reduce_args* A = (const global_reduce_args*)dargs;
+#define RG(NC) hipLaunchKernelGGL((k_global_reduce_rt<NC>), g, dim3(256), 0, s, A, dboff, nr)
+      switch (h.key) { case 1: RG(1); break; case 2: RG(2); break; case 3: RG(3); break; case 4: RG(4); break;
+                       case 5: RG(5); break; default: return -2; }
+#undef RG
+      break;
+    }
+    case RT_RESET:
+      hipLaunchKernelGGL(k_reset_rt, dim3((nr + 63) / 64), dim3(64), 0, s, (const reset_args*)dargs, nr);
+      break;
+    case RT_COPY:
+    case RT_COPY_CHECK:
+      hipLaunchKernelGGL(k_copy_rt, g, dim3(256), 0, s, (const copy_args*)dargs, dboff, nr);
+      break;
+    case RT_SNAP_U:
+      hipLaunchKernelGGL(k_snap_check_U_rt, g, dim3(256), 0, s, (const snap_args*)dargs, dboff, nr);
+      break;
+    default:
+      return 1;  // not a kind of this file
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
 }

@@ -54,17 +54,17 @@ __device__ __forceinline__ void load_B(double* bx, double* by, double* bz, const
 // Gauss rule; N parts int B_z (-d_y psi) and int B_z d_x psi with the (m+1)-point rule.
 // ---------------------------------------------------------------------------------------------
 template <int P, int M, int BS, bool R2>
-__global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, const double* __restrict__ By,
+__device__ __forceinline__ void J_loads_body(const double* __restrict__ Bx, const double* __restrict__ By,
                                                  const double* __restrict__ Bz, double* __restrict__ Lx,
                                                  double* __restrict__ Ly, double* __restrict__ Lz,
-                                                 const MagTab* __restrict__ T, MeshP mp) {
+                                                 const MagTab* __restrict__ T, MeshP mp, long blk) {
   using C = MC<P, M, BS>;
   constexpr int A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB, NT = C::NT;
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB], swx[EB][AA], swy[EB][AA], szg[EB][BB];
   __shared__ double sh[EB][2][AA];  // first half of the sum factorisation of the W loads
   __shared__ double tWQ[A][A], tGQ[A][B], tDWQ[A][A], tVG[B][B], tDWG[B][A], twq[A], twg[B];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
-  const long e = xcd_block() * EB + el;
+  const long e = blk * EB + el;
   const bool act = el < EB && e < mp.K;
   long ex, ey;
   elem_xy(mp, act ? e : 0, ex, ey);
@@ -155,17 +155,43 @@ __global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, c
   }
 }
 
+template <int P, int M, int BS, bool R2>
+__global__ __launch_bounds__(BS) void k_J_loads(const double* __restrict__ Bx, const double* __restrict__ By,
+                                                 const double* __restrict__ Bz, double* __restrict__ Lx,
+                                                 double* __restrict__ Ly, double* __restrict__ Lz,
+                                                 const MagTab* __restrict__ T, MeshP mp) {
+  J_loads_body<P, M, BS, R2>(Bx, By, Bz, Lx, Ly, Lz, T, mp, xcd_block());
+}
+
+struct J_loads_args {
+  const double* Bx;
+  const double* By;
+  const double* Bz;
+  double* Lx;
+  double* Ly;
+  double* Lz;
+  const MagTab* T;
+  MeshP mp;
+};
+
+template <int P, int M, int BS, bool R2>
+__global__ __launch_bounds__(BS) void k_J_loads_rt(const J_loads_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const J_loads_args a = A[r];
+  J_loads_body<P, M, BS, R2>(a.Bx, a.By, a.Bz, a.Lx, a.Ly, a.Lz, a.T, a.mp, (long)blockIdx.x - boff[r]);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Electric-field loads (eq. mag-electric-proj): w_a (-u x B)|_K at the element's own auxiliary
 // nodes, plus eta_K sum_q M_q J(x_q) . phi_a(x_q) by the degree-p GLL rule.
 // ---------------------------------------------------------------------------------------------
 template <int P, int M, int BS, bool R2>
-__global__ __launch_bounds__(BS, (!R2 && P <= 5) ? 5 : 1) void k_E_loads(const double* __restrict__ u, const double* __restrict__ Bx,
+__device__ __forceinline__ void E_loads_body(const double* __restrict__ u, const double* __restrict__ Bx,
                                                  const double* __restrict__ By, const double* __restrict__ Bz,
                                                  const double* __restrict__ Jx, const double* __restrict__ Jy,
                                                  const double* __restrict__ Jz, const double* __restrict__ eta,
                                                  double* __restrict__ Lx, double* __restrict__ Ly,
-                                                 double* __restrict__ Lz, const MagTab* __restrict__ T, MeshP mp) {
+                                                 double* __restrict__ Lz, const MagTab* __restrict__ T, MeshP mp, long blk) {
   using C = MC<P, M, BS>;
   constexpr int NP = C::NP, NN = C::NN, A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB,
                 NT = C::NT;
@@ -178,7 +204,7 @@ __global__ __launch_bounds__(BS, (!R2 && P <= 5) ? 5 : 1) void k_E_loads(const d
   __shared__ double tGP[NP][B], tWP[NP][A], tPW[A][NP], tPG[B][NP], tGW[A][B], tVG[B][B], tVW[A][B];
   __shared__ double twp[NP], tww[A], twg[B];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
-  const long e = xcd_block() * EB + el;
+  const long e = blk * EB + el;
   const bool act = el < EB && e < mp.K;
   long ex, ey;
   elem_xy(mp, act ? e : 0, ex, ey);
@@ -325,6 +351,39 @@ __global__ __launch_bounds__(BS, (!R2 && P <= 5) ? 5 : 1) void k_E_loads(const d
   }
 }
 
+template <int P, int M, int BS, bool R2>
+__global__ __launch_bounds__(BS, (!R2 && P <= 5) ? 5 : 1) void k_E_loads(const double* __restrict__ u, const double* __restrict__ Bx,
+                                                 const double* __restrict__ By, const double* __restrict__ Bz,
+                                                 const double* __restrict__ Jx, const double* __restrict__ Jy,
+                                                 const double* __restrict__ Jz, const double* __restrict__ eta,
+                                                 double* __restrict__ Lx, double* __restrict__ Ly,
+                                                 double* __restrict__ Lz, const MagTab* __restrict__ T, MeshP mp) {
+  E_loads_body<P, M, BS, R2>(u, Bx, By, Bz, Jx, Jy, Jz, eta, Lx, Ly, Lz, T, mp, xcd_block());
+}
+
+struct E_loads_args {
+  const double* u;
+  const double* Bx;
+  const double* By;
+  const double* Bz;
+  const double* Jx;
+  const double* Jy;
+  const double* Jz;
+  const double* eta;
+  double* Lx;
+  double* Ly;
+  double* Lz;
+  const MagTab* T;
+  MeshP mp;
+};
+
+template <int P, int M, int BS, bool R2>
+__global__ __launch_bounds__(BS, (!R2 && P <= 5) ? 5 : 1) void k_E_loads_rt(const E_loads_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const E_loads_args a = A[r];
+  E_loads_body<P, M, BS, R2>(a.u, a.Bx, a.By, a.Bz, a.Jx, a.Jy, a.Jz, a.eta, a.Lx, a.Ly, a.Lz, a.T, a.mp, (long)blockIdx.x - boff[r]);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Curl update, Lorentz transpose and Ohmic heating (eq. magnetic-dae with J, E eliminated).
 // MODE 0: write L_M.  MODE 1: write the SSP stage (ca*Y^n + cb*Y_s) + cb*tau*L_M(Y_s).
@@ -333,7 +392,7 @@ __global__ __launch_bounds__(BS, (!R2 && P <= 5) ? 5 : 1) void k_E_loads(const d
 // (the 2D2V variants up to N = 4 fit 72 VGPRs, i.e. 7 waves per SIMD, without spills; the bound
 // keeps the compiler there)
 template <int P, int M, int MODE, int BS, bool R2>
-__global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update(MagIO io, const MagTab* __restrict__ T, MeshP mp) {
+__device__ __forceinline__ void mag_update_body(MagIO io, const MagTab* __restrict__ T, MeshP mp, long blk) {
   using C = MC<P, M, BS>;
   constexpr int NP = C::NP, NN = C::NN, A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB,
                 NT = C::NT;
@@ -350,7 +409,7 @@ __global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update(MagIO
   __shared__ double tDWG[B][A], tDWV[B][A], tIGV[B][B], tIGW[A][B], tIVG[B][B], tIVW[A][B], tIPW[A][NP], tIPG[B][NP], tIGP[NP][B], tIWP[NP][A];
   __shared__ double tww[A], twg[B], twp[NP];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
-  const long e = xcd_block() * EB + el;
+  const long e = blk * EB + el;
   const bool act = el < EB && e < mp.K;
   long ex, ey;
   elem_xy(mp, act ? e : 0, ex, ey);
@@ -597,6 +656,24 @@ __global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update(MagIO
   }
 }
 
+template <int P, int M, int MODE, int BS, bool R2>
+__global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update(MagIO io, const MagTab* __restrict__ T, MeshP mp) {
+  mag_update_body<P, M, MODE, BS, R2>(io, T, mp, xcd_block());
+}
+
+struct mag_update_args {
+  MagIO io;
+  const MagTab* T;
+  MeshP mp;
+};
+
+template <int P, int M, int MODE, int BS, bool R2>
+__global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update_rt(const mag_update_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const mag_update_args a = A[r];
+  mag_update_body<P, M, MODE, BS, R2>(a.io, a.T, a.mp, (long)blockIdx.x - boff[r]);
+}
+
 // per-element statistics of NC nodal fields [NC][K][NN] -> [K][NC][3] (GLL-weighted sum, min, max)
 template <int P, int NC>
 __global__ __launch_bounds__(256) void k_field_stats(const double* __restrict__ f, double* __restrict__ stats,
@@ -660,8 +737,8 @@ struct VP {
 // the steps stay branch-free; the Cholesky dot products run on two accumulators to halve their FMA
 // chains (a second accumulator in the substitution as well would cost 50 more VGPRs).
 template <int P>
-__global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho, double* __restrict__ Psi,
-                                                 const HydroTab* __restrict__ H, MeshP mp) {
+__device__ __forceinline__ void vel_prep_body(const double* __restrict__ rho, double* __restrict__ Psi,
+                                                 const HydroTab* __restrict__ H, MeshP mp, long blk) {
   constexpr int NP = P + 1, NN = NP * NP, EB = VP<P>::EB, NL = NN * (NN + 1) / 2;
   constexpr int NPS = NP * (NP + 1) / 2;  // pairs a <= a'
   // LDS, sized so that 24 one-wave blocks fit on a CU at N = 4 (6 waves per SIMD):
@@ -675,10 +752,10 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
   double(*const sw)[NN] = reinterpret_cast<double(*)[NN]>(&sL[0][0]);
   double(*const srd)[NN] = reinterpret_cast<double(*)[NN]>(&sH[0][0][0]);
   const int tid = threadIdx.x, el0 = tid / NN;
-  const bool act0 = el0 < EB && (long)blockIdx.x * EB + el0 < mp.K;
+  const bool act0 = el0 < EB && blk * EB + el0 < mp.K;
   const int el = act0 ? el0 : 0, q = act0 ? tid - el0 * NN : 0;  // idle lanes shadow lane 0
   const int qi = q % NP, qj = q / NP;
-  const long e = (long)blockIdx.x * EB + el;
+  const long e = blk * EB + el;
   for (int t = tid; t < NP * NP; t += 64) sV[t / NP][t % NP] = H->V[t / NP][t % NP];
   if (act0) sw[el][q] = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
   __syncthreads();
@@ -779,6 +856,26 @@ __global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho,
   }
 }
 
+template <int P>
+__global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho, double* __restrict__ Psi,
+                                                 const HydroTab* __restrict__ H, MeshP mp) {
+  vel_prep_body<P>(rho, Psi, H, mp, (long)blockIdx.x);
+}
+
+struct vel_prep_args {
+  const double* rho;
+  double* Psi;
+  const HydroTab* H;
+  MeshP mp;
+};
+
+template <int P>
+__global__ __launch_bounds__(64) void k_vel_prep_rt(const vel_prep_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const vel_prep_args a = A[r];
+  vel_prep_body<P>(a.rho, a.Psi, a.H, a.mp, (long)blockIdx.x - boff[r]);
+}
+
 template <int P, int M>
 struct VS {
   static constexpr int NP = P + 1, NN = NP * NP, EB = 256 / NN;
@@ -791,12 +888,12 @@ struct VS {
 // loads.  u is only read here (the projection kernel that updates it runs afterwards).
 // (at N = 4, k = 3 the kernel fits 80 VGPRs and 27 KB of LDS without spills: 6 waves per SIMD)
 template <int P, int M, bool R2>
-__global__ __launch_bounds__(256, (P == 4 && M == 3) ? 6 : 1) void k_vel_sensor(const double* __restrict__ rho, const double* __restrict__ u,
+__device__ __forceinline__ void vel_sensor_body(const double* __restrict__ rho, const double* __restrict__ u,
                                                     const double* __restrict__ Bx, const double* __restrict__ By,
                                                     const double* __restrict__ Bz, const double* __restrict__ lines,
                                                     const double* __restrict__ glob, double* __restrict__ Dfac,
                                                     const HydroTab* __restrict__ H, const MagTab* __restrict__ T,
-                                                    MeshP mp, double tau, double sM) {
+                                                    MeshP mp, double tau, double sM, long blk) {
   using C = VS<P, M>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, A = C::A, B = C::B, AB = C::AB;
   // sbb holds an element's B coefficients (B_x, B_y, B_z at offsets 0, AB, 2 AB) and, once they
@@ -811,7 +908,7 @@ __global__ __launch_bounds__(256, (P == 4 && M == 3) ? 6 : 1) void k_vel_sensor(
   constexpr int NU = R2 ? 2 : 3;  // velocity components (u_z = 0 in the 2D2V system)
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
   const int qi = q % NP, qj = q / NP;
-  const long e = xcd_block() * EB + el;
+  const long e = blk * EB + el;
   const bool act = el < EB && e < mp.K;
   long ex, ey;
   elem_xy(mp, act ? e : 0, ex, ey);
@@ -974,6 +1071,39 @@ __global__ __launch_bounds__(256, (P == 4 && M == 3) ? 6 : 1) void k_vel_sensor(
   }
 }
 
+template <int P, int M, bool R2>
+__global__ __launch_bounds__(256, (P == 4 && M == 3) ? 6 : 1) void k_vel_sensor(const double* __restrict__ rho, const double* __restrict__ u,
+                                                    const double* __restrict__ Bx, const double* __restrict__ By,
+                                                    const double* __restrict__ Bz, const double* __restrict__ lines,
+                                                    const double* __restrict__ glob, double* __restrict__ Dfac,
+                                                    const HydroTab* __restrict__ H, const MagTab* __restrict__ T,
+                                                    MeshP mp, double tau, double sM) {
+  vel_sensor_body<P, M, R2>(rho, u, Bx, By, Bz, lines, glob, Dfac, H, T, mp, tau, sM, xcd_block());
+}
+
+struct vel_sensor_args {
+  const double* rho;
+  const double* u;
+  const double* Bx;
+  const double* By;
+  const double* Bz;
+  const double* lines;
+  const double* glob;
+  double* Dfac;
+  const HydroTab* H;
+  const MagTab* T;
+  MeshP mp;
+  double tau;
+  double sM;
+};
+
+template <int P, int M, bool R2>
+__global__ __launch_bounds__(256, (P == 4 && M == 3) ? 6 : 1) void k_vel_sensor_rt(const vel_sensor_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const vel_sensor_args a = A[r];
+  vel_sensor_body<P, M, R2>(a.rho, a.u, a.Bx, a.By, a.Bz, a.lines, a.glob, a.Dfac, a.H, a.T, a.mp, a.tau, a.sM, (long)blockIdx.x - boff[r]);
+}
+
 // Velocity-OE map (eq. magnetic-oe-map) with the prepared basis: one thread per node, EB elements
 // per block.  The block's basis tables are copied to LDS first (all of a thread's
 // 16-byte loads are issued before the first store; rows keep an odd LDS stride), so the basis is
@@ -986,10 +1116,10 @@ struct VPJ {
 };
 
 template <int P, int BS, bool R2>
-__global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho, double* __restrict__ u,
+__device__ __forceinline__ void vel_proj_body(const double* __restrict__ rho, double* __restrict__ u,
                                                   double* __restrict__ en, const double* __restrict__ Psi,
                                                   const double* __restrict__ Dfac, const HydroTab* __restrict__ H,
-                                                  MeshP mp) {
+                                                  MeshP mp, long blk) {
   using C = VPJ<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NNP = C::NNP;
   constexpr long PS = C::PS, RS = C::RS;
@@ -997,7 +1127,7 @@ __global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho,
   __shared__ double sv[EB][3][NN], sc[EB][3][NN], sD[EB][NP];
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN;
   const int qi = q % NP, qj = q / NP;
-  const long e0 = (long)blockIdx.x * EB, e = e0 + el;
+  const long e0 = blk * EB, e = e0 + el;
   const bool act = el < EB && e < mp.K;
   const long KN = mp.K * NN;
   {
@@ -1071,6 +1201,31 @@ __global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho,
   en[e * NN + q] += heat;
 }
 
+template <int P, int BS, bool R2>
+__global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho, double* __restrict__ u,
+                                                  double* __restrict__ en, const double* __restrict__ Psi,
+                                                  const double* __restrict__ Dfac, const HydroTab* __restrict__ H,
+                                                  MeshP mp) {
+  vel_proj_body<P, BS, R2>(rho, u, en, Psi, Dfac, H, mp, (long)blockIdx.x);
+}
+
+struct vel_proj_args {
+  const double* rho;
+  double* u;
+  double* en;
+  const double* Psi;
+  const double* Dfac;
+  const HydroTab* H;
+  MeshP mp;
+};
+
+template <int P, int BS, bool R2>
+__global__ __launch_bounds__(BS) void k_vel_proj_rt(const vel_proj_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const vel_proj_args a = A[r];
+  vel_proj_body<P, BS, R2>(a.rho, a.u, a.en, a.Psi, a.Dfac, a.H, a.mp, (long)blockIdx.x - boff[r]);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Artificial resistivity (eq. magnetic-ar-sensor, eq. magnetic-ar-coefficient) in two passes.
 // Pass 1 (one thread per GLL_p node, B coefficients staged in LDS): each element's tangential
@@ -1080,16 +1235,16 @@ __global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho,
 // Pass 2 (one thread per element): squared jumps against the neighbours' traces, sigma^B, R, eta.
 // ---------------------------------------------------------------------------------------------
 template <int P, int M>
-__global__ __launch_bounds__(256) void k_ar_traces(const double* __restrict__ rho, const double* __restrict__ u,
+__device__ __forceinline__ void ar_traces_body(const double* __restrict__ rho, const double* __restrict__ u,
                                                    const double* __restrict__ Bx, const double* __restrict__ By,
                                                    const double* __restrict__ Bz, double* __restrict__ tr,
-                                                   const MagTab* __restrict__ T, MeshP mp) {
+                                                   const MagTab* __restrict__ T, MeshP mp, long blk) {
   constexpr int NP = P + 1, NN = NP * NP, EB = 256 / NN, A = M + 2, B = M + 1, AB = A * B, BB = B * B;
   constexpr int NT = 8 * A + 2;
   __shared__ double sbx[EB][AB], sby[EB][AB], sbz[EB][BB], sv[EB][2][NN];
   __shared__ double tWP[NP][A], tGP[NP][B], tVP[NP][B], tWQ[A][A], tVQ[A][B], tGE[2][B], tVE[2][B];
   const int tid = threadIdx.x, el = tid / NN, q = tid - el * NN, qi = q % NP, qj = q / NP;
-  const long e = (long)blockIdx.x * EB + el;
+  const long e = blk * EB + el;
   const bool act = el < EB && e < mp.K;
   long ex, ey;
   elem_xy(mp, act ? e : 0, ex, ey);
@@ -1165,13 +1320,39 @@ __global__ __launch_bounds__(256) void k_ar_traces(const double* __restrict__ rh
   }
 }
 
+template <int P, int M>
+__global__ __launch_bounds__(256) void k_ar_traces(const double* __restrict__ rho, const double* __restrict__ u,
+                                                   const double* __restrict__ Bx, const double* __restrict__ By,
+                                                   const double* __restrict__ Bz, double* __restrict__ tr,
+                                                   const MagTab* __restrict__ T, MeshP mp) {
+  ar_traces_body<P, M>(rho, u, Bx, By, Bz, tr, T, mp, (long)blockIdx.x);
+}
+
+struct ar_traces_args {
+  const double* rho;
+  const double* u;
+  const double* Bx;
+  const double* By;
+  const double* Bz;
+  double* tr;
+  const MagTab* T;
+  MeshP mp;
+};
+
+template <int P, int M>
+__global__ __launch_bounds__(256) void k_ar_traces_rt(const ar_traces_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const ar_traces_args a = A[r];
+  ar_traces_body<P, M>(a.rho, a.u, a.Bx, a.By, a.Bz, a.tr, a.T, a.mp, (long)blockIdx.x - boff[r]);
+}
+
 // bglob[3][3]: (integral, min, max) of B_x, B_y, B_z over the domain.
 template <int P, int M>
-__global__ __launch_bounds__(256) void k_ar_eta(const double* __restrict__ tr, const double* __restrict__ bglob,
+__device__ __forceinline__ void ar_eta_body(const double* __restrict__ tr, const double* __restrict__ bglob,
                                                 double* __restrict__ eta, const MagTab* __restrict__ T, MeshP mp,
-                                                double Cs, double Ceta) {
+                                                double Cs, double Ceta, long blk) {
   constexpr int A = M + 2, NT = 8 * A + 2;
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long e = blk * blockDim.x + threadIdx.x;
   if (e >= mp.K) return;
   long ex, ey;
   elem_xy(mp, e, ex, ey);
@@ -1217,13 +1398,37 @@ __global__ __launch_bounds__(256) void k_ar_eta(const double* __restrict__ tr, c
   eta[e] = Ceta * fmax(v0, v1);
 }
 
+template <int P, int M>
+__global__ __launch_bounds__(256) void k_ar_eta(const double* __restrict__ tr, const double* __restrict__ bglob,
+                                                double* __restrict__ eta, const MagTab* __restrict__ T, MeshP mp,
+                                                double Cs, double Ceta) {
+  ar_eta_body<P, M>(tr, bglob, eta, T, mp, Cs, Ceta, (long)blockIdx.x);
+}
+
+struct ar_eta_args {
+  const double* tr;
+  const double* bglob;
+  double* eta;
+  const MagTab* T;
+  MeshP mp;
+  double Cs;
+  double Ceta;
+};
+
+template <int P, int M>
+__global__ __launch_bounds__(256) void k_ar_eta_rt(const ar_eta_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const ar_eta_args a = A[r];
+  ar_eta_body<P, M>(a.tr, a.bglob, a.eta, a.T, a.mp, a.Cs, a.Ceta, (long)blockIdx.x - boff[r]);
+}
+
 // per-element exact integral and owned-node min / max of each B component -> [K][3][3]
 template <int M>
-__global__ __launch_bounds__(256) void k_B_stats(const double* __restrict__ Bx, const double* __restrict__ By,
+__device__ __forceinline__ void B_stats_body(const double* __restrict__ Bx, const double* __restrict__ By,
                                                  const double* __restrict__ Bz, double* __restrict__ stats,
-                                                 const MagTab* __restrict__ T, MeshP mp) {
+                                                 const MagTab* __restrict__ T, MeshP mp, long blk) {
   constexpr int A = M + 2, B = M + 1;
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long e = blk * blockDim.x + threadIdx.x;
   if (e >= mp.K) return;
   long ex, ey;
   elem_xy(mp, e, ex, ey);
@@ -1253,17 +1458,40 @@ __global__ __launch_bounds__(256) void k_B_stats(const double* __restrict__ Bx, 
   }
 }
 
+template <int M>
+__global__ __launch_bounds__(256) void k_B_stats(const double* __restrict__ Bx, const double* __restrict__ By,
+                                                 const double* __restrict__ Bz, double* __restrict__ stats,
+                                                 const MagTab* __restrict__ T, MeshP mp) {
+  B_stats_body<M>(Bx, By, Bz, stats, T, mp, (long)blockIdx.x);
+}
+
+struct B_stats_args {
+  const double* Bx;
+  const double* By;
+  const double* Bz;
+  double* stats;
+  const MagTab* T;
+  MeshP mp;
+};
+
+template <int M>
+__global__ __launch_bounds__(256) void k_B_stats_rt(const B_stats_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const B_stats_args a = A[r];
+  B_stats_body<M>(a.Bx, a.By, a.Bz, a.stats, a.T, a.mp, (long)blockIdx.x - boff[r]);
+}
+
 }  // namespace
 
 // gather of per-element loads at shared nodes and division by the lumped weights
 template <int M, bool R2>
-__global__ __launch_bounds__(256) void k_gather(const double* __restrict__ Lx, const double* __restrict__ Ly,
+__device__ __forceinline__ void gather_body(const double* __restrict__ Lx, const double* __restrict__ Ly,
                                                 const double* __restrict__ Lz, double* __restrict__ Ox,
                                                 double* __restrict__ Oy, double* __restrict__ Oz,
-                                                const MagTab* __restrict__ T, MeshP mp) {
+                                                const MagTab* __restrict__ T, MeshP mp, long blk) {
   constexpr int A = M + 2, B = M + 1, AA = A * A, AB = A * B;
   const long NX = (long)mp.nx * B, G = NX * mp.ny * B;
-  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long g = blk * blockDim.x + threadIdx.x;
   if (g >= G) return;
   const long gy = row_of(mp, g / B), gx = g - gy * NX;  // g / (nx B) = (g / B) / nx
   const long ex = gx / B, ey = gy / B;
@@ -1289,6 +1517,32 @@ __global__ __launch_bounds__(256) void k_gather(const double* __restrict__ Lx, c
     if (i == 0) { s += Ly[eL * AB + j * A + (A - 1)]; w += T->ww[A - 1] * T->wg[j]; }
     Oy[g] = s / (mp.J * w);
   }
+}
+
+template <int M, bool R2>
+__global__ __launch_bounds__(256) void k_gather(const double* __restrict__ Lx, const double* __restrict__ Ly,
+                                                const double* __restrict__ Lz, double* __restrict__ Ox,
+                                                double* __restrict__ Oy, double* __restrict__ Oz,
+                                                const MagTab* __restrict__ T, MeshP mp) {
+  gather_body<M, R2>(Lx, Ly, Lz, Ox, Oy, Oz, T, mp, (long)blockIdx.x);
+}
+
+struct gather_args {
+  const double* Lx;
+  const double* Ly;
+  const double* Lz;
+  double* Ox;
+  double* Oy;
+  double* Oz;
+  const MagTab* T;
+  MeshP mp;
+};
+
+template <int M, bool R2>
+__global__ __launch_bounds__(256) void k_gather_rt(const gather_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const gather_args a = A[r];
+  gather_body<M, R2>(a.Lx, a.Ly, a.Lz, a.Ox, a.Oy, a.Oz, a.T, a.mp, (long)blockIdx.x - boff[r]);
 }
 
 // Local-to-global maps of the six magnetic node sets of each element (B_x, B_y, B_z, W, N_x, N_y;
@@ -1330,22 +1584,31 @@ __global__ __launch_bounds__(256) void k_check_mag(const double* __restrict__ rh
   if (!ok) atomicOr(flag + 1, 2);
 }
 
+__device__ __forceinline__ void to_primitive_node(const double* __restrict__ U, double* __restrict__ rho,
+                                                  double* __restrict__ e, double* __restrict__ u, long n, long k) {
+  const double r = U[k], ux = U[n + k] / r, uy = U[2 * n + k] / r, uz = U[3 * n + k] / r;
+  rho[k] = r; u[k] = ux; u[n + k] = uy; u[2 * n + k] = uz;
+  e[k] = (U[4 * n + k] - 0.5 * r * (ux * ux + uy * uy + uz * uz)) / r;
+}
+
+__device__ __forceinline__ void to_conservative_node(const double* __restrict__ rho, const double* __restrict__ e,
+                                                     const double* __restrict__ u, double* __restrict__ U, long n,
+                                                     long k) {
+  const double r = rho[k], ux = u[k], uy = u[n + k], uz = u[2 * n + k];
+  U[k] = r; U[n + k] = r * ux; U[2 * n + k] = r * uy; U[3 * n + k] = r * uz;
+  U[4 * n + k] = r * e[k] + 0.5 * r * (ux * ux + uy * uy + uz * uz);
+}
+
 __global__ void k_to_primitive(const double* __restrict__ U, double* __restrict__ rho, double* __restrict__ e,
                                double* __restrict__ u, long n) {
-  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-    const double r = U[k], ux = U[n + k] / r, uy = U[2 * n + k] / r, uz = U[3 * n + k] / r;
-    rho[k] = r; u[k] = ux; u[n + k] = uy; u[2 * n + k] = uz;
-    e[k] = (U[4 * n + k] - 0.5 * r * (ux * ux + uy * uy + uz * uz)) / r;
-  }
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+    to_primitive_node(U, rho, e, u, n, k);
 }
 
 __global__ void k_to_conservative(const double* __restrict__ rho, const double* __restrict__ e,
                                   const double* __restrict__ u, double* __restrict__ U, long n) {
-  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-    const double r = rho[k], ux = u[k], uy = u[n + k], uz = u[2 * n + k];
-    U[k] = r; U[n + k] = r * ux; U[2 * n + k] = r * uy; U[3 * n + k] = r * uz;
-    U[4 * n + k] = r * e[k] + 0.5 * r * (ux * ux + uy * uy + uz * uz);
-  }
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x)
+    to_conservative_node(rho, e, u, U, n, k);
 }
 
 // B_par = (-d_y A, d_x A) for A on the E_z grid
@@ -1380,6 +1643,14 @@ static int chk(mhd25_ctx* c, const char* what) {
   return 0;
 }
 
+hipEvent_t* timing_slot(mhd25_ctx* c, int kid);
+// HIP-event timing of one launch (kernel id kid) when the context's timing is on
+#define T_BEGIN(kid)                                                   \
+  hipEvent_t* ev_ = c->timing ? timing_slot(c, kid) : nullptr;         \
+  if (ev_) hipEventRecord(ev_[0], c->stream)
+#define T_END() \
+  if (ev_) hipEventRecord(ev_[1], c->stream)
+
 #define DISPATCH_PM(p, m, F)                                                                              \
   if (p == 1 && m == 0) { F(1, 0); } else if (p == 1 && m == 1) { F(1, 1); }                              \
   else if (p == 2 && m == 1) { F(2, 1); } else if (p == 2 && m == 2) { F(2, 2); }                         \
@@ -1392,6 +1663,9 @@ static int chk(mhd25_ctx* c, const char* what) {
 #define DISPATCH_M(m, F) \
   switch (m) { case 0: F(0); break; case 1: F(1); break; case 2: F(2); break; case 3: F(3); break; \
                case 4: F(4); break; case 5: F(5); break; case 6: F(6); break; default: return -4; }
+
+// template keys of run-table records: degree p, magnetic degree m, 2D2V flag, mode
+static int mkey(int p, int m, bool r2, int mode = 0) { return p * 1000 + m * 100 + (r2 ? 10 : 0) + mode; }
 
 static long mblocks(int p, int m, long K, int bs = 256) {
   const int nn = (p + 1) * (p + 1), aa = (m + 2) * (m + 2);
@@ -1428,33 +1702,58 @@ static int reconstruct_JE_ws(mhd25_ctx* c, const double* u, const double* Bx, co
   double* Lz = Ly + K * a * b;
   const long nbj = mblocks(c->p, c->m, K, MHD_JL_BS), nbe = mblocks(c->p, c->m, K, MHD_EL_BS);
   const long gb = (G + 255) / 256;
+  if (c->rec) {
+    const int k = mkey(c->p, c->m, r2);
+    rt_record(c, RT_J_LOADS, k, nbj, J_loads_args{Bx, By, Bz, Lx, Ly, Lz, c->d_mt, c->mp});
+    rt_record(c, RT_GATHER, k, gb, gather_args{Lx, Ly, Lz, JE, JE + G, JE + 2 * G, c->d_mt, c->mp});
+    rt_record(c, RT_E_LOADS, k, nbe,
+              E_loads_args{u, Bx, By, Bz, JE, JE + G, JE + 2 * G, eta, Lx, Ly, Lz, c->d_mt, c->mp});
+    rt_record(c, RT_GATHER, k, gb, gather_args{Lx, Ly, Lz, JE + 3 * G, JE + 4 * G, JE + 5 * G, c->d_mt, c->mp});
+    return 0;
+  }
 #define LJ(P, M)                                                                                                    \
   if (r2) hipLaunchKernelGGL((k_J_loads<P, M, MHD_JL_BS, true>), dim3(nbj), dim3(MHD_JL_BS), 0, c->stream, Bx, By, \
                              Bz, Lx, Ly, Lz, c->d_mt, c->mp);                                                       \
   else hipLaunchKernelGGL((k_J_loads<P, M, MHD_JL_BS, false>), dim3(nbj), dim3(MHD_JL_BS), 0, c->stream, Bx, By, Bz, \
                           Lx, Ly, Lz, c->d_mt, c->mp)
-  DISPATCH_PM(c->p, c->m, LJ);
+  {
+    T_BEGIN(7);
+    DISPATCH_PM(c->p, c->m, LJ);
+    T_END();
+  }
 #undef LJ
 #define GJ(M)                                                                                                       \
   if (r2) hipLaunchKernelGGL((k_gather<M, true>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE, JE + G,       \
                              JE + 2 * G, c->d_mt, c->mp);                                                           \
   else hipLaunchKernelGGL((k_gather<M, false>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE, JE + G,         \
                           JE + 2 * G, c->d_mt, c->mp)
-  DISPATCH_M(c->m, GJ);
+  {
+    T_BEGIN(8);
+    DISPATCH_M(c->m, GJ);
+    T_END();
+  }
 #undef GJ
 #define LE(P, M)                                                                                                    \
   if (r2) hipLaunchKernelGGL((k_E_loads<P, M, MHD_EL_BS, true>), dim3(nbe), dim3(MHD_EL_BS), 0, c->stream, u, Bx,  \
                              By, Bz, JE, JE + G, JE + 2 * G, eta, Lx, Ly, Lz, c->d_mt, c->mp);                      \
   else hipLaunchKernelGGL((k_E_loads<P, M, MHD_EL_BS, false>), dim3(nbe), dim3(MHD_EL_BS), 0, c->stream, u, Bx, By, \
                           Bz, JE, JE + G, JE + 2 * G, eta, Lx, Ly, Lz, c->d_mt, c->mp)
-  DISPATCH_PM(c->p, c->m, LE);
+  {
+    T_BEGIN(5);
+    DISPATCH_PM(c->p, c->m, LE);
+    T_END();
+  }
 #undef LE
 #define GE(M)                                                                                                       \
   if (r2) hipLaunchKernelGGL((k_gather<M, true>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE + 3 * G,       \
                              JE + 4 * G, JE + 5 * G, c->d_mt, c->mp);                                               \
   else hipLaunchKernelGGL((k_gather<M, false>), dim3(gb), dim3(256), 0, c->stream, Lx, Ly, Lz, JE + 3 * G,         \
                           JE + 4 * G, JE + 5 * G, c->d_mt, c->mp)
-  DISPATCH_M(c->m, GE);
+  {
+    T_BEGIN(8);
+    DISPATCH_M(c->m, GE);
+    T_END();
+  }
 #undef GE
   return chk(c, "reconstruct launch");
 }
@@ -1467,6 +1766,7 @@ int mag_reconstruct_JE(mhd25_ctx* c, const double* u, const double* Bx, const do
 int mag_update(mhd25_ctx* c, const MagIO& io, int mode) {
   const long nb = mblocks(c->p, c->m, c->mp.K, MHD_MU_BS);
   const bool r2 = c->opt.reduced_2d2v != 0;
+  if (c->rec) { rt_record(c, RT_MAG_UPDATE, mkey(c->p, c->m, r2, mode), nb, mag_update_args{io, c->d_mt, c->mp}); return 0; }
 #define U0(P, M)                                                                                                    \
   if (r2) hipLaunchKernelGGL((k_mag_update<P, M, 0, MHD_MU_BS, true>), dim3(nb), dim3(MHD_MU_BS), 0, c->stream, io, \
                              c->d_mt, c->mp);                                                                        \
@@ -1477,14 +1777,21 @@ int mag_update(mhd25_ctx* c, const MagIO& io, int mode) {
                              c->d_mt, c->mp);                                                                        \
   else hipLaunchKernelGGL((k_mag_update<P, M, 1, MHD_MU_BS, false>), dim3(nb), dim3(MHD_MU_BS), 0, c->stream, io,   \
                           c->d_mt, c->mp)
+  T_BEGIN(2);
   if (mode == 0) {
     DISPATCH_PM(c->p, c->m, U0);
   } else {
     DISPATCH_PM(c->p, c->m, U1);
   }
+  T_END();
 #undef U0
 #undef U1
   return chk(c, "magnetic update launch");
+}
+
+static int vp_eb(int p) {
+  switch (p) { case 1: return VP<1>::EB; case 2: return VP<2>::EB; case 3: return VP<3>::EB;
+               case 4: return VP<4>::EB; case 5: return VP<5>::EB; default: return VP<6>::EB; }
 }
 
 int mag_velocity_prep(mhd25_ctx* c, const double* rho) {
@@ -1492,10 +1799,17 @@ int mag_velocity_prep(mhd25_ctx* c, const double* rho) {
   const long nn = (long)(c->p + 1) * (c->p + 1);
   (void)nn;
   if (!c->psi) { c->err = "velocity-OE basis not allocated"; return -2; }
+  if (c->rec) {
+    rt_record(c, RT_VEL_PREP, c->p, (K + vp_eb(c->p) - 1) / vp_eb(c->p),
+              vel_prep_args{rho, c->psi, c->d_ht, c->mp});
+    return 0;
+  }
 #define VPR(P) hipLaunchKernelGGL((k_vel_prep<P>), dim3((K + VP<P>::EB - 1) / VP<P>::EB), dim3(64), 0, c->stream, rho, \
                                   c->psi, c->d_ht, c->mp)
+  T_BEGIN(4);
   switch (c->p) { case 1: VPR(1); break; case 2: VPR(2); break; case 3: VPR(3); break; case 4: VPR(4); break;
                   case 5: VPR(5); break; case 6: VPR(6); break; default: return -4; }
+  T_END();
 #undef VPR
   return chk(c, "velocity OE prep launch");
 }
@@ -1507,7 +1821,7 @@ int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, d
   const long nb = (K + eb - 1) / eb, nb2 = (K + eb2 - 1) / eb2;
   const bool r2 = c->opt.reduced_2d2v != 0;
   const int nu = r2 ? 2 : 3;  // velocity components carried
-  if (!stats_ready) {
+  if (!stats_ready && !c->rec) {
 #define FS(P)                                                                                                       \
   if (r2) hipLaunchKernelGGL((k_field_stats<P, 2>), dim3(nb), dim3(256), 0, c->stream, u, c->stats, c->d_mt, c->mp); \
   else hipLaunchKernelGGL((k_field_stats<P, 3>), dim3(nb), dim3(256), 0, c->stream, u, c->stats, c->d_mt, c->mp)
@@ -1516,20 +1830,35 @@ int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, d
 #undef FS
   }
   line_global_reduce(c, c->stats, nu, nullptr);
+  if (c->rec) {
+    if (!stats_ready) { c->err = "run-table plan: velocity statistics must come from the update"; return -2; }
+    rt_record(c, RT_VEL_SENSOR, mkey(c->p, c->m, r2), nb,
+              vel_sensor_args{rho, u, Bx, By, Bz, c->lines, c->glob, c->dfac, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M});
+    rt_record(c, RT_VEL_PROJ, mkey(c->p, c->m, r2), nb2, vel_proj_args{rho, u, e, c->psi, c->dfac, c->d_ht, c->mp});
+    return 0;
+  }
 #define VSN(P, M)                                                                                                   \
   if (r2) hipLaunchKernelGGL((k_vel_sensor<P, M, true>), dim3(nb), dim3(256), 0, c->stream, rho, u, Bx, By, Bz,    \
                              c->lines, c->glob, c->dfac, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M);                 \
   else hipLaunchKernelGGL((k_vel_sensor<P, M, false>), dim3(nb), dim3(256), 0, c->stream, rho, u, Bx, By, Bz,      \
                           c->lines, c->glob, c->dfac, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M)
-  DISPATCH_PM(c->p, c->m, VSN);
+  {
+    T_BEGIN(6);
+    DISPATCH_PM(c->p, c->m, VSN);
+    T_END();
+  }
 #undef VSN
 #define VPR(P)                                                                                                      \
   if (r2) hipLaunchKernelGGL((k_vel_proj<P, MHD_VP_BS, true>), dim3(nb2), dim3(MHD_VP_BS), 0, c->stream, rho, u, e, \
                              c->psi, c->dfac, c->d_ht, c->mp);                                                        \
   else hipLaunchKernelGGL((k_vel_proj<P, MHD_VP_BS, false>), dim3(nb2), dim3(MHD_VP_BS), 0, c->stream, rho, u, e,   \
                           c->psi, c->dfac, c->d_ht, c->mp)
-  switch (c->p) { case 1: VPR(1); break; case 2: VPR(2); break; case 3: VPR(3); break; case 4: VPR(4); break;
-                  case 5: VPR(5); break; case 6: VPR(6); break; default: return -4; }
+  {
+    T_BEGIN(3);
+    switch (c->p) { case 1: VPR(1); break; case 2: VPR(2); break; case 3: VPR(3); break; case 4: VPR(4); break;
+                    case 5: VPR(5); break; case 6: VPR(6); break; default: return -4; }
+    T_END();
+  }
 #undef VPR
   return chk(c, "velocity OE launch");
 }
@@ -1545,6 +1874,16 @@ int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* B
                const double* Bz, double* eta) {
   const long K = c->mp.K;
   const long nb = (K + 255) / 256;
+  if (c->rec) {
+    const long eb = 256 / ((c->p + 1) * (c->p + 1));
+    rt_record(c, RT_B_STATS, c->m, nb, B_stats_args{Bx, By, Bz, c->stats, c->d_mt, c->mp});
+    line_global_reduce(c, c->stats, 3, nullptr);
+    rt_record(c, RT_AR_TRACES, mkey(c->p, c->m, false), (K + eb - 1) / eb,
+              ar_traces_args{rho, u, Bx, By, Bz, c->artr, c->d_mt, c->mp});
+    rt_record(c, RT_AR_ETA, mkey(c->p, c->m, false), nb,
+              ar_eta_args{c->artr, c->glob, eta, c->d_mt, c->mp, c->opt.C_s, c->opt.C_eta});
+    return 0;
+  }
 #define BS(M) hipLaunchKernelGGL((k_B_stats<M>), dim3(nb), dim3(256), 0, c->stream, Bx, By, Bz, c->stats, c->d_mt, c->mp)
   DISPATCH_M(c->m, BS);
 #undef BS
@@ -1553,7 +1892,11 @@ int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* B
   const long nb1 = (K + eb - 1) / eb;
 #define ART(P, M) hipLaunchKernelGGL((k_ar_traces<P, M>), dim3(nb1), dim3(256), 0, c->stream, rho, u, Bx, By, Bz, c->artr, \
                                      c->d_mt, c->mp)
-  DISPATCH_PM(c->p, c->m, ART);
+  {
+    T_BEGIN(9);
+    DISPATCH_PM(c->p, c->m, ART);
+    T_END();
+  }
 #undef ART
 #define AR(P, M) hipLaunchKernelGGL((k_ar_eta<P, M>), dim3(nb), dim3(256), 0, c->stream, c->artr, c->glob, eta, c->d_mt, \
                                     c->mp, c->opt.C_s, c->opt.C_eta)
@@ -1562,9 +1905,16 @@ int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* B
   return chk(c, "A.R. launch");
 }
 
+struct prim_args {
+  const double* U;
+  double *rho, *e, *u;
+  long n;
+};
+
 int mag_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u) {
   const long n = c->mp.K * c->nn;
   long nb = (n + 255) / 256; if (nb > 65536) nb = 65536;
+  if (c->rec) { rt_record(c, RT_TO_PRIM, 0, nb, prim_args{U, rho, e, u, n}); return 0; }
   hipLaunchKernelGGL(k_to_primitive, dim3(nb), dim3(256), 0, c->stream, U, rho, e, u, n);
   return chk(c, "exchange launch");
 }
@@ -1572,6 +1922,7 @@ int mag_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, doub
 int mag_to_conservative(mhd25_ctx* c, const double* rho, const double* e, const double* u, double* U) {
   const long n = c->mp.K * c->nn;
   long nb = (n + 255) / 256; if (nb > 65536) nb = 65536;
+  if (c->rec) { rt_record(c, RT_TO_CONS, 0, nb, prim_args{U, const_cast<double*>(rho), const_cast<double*>(e), const_cast<double*>(u), n}); return 0; }
   hipLaunchKernelGGL(k_to_conservative, dim3(nb), dim3(256), 0, c->stream, rho, e, u, U, n);
   return chk(c, "exchange launch");
 }
@@ -1602,6 +1953,129 @@ int mag_B_from_potential(mhd25_ctx* c, const double* A, double* Bx, double* By) 
   DISPATCH_M(c->m, BP);
 #undef BP
   return chk(c, "potential launch");
+}
+
+// ---------------------------------------------------------------------------------------------
+// Run-table launches of this file's kernels (batched ensembles).
+// ---------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_to_primitive_rt(const prim_args* __restrict__ A, const int* __restrict__ boff,
+                                                         int nr) {
+  const int r = rt_run(boff, nr);
+  const prim_args a = A[r];
+  const long stride = (long)(boff[r + 1] - boff[r]) * blockDim.x;
+  for (long k = (long)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x; k < a.n; k += stride)
+    to_primitive_node(a.U, a.rho, a.e, a.u, a.n, k);
+}
+
+__global__ __launch_bounds__(256) void k_to_conservative_rt(const prim_args* __restrict__ A,
+                                                            const int* __restrict__ boff, int nr) {
+  const int r = rt_run(boff, nr);
+  const prim_args a = A[r];
+  const long stride = (long)(boff[r + 1] - boff[r]) * blockDim.x;
+  for (long k = (long)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x; k < a.n; k += stride)
+    to_conservative_node(a.rho, a.e, a.u, const_cast<double*>(a.U), a.n, k);
+}
+
+int magnetic_rt_launch(const RtRecord& h, const void* dargs, const int* dboff, int nr, long nblocks, hipStream_t s) {
+  const dim3 g((unsigned)nblocks);
+  const int p = h.key / 1000, m = (h.key / 100) % 10, mode = h.key % 10;
+  const bool r2 = (h.key / 10) % 10 != 0;
+  switch (h.kind) {
+    case RT_J_LOADS: {
+      const J_loads_args* A = (const J_loads_args*)dargs;
+#define F(P, M)                                                                                                     \
+  if (r2) hipLaunchKernelGGL((k_J_loads_rt<P, M, MHD_JL_BS, true>), g, dim3(MHD_JL_BS), 0, s, A, dboff, nr);       \
+  else hipLaunchKernelGGL((k_J_loads_rt<P, M, MHD_JL_BS, false>), g, dim3(MHD_JL_BS), 0, s, A, dboff, nr)
+      DISPATCH_PM(p, m, F);
+#undef F
+      break;
+    }
+    case RT_E_LOADS: {
+      const E_loads_args* A = (const E_loads_args*)dargs;
+#define F(P, M)                                                                                                     \
+  if (r2) hipLaunchKernelGGL((k_E_loads_rt<P, M, MHD_EL_BS, true>), g, dim3(MHD_EL_BS), 0, s, A, dboff, nr);       \
+  else hipLaunchKernelGGL((k_E_loads_rt<P, M, MHD_EL_BS, false>), g, dim3(MHD_EL_BS), 0, s, A, dboff, nr)
+      DISPATCH_PM(p, m, F);
+#undef F
+      break;
+    }
+    case RT_GATHER: {
+      const gather_args* A = (const gather_args*)dargs;
+#define F(M)                                                                                                        \
+  if (r2) hipLaunchKernelGGL((k_gather_rt<M, true>), g, dim3(256), 0, s, A, dboff, nr);                             \
+  else hipLaunchKernelGGL((k_gather_rt<M, false>), g, dim3(256), 0, s, A, dboff, nr)
+      DISPATCH_M(m, F);
+#undef F
+      break;
+    }
+    case RT_MAG_UPDATE: {
+      const mag_update_args* A = (const mag_update_args*)dargs;
+      if (mode != 1) return -2;  // plans hold SSP stages only
+#define F(P, M)                                                                                                     \
+  if (r2) hipLaunchKernelGGL((k_mag_update_rt<P, M, 1, MHD_MU_BS, true>), g, dim3(MHD_MU_BS), 0, s, A, dboff, nr);  \
+  else hipLaunchKernelGGL((k_mag_update_rt<P, M, 1, MHD_MU_BS, false>), g, dim3(MHD_MU_BS), 0, s, A, dboff, nr)
+      DISPATCH_PM(p, m, F);
+#undef F
+      break;
+    }
+    case RT_VEL_PREP: {
+      const vel_prep_args* A = (const vel_prep_args*)dargs;
+#define F(P) hipLaunchKernelGGL((k_vel_prep_rt<P>), g, dim3(64), 0, s, A, dboff, nr)
+      switch (h.key) { case 1: F(1); break; case 2: F(2); break; case 3: F(3); break; case 4: F(4); break;
+                       case 5: F(5); break; case 6: F(6); break; default: return -4; }
+#undef F
+      break;
+    }
+    case RT_VEL_SENSOR: {
+      const vel_sensor_args* A = (const vel_sensor_args*)dargs;
+#define F(P, M)                                                                                                     \
+  if (r2) hipLaunchKernelGGL((k_vel_sensor_rt<P, M, true>), g, dim3(256), 0, s, A, dboff, nr);                      \
+  else hipLaunchKernelGGL((k_vel_sensor_rt<P, M, false>), g, dim3(256), 0, s, A, dboff, nr)
+      DISPATCH_PM(p, m, F);
+#undef F
+      break;
+    }
+    case RT_VEL_PROJ: {
+      const vel_proj_args* A = (const vel_proj_args*)dargs;
+#define F(P)                                                                                                        \
+  if (r2) hipLaunchKernelGGL((k_vel_proj_rt<P, MHD_VP_BS, true>), g, dim3(MHD_VP_BS), 0, s, A, dboff, nr);          \
+  else hipLaunchKernelGGL((k_vel_proj_rt<P, MHD_VP_BS, false>), g, dim3(MHD_VP_BS), 0, s, A, dboff, nr)
+      switch (p) { case 1: F(1); break; case 2: F(2); break; case 3: F(3); break; case 4: F(4); break;
+                   case 5: F(5); break; case 6: F(6); break; default: return -4; }
+#undef F
+      break;
+    }
+    case RT_B_STATS: {
+      const B_stats_args* A = (const B_stats_args*)dargs;
+#define F(M) hipLaunchKernelGGL((k_B_stats_rt<M>), g, dim3(256), 0, s, A, dboff, nr)
+      DISPATCH_M(h.key, F);
+#undef F
+      break;
+    }
+    case RT_AR_TRACES: {
+      const ar_traces_args* A = (const ar_traces_args*)dargs;
+#define F(P, M) hipLaunchKernelGGL((k_ar_traces_rt<P, M>), g, dim3(256), 0, s, A, dboff, nr)
+      DISPATCH_PM(p, m, F);
+#undef F
+      break;
+    }
+    case RT_AR_ETA: {
+      const ar_eta_args* A = (const ar_eta_args*)dargs;
+#define F(P, M) hipLaunchKernelGGL((k_ar_eta_rt<P, M>), g, dim3(256), 0, s, A, dboff, nr)
+      DISPATCH_PM(p, m, F);
+#undef F
+      break;
+    }
+    case RT_TO_PRIM:
+      hipLaunchKernelGGL(k_to_primitive_rt, g, dim3(256), 0, s, (const prim_args*)dargs, dboff, nr);
+      break;
+    case RT_TO_CONS:
+      hipLaunchKernelGGL(k_to_conservative_rt, g, dim3(256), 0, s, (const prim_args*)dargs, dboff, nr);
+      break;
+    default:
+      return 1;  // not a kind of this file
+  }
+  return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 // ---------------------------------------------------------------------------------------------

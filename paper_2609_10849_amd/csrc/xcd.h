@@ -12,3 +12,17 @@ __device__ __forceinline__ long xcd_block() {
   const long q = nb >> 3, r = nb & 7, x = b & 7;
   return x * q + (x < r ? x : r) + (b >> 3);
 }
+
+// Run-table launches: one launch covers several independent runs, whose blocks are consecutive
+// ranges; boff[r] is the first block of run r and boff[nr] the grid size.  Returns the run of the
+// calling block (the same for all its threads) by bisection.
+__device__ __forceinline__ int rt_run(const int* __restrict__ boff, int nr) {
+  const int b = (int)blockIdx.x;
+  int lo = 0, hi = nr;  // boff[lo] <= b < boff[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (boff[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}

@@ -65,7 +65,18 @@ void emu_launch(F f, dim3 g, dim3 b, A... args) {
         for (auto& x : th) x.join();
       }
 }
-#define hipLaunchKernelGGL(F, G, B, S, STREAM, ...) emu_launch(F, dim3(G), dim3(B), __VA_ARGS__)
+// Stream capture: while a capture is open, launches are recorded (with their arguments) instead of
+// run; a graph is that list, and launching it runs the launches in order.  Only kernel launches may
+// be captured (copies and memsets made while capturing are reported by the end of the capture).
+struct EmuGraph { std::vector<std::function<void()>> ops; };
+inline thread_local EmuGraph* emu_capture = nullptr;
+inline thread_local bool emu_capture_bad = false;
+template <class F, class... A>
+void emu_launch_or_record(F f, dim3 g, dim3 b, A... args) {
+  if (emu_capture) emu_capture->ops.push_back([=] { emu_launch(f, g, b, args...); });
+  else emu_launch(f, g, b, args...);
+}
+#define hipLaunchKernelGGL(F, G, B, S, STREAM, ...) emu_launch_or_record(F, dim3(G), dim3(B), __VA_ARGS__)
 
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorOutOfMemory = 2, hipErrorInvalidValue = 1 };
@@ -83,10 +94,10 @@ inline hipError_t hipMalloc(void** p, size_t n) { *p = std::calloc(1, n ? n : 8)
 inline hipError_t hipHostMalloc(void** p, size_t n, unsigned = 0) { return hipMalloc(p, n); }
 inline hipError_t hipFree(void* p) { std::free(p); return hipSuccess; }
 inline hipError_t hipHostFree(void* p) { std::free(p); return hipSuccess; }
-inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { std::memmove(d, s, n); return hipSuccess; }
-inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t = nullptr) { std::memmove(d, s, n); return hipSuccess; }
-inline hipError_t hipMemset(void* d, int v, size_t n) { std::memset(d, v, n); return hipSuccess; }
-inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t = nullptr) { std::memset(d, v, n); return hipSuccess; }
+inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { if (emu_capture) emu_capture_bad = true; std::memmove(d, s, n); return hipSuccess; }
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t = nullptr) { if (emu_capture) emu_capture_bad = true; std::memmove(d, s, n); return hipSuccess; }
+inline hipError_t hipMemset(void* d, int v, size_t n) { if (emu_capture) emu_capture_bad = true; std::memset(d, v, n); return hipSuccess; }
+inline hipError_t hipMemsetAsync(void* d, int v, size_t n, hipStream_t = nullptr) { if (emu_capture) emu_capture_bad = true; std::memset(d, v, n); return hipSuccess; }
 enum { hipStreamNonBlocking = 1, hipEventDisableTiming = 2 };
 inline hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = nullptr; return hipSuccess; }
 inline hipError_t hipStreamDestroy(hipStream_t) { return hipSuccess; }
@@ -97,15 +108,33 @@ inline hipError_t hipEventDestroy(hipEvent_t e) { std::free(e); return hipSucces
 inline hipError_t hipEventRecord(hipEvent_t, hipStream_t = nullptr) { return hipSuccess; }
 inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 inline hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 0.f; return hipSuccess; }
-// Graph capture is not emulated: beginning a capture reports "not supported", so the captured batch
-// step fails cleanly here and only the uncaptured paths (streams, sequential) run on the CPU.
-typedef void* hipGraph_t;
-typedef void* hipGraphExec_t;
-enum hipStreamCaptureMode { hipStreamCaptureModeRelaxed };
-enum { hipErrorNotSupported = 801 };
-inline hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipErrorNotSupported; }
-inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) { *g = nullptr; return hipErrorNotSupported; }
-inline hipError_t hipGraphInstantiate(hipGraphExec_t*, hipGraph_t, void*, void*, size_t) { return hipErrorNotSupported; }
-inline hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipErrorNotSupported; }
-inline hipError_t hipGraphExecDestroy(hipGraphExec_t) { return hipSuccess; }
-inline hipError_t hipGraphDestroy(hipGraph_t) { return hipSuccess; }
+// Graph capture on one stream (see emu_launch_or_record); a second open capture, or a copy or
+// memset inside one, makes the end of the capture fail.
+typedef EmuGraph* hipGraph_t;
+typedef EmuGraph* hipGraphExec_t;
+enum hipStreamCaptureMode { hipStreamCaptureModeGlobal, hipStreamCaptureModeThreadLocal, hipStreamCaptureModeRelaxed };
+enum { hipErrorNotSupported = 801, hipErrorStreamCaptureInvalidated = 901 };
+inline hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) {
+  if (emu_capture) return hipErrorNotSupported;
+  emu_capture = new EmuGraph();
+  emu_capture_bad = false;
+  return hipSuccess;
+}
+inline hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t* g) {
+  if (!emu_capture) { *g = nullptr; return hipErrorInvalidValue; }
+  EmuGraph* c = emu_capture;
+  emu_capture = nullptr;
+  if (emu_capture_bad) { delete c; *g = nullptr; return hipErrorStreamCaptureInvalidated; }
+  *g = c;
+  return hipSuccess;
+}
+inline hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, void*, void*, size_t) {
+  *e = new EmuGraph(*g);
+  return hipSuccess;
+}
+inline hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+  for (auto& op : e->ops) op();
+  return hipSuccess;
+}
+inline hipError_t hipGraphExecDestroy(hipGraphExec_t e) { delete e; return hipSuccess; }
+inline hipError_t hipGraphDestroy(hipGraph_t g) { delete g; return hipSuccess; }

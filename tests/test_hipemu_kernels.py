@@ -311,7 +311,6 @@ def test_emulated_batch_streams_equals_individual(emu):
     dts = (ctypes.c_double * len(runs))(*[1e-3, 2e-3, 1.5e-3])
     reps = (pk.Report * len(runs))()
     assert lib.mhd25_batch_strang_step_streams(b, arr(0), arr(1), arr(2), arr(3), dts, reps) == 0
-    assert lib.mhd25_batch_strang_step(b, arr(0), arr(1), arr(2), arr(3), dts, reps) < 0  # no capture here
     lib.mhd25_batch_destroy(b)
     for (L, U, Bx, By, Bz), got, dt in zip(runs, bat, dts):
         h = context(lib, pk, L, opts)
@@ -406,3 +405,63 @@ def test_emulated_rhs_magnetic_noalloc(emu):
     assert b"limit" in lib.mhd25_last_error(h)
     lib.mhd25_destroy(h)
 
+
+def test_emulated_strang_step_magnetic_outer(emu):
+    """The magnetic-outer composition M(dt/2) H(dt) M(dt/2) (strang_order = 1) with every
+    stabilisation on equals the oracle's to 1e-12."""
+    lib, pk = emu
+    L, U, Bx, By, Bz = W.orszag_tang_scaled(5, 4, 3, 2)
+    h = context(lib, pk, L, pk.Options.full(strang_order=1))
+    st = [np.ascontiguousarray(a.copy()) for a in (U, Bx, By, Bz)]
+    dt = ctypes.c_double()
+    assert lib.mhd25_cfl_dt(h, *[ptr(a) for a in st], 0.3, ctypes.byref(dt)) == 0
+    rep = pk.Report()
+    assert lib.mhd25_strang_step(h, *[ptr(a) for a in st], dt.value, ctypes.byref(rep)) == 0
+    assert rep.substeps_accepted == 1
+    lib.mhd25_destroy(h)
+    ref = O.strang_step(omesh(L), O.Options.full(strang_order=1), U, Bx, By, Bz, dt.value)
+    assert ref[4]["accepted"] == 1
+    for a, r in zip(st, ref[:4]):
+        if np.abs(r).max() > 0:
+            assert np.abs(a - r).max() <= 1e-12 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("graph", [1])
+def test_emulated_batch_run_table_equals_individual(emu, graph):
+    """The run-table batch step (launches covering every run of a degree group; with graph = 1
+    replayed from a captured graph of those launches) equals, bit for bit, every run stepped alone,
+    on two steps; the plan is rebuilt when a step changes; a member whose hydro substep needs a
+    halving is redone individually."""
+    lib, pk = emu
+    specs = [(3, 3, 2, 1, 0.3), (3, 2, 3, 2, 0.5), (2, 3, 2, 2, 0.6)]
+    runs = [W.isentropic_vortex(nx, ny, p, m, kappa=k, background=(0.3, -0.2)) for nx, ny, p, m, k in specs]
+    Lb, Ub, Bxb, Byb, Bzb = W.blast(6, 6, 2, 1, p_in=1000.0)
+    runs.append((Lb, Ub, Bxb, Byb, Bzb))
+    opts = pk.Options.full()
+    descs = (pk.MeshDesc * len(runs))(*[pk.MeshDesc(L.nx, L.ny, L.x0, L.x1, L.y0, L.y1, L.p, L.m, L.gamma)
+                                        for L, *_ in runs])
+    b = ctypes.c_void_p()
+    assert lib.mhd25_batch_create(descs, len(runs), ctypes.byref(opts), None, ctypes.byref(b)) == 0
+    assert lib.mhd25_batch_graph(b, graph) == 0
+    bat = [[np.ascontiguousarray(a.copy()) for a in r[1:]] for r in runs]
+    single = [[np.ascontiguousarray(a.copy()) for a in r[1:]] for r in runs]
+    arr = lambda i: (ctypes.c_void_p * len(runs))(*[x[i].ctypes.data for x in bat])
+    steps = [[1e-3, 2e-3, 1.5e-3, 1.5e-2], [1e-3, 2e-3, 1.2e-3, 1.5e-2]]
+    halved = False
+    for dtl in steps:
+        dts = (ctypes.c_double * len(runs))(*dtl)
+        reps = (pk.Report * len(runs))()
+        assert lib.mhd25_batch_strang_step(b, arr(0), arr(1), arr(2), arr(3), dts, reps) == 0
+        for (L, *_), st, dt, rep in zip(runs, single, dtl, reps):
+            h = context(lib, pk, L, opts)
+            r1 = pk.Report()
+            assert lib.mhd25_strang_step(h, *[ptr(a) for a in st], dt, ctypes.byref(r1)) == 0
+            lib.mhd25_destroy(h)
+            assert rep.substeps_attempted == r1.substeps_attempted and rep.n_p_limited == r1.n_p_limited
+            assert rep.eta_max == r1.eta_max
+            halved = halved or r1.substeps_attempted > r1.substeps_accepted
+        for got, st in zip(bat, single):
+            for a, r in zip(got, st):
+                assert (a == r).all()
+    assert halved  # the blast member needed a halving and took the individual redo
+    lib.mhd25_batch_destroy(b)
