@@ -195,10 +195,12 @@ __device__ __forceinline__ void E_loads_body(const double* __restrict__ u, const
   using C = MC<P, M, BS>;
   constexpr int NP = C::NP, NN = C::NN, A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB,
                 NT = C::NT;
+  // J on the auxiliary grids (sjx, sjy, sjz), and later the x sums of the eta term (sxj)
+  constexpr int NJ = 2 * AB + AA, NXJ = NP * (B + 2 * A), NJB = NJ > NXJ ? NJ : NXJ;
   __shared__ double su[EB][3][NN], sbx[EB][AB], sby[EB][AB], sbz[EB][BB];
-  __shared__ double sjx[EB][AB], sjy[EB][AB], sjz[EB][AA];
+  __shared__ double sjb[EB][NJB];
   // the eta-weighted J values at the GLL_p nodes reuse su once the x interpolation has read it
-  // (with 96 VGPRs and 14.6 KB of LDS per 128-thread block at N = 4: 5 waves per SIMD)
+  // (with 96 VGPRs and 14.8 KB of LDS per 128-thread block at N = 4: 5 waves per SIMD)
   double(*const swj)[3][NN] = su;
   __shared__ double sux[EB][3][NP][A + B];  // velocity interpolated in x: [d][qj][W nodes | Gauss nodes]
   __shared__ double tGP[NP][B], tWP[NP][A], tPW[A][NP], tPG[B][NP], tGW[A][B], tVG[B][B], tVW[A][B];
@@ -206,6 +208,9 @@ __device__ __forceinline__ void E_loads_body(const double* __restrict__ u, const
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
   const long e = blk * EB + el;
   const bool act = el < EB && e < mp.K;
+  double* const sjx = sjb[el < EB ? el : 0];  // [j < A][i < B]
+  double* const sjy = sjx + AB;                // [j < B][i < A]
+  double* const sjz = sjx + 2 * AB;            // [j < A][i < A]
   long ex, ey;
   elem_xy(mp, act ? e : 0, ex, ey);
   const long KN = mp.K * NN;
@@ -232,10 +237,10 @@ __device__ __forceinline__ void E_loads_body(const double* __restrict__ u, const
     if (et != 0.0) {
       if constexpr (!R2)
         for (int k = t; k < AB; k += NT) {
-          sjx[el][k] = Jx[gix(mp, B, ex, ey, k % B, k / B)];
-          sjy[el][k] = Jy[gix(mp, B, ex, ey, k % A, k / A)];
+          sjx[k] = Jx[gix(mp, B, ex, ey, k % B, k / B)];
+          sjy[k] = Jy[gix(mp, B, ex, ey, k % A, k / A)];
         }
-      for (int k = t; k < AA; k += NT) sjz[el][k] = Jz[gix(mp, B, ex, ey, k % A, k / A)];
+      for (int k = t; k < AA; k += NT) sjz[k] = Jz[gix(mp, B, ex, ey, k % A, k / A)];
     }
   }
   __syncthreads();
@@ -262,14 +267,14 @@ __device__ __forceinline__ void E_loads_body(const double* __restrict__ u, const
       for (int j = 0; j < A; ++j) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < B; ++i) s += tGP[qi][i] * sjx[el][j * B + i];
+        for (int i = 0; i < B; ++i) s += tGP[qi][i] * sjx[j * B + i];
         jx += tWP[qj][j] * s;
       }
 #pragma unroll
       for (int j = 0; j < B; ++j) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < A; ++i) s += tWP[qi][i] * sjy[el][j * A + i];
+        for (int i = 0; i < A; ++i) s += tWP[qi][i] * sjy[j * A + i];
         jy += tGP[qj][j] * s;
       }
     }
@@ -277,14 +282,32 @@ __device__ __forceinline__ void E_loads_body(const double* __restrict__ u, const
     for (int j = 0; j < A; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sjz[el][j * A + i];
+      for (int i = 0; i < A; ++i) s += tWP[qi][i] * sjz[j * A + i];
       jz += tWP[qj][j] * s;
     }
     const double w = et * mp.J * twp[qi] * twp[qj];
     jw[0] = w * jx; jw[1] = w * jy; jw[2] = w * jz;
   }
-  __syncthreads();  // every lane has finished reading su
+  __syncthreads();  // every lane has finished reading su and the J grids
   if (jnode) { swj[el][0][t] = jw[0]; swj[el][1][t] = jw[1]; swj[el][2][t] = jw[2]; }
+  __syncthreads();
+  // the eta term sum_q M_q (eta J)(x_q) phi_a(x_q) by sum factorisation: x sums first, into the
+  // J-grid space, xs0[qj][i < B] (G in x, for E_x), xs1[qj][i < A] and xs2[qj][i < A] (W in x)
+  double* const xs0 = sjx;
+  double* const xs1 = xs0 + NP * B;
+  double* const xs2 = xs1 + NP * A;
+  if (act && et != 0.0) {
+    for (int tk = t; tk < NXJ; tk += NT) {
+      int c, qj, i;
+      if (tk < NP * B) { c = 0; qj = tk / B; i = tk - qj * B; }
+      else { const int r = (tk - NP * B) % (NP * A); c = 1 + (tk - NP * B) / (NP * A); qj = r / A; i = r - qj * A; }
+      if (R2 && c < 2) continue;
+      double v = 0.0;
+#pragma unroll
+      for (int qi = 0; qi < NP; ++qi) v += (c == 0 ? tGP[qi][i] : tWP[qi][i]) * swj[el][c][qj * NP + qi];
+      xs0[tk] = v;
+    }
+  }
   __syncthreads();
   if (!act) return;
   // second half: interpolate in y (Iy = I_P_W or I_P_G row aj; x column xc of sux)
@@ -294,12 +317,11 @@ __device__ __forceinline__ void E_loads_body(const double* __restrict__ u, const
     for (int qj = 0; qj < NP; ++qj) v += Iy[qj] * sux[el][d][qj][xc];
     return v;
   };
-  auto eta_term = [&](int c, const double (*Px)[MHD_MAXN], int ai, const double (*Py)[MHD_MAXN], int aj) {
+  // y sums of the eta term: xs[qj * nx + ai] against the y basis column aj
+  auto eta_term = [&](const double* xs, int nx, int ai, bool ygauss, int aj) {
     double v = 0.0;
 #pragma unroll
-    for (int qj = 0; qj < NP; ++qj)
-#pragma unroll
-      for (int qi = 0; qi < NP; ++qi) v += swj[el][c][qj * NP + qi] * (Px[qi][ai] * Py[qj][aj]);
+    for (int qj = 0; qj < NP; ++qj) v += (ygauss ? tGP[qj][aj] : tWP[qj][aj]) * xs[qj * nx + ai];
     return v;
   };
   if (t < AA) {  // W node (xw[i], xw[j]): z-component
@@ -312,7 +334,7 @@ __device__ __forceinline__ void E_loads_body(const double* __restrict__ u, const
       byv += tGW[i][k] * sby[el][j * B + k];
     }
     double s = mp.J * tww[i] * tww[j] * (-(ux * byv - uy * bxv));
-    if (et != 0.0) s += eta_term(2, T->I_W_P, i, T->I_W_P, j);
+    if (et != 0.0) s += eta_term(xs2, A, i, false, j);
     Lz[e * AA + t] = s;
   }
   if (!R2 && t < AB) {
@@ -329,7 +351,7 @@ __device__ __forceinline__ void E_loads_body(const double* __restrict__ u, const
         bzv += tVW[j][jj] * s;
       }
       double s = mp.J * twg[i] * tww[j] * (-(uy * bzv - uz * byv));
-      if (et != 0.0) s += eta_term(0, T->I_G_P, i, T->I_W_P, j);
+      if (et != 0.0) s += eta_term(xs0, B, i, false, j);
       Lx[e * AB + t] = s;
     }
     {  // N_y node (xw[i], xg[j]): y-component; B_x lives on these nodes
@@ -345,7 +367,7 @@ __device__ __forceinline__ void E_loads_body(const double* __restrict__ u, const
         bzv += tVG[j][jj] * s;
       }
       double s = mp.J * tww[i] * twg[j] * (-(uz * bxv - ux * bzv));
-      if (et != 0.0) s += eta_term(1, T->I_W_P, i, T->I_G_P, j);
+      if (et != 0.0) s += eta_term(xs1, A, i, true, j);
       Ly[e * AB + t] = s;
     }
   }
@@ -1271,21 +1293,23 @@ __device__ __forceinline__ void ar_traces_body(const double* __restrict__ rho, c
   double* o = tr + (act ? e : 0) * NT;
   if (act) {
     double bxv = 0.0, byv = 0.0, bzv = 0.0;
-#pragma unroll
+    // the outer loops stay rolled: unrolled, the scheduler hoists every LDS operand of the three
+    // evaluations at once (170 VGPRs, 2 waves per SIMD)
+#pragma unroll 1
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
 #pragma unroll
       for (int i = 0; i < A; ++i) s += tWP[qi][i] * sbx[el][j * A + i];
       bxv += tGP[qj][j] * s;
     }
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < A; ++j) {
       double s = 0.0;
 #pragma unroll
       for (int i = 0; i < B; ++i) s += tGP[qi][i] * sby[el][j * B + i];
       byv += tWP[qj][j] * s;
     }
-#pragma unroll
+#pragma unroll 1
     for (int j = 0; j < B; ++j) {
       double s = 0.0;
 #pragma unroll

@@ -54,15 +54,22 @@ def test_traffic_rate():
 
 def test_counter_records_apply_only_to_their_workload():
     import bench
-    for kind in ("stage", "oe_pp"):
+    for prefix, fname in (("k_hydro_stage<", "hydro.hip"), ("k_hydro_oe_pp<", "hydro.hip"), ("k_vel_proj<", "magnetic.hip")):
         # a record is never attached to another mesh size or degree
-        assert bench.traffic_per_launch(kind, 64 * 64, 4) is None
-        assert bench.traffic_per_launch(kind, 1024 * 1024, 3) is None
-        assert bench.valu_per_launch(kind, 64 * 64, 4) is None
+        assert bench.counter_record(prefix, fname, 64 * 64, 4) is None
+        assert bench.counter_record(prefix, fname, 1024 * 1024, 3) is None
 
 
 def test_kernel_hashes():
     import bench
-    h, g = bench.kernel_sha("stage"), bench.kernel_sha("oe_pp")
+    h, g = bench.source_sha("hydro.hip"), bench.source_sha("magnetic.hip")
     assert len(h) == 16 and int(h, 16) >= 0 and len(g) == 16 and g != h
-    assert bench.kernel_sha() == h
+    assert bench.source_sha("hydro.hip") == h
+
+
+def test_velocity_oe_bytes():
+    import bench
+    # N = 4: the basis table holds 25 rows of 25 values, each row padded to 26
+    t = {r[2]: r for r in bench.kernel_table(4, 3)}
+    assert t["k_vel_prep<"][4] == 25 * 8 + 25 * 26 * 8
+    assert t["k_vel_proj<"][4] == 25 * 26 * 8 + 3 * 25 * 8 + 2 * 25 * 8 + 5 * 8 + 4 * 25 * 8
