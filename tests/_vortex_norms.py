@@ -70,3 +70,43 @@ def vortex_errors(L, U, Bx, By, Bz, t, box=5.0):
     bz = np.einsum("ki,eji,lj->elk", Iv, patch(Bz, m + 1, m + 1), Iv)
     err["B"] = math.sqrt(sum((W2 * (b - B_e[d]) ** 2).sum() for d, b in enumerate((bx, by, bz))))
     return err
+
+
+def exact_EJ(x, y, t):
+    """E_z and J_z of the advected vortex: u = (1, 1, 0) + B, so E_z = -(u x B)_z = B_x - B_y =
+    -g (dx + dy) / (2 pi), and J_z = d_x B_y - d_y B_x = g (2 - r^2) / (2 pi)."""
+    dx = (x - t) - 20.0 * np.round((x - t) / 20.0)
+    dy = (y - t) - 20.0 * np.round((y - t) / 20.0)
+    r2 = dx * dx + dy * dy
+    g = np.exp(0.5 * (1.0 - r2))
+    return -g * (dx + dy) / (2 * math.pi), g * (2.0 - r2) / (2 * math.pi)
+
+
+def EJ_errors(L, JE, t, box=5.0):
+    """L2(Omega_e) errors of the reconstructed E_z and J_z (continuous GLL_{m+1} x GLL_{m+1} fields,
+    grids 5 and 2 of JE = (J_x, J_y, J_z, E_x, E_y, E_z)) against the exact vortex fields, with the
+    same per-element Gauss rule as vortex_errors."""
+    p, m = L.p, L.m
+    zq, wq = np.polynomial.legendre.leggauss(p + 3)
+    Iw = lagrange_matrix(gll_nodes(m + 1), zq)
+    W2 = np.outer(wq, wq) * L.hx * L.hy / 4.0
+    EX, EY = np.meshgrid(np.arange(L.nx), np.arange(L.ny), indexing="xy")
+    EX = EX.ravel(); EY = EY.ravel()
+    x0 = L.x0 + EX * L.hx; y0 = L.y0 + EY * L.hy
+    inside = (x0 >= -box - 1e-12) & (x0 + L.hx <= box + 1e-12) & (y0 >= -box - 1e-12) & (y0 + L.hy <= box + 1e-12)
+    idx = np.nonzero(inside)[0]
+    X = x0[idx, None, None] + 0.5 * (zq[None, None, :] + 1.0) * L.hx
+    Y = y0[idx, None, None] + 0.5 * (zq[None, :, None] + 1.0) * L.hy
+    X = np.broadcast_to(X, (len(idx), len(zq), len(zq))); Y = np.broadcast_to(Y, X.shape)
+    Ez_e, Jz_e = exact_EJ(X, Y, t)
+    M1 = m + 1
+
+    def patch(G):
+        ny_t, nx_t = G.shape
+        rows = (EY[idx, None] * M1 + np.arange(m + 2)[None, :]) % ny_t
+        cols = (EX[idx, None] * M1 + np.arange(m + 2)[None, :]) % nx_t
+        return G[rows[:, :, None], cols[:, None, :]]
+
+    at_q = lambda G: np.einsum("ki,eji,lj->elk", Iw, patch(G), Iw)
+    return {"Ez": math.sqrt((W2 * (at_q(JE[5]) - Ez_e) ** 2).sum()),
+            "Jz": math.sqrt((W2 * (at_q(JE[2]) - Jz_e) ** 2).sum())}

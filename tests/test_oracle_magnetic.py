@@ -307,3 +307,24 @@ def test_ar_uniform_field_contributes_nothing_on_large_mesh():
     u = u + 0.1  # nonzero speeds, so a spurious sensor response would show in eta
     eta = O.ar_eta(M, O.Options(ar=1), rho, u, Bx, By, Bz)
     assert (eta == 0.0).all(), eta.max()
+
+
+@pytest.mark.parametrize("pmn", [(1, 0, 4), (2, 1, 5), (3, 3, 4)])
+def test_vectorised_alfven_norms_equal_per_element_norms(pmn):
+    """The vectorised Alfven-wave norms that the GPU table tests use (tests/_alfven_norms.py) equal
+    the per-element evaluation above on an oracle state after three magnetic substeps."""
+    from tests._alfven_norms import alfven_errors
+    p, m, n = pmn
+    L, U, Bx, By, Bz, _ = W.alfven_wave(n, n, p, m)
+    M = mesh_of(L)
+    rho, e, u = O.to_primitive(M, U)
+    o = O.Options()
+    for _ in range(3):
+        e, u, Bx, By, Bz, _ = O.step_magnetic(M, o, rho, e, u, Bx, By, Bz, 0.01)
+    _, _, _, _, _, f_end = W.alfven_wave(n, n, p, m, t=0.03)
+    f_end.t = 0.03
+    JE = O.reconstruct_JE(M, u, Bx, By, Bz)
+    a = l2_errors(L, M, u, Bx, By, Bz, JE, f_end)
+    b = alfven_errors(L, u, Bx, By, Bz, JE, 0.03)
+    for x, y in zip(a, b):
+        assert abs(x / y - 1.0) < 1e-12, (a, b)
