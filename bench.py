@@ -305,6 +305,60 @@ def adjoint_ratio():
             "workload": "noisy isentropic vortex, 128x128 elements, N=3, k=2"}
 
 
+def adjoint_ratio_full(S, U, Bx, By, Bz, reps=10):
+    """The same ratios on the timed workload itself (the blast-like state at 1024 x 1024, N = 4,
+    k = 3, where neither operator is launch-bound); cotangents N(0,1) from torch's generator
+    (seed 7), eta U[0, 1e-3]."""
+    import torch
+
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    cot = torch.randn(U.shape, dtype=U.dtype, device="cuda", generator=gen)
+    out, gb = torch.empty_like(U), torch.empty_like(U)
+    tf = _event_ms(lambda: S.rhs_hydro(U, out), reps)
+    tb = _event_ms(lambda: S.rhs_hydro_vjp(U, cot, gb), reps)
+    del cot, out, gb
+    rho, e, u = S.to_primitive(U)
+    eta = torch.rand(S.K, dtype=U.dtype, device="cuda", generator=gen) * 1e-3
+    cots = [torch.randn(a.shape, dtype=U.dtype, device="cuda", generator=gen) for a in (e, u, Bx, By, Bz)]
+    mf = _event_ms(lambda: S.rhs_magnetic(rho, u, Bx, By, Bz, eta), reps)
+    mb = _event_ms(lambda: S.rhs_magnetic_vjp(rho, u, Bx, By, Bz, eta, *cots), reps)
+    return {"hydro": tb / tf, "magnetic": mb / mf, "hydro_fwd_ms": tf, "hydro_vjp_ms": tb,
+            "magnetic_fwd_ms": mf, "magnetic_vjp_ms": mb, "workload": "the timed blast-like state"}
+
+
+def rejection_cost(S, U, Bx, By, Bz):
+    """Cost of reject-and-halve on the timed workload: one hydro substep of the step's first half
+    (tau = dt/2, dt from CFL 0.3) from the current state, at tau and then at 2^k tau (k = 4, 5, ...
+    up to 12) until the positivity check refuses an attempt and the substep is bisected; each run
+    starts from a copy of the state.  Reports the attempts, the bisection depth and the time per
+    attempt of the plain and of the bisected substep."""
+    import torch
+
+    dt = S.cfl_dt(U, Bx, By, Bz, 0.3)
+    W = torch.empty_like(U)
+
+    def run(m):
+        W.copy_(U)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        r, rep = S.hydro_substep(W, m * dt / 2)
+        b.record()
+        torch.cuda.synchronize()
+        return {"multiple": m, "status": r, "ms": a.elapsed_time(b), "attempted": rep["substeps_attempted"],
+                "accepted": rep["substeps_accepted"], "max_depth": rep["max_depth"]}
+
+    plain = run(1)
+    out = {"plain": plain, "ms_per_attempt_plain": plain["ms"] / max(plain["attempted"], 1), "bisected": None}
+    for k in range(4, 13):
+        o = run(2 ** k)
+        if o["attempted"] > o["accepted"] or o["status"] != 0:
+            out["bisected"] = o
+            out["ms_per_attempt_bisected"] = o["ms"] / max(o["attempted"], 1)
+            break
+    return out
+
+
 def batched_speedup(steps=50, only=None):
     """Ensemble of 64 uneven runs (n in {32..192}, N in {2,3,4}, k = N-1, vortex amplitude and
     field drawn from PCG64 seed 0; full stabilisation; per-run dt from CFL 0.3 at the start):
@@ -447,8 +501,7 @@ def main():
         print(json.dumps({k: v["bytes_per_launch"] for k, v in out["kernels"].items()}))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md, "
-              "'How the path would shard')", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -542,6 +595,8 @@ def main():
         out["hydro_only"] = hydro_only(S, g, steps=min(args.steps, 10))
         out["reduced_2d2v"] = reduced_2d2v(S, g, steps=min(args.steps, 10))
         out["adjoint_cost_ratio"] = adjoint_ratio()
+        out["adjoint_cost_ratio_full_size"] = adjoint_ratio_full(S, *g)
+        out["rejection_cost"] = rejection_cost(S, *g)
         out["batched_speedup"] = batched_speedup(steps=min(args.steps, 20))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

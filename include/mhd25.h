@@ -240,10 +240,11 @@ void mhd25_batch_destroy(mhd25_batch* b);
 const char* mhd25_batch_last_error(const mhd25_batch* b);
 /* One Strang step of every run (extension: batched ensembles) by run-table launches: every launch
  * of the step covers all runs of one degree group, its blocks split into consecutive per-run
- * ranges, so one step issues about 150 launches for 64 runs.  The per-run arguments are uploaded
- * once per set of pointers and steps (a change of either rebuilds the plan: one host-to-device
- * copy).  With mhd25_batch_graph(b, 1) the step replays a HIP graph of those launches captured on
- * the batch's stream.  U, Bx, By, Bz: host arrays of nruns device pointers; dt: host [nruns]; rep:
+ * ranges, so one step issues about 150 launches for 64 runs; each degree group's launches go to a
+ * branch stream of its own (between fork and join events on hip_stream), so the groups overlap.
+ * The per-run arguments are uploaded once per set of pointers and steps (a change of either
+ * rebuilds the plan: one host-to-device copy).  With mhd25_batch_graph(b, 1) the step instead
+ * replays a HIP graph of those launches, captured in order on one stream of the batch.  U, Bx, By, Bz: host arrays of nruns device pointers; dt: host [nruns]; rep:
  * host [nruns] (may be NULL).  Runs whose hydro substep needs a halving, or whose input is
  * inadmissible, are restored and re-done individually with mhd25_strang_step.  Results equal
  * mhd25_strang_step of each run bit for bit.  Returns 0, or the first nonzero run status (1, 2, <0). */

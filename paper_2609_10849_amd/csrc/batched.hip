@@ -7,9 +7,10 @@
 // every launch of the step, each run's kernel arguments and block count; the plan then issues one
 // launch per kernel and template instantiation (degree group) whose blocks are split into
 // consecutive per-run ranges (a run table of (run, element tile) work items).  About 150 launches
-// replace about 4 600 for the 64-run ensemble.  The argument tables are uploaded once per set of
-// run pointers and steps, so the plan issues kernels only and can be captured on one stream into a
-// HIP graph (mhd25_batch_graph).  After the step one small copy returns all runs' failure words; a
+// replace about 4 600 for the 64-run ensemble.  The degree groups share no data, so launched
+// directly each group's sequence goes to a branch stream of its own and the groups overlap.  The
+// argument tables are uploaded once per set of run pointers and steps, so the plan issues kernels
+// only and can be captured on one stream into a HIP graph (mhd25_batch_graph).  After the step one small copy returns all runs' failure words; a
 // run that needs a halving (or has an inadmissible input) is restored from its entry snapshot and
 // redone with the ordinary step.
 //
@@ -94,6 +95,7 @@ static int batched_rt_launch(const RtRecord& h, const void* dargs, int nr, hipSt
 // offsets of its argument table and block offsets in the plan's device buffer
 struct PlanLaunch {
   RtRecord hdr;  // kind and key (no arguments)
+  int group;     // degree group of the runs it covers (runs of one degree p)
   int nr;
   long nblocks;
   size_t arg_off, boff_off;
@@ -115,8 +117,9 @@ struct mhd25_batch {
   int* h_fail;
   long long* h_acc;
   double* h_eta;
-  // run-table plan of the last (pointers, dt) set
+  // run-table plan of the last (pointers, dt) set: the launches of degree group 0, then of group 1, ...
   std::vector<PlanLaunch> plan;
+  int ngroups;
   unsigned char* d_plan;
   size_t d_plan_cap;
   bool plan_valid;
@@ -249,16 +252,27 @@ static int build_plan(mhd25_batch* b, double* const* U, double* const* Bx, doubl
     for (size_t i = 0; i < n; ++i)
       if (recs[r][i].kind != recs[0][i].kind) { b->err = "plan: runs record different launch sequences"; return -2; }
   }
-  // one launch per (position, key): runs grouped by template key in order of first appearance
+  // degree groups (runs of one degree p, in order of first appearance): the groups share no data,
+  // so each group's launches form an independent sequence that may run on a stream of its own
+  std::vector<int> degs, grp(b->nruns);
+  for (int r = 0; r < b->nruns; ++r) {
+    auto it = std::find(degs.begin(), degs.end(), b->ctx[r]->p);
+    grp[r] = (int)(it - degs.begin());
+    if (it == degs.end()) degs.push_back(b->ctx[r]->p);
+  }
+  b->ngroups = (int)degs.size();
+  // per group, one launch per (position, key): runs grouped by template key in order of first appearance
   std::vector<unsigned char> host;
   auto align = [&]() { host.resize((host.size() + 15) & ~size_t(15)); };
+  for (int g = 0; g < b->ngroups; ++g)
   for (size_t i = 0; i < n; ++i) {
     std::vector<int> keys;
     for (int r = 0; r < b->nruns; ++r)
-      if (std::find(keys.begin(), keys.end(), recs[r][i].key) == keys.end()) keys.push_back(recs[r][i].key);
+      if (grp[r] == g && std::find(keys.begin(), keys.end(), recs[r][i].key) == keys.end()) keys.push_back(recs[r][i].key);
     for (int key : keys) {
       PlanLaunch L;
       L.hdr.kind = recs[0][i].kind; L.hdr.key = key; L.hdr.blocks = 0;
+      L.group = g;
       std::vector<int> boff(1, 0);
       align();
       L.arg_off = host.size();
@@ -266,7 +280,7 @@ static int build_plan(mhd25_batch* b, double* const* U, double* const* Bx, doubl
       long tot = 0;
       for (int r = 0; r < b->nruns; ++r) {
         const RtRecord& rr = recs[r][i];
-        if (rr.key != key) continue;
+        if (grp[r] != g || rr.key != key) continue;
         host.insert(host.end(), rr.args.begin(), rr.args.end());
         tot += rr.blocks;
         if (tot > (1L << 31) - 1) { b->err = "plan: grid too large"; return -1; }
@@ -313,6 +327,36 @@ static int exec_plan(mhd25_batch* b, hipStream_t s) {
     if (rc) { b->err = "plan: launch of kind " + std::to_string(L.hdr.kind) + " failed"; return rc == 1 ? -2 : rc; }
   }
   return 0;
+}
+
+// issue the plan with each degree group on a branch stream of its own (group g on branch
+// g mod nbranch), between a fork event on the caller's stream and join events that the caller's
+// stream waits on; the joins are recorded even when a launch fails
+static int exec_plan_groups(mhd25_batch* b) {
+  if (b->ngroups <= 1 || b->nbranch <= 1) return exec_plan(b, b->main);
+  const int nb = std::min(b->ngroups, b->nbranch);
+  if (hipEventRecord(b->ev_fork, b->main) != hipSuccess) { b->err = "fork event"; return -2; }
+  for (int k = 0; k < nb; ++k)
+    if (hipStreamWaitEvent(b->br[k], b->ev_fork, 0) != hipSuccess) { b->err = "fork wait"; return -2; }
+  int rc = 0;
+  for (const PlanLaunch& L : b->plan) {
+    if (rc) break;
+    const hipStream_t st = b->br[L.group % nb];
+    const void* da = b->d_plan + L.arg_off;
+    const int* db = reinterpret_cast<const int*>(b->d_plan + L.boff_off);
+    rc = hydro_rt_launch(L.hdr, da, db, L.nr, L.nblocks, st);
+    if (rc == 1) rc = magnetic_rt_launch(L.hdr, da, db, L.nr, L.nblocks, st);
+    if (rc == 1) rc = extra_rt_launch(L.hdr, da, db, L.nr, L.nblocks, st);
+    if (rc == 1) rc = batched_rt_launch(L.hdr, da, L.nr, st);
+    if (rc) { b->err = "plan: launch of kind " + std::to_string(L.hdr.kind) + " failed"; rc = rc == 1 ? -2 : rc; }
+  }
+  for (int k = 0; k < nb; ++k) {
+    if (hipEventRecord(b->ev_join[k], b->br[k]) != hipSuccess || hipStreamWaitEvent(b->main, b->ev_join[k], 0) != hipSuccess) {
+      b->err = "join";
+      if (!rc) rc = -2;
+    }
+  }
+  return rc;
 }
 
 // capture the plan on the batch's own idle stream (one stream, kernel nodes only) and instantiate
@@ -384,6 +428,7 @@ int mhd25_batch_create(const mhd25_mesh_desc* runs, int32_t nruns, const mhd25_o
   b->d_plan = nullptr;
   b->d_plan_cap = 0;
   b->plan_valid = false;
+  b->ngroups = 0;
   b->graph_mode = 0;
   for (int r = 0; r < nruns; ++r) {
     mhd25_ctx* c = nullptr;
@@ -480,7 +525,7 @@ int mhd25_batch_strang_step(mhd25_batch* b, double* const* U, double* const* Bx,
     if (!b->captured) BTRY(capture_plan(b));
     if (hipGraphLaunch(b->exec, b->main) != hipSuccess) { b->err = "graph launch"; return -2; }
   } else {
-    BTRY(exec_plan(b, b->main));
+    BTRY(exec_plan_groups(b));
   }
   return finish_step(b, U, Bx, By, Bz, dt, rep);
 }

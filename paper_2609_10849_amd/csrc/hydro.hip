@@ -383,8 +383,8 @@ struct hydro_stage_args {
 template <int P, int MODE, int BS>
 __global__ __launch_bounds__(BS, P == 4 ? 4 : 1) void k_hydro_stage_rt(const hydro_stage_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const hydro_stage_args a = A[r];
-  hydro_stage_body<P, MODE, BS>(a.Us, a.Un, a.out, a.stats, a.flag, a.T, a.mp, a.ca, a.cb, a.tau, a.iface, (long)blockIdx.x - boff[r]);
+  const hydro_stage_args& a = A[r];
+  hydro_stage_body<P, MODE, BS>(gl(a.Us), gl(a.Un), gl(a.out), gl(a.stats), gl(a.flag), gl(a.T), a.mp, a.ca, a.cb, a.tau, a.iface, (long)blockIdx.x - boff[r]);
 }
 
 template <int P>
@@ -447,6 +447,18 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
   // grid line ln of direction D (D = 0: row, index along x; D = 1: column), position k on it
   auto nodeof = [](int D, int ln, int k) { return D == 0 ? ln * NP + k : k * NP + ln; };
   double U[5], a[5];
+  // the four neighbours' nodes (x minus, x plus, y minus, y plus) are loaded into registers up
+  // front with the element's own, so that their latency overlaps the amplitude and x phases; they
+  // go to LDS when their direction comes
+  double nb[4][5];
+  if (act && do_oe) {
+    const long nbe[4] = {ey * mp.nx + wrap(ex - 1, mp.nx), ey * mp.nx + wrap(ex + 1, mp.nx),
+                         wrap(ey - 1, mp.ny) * mp.nx + ex, wrap(ey + 1, mp.ny) * mp.nx + ex};
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) nb[s][c] = Ust[c * KN + nbe[s] * NN + q];
+  }
   if (act) {
 #pragma unroll
     for (int c = 0; c < 5; ++c) { U[c] = Ust[c * KN + e * NN + q]; su[c][tid] = U[c]; }
@@ -472,15 +484,12 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
 #pragma unroll
     for (int D = 0; D < 2; ++D) {
       // neighbours across the two faces normal to direction D, staged in st rows 0..9
-      // (row c: minus-side neighbour, row 5 + c: plus-side neighbour) with coalesced loads
+      // (row c: minus-side neighbour, row 5 + c: plus-side neighbour)
       if (act) {
-        long em, ep;
-        if (D == 0) { em = ey * mp.nx + wrap(ex - 1, mp.nx); ep = ey * mp.nx + wrap(ex + 1, mp.nx); }
-        else { em = wrap(ey - 1, mp.ny) * mp.nx + ex; ep = wrap(ey + 1, mp.ny) * mp.nx + ex; }
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-          st[c][tid] = Ust[c * KN + em * NN + q];
-          st[5 + c][tid] = Ust[c * KN + ep * NN + q];
+          st[c][tid] = nb[2 * D][c];
+          st[5 + c][tid] = nb[2 * D + 1][c];
         }
       }
       if (D == 1 && act && q < NP) {  // direction-0 sigma: maximum over the components
@@ -732,8 +741,8 @@ struct hydro_oe_pp_args {
 template <int P, int BS>
 __global__ __launch_bounds__(BS) void k_hydro_oe_pp_rt(const hydro_oe_pp_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const hydro_oe_pp_args a = A[r];
-  hydro_oe_pp_body<P, BS>(a.Ust, a.Uout, a.stats, a.lines, a.glob, a.flags, a.counts, a.flag, a.T, a.mp, a.tau, a.sH, a.do_oe, a.do_pp, a.rho_o, a.e_o, a.u_o, (long)blockIdx.x - boff[r]);
+  const hydro_oe_pp_args& a = A[r];
+  hydro_oe_pp_body<P, BS>(gl(a.Ust), gl(a.Uout), gl(a.stats), gl(a.lines), gl(a.glob), gl(a.flags), gl(a.counts), gl(a.flag), gl(a.T), a.mp, a.tau, a.sH, a.do_oe, a.do_pp, gl(a.rho_o), gl(a.e_o), gl(a.u_o), (long)blockIdx.x - boff[r]);
 }
 
 // Connectivity export: nbr[K][4] (left, right, bottom, top neighbour) and the face map
@@ -871,8 +880,8 @@ struct line_reduce_args {
 template <int NC>
 __global__ __launch_bounds__(256) void k_line_reduce_rt(const line_reduce_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const line_reduce_args a = A[r];
-  line_reduce_body<NC>(a.stats, a.lines, a.nx, a.ny, a.flag, (long)blockIdx.x - boff[r]);
+  const line_reduce_args& a = A[r];
+  line_reduce_body<NC>(gl(a.stats), gl(a.lines), a.nx, a.ny, gl(a.flag), (long)blockIdx.x - boff[r]);
 }
 
 // Global reduction of the first `n` line results (the rows) into glob[nc][3]: all NC components in
@@ -928,8 +937,8 @@ struct global_reduce_args {
 template <int NC>
 __global__ __launch_bounds__(256) void k_global_reduce_rt(const global_reduce_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const global_reduce_args a = A[r];
-  global_reduce_body<NC>(a.lines, a.glob, a.n, a.flag, (long)blockIdx.x - boff[r]);
+  const global_reduce_args& a = A[r];
+  global_reduce_body<NC>(gl(a.lines), gl(a.glob), a.n, gl(a.flag), (long)blockIdx.x - boff[r]);
 }
 
 // argument structs of the small and flat kernels for run-table launches
@@ -1156,31 +1165,31 @@ int dcopy(mhd25_ctx* c, const double* a, double* b, long n) {
 __global__ void k_reset_rt(const reset_args* __restrict__ A, int nr) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nr) return;
-  const reset_args a = A[r];
-  if (a.clear_input) a.flag[1] = 0;
-  a.flag[0] = a.flag[1];
-  a.counts[0] = 0; a.counts[1] = 0; a.counts[2] = 0;
+  const reset_args& a = A[r];
+  if (a.clear_input) gl(a.flag)[1] = 0;
+  gl(a.flag)[0] = gl(a.flag)[1];
+  gl(a.counts)[0] = 0; gl(a.counts)[1] = 0; gl(a.counts)[2] = 0;
 }
 
 // flat kernels: run r owns blocks boff[r] .. boff[r+1) and strides over its n entries with them
 __global__ __launch_bounds__(256) void k_copy_rt(const copy_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const copy_args a = A[r];
+  const copy_args& a = A[r];
   const long stride = (long)(boff[r + 1] - boff[r]) * blockDim.x;
   for (long k = (long)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x; k < a.n; k += stride) {
-    const double v = a.a[k];
-    a.b[k] = v;
-    if (a.flag && !(fabs(v) <= DBL_MAX)) atomicOr(a.flag + 1, 2);
+    const double v = gl(a.a)[k];
+    gl(a.b)[k] = v;
+    if (gl(a.flag) && !(fabs(v) <= DBL_MAX)) atomicOr(gl(a.flag) + 1, 2);
   }
 }
 
 __global__ __launch_bounds__(256) void k_snap_check_U_rt(const snap_args* __restrict__ A, const int* __restrict__ boff,
                                                          int nr) {
   const int r = rt_run(boff, nr);
-  const snap_args a = A[r];
+  const snap_args& a = A[r];
   const long stride = (long)(boff[r + 1] - boff[r]) * blockDim.x;
   for (long n = (long)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x; n < a.KN; n += stride)
-    snap_check_node(a.U, a.snap, a.KN, a.g, a.flag, n);
+    snap_check_node(gl(a.U), gl(a.snap), a.KN, a.g, gl(a.flag), n);
 }
 
 int hydro_rt_launch(const RtRecord& h, const void* dargs, const int* dboff, int nr, long nblocks, hipStream_t s) {

@@ -177,8 +177,8 @@ struct J_loads_args {
 template <int P, int M, int BS, bool R2>
 __global__ __launch_bounds__(BS) void k_J_loads_rt(const J_loads_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const J_loads_args a = A[r];
-  J_loads_body<P, M, BS, R2>(a.Bx, a.By, a.Bz, a.Lx, a.Ly, a.Lz, a.T, a.mp, (long)blockIdx.x - boff[r]);
+  const J_loads_args& a = A[r];
+  J_loads_body<P, M, BS, R2>(gl(a.Bx), gl(a.By), gl(a.Bz), gl(a.Lx), gl(a.Ly), gl(a.Lz), gl(a.T), a.mp, (long)blockIdx.x - boff[r]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -402,8 +402,8 @@ struct E_loads_args {
 template <int P, int M, int BS, bool R2>
 __global__ __launch_bounds__(BS, (!R2 && P <= 5) ? 5 : 1) void k_E_loads_rt(const E_loads_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const E_loads_args a = A[r];
-  E_loads_body<P, M, BS, R2>(a.u, a.Bx, a.By, a.Bz, a.Jx, a.Jy, a.Jz, a.eta, a.Lx, a.Ly, a.Lz, a.T, a.mp, (long)blockIdx.x - boff[r]);
+  const E_loads_args& a = A[r];
+  E_loads_body<P, M, BS, R2>(gl(a.u), gl(a.Bx), gl(a.By), gl(a.Bz), gl(a.Jx), gl(a.Jy), gl(a.Jz), gl(a.eta), gl(a.Lx), gl(a.Ly), gl(a.Lz), gl(a.T), a.mp, (long)blockIdx.x - boff[r]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -683,6 +683,19 @@ __global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update(MagIO
   mag_update_body<P, M, MODE, BS, R2>(io, T, mp, xcd_block());
 }
 
+using ::gl;
+// a MagIO read from a run-table argument struct, its pointers loaded as global-memory pointers
+__device__ __forceinline__ MagIO gl(const MagIO& s) {
+  MagIO o = s;
+  o.rho = gl(s.rho); o.us = gl(s.us); o.es = gl(s.es); o.bxs = gl(s.bxs); o.bys = gl(s.bys); o.bzs = gl(s.bzs);
+  o.un = gl(s.un); o.en = gl(s.en); o.bxn = gl(s.bxn); o.byn = gl(s.byn); o.bzn = gl(s.bzn);
+  o.jx = gl(s.jx); o.jy = gl(s.jy); o.jz = gl(s.jz); o.ex = gl(s.ex); o.ey = gl(s.ey); o.ez = gl(s.ez);
+  o.eta = gl(s.eta);
+  o.oe = gl(s.oe); o.ou = gl(s.ou); o.obx = gl(s.obx); o.oby = gl(s.oby); o.obz = gl(s.obz);
+  o.ustats = gl(s.ustats);
+  return o;
+}
+
 struct mag_update_args {
   MagIO io;
   const MagTab* T;
@@ -692,8 +705,8 @@ struct mag_update_args {
 template <int P, int M, int MODE, int BS, bool R2>
 __global__ __launch_bounds__(BS, (R2 && P <= 4) ? 7 : 1) void k_mag_update_rt(const mag_update_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const mag_update_args a = A[r];
-  mag_update_body<P, M, MODE, BS, R2>(a.io, a.T, a.mp, (long)blockIdx.x - boff[r]);
+  const mag_update_args& a = A[r];
+  mag_update_body<P, M, MODE, BS, R2>(gl(a.io), gl(a.T), a.mp, (long)blockIdx.x - boff[r]);
 }
 
 // per-element statistics of NC nodal fields [NC][K][NN] -> [K][NC][3] (GLL-weighted sum, min, max)
@@ -894,8 +907,8 @@ struct vel_prep_args {
 template <int P>
 __global__ __launch_bounds__(64) void k_vel_prep_rt(const vel_prep_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const vel_prep_args a = A[r];
-  vel_prep_body<P>(a.rho, a.Psi, a.H, a.mp, (long)blockIdx.x - boff[r]);
+  const vel_prep_args& a = A[r];
+  vel_prep_body<P>(gl(a.rho), gl(a.Psi), gl(a.H), a.mp, (long)blockIdx.x - boff[r]);
 }
 
 template <int P, int M>
@@ -1000,17 +1013,31 @@ __device__ __forceinline__ void vel_sensor_body(const double* __restrict__ rho, 
   }
   __syncthreads();  // every lane has read the B coefficients
   if (act) { sbb[el][q] = wsx; sbb[el][NN + q] = wsy; }
+  // the y neighbours' velocities are loaded into registers here, so that their latency overlaps
+  // the x-direction phases (they go to LDS once those are done)
+  double uy_nb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (act) {
+    const long em = wrapl(ey - 1, mp.ny) * mp.nx + ex, ep = wrapl(ey + 1, mp.ny) * mp.nx + ex;
+#pragma unroll
+    for (int c = 0; c < NU; ++c) {
+      uy_nb[c] = u[c * KN + em * NN + q];
+      uy_nb[3 + c] = u[c * KN + ep * NN + q];
+    }
+  }
 #pragma unroll
   for (int D = 0; D < 2; ++D) {
     // neighbours across the faces normal to D: sx rows 0..2 minus side, 3..5 plus side
     if (act) {
-      long em, ep;
-      if (D == 0) { em = ey * mp.nx + wrapl(ex - 1, mp.nx); ep = ey * mp.nx + wrapl(ex + 1, mp.nx); }
-      else { em = wrapl(ey - 1, mp.ny) * mp.nx + ex; ep = wrapl(ey + 1, mp.ny) * mp.nx + ex; }
+      if (D == 0) {
+        const long em = ey * mp.nx + wrapl(ex - 1, mp.nx), ep = ey * mp.nx + wrapl(ex + 1, mp.nx);
 #pragma unroll
-      for (int c = 0; c < NU; ++c) {
-        sx[el][c][q] = u[c * KN + em * NN + q];
-        sx[el][3 + c][q] = u[c * KN + ep * NN + q];
+        for (int c = 0; c < NU; ++c) {
+          sx[el][c][q] = u[c * KN + em * NN + q];
+          sx[el][3 + c][q] = u[c * KN + ep * NN + q];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < NU; ++c) { sx[el][c][q] = uy_nb[c]; sx[el][3 + c][q] = uy_nb[3 + c]; }
       }
     }
     __syncthreads();
@@ -1122,8 +1149,8 @@ struct vel_sensor_args {
 template <int P, int M, bool R2>
 __global__ __launch_bounds__(256, (P == 4 && M == 3) ? 6 : 1) void k_vel_sensor_rt(const vel_sensor_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const vel_sensor_args a = A[r];
-  vel_sensor_body<P, M, R2>(a.rho, a.u, a.Bx, a.By, a.Bz, a.lines, a.glob, a.Dfac, a.H, a.T, a.mp, a.tau, a.sM, (long)blockIdx.x - boff[r]);
+  const vel_sensor_args& a = A[r];
+  vel_sensor_body<P, M, R2>(gl(a.rho), gl(a.u), gl(a.Bx), gl(a.By), gl(a.Bz), gl(a.lines), gl(a.glob), gl(a.Dfac), gl(a.H), gl(a.T), a.mp, a.tau, a.sM, (long)blockIdx.x - boff[r]);
 }
 
 // Velocity-OE map (eq. magnetic-oe-map) with the prepared basis: one thread per node, EB elements
@@ -1244,8 +1271,8 @@ struct vel_proj_args {
 template <int P, int BS, bool R2>
 __global__ __launch_bounds__(BS) void k_vel_proj_rt(const vel_proj_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const vel_proj_args a = A[r];
-  vel_proj_body<P, BS, R2>(a.rho, a.u, a.en, a.Psi, a.Dfac, a.H, a.mp, (long)blockIdx.x - boff[r]);
+  const vel_proj_args& a = A[r];
+  vel_proj_body<P, BS, R2>(gl(a.rho), gl(a.u), gl(a.en), gl(a.Psi), gl(a.Dfac), gl(a.H), a.mp, (long)blockIdx.x - boff[r]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1366,8 +1393,8 @@ struct ar_traces_args {
 template <int P, int M>
 __global__ __launch_bounds__(256) void k_ar_traces_rt(const ar_traces_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const ar_traces_args a = A[r];
-  ar_traces_body<P, M>(a.rho, a.u, a.Bx, a.By, a.Bz, a.tr, a.T, a.mp, (long)blockIdx.x - boff[r]);
+  const ar_traces_args& a = A[r];
+  ar_traces_body<P, M>(gl(a.rho), gl(a.u), gl(a.Bx), gl(a.By), gl(a.Bz), gl(a.tr), gl(a.T), a.mp, (long)blockIdx.x - boff[r]);
 }
 
 // bglob[3][3]: (integral, min, max) of B_x, B_y, B_z over the domain.
@@ -1442,8 +1469,8 @@ struct ar_eta_args {
 template <int P, int M>
 __global__ __launch_bounds__(256) void k_ar_eta_rt(const ar_eta_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const ar_eta_args a = A[r];
-  ar_eta_body<P, M>(a.tr, a.bglob, a.eta, a.T, a.mp, a.Cs, a.Ceta, (long)blockIdx.x - boff[r]);
+  const ar_eta_args& a = A[r];
+  ar_eta_body<P, M>(gl(a.tr), gl(a.bglob), gl(a.eta), gl(a.T), a.mp, a.Cs, a.Ceta, (long)blockIdx.x - boff[r]);
 }
 
 // per-element exact integral and owned-node min / max of each B component -> [K][3][3]
@@ -1501,8 +1528,8 @@ struct B_stats_args {
 template <int M>
 __global__ __launch_bounds__(256) void k_B_stats_rt(const B_stats_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const B_stats_args a = A[r];
-  B_stats_body<M>(a.Bx, a.By, a.Bz, a.stats, a.T, a.mp, (long)blockIdx.x - boff[r]);
+  const B_stats_args& a = A[r];
+  B_stats_body<M>(gl(a.Bx), gl(a.By), gl(a.Bz), gl(a.stats), gl(a.T), a.mp, (long)blockIdx.x - boff[r]);
 }
 
 }  // namespace
@@ -1565,8 +1592,8 @@ struct gather_args {
 template <int M, bool R2>
 __global__ __launch_bounds__(256) void k_gather_rt(const gather_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const gather_args a = A[r];
-  gather_body<M, R2>(a.Lx, a.Ly, a.Lz, a.Ox, a.Oy, a.Oz, a.T, a.mp, (long)blockIdx.x - boff[r]);
+  const gather_args& a = A[r];
+  gather_body<M, R2>(gl(a.Lx), gl(a.Ly), gl(a.Lz), gl(a.Ox), gl(a.Oy), gl(a.Oz), gl(a.T), a.mp, (long)blockIdx.x - boff[r]);
 }
 
 // Local-to-global maps of the six magnetic node sets of each element (B_x, B_y, B_z, W, N_x, N_y;
@@ -1985,19 +2012,19 @@ int mag_B_from_potential(mhd25_ctx* c, const double* A, double* Bx, double* By) 
 __global__ __launch_bounds__(256) void k_to_primitive_rt(const prim_args* __restrict__ A, const int* __restrict__ boff,
                                                          int nr) {
   const int r = rt_run(boff, nr);
-  const prim_args a = A[r];
+  const prim_args& a = A[r];
   const long stride = (long)(boff[r + 1] - boff[r]) * blockDim.x;
   for (long k = (long)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x; k < a.n; k += stride)
-    to_primitive_node(a.U, a.rho, a.e, a.u, a.n, k);
+    to_primitive_node(gl(a.U), gl(a.rho), gl(a.e), gl(a.u), a.n, k);
 }
 
 __global__ __launch_bounds__(256) void k_to_conservative_rt(const prim_args* __restrict__ A,
                                                             const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
-  const prim_args a = A[r];
+  const prim_args& a = A[r];
   const long stride = (long)(boff[r + 1] - boff[r]) * blockDim.x;
   for (long k = (long)(blockIdx.x - boff[r]) * blockDim.x + threadIdx.x; k < a.n; k += stride)
-    to_conservative_node(a.rho, a.e, a.u, const_cast<double*>(a.U), a.n, k);
+    to_conservative_node(gl(a.rho), gl(a.e), gl(a.u), const_cast<double*>(gl(a.U)), a.n, k);
 }
 
 int magnetic_rt_launch(const RtRecord& h, const void* dargs, const int* dboff, int nr, long nblocks, hipStream_t s) {

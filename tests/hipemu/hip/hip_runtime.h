@@ -27,6 +27,8 @@
 #define __align__(n) alignas(n)
 #define __builtin_amdgcn_rsq(x) (1.0 / std::sqrt(x))  // hardware 1/sqrt estimate
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))  // hardware 1/x estimate
+#define __builtin_amdgcn_readfirstlane(x) (x)  // callers pass wave-uniform values
+#define MHD_GLOBAL_AS  // one address space on the host
 
 struct dim3 {
   unsigned x, y, z;

@@ -148,3 +148,37 @@ def test_strang_magnetic_outer_parity():
         assert (S.decisions() == out[5]).all()
     compare(g, st, 1e-12, "OT magnetic-outer")
     S.close()
+
+
+def test_checkpoint_restart_bit_exact():
+    """Checkpoint and restart through host memory: n Strang steps, the state copied to the host,
+    the context closed, a new context and fresh device buffers filled from the host copy, then n
+    more steps; the result equals 2n uninterrupted steps bit for bit (full stabilisation, dt from
+    the CFL rule at every step, 64^2, N = 4)."""
+    import paper_2609_10849_amd as pk
+    announce("checkpoint/restart, OT 64^2 N=4, 3 + 3 steps")
+    L, U, Bx, By, Bz = W.orszag_tang_scaled(64, 64, 4, 3)
+
+    def advance(S, g, n):
+        for _ in range(n):
+            r, _ = S.strang_step(*g, S.cfl_dt(*g, 0.3))
+            assert r == 0
+
+    S = pk.Solver.from_layout(L, pk.Options.full())
+    g = [dev(a) for a in (U, Bx, By, Bz)]
+    advance(S, g, 6)
+    straight = [host(a) for a in g]
+    S.close()
+    S = pk.Solver.from_layout(L, pk.Options.full())
+    g = [dev(a) for a in (U, Bx, By, Bz)]
+    advance(S, g, 3)
+    ckpt = [host(a).copy() for a in g]
+    S.close()
+    del g
+    S = pk.Solver.from_layout(L, pk.Options.full())
+    g = [dev(a) for a in ckpt]
+    advance(S, g, 3)
+    restarted = [host(a) for a in g]
+    S.close()
+    for a, b in zip(restarted, straight):
+        assert np.array_equal(a, b)

@@ -426,10 +426,11 @@ def test_emulated_strang_step_magnetic_outer(emu):
             assert np.abs(a - r).max() <= 1e-12 * np.abs(r).max()
 
 
-@pytest.mark.parametrize("graph", [1])
+@pytest.mark.parametrize("graph", [0, 1])
 def test_emulated_batch_run_table_equals_individual(emu, graph):
-    """The run-table batch step (launches covering every run of a degree group; with graph = 1
-    replayed from a captured graph of those launches) equals, bit for bit, every run stepped alone,
+    """The run-table batch step (launches covering every run of a degree group, the groups on branch
+    streams of their own; with graph = 1 replayed from a captured graph of those launches) equals,
+    bit for bit, every run stepped alone,
     on two steps; the plan is rebuilt when a step changes; a member whose hydro substep needs a
     halving is redone individually."""
     lib, pk = emu
