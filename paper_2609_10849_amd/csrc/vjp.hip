@@ -319,7 +319,26 @@ __global__ __launch_bounds__(256) void k_vjp_update(const double* __restrict__ r
   __shared__ double sup[EB][3][NN];                         // du_cot / (rho M)
   __shared__ double sjq[EB][3][NN];                         // J-bar at GLL_p nodes (Ohm)
   __shared__ double sfb[EB][3][AA + 2 * AB];                // B-bar at aux nodes: W (AA), Nx (AB), Ny (AB)
+  // the interpolation and derivative tables, staged in LDS (lane-dependent indexes into the
+  // device table would each be a vector memory load)
+  __shared__ double tDWG[MHD_MAXN][MHD_MAXN], tDWV[MHD_MAXN][MHD_MAXN], tIGP[MHD_MAXN][MHD_MAXN], tIGV[MHD_MAXN][MHD_MAXN], tIGW[MHD_MAXN][MHD_MAXN], tIVG[MHD_MAXN][MHD_MAXN], tIVW[MHD_MAXN][MHD_MAXN], tIWP[MHD_MAXN][MHD_MAXN], tIPW[MHD_MAXN][MHD_MAXN], tIPG[MHD_MAXN][MHD_MAXN];
+  __shared__ double tww[MHD_MAXN], twg[MHD_MAXN], twp[MHD_MAXN];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
+  for (int k = threadIdx.x; k < MHD_MAXN * MHD_MAXN; k += 256) {
+    const int r = k / MHD_MAXN, c = k % MHD_MAXN;
+    tDWG[r][c] = T->D_W_G[r][c];
+    tDWV[r][c] = T->D_W_V[r][c];
+    tIGP[r][c] = T->I_G_P[r][c];
+    tIGV[r][c] = T->I_G_V[r][c];
+    tIGW[r][c] = T->I_G_W[r][c];
+    tIVG[r][c] = T->I_V_G[r][c];
+    tIVW[r][c] = T->I_V_W[r][c];
+    tIWP[r][c] = T->I_W_P[r][c];
+    tIPW[r][c] = T->I_P_W[r][c];
+    tIPG[r][c] = T->I_P_G[r][c];
+  }
+  if (threadIdx.x < MHD_MAXN) { tww[threadIdx.x] = T->ww[threadIdx.x]; twg[threadIdx.x] = T->wg[threadIdx.x]; twp[threadIdx.x] = T->wp[threadIdx.x]; }
+  __syncthreads();  // the load phase below already reads the tables
   const long e = (long)blockIdx.x * EB + el;
   const bool act = el < EB && e < mp.K;
   long ex, ey;
@@ -343,25 +362,25 @@ __global__ __launch_bounds__(256) void k_vjp_update(const double* __restrict__ r
     if (t < NN) {
       const int qi = t % NP, qj = t / NP;
       const long n = e * NN + t;
-      const double w = 1.0 / (rho[n] * mp.J * T->wp[qi] * T->wp[qj]);
+      const double w = 1.0 / (rho[n] * mp.J * twp[qi] * twp[qj]);
       for (int d = 0; d < 3; ++d) sup[el][d][t] = du_c[d * KN + n] * w;
       // Ohm: de = eta |J(x_q)|^2 / rho  ->  J-bar(x_q) = de_c * 2 eta J / rho
       double jx = 0.0, jy = 0.0, jz = 0.0;
       if (et != 0.0) {
         for (int jj = 0; jj < A; ++jj) {
           double s = 0.0;
-          for (int ii = 0; ii < B; ++ii) s += T->I_G_P[qi][ii] * Jx[gix(mp, B, ex, ey, ii, jj)];
-          jx += T->I_W_P[qj][jj] * s;
+          for (int ii = 0; ii < B; ++ii) s += tIGP[qi][ii] * Jx[gix(mp, B, ex, ey, ii, jj)];
+          jx += tIWP[qj][jj] * s;
         }
         for (int jj = 0; jj < B; ++jj) {
           double s = 0.0;
-          for (int ii = 0; ii < A; ++ii) s += T->I_W_P[qi][ii] * Jy[gix(mp, B, ex, ey, ii, jj)];
-          jy += T->I_G_P[qj][jj] * s;
+          for (int ii = 0; ii < A; ++ii) s += tIWP[qi][ii] * Jy[gix(mp, B, ex, ey, ii, jj)];
+          jy += tIGP[qj][jj] * s;
         }
         for (int jj = 0; jj < A; ++jj) {
           double s = 0.0;
-          for (int ii = 0; ii < A; ++ii) s += T->I_W_P[qi][ii] * Jz[gix(mp, B, ex, ey, ii, jj)];
-          jz += T->I_W_P[qj][jj] * s;
+          for (int ii = 0; ii < A; ++ii) s += tIWP[qi][ii] * Jz[gix(mp, B, ex, ey, ii, jj)];
+          jz += tIWP[qj][jj] * s;
         }
       }
       const double f = et != 0.0 ? de_c[n] * 2.0 * et / rho[n] : 0.0;
@@ -379,9 +398,9 @@ __global__ __launch_bounds__(256) void k_vjp_update(const double* __restrict__ r
       const int i = t % A, k = t / A;
       double s = 0.0;
       if (i < B)
-        for (int j = 0; j < B; ++j) s += -(2.0 / mp.hy) * T->D_W_G[j][k] * scx[el][j * B + i];
+        for (int j = 0; j < B; ++j) s += -(2.0 / mp.hy) * tDWG[j][k] * scx[el][j * B + i];
       if (k < B)
-        for (int ii = 0; ii < B; ++ii) s += (2.0 / mp.hx) * T->D_W_G[ii][i] * scy[el][k * B + ii];
+        for (int ii = 0; ii < B; ++ii) s += (2.0 / mp.hx) * tDWG[ii][i] * scy[el][k * B + ii];
       ELe[2 * AB + t] = s;
     }
     if (t < AB) {
@@ -389,14 +408,14 @@ __global__ __launch_bounds__(256) void k_vjp_update(const double* __restrict__ r
         const int i = t % A, l = t / A;
         double s = 0.0;
         for (int jj = 0; jj < B; ++jj)
-          for (int ii = 0; ii < B; ++ii) s += T->I_G_V[jj][l] * T->D_W_V[ii][i] * scz[el][jj * B + ii];
+          for (int ii = 0; ii < B; ++ii) s += tIGV[jj][l] * tDWV[ii][i] * scz[el][jj * B + ii];
         ELe[AB + t] = -(2.0 / mp.hx) * s;
       }
       {  // E_x local: Nx layout (k < B Gauss x, l < A GLL y); dBz += (2/hy) sum D_W_V[j][l] I_G_V[i][k] E_x
         const int k = t % B, l = t / B;
         double s = 0.0;
         for (int jj = 0; jj < B; ++jj)
-          for (int ii = 0; ii < B; ++ii) s += T->D_W_V[jj][l] * T->I_G_V[ii][k] * scz[el][jj * B + ii];
+          for (int ii = 0; ii < B; ++ii) s += tDWV[jj][l] * tIGV[ii][k] * scz[el][jj * B + ii];
         ELe[t] = (2.0 / mp.hy) * s;
       }
     }
@@ -419,12 +438,12 @@ __global__ __launch_bounds__(256) void k_vjp_update(const double* __restrict__ r
     };
     if (t < AA) {  // W node: f = (-B_y J_z, B_x J_z, 0)
       const int i = t % A, j = t / A;
-      const double w = mp.J * T->ww[i] * T->ww[j];
-      const double fx = w * fbar(0, T->I_P_W, i, T->I_P_W, j), fy = w * fbar(1, T->I_P_W, i, T->I_P_W, j);
+      const double w = mp.J * tww[i] * tww[j];
+      const double fx = w * fbar(0, tIPW, i, tIPW, j), fy = w * fbar(1, tIPW, i, tIPW, j);
       double bxv = 0.0, byv = 0.0;
-      for (int k = 0; k < B; ++k) { bxv += T->I_G_W[j][k] * sbx[el][k * A + i]; byv += T->I_G_W[i][k] * sby[el][j * B + k]; }
+      for (int k = 0; k < B; ++k) { bxv += tIGW[j][k] * sbx[el][k * A + i]; byv += tIGW[i][k] * sby[el][j * B + k]; }
       const double jz = sjz[el][t];
-      JLe[2 * AB + t] = -fx * byv + fy * bxv + (et != 0.0 ? ohm(2, T->I_W_P, i, T->I_W_P, j) : 0.0);
+      JLe[2 * AB + t] = -fx * byv + fy * bxv + (et != 0.0 ? ohm(2, tIWP, i, tIWP, j) : 0.0);
       sfb[el][0][t] = fy * jz;   // B_x bar at W node
       sfb[el][1][t] = -fx * jz;  // B_y bar
       sfb[el][2][t] = 0.0;
@@ -432,32 +451,32 @@ __global__ __launch_bounds__(256) void k_vjp_update(const double* __restrict__ r
     if (t < AB) {
       {  // N_x node (i < B, j < A): f = (0, -B_z J_x, B_y J_x)
         const int i = t % B, j = t / B;
-        const double w = mp.J * T->wg[i] * T->ww[j];
-        const double fy = w * fbar(1, T->I_P_G, i, T->I_P_W, j), fz = w * fbar(2, T->I_P_G, i, T->I_P_W, j);
+        const double w = mp.J * twg[i] * tww[j];
+        const double fy = w * fbar(1, tIPG, i, tIPW, j), fz = w * fbar(2, tIPG, i, tIPW, j);
         double bzv = 0.0;
         for (int jj = 0; jj < B; ++jj) {
           double s = 0.0;
-          for (int ii = 0; ii < B; ++ii) s += T->I_V_G[i][ii] * sbz[el][jj * B + ii];
-          bzv += T->I_V_W[j][jj] * s;
+          for (int ii = 0; ii < B; ++ii) s += tIVG[i][ii] * sbz[el][jj * B + ii];
+          bzv += tIVW[j][jj] * s;
         }
         const double jx = sjx[el][t];
-        JLe[t] = -fy * bzv + fz * sby[el][t] + (et != 0.0 ? ohm(0, T->I_G_P, i, T->I_W_P, j) : 0.0);
+        JLe[t] = -fy * bzv + fz * sby[el][t] + (et != 0.0 ? ohm(0, tIGP, i, tIWP, j) : 0.0);
         sfb[el][0][AA + t] = 0.0;
         sfb[el][1][AA + t] = fz * jx;   // B_y bar (B_y lives on these nodes)
         sfb[el][2][AA + t] = -fy * jx;  // B_z bar at the node
       }
       {  // N_y node (i < A, j < B): f = (B_z J_y, 0, -B_x J_y)
         const int i = t % A, j = t / A;
-        const double w = mp.J * T->ww[i] * T->wg[j];
-        const double fx = w * fbar(0, T->I_P_W, i, T->I_P_G, j), fz = w * fbar(2, T->I_P_W, i, T->I_P_G, j);
+        const double w = mp.J * tww[i] * twg[j];
+        const double fx = w * fbar(0, tIPW, i, tIPG, j), fz = w * fbar(2, tIPW, i, tIPG, j);
         double bzv = 0.0;
         for (int jj = 0; jj < B; ++jj) {
           double s = 0.0;
-          for (int ii = 0; ii < B; ++ii) s += T->I_V_W[i][ii] * sbz[el][jj * B + ii];
-          bzv += T->I_V_G[j][jj] * s;
+          for (int ii = 0; ii < B; ++ii) s += tIVW[i][ii] * sbz[el][jj * B + ii];
+          bzv += tIVG[j][jj] * s;
         }
         const double jy = sjy[el][t];
-        JLe[AB + t] = fx * bzv - fz * sbx[el][t] + (et != 0.0 ? ohm(1, T->I_W_P, i, T->I_G_P, j) : 0.0);
+        JLe[AB + t] = fx * bzv - fz * sbx[el][t] + (et != 0.0 ? ohm(1, tIWP, i, tIGP, j) : 0.0);
         sfb[el][0][AA + AB + t] = -fz * jy;  // B_x bar (B_x lives on these nodes)
         sfb[el][1][AA + AB + t] = 0.0;
         sfb[el][2][AA + AB + t] = fx * jy;   // B_z bar
@@ -471,13 +490,13 @@ __global__ __launch_bounds__(256) void k_vjp_update(const double* __restrict__ r
     {  // B_x local (i < A, k < B): from W nodes (i, j) via I_G_W[j][k] and from N_y node t directly
       const int i = t % A, k = t / A;
       double s = sfb[el][0][AA + AB + t];
-      for (int j = 0; j < A; ++j) s += T->I_G_W[j][k] * sfb[el][0][j * A + i];
+      for (int j = 0; j < A; ++j) s += tIGW[j][k] * sfb[el][0][j * A + i];
       BLe[t] = s;
     }
     {  // B_y local (k < B, j < A): from W nodes (i, j) via I_G_W[i][k] and from N_x node t directly
       const int k = t % B, j = t / B;
       double s = sfb[el][1][AA + t];
-      for (int i = 0; i < A; ++i) s += T->I_G_W[i][k] * sfb[el][1][j * A + i];
+      for (int i = 0; i < A; ++i) s += tIGW[i][k] * sfb[el][1][j * A + i];
       BLe[AB + t] = s;
     }
   }
@@ -485,9 +504,9 @@ __global__ __launch_bounds__(256) void k_vjp_update(const double* __restrict__ r
     const int ii = t % B, jj = t / B;
     double s = 0.0;
     for (int j = 0; j < A; ++j)
-      for (int i = 0; i < B; ++i) s += T->I_V_G[i][ii] * T->I_V_W[j][jj] * sfb[el][2][AA + j * B + i];
+      for (int i = 0; i < B; ++i) s += tIVG[i][ii] * tIVW[j][jj] * sfb[el][2][AA + j * B + i];
     for (int j = 0; j < B; ++j)
-      for (int i = 0; i < A; ++i) s += T->I_V_W[i][ii] * T->I_V_G[j][jj] * sfb[el][2][AA + AB + j * A + i];
+      for (int i = 0; i < A; ++i) s += tIVW[i][ii] * tIVG[j][jj] * sfb[el][2][AA + AB + j * A + i];
     BLe[2 * AB + t] = s;
   }
 }
@@ -508,7 +527,24 @@ __global__ __launch_bounds__(256) void k_vjp_E(const double* __restrict__ u, con
   __shared__ double sl[EB][AA + 2 * AB];          // load-bar = E-bar / m at the element's aux nodes (W, Nx, Ny)
   __shared__ double sub[EB][3][AA + 2 * AB];      // u-bar at aux nodes
   __shared__ double sbb[EB][3][AA + 2 * AB];      // B-bar at aux nodes
+  __shared__ double tWP[NP][A], tGP[NP][B];         // W and Gauss bases at the GLL_p nodes (eta term)
+  // the interpolation tables, staged in LDS (lane-dependent indexes into the device table would
+  // each be a vector memory load)
+  __shared__ double tIGW[MHD_MAXN][MHD_MAXN], tIPG[MHD_MAXN][MHD_MAXN], tIPW[MHD_MAXN][MHD_MAXN], tIVG[MHD_MAXN][MHD_MAXN], tIVW[MHD_MAXN][MHD_MAXN];
+  __shared__ double tww[MHD_MAXN], twg[MHD_MAXN], twp[MHD_MAXN];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
+  for (int k = tid; k < NP * A; k += 256) tWP[k / A][k % A] = T->I_W_P[k / A][k % A];
+  for (int k = tid; k < NP * B; k += 256) tGP[k / B][k % B] = T->I_G_P[k / B][k % B];
+  for (int k = tid; k < MHD_MAXN * MHD_MAXN; k += 256) {
+    const int r = k / MHD_MAXN, c = k % MHD_MAXN;
+    tIGW[r][c] = T->I_G_W[r][c];
+    tIPG[r][c] = T->I_P_G[r][c];
+    tIPW[r][c] = T->I_P_W[r][c];
+    tIVG[r][c] = T->I_V_G[r][c];
+    tIVW[r][c] = T->I_V_W[r][c];
+  }
+  if (tid < MHD_MAXN) { tww[tid] = T->ww[tid]; twg[tid] = T->wg[tid]; twp[tid] = T->wp[tid]; }
+  __syncthreads();  // the load phase below already reads the tables
   const long e = (long)blockIdx.x * EB + el;
   const bool act = el < EB && e < mp.K;
   long ex, ey;
@@ -527,20 +563,20 @@ __global__ __launch_bounds__(256) void k_vjp_E(const double* __restrict__ u, con
     // load-bar = E-bar / (assembled lumped weight); weights are sums over the sharing elements
     for (int k = t; k < AA; k += NT) {
       const int i = k % A, j = k / A;
-      const double wx = (i == 0 || i == A - 1) ? T->ww[0] + T->ww[A - 1] : T->ww[i];
-      const double wy = (j == 0 || j == A - 1) ? T->ww[0] + T->ww[A - 1] : T->ww[j];
+      const double wx = (i == 0 || i == A - 1) ? tww[0] + tww[A - 1] : tww[i];
+      const double wy = (j == 0 || j == A - 1) ? tww[0] + tww[A - 1] : tww[j];
       sl[el][k] = Ezb[gix(mp, B, ex, ey, i, j)] / (mp.J * wx * wy);
     }
     for (int k = t; k < AB; k += NT) {
       {
         const int i = k % B, j = k / B;  // Nx
-        const double wy = (j == 0 || j == A - 1) ? T->ww[0] + T->ww[A - 1] : T->ww[j];
-        sl[el][AA + k] = Exb[gix(mp, B, ex, ey, i, j)] / (mp.J * T->wg[i] * wy);
+        const double wy = (j == 0 || j == A - 1) ? tww[0] + tww[A - 1] : tww[j];
+        sl[el][AA + k] = Exb[gix(mp, B, ex, ey, i, j)] / (mp.J * twg[i] * wy);
       }
       {
         const int i = k % A, j = k / A;  // Ny
-        const double wx = (i == 0 || i == A - 1) ? T->ww[0] + T->ww[A - 1] : T->ww[i];
-        sl[el][AA + AB + k] = Eyb[gix(mp, B, ex, ey, i, j)] / (mp.J * wx * T->wg[j]);
+        const double wx = (i == 0 || i == A - 1) ? tww[0] + tww[A - 1] : tww[i];
+        sl[el][AA + AB + k] = Eyb[gix(mp, B, ex, ey, i, j)] / (mp.J * wx * twg[j]);
       }
     }
   }
@@ -557,45 +593,63 @@ __global__ __launch_bounds__(256) void k_vjp_E(const double* __restrict__ u, con
   if (act) {
     if (t < AA) {  // W node: X_z = -(u_x B_y - u_y B_x)
       const int i = t % A, j = t / A;
-      const double ux = u_at(0, T->I_P_W, i, T->I_P_W, j), uy = u_at(1, T->I_P_W, i, T->I_P_W, j);
+      const double ux = u_at(0, tIPW, i, tIPW, j), uy = u_at(1, tIPW, i, tIPW, j);
       double bxv = 0.0, byv = 0.0;
-      for (int k = 0; k < B; ++k) { bxv += T->I_G_W[j][k] * sbx[el][k * A + i]; byv += T->I_G_W[i][k] * sby[el][j * B + k]; }
-      const double s = mp.J * T->ww[i] * T->ww[j] * sl[el][t];
+      for (int k = 0; k < B; ++k) { bxv += tIGW[j][k] * sbx[el][k * A + i]; byv += tIGW[i][k] * sby[el][j * B + k]; }
+      const double s = mp.J * tww[i] * tww[j] * sl[el][t];
       sub[el][0][t] = -s * byv; sub[el][1][t] = s * bxv; sub[el][2][t] = 0.0;
       sbb[el][0][t] = s * uy; sbb[el][1][t] = -s * ux; sbb[el][2][t] = 0.0;
     }
     if (t < AB) {
       {  // N_x node: X_x = -(u_y B_z - u_z B_y)
         const int i = t % B, j = t / B;
-        const double uy = u_at(1, T->I_P_G, i, T->I_P_W, j), uz = u_at(2, T->I_P_G, i, T->I_P_W, j);
+        const double uy = u_at(1, tIPG, i, tIPW, j), uz = u_at(2, tIPG, i, tIPW, j);
         const double byv = sby[el][t];
         double bzv = 0.0;
         for (int jj = 0; jj < B; ++jj) {
           double s = 0.0;
-          for (int ii = 0; ii < B; ++ii) s += T->I_V_G[i][ii] * sbz[el][jj * B + ii];
-          bzv += T->I_V_W[j][jj] * s;
+          for (int ii = 0; ii < B; ++ii) s += tIVG[i][ii] * sbz[el][jj * B + ii];
+          bzv += tIVW[j][jj] * s;
         }
-        const double s = mp.J * T->wg[i] * T->ww[j] * sl[el][AA + t];
+        const double s = mp.J * twg[i] * tww[j] * sl[el][AA + t];
         sub[el][0][AA + t] = 0.0; sub[el][1][AA + t] = -s * bzv; sub[el][2][AA + t] = s * byv;
         sbb[el][0][AA + t] = 0.0; sbb[el][1][AA + t] = s * uz; sbb[el][2][AA + t] = -s * uy;
       }
       {  // N_y node: X_y = -(u_z B_x - u_x B_z)
         const int i = t % A, j = t / A;
-        const double ux = u_at(0, T->I_P_W, i, T->I_P_G, j), uz = u_at(2, T->I_P_W, i, T->I_P_G, j);
+        const double ux = u_at(0, tIPW, i, tIPG, j), uz = u_at(2, tIPW, i, tIPG, j);
         const double bxv = sbx[el][t];
         double bzv = 0.0;
         for (int jj = 0; jj < B; ++jj) {
           double s = 0.0;
-          for (int ii = 0; ii < B; ++ii) s += T->I_V_W[i][ii] * sbz[el][jj * B + ii];
-          bzv += T->I_V_G[j][jj] * s;
+          for (int ii = 0; ii < B; ++ii) s += tIVW[i][ii] * sbz[el][jj * B + ii];
+          bzv += tIVG[j][jj] * s;
         }
-        const double s = mp.J * T->ww[i] * T->wg[j] * sl[el][AA + AB + t];
+        const double s = mp.J * tww[i] * twg[j] * sl[el][AA + AB + t];
         sub[el][0][AA + AB + t] = s * bzv; sub[el][1][AA + AB + t] = 0.0; sub[el][2][AA + AB + t] = -s * bxv;
         sbb[el][0][AA + AB + t] = -s * uz; sbb[el][1][AA + AB + t] = 0.0; sbb[el][2][AA + AB + t] = s * ux;
       }
     }
   }
-  __syncthreads();
+  // eta term: load_a += eta sum_q M_q J_c(x_q) phi_a(x_q), so J-bar_c(x_q) = eta M_q sum_a phi_a(x_q)
+  // lbar_a; it is formed once per GLL_p node (into su, whose last reads precede this barrier) and
+  // then moved to the J-bar locals by the transpose of the J interpolation to GLL_p
+  const int any_eta = __syncthreads_or(act && et != 0.0);
+  if (any_eta) {
+    if (act && et != 0.0 && t < NN) {
+      const int qi = t % NP, qj = t / NP;
+      double vz = 0.0, vx = 0.0, vy = 0.0;
+      for (int j = 0; j < A; ++j)
+        for (int i = 0; i < A; ++i) vz += tWP[qi][i] * tWP[qj][j] * sl[el][j * A + i];
+      for (int j = 0; j < A; ++j)
+        for (int i = 0; i < B; ++i) vx += tGP[qi][i] * tWP[qj][j] * sl[el][AA + j * B + i];
+      for (int j = 0; j < B; ++j)
+        for (int i = 0; i < A; ++i) vy += tWP[qi][i] * tGP[qj][j] * sl[el][AA + AB + j * A + i];
+      const double wq = et * mp.J * twp[qi] * twp[qj];
+      su[el][0][t] = wq * vx; su[el][1][t] = wq * vy; su[el][2][t] = wq * vz;
+    }
+    __syncthreads();
+  }
   if (!act) return;
   double* JLe = JL + e * LOC;
   double* BLe = BL + e * (2 * AB + BB);
@@ -604,11 +658,11 @@ __global__ __launch_bounds__(256) void k_vjp_E(const double* __restrict__ u, con
     for (int d = 0; d < 3; ++d) {
       double s = 0.0;
       for (int j = 0; j < A; ++j)
-        for (int i = 0; i < A; ++i) s += T->I_P_W[i][qi] * T->I_P_W[j][qj] * sub[el][d][j * A + i];
+        for (int i = 0; i < A; ++i) s += tIPW[i][qi] * tIPW[j][qj] * sub[el][d][j * A + i];
       for (int j = 0; j < A; ++j)
-        for (int i = 0; i < B; ++i) s += T->I_P_G[i][qi] * T->I_P_W[j][qj] * sub[el][d][AA + j * B + i];
+        for (int i = 0; i < B; ++i) s += tIPG[i][qi] * tIPW[j][qj] * sub[el][d][AA + j * B + i];
       for (int j = 0; j < B; ++j)
-        for (int i = 0; i < A; ++i) s += T->I_P_W[i][qi] * T->I_P_G[j][qj] * sub[el][d][AA + AB + j * A + i];
+        for (int i = 0; i < A; ++i) s += tIPW[i][qi] * tIPG[j][qj] * sub[el][d][AA + AB + j * A + i];
       ubar[d * KN + e * NN + t] = s;
     }
   }
@@ -616,13 +670,13 @@ __global__ __launch_bounds__(256) void k_vjp_E(const double* __restrict__ u, con
     {  // B_x local (i < A, k < B)
       const int i = t % A, k = t / A;
       double s = sbb[el][0][AA + AB + t];
-      for (int j = 0; j < A; ++j) s += T->I_G_W[j][k] * sbb[el][0][j * A + i];
+      for (int j = 0; j < A; ++j) s += tIGW[j][k] * sbb[el][0][j * A + i];
       BLe[t] += s;
     }
     {  // B_y local (k < B, j < A)
       const int k = t % B, j = t / B;
       double s = sbb[el][1][AA + t];
-      for (int i = 0; i < A; ++i) s += T->I_G_W[i][k] * sbb[el][1][j * A + i];
+      for (int i = 0; i < A; ++i) s += tIGW[i][k] * sbb[el][1][j * A + i];
       BLe[AB + t] += s;
     }
   }
@@ -630,33 +684,18 @@ __global__ __launch_bounds__(256) void k_vjp_E(const double* __restrict__ u, con
     const int ii = t % B, jj = t / B;
     double s = 0.0;
     for (int j = 0; j < A; ++j)
-      for (int i = 0; i < B; ++i) s += T->I_V_G[i][ii] * T->I_V_W[j][jj] * sbb[el][2][AA + j * B + i];
+      for (int i = 0; i < B; ++i) s += tIVG[i][ii] * tIVW[j][jj] * sbb[el][2][AA + j * B + i];
     for (int j = 0; j < B; ++j)
-      for (int i = 0; i < A; ++i) s += T->I_V_W[i][ii] * T->I_V_G[j][jj] * sbb[el][2][AA + AB + j * A + i];
+      for (int i = 0; i < A; ++i) s += tIVW[i][ii] * tIVG[j][jj] * sbb[el][2][AA + AB + j * A + i];
     BLe[2 * AB + t] += s;
   }
   if (et != 0.0) {
-    // eta term: load_a += eta sum_q M_q J_c(x_q) phi_a(x_q) -> J-bar_c(x_q) = eta M_q sum_a phi_a(x_q) lbar_a,
-    // then J-bar locals by the transpose of the J interpolation to GLL_p
-    auto jbar_q = [&](int qi, int qj, int c) {
-      double v = 0.0;
-      if (c == 2) {
-        for (int j = 0; j < A; ++j)
-          for (int i = 0; i < A; ++i) v += T->I_W_P[qi][i] * T->I_W_P[qj][j] * sl[el][j * A + i];
-      } else if (c == 0) {
-        for (int j = 0; j < A; ++j)
-          for (int i = 0; i < B; ++i) v += T->I_G_P[qi][i] * T->I_W_P[qj][j] * sl[el][AA + j * B + i];
-      } else {
-        for (int j = 0; j < B; ++j)
-          for (int i = 0; i < A; ++i) v += T->I_W_P[qi][i] * T->I_G_P[qj][j] * sl[el][AA + AB + j * A + i];
-      }
-      return et * mp.J * T->wp[qi] * T->wp[qj] * v;
-    };
+    const double(*jq)[NN] = su[el];  // J-bar_x, J-bar_y, J-bar_z at the GLL_p nodes
     if (t < AA) {
       const int i = t % A, j = t / A;
       double s = 0.0;
       for (int qj = 0; qj < NP; ++qj)
-        for (int qi = 0; qi < NP; ++qi) s += T->I_W_P[qi][i] * T->I_W_P[qj][j] * jbar_q(qi, qj, 2);
+        for (int qi = 0; qi < NP; ++qi) s += tWP[qi][i] * tWP[qj][j] * jq[2][qj * NP + qi];
       JLe[2 * AB + t] += s;
     }
     if (t < AB) {
@@ -664,14 +703,14 @@ __global__ __launch_bounds__(256) void k_vjp_E(const double* __restrict__ u, con
         const int i = t % B, j = t / B;
         double s = 0.0;
         for (int qj = 0; qj < NP; ++qj)
-          for (int qi = 0; qi < NP; ++qi) s += T->I_G_P[qi][i] * T->I_W_P[qj][j] * jbar_q(qi, qj, 0);
+          for (int qi = 0; qi < NP; ++qi) s += tGP[qi][i] * tWP[qj][j] * jq[0][qj * NP + qi];
         JLe[t] += s;
       }
       {
         const int i = t % A, j = t / A;
         double s = 0.0;
         for (int qj = 0; qj < NP; ++qj)
-          for (int qi = 0; qi < NP; ++qi) s += T->I_W_P[qi][i] * T->I_G_P[qj][j] * jbar_q(qi, qj, 1);
+          for (int qi = 0; qi < NP; ++qi) s += tWP[qi][i] * tGP[qj][j] * jq[1][qj * NP + qi];
         JLe[AB + t] += s;
       }
     }

@@ -40,6 +40,18 @@ inline thread_local EmuIdx threadIdx{0, 0, 0}, blockIdx{0, 0, 0};
 inline thread_local dim3 blockDim, gridDim;
 inline thread_local std::barrier<>* emu_bar = nullptr;
 inline void __syncthreads() { emu_bar->arrive_and_wait(); }
+// barrier that returns nonzero in every thread when pred is nonzero in any thread of the block
+// (blocks run one after another, so one accumulator serves them all)
+inline std::atomic<int> emu_or_acc{0};
+inline int __syncthreads_or(int pred) {
+  emu_bar->arrive_and_wait();
+  if (pred) emu_or_acc.fetch_or(1);
+  emu_bar->arrive_and_wait();
+  const int r = emu_or_acc.load();
+  emu_bar->arrive_and_wait();
+  emu_or_acc.store(0);
+  return r;
+}
 
 inline int atomicOr(int* a, int v) { return __atomic_fetch_or(a, v, __ATOMIC_SEQ_CST); }
 inline unsigned long long atomicAdd(unsigned long long* a, unsigned long long v) {

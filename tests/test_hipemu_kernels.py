@@ -466,3 +466,34 @@ def test_emulated_batch_run_table_equals_individual(emu, graph):
                 assert (a == r).all()
     assert halved  # the blast member needed a halving and took the individual redo
     lib.mhd25_batch_destroy(b)
+
+
+@pytest.mark.parametrize("pm", [(2, 1), (3, 3)])
+def test_emulated_magnetic_vjp_with_eta(emu, pm):
+    """The magnetic VJP kernels (eta term included, on every element and on none) equal the oracle's
+    transposed JVP element by element on a 3 x 2 mesh."""
+    lib, pk = emu
+    p, m = pm
+    L, U, Bx, By, Bz = W.random_state(3, 2, p, m, seed=3, domain=(0, 1.5, 0, 1.0), amp=0.3)
+    M = omesh(L)
+    rho, e, u = O.to_primitive(M, U)
+    rng = np.random.default_rng(7)
+    cots = [rng.standard_normal(a.shape) for a in (e, u, Bx, By, Bz)]
+    ins = [u, Bx, By, Bz]
+    for eta in (np.random.default_rng(5).uniform(0, 0.05, M.K), None):
+        grads = [np.zeros(a.size) for a in ins]
+        for blk, a in enumerate(ins):
+            for k in range(a.size):
+                V = [np.zeros_like(x) for x in ins]
+                V[blk].reshape(-1)[k] = 1.0
+                outs = O.rhs_magnetic_jvp(M, rho, u, Bx, By, Bz, eta, *V)
+                grads[blk][k] = sum((c * o).sum() for c, o in zip(cots, outs))
+        h = context(lib, pk, L, pk.Options.make())
+        got = [np.zeros_like(a) for a in ins]
+        args = [np.ascontiguousarray(a) for a in (rho, u, Bx, By, Bz)]
+        assert lib.mhd25_rhs_magnetic_vjp(h, *[ptr(a) for a in args], None if eta is None else ptr(eta),
+                                          *[ptr(np.ascontiguousarray(c)) for c in cots], *[ptr(g) for g in got]) == 0
+        lib.mhd25_destroy(h)
+        for g, r, a in zip(got, grads, ins):
+            r = r.reshape(a.shape)
+            assert np.abs(g - r).max() <= 1e-12 * np.abs(r).max()
