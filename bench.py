@@ -495,6 +495,8 @@ def main():
                     help="write profiles/kernel_counters.json from three rocprofv3 --pmc output directories (no GPU)")
     ap.add_argument("--ensemble-graph-only", action="store_true",
                     help="time only the graph-replayed run-table batch step of the 64-run ensemble (for profiling)")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="time only the forward operators and their VJPs on the timed workload (for profiling)")
     args = ap.parse_args()
     if args.ingest:
         out = ingest_counters(args.ingest)
@@ -521,6 +523,9 @@ def main():
     S = pk.Solver.from_layout(L, pk.Options.full(reduced_2d2v=int(args.reduced_2d2v)))
     g = [torch.from_numpy(a).to("cuda") for a in (U, Bx, By, Bz)]
     del U, Bx, By, Bz
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_cost_ratio_full_size": adjoint_ratio_full(S, *g, reps=5)}), flush=True)
+        return
     K = L.K
     nn = (N + 1) ** 2
 

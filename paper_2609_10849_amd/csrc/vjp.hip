@@ -725,7 +725,21 @@ __global__ __launch_bounds__(256) void k_vjp_J(const double* __restrict__ Jbar, 
   constexpr int A = C::A, B = C::B, AA = C::AA, AB = C::AB, BB = C::BB, EB = C::EB, NT = C::NT;
   __shared__ double lz[EB][AA], lx[EB][AB], ly[EB][AB];
   __shared__ double qx_[EB][AA], qy_[EB][AA], zg[EB][BB];
+  // the interpolation and derivative tables, staged in LDS (lane-dependent indexes into the device
+  // table would each be a vector memory load)
+  __shared__ double tDWG[MHD_MAXN][MHD_MAXN], tDWQ[MHD_MAXN][MHD_MAXN], tIGQ[MHD_MAXN][MHD_MAXN], tIVG[MHD_MAXN][MHD_MAXN], tIWQ[MHD_MAXN][MHD_MAXN];
+  __shared__ double tww[MHD_MAXN], twg[MHD_MAXN], twq[MHD_MAXN];
   const int tid = threadIdx.x, el = tid / NT, t = tid - el * NT;
+  for (int k = tid; k < MHD_MAXN * MHD_MAXN; k += 256) {
+    const int r = k / MHD_MAXN, c = k % MHD_MAXN;
+    tDWG[r][c] = T->D_W_G[r][c];
+    tDWQ[r][c] = T->D_W_Q[r][c];
+    tIGQ[r][c] = T->I_G_Q[r][c];
+    tIVG[r][c] = T->I_V_G[r][c];
+    tIWQ[r][c] = T->I_W_Q[r][c];
+  }
+  if (tid < MHD_MAXN) { tww[tid] = T->ww[tid]; twg[tid] = T->wg[tid]; twq[tid] = T->wq[tid]; }
+  __syncthreads();  // the load phase below already reads the tables
   const long e = (long)blockIdx.x * EB + el;
   const bool act = el < EB && e < mp.K;
   long ex, ey;
@@ -734,20 +748,20 @@ __global__ __launch_bounds__(256) void k_vjp_J(const double* __restrict__ Jbar, 
   if (act) {
     for (int k = t; k < AA; k += NT) {
       const int i = k % A, j = k / A;
-      const double wx = (i == 0 || i == A - 1) ? T->ww[0] + T->ww[A - 1] : T->ww[i];
-      const double wy = (j == 0 || j == A - 1) ? T->ww[0] + T->ww[A - 1] : T->ww[j];
+      const double wx = (i == 0 || i == A - 1) ? tww[0] + tww[A - 1] : tww[i];
+      const double wy = (j == 0 || j == A - 1) ? tww[0] + tww[A - 1] : tww[j];
       lz[el][k] = Jzb[gix(mp, B, ex, ey, i, j)] / (mp.J * wx * wy);
     }
     for (int k = t; k < AB; k += NT) {
       {
         const int i = k % B, j = k / B;
-        const double wy = (j == 0 || j == A - 1) ? T->ww[0] + T->ww[A - 1] : T->ww[j];
-        lx[el][k] = Jxb[gix(mp, B, ex, ey, i, j)] / (mp.J * T->wg[i] * wy);
+        const double wy = (j == 0 || j == A - 1) ? tww[0] + tww[A - 1] : tww[j];
+        lx[el][k] = Jxb[gix(mp, B, ex, ey, i, j)] / (mp.J * twg[i] * wy);
       }
       {
         const int i = k % A, j = k / A;
-        const double wx = (i == 0 || i == A - 1) ? T->ww[0] + T->ww[A - 1] : T->ww[i];
-        ly[el][k] = Jyb[gix(mp, B, ex, ey, i, j)] / (mp.J * wx * T->wg[j]);
+        const double wx = (i == 0 || i == A - 1) ? tww[0] + tww[A - 1] : tww[i];
+        ly[el][k] = Jyb[gix(mp, B, ex, ey, i, j)] / (mp.J * wx * twg[j]);
       }
     }
   }
@@ -757,18 +771,18 @@ __global__ __launch_bounds__(256) void k_vjp_J(const double* __restrict__ Jbar, 
     double sx = 0.0, sy = 0.0;
     for (int j = 0; j < A; ++j)
       for (int i = 0; i < A; ++i) {
-        sx += lz[el][j * A + i] * T->I_W_Q[qx][i] * T->D_W_Q[qy][j];
-        sy += lz[el][j * A + i] * T->D_W_Q[qx][i] * T->I_W_Q[qy][j];
+        sx += lz[el][j * A + i] * tIWQ[qx][i] * tDWQ[qy][j];
+        sy += lz[el][j * A + i] * tDWQ[qx][i] * tIWQ[qy][j];
       }
-    const double wgt = mp.J * T->wq[qx] * T->wq[qy];
+    const double wgt = mp.J * twq[qx] * twq[qy];
     qx_[el][t] = wgt * (2.0 / mp.hy) * sx;
     qy_[el][t] = -wgt * (2.0 / mp.hx) * sy;
   }
   if (act && t < BB) {  // B_z-bar at the Gauss_m points (gx, gy)
     const int gx = t % B, gy = t / B;
     double s = 0.0;
-    for (int j = 0; j < A; ++j) s += -(2.0 / mp.hy) * mp.J * T->wg[gx] * T->wg[gy] * T->D_W_G[gy][j] * lx[el][j * B + gx];
-    for (int i = 0; i < A; ++i) s += (2.0 / mp.hx) * mp.J * T->wg[gy] * T->wg[gx] * T->D_W_G[gx][i] * ly[el][gy * A + i];
+    for (int j = 0; j < A; ++j) s += -(2.0 / mp.hy) * mp.J * twg[gx] * twg[gy] * tDWG[gy][j] * lx[el][j * B + gx];
+    for (int i = 0; i < A; ++i) s += (2.0 / mp.hx) * mp.J * twg[gy] * twg[gx] * tDWG[gx][i] * ly[el][gy * A + i];
     zg[el][t] = s;
   }
   __syncthreads();
@@ -779,14 +793,14 @@ __global__ __launch_bounds__(256) void k_vjp_J(const double* __restrict__ Jbar, 
       const int i = t % A, j = t / A;
       double s = 0.0;
       for (int qy = 0; qy < A; ++qy)
-        for (int qx = 0; qx < A; ++qx) s += T->I_G_Q[qy][j] * T->I_W_Q[qx][i] * qx_[el][qy * A + qx];
+        for (int qx = 0; qx < A; ++qx) s += tIGQ[qy][j] * tIWQ[qx][i] * qx_[el][qy * A + qx];
       BLe[t] += s;
     }
     {  // B_y local (i < B, j < A): B_y(q) = sum I_W_Q[qy][j] I_G_Q[qx][i] by
       const int i = t % B, j = t / B;
       double s = 0.0;
       for (int qy = 0; qy < A; ++qy)
-        for (int qx = 0; qx < A; ++qx) s += T->I_W_Q[qy][j] * T->I_G_Q[qx][i] * qy_[el][qy * A + qx];
+        for (int qx = 0; qx < A; ++qx) s += tIWQ[qy][j] * tIGQ[qx][i] * qy_[el][qy * A + qx];
       BLe[AB + t] += s;
     }
   }
@@ -794,7 +808,7 @@ __global__ __launch_bounds__(256) void k_vjp_J(const double* __restrict__ Jbar, 
     const int ii = t % B, jj = t / B;
     double s = 0.0;
     for (int gy = 0; gy < B; ++gy)
-      for (int gx = 0; gx < B; ++gx) s += T->I_V_G[gx][ii] * T->I_V_G[gy][jj] * zg[el][gy * B + gx];
+      for (int gx = 0; gx < B; ++gx) s += tIVG[gx][ii] * tIVG[gy][jj] * zg[el][gy * B + gx];
     BLe[2 * AB + t] += s;
   }
 }
