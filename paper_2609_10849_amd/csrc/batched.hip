@@ -38,14 +38,13 @@ int hydro_stage_b(mhd25_ctx* c, const double* Ust, double* Uout, double tau, con
 int reset_attempt(mhd25_ctx* c);
 int dcopy(mhd25_ctx* c, const double* a, double* b, long n);
 int mag_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u);
-int mag_to_conservative(mhd25_ctx* c, const double* rho, const double* e, const double* u, double* U);
 int extra_max_dev(mhd25_ctx* c, const double* a, long n, double* d_out);
 int entry_snapshot(mhd25_ctx* c, const double* U, double* snapU, const double* const* B, double* saveB);
 int hydro_rt_launch(const RtRecord& h, const void* dargs, const int* dboff, int nr, long nblocks, hipStream_t s);
 int magnetic_rt_launch(const RtRecord& h, const void* dargs, const int* dboff, int nr, long nblocks, hipStream_t s);
 int extra_rt_launch(const RtRecord& h, const void* dargs, const int* dboff, int nr, long nblocks, hipStream_t s);
 int step_magnetic_impl(mhd25_ctx* c, const double* rho, double* e, double* u, double* Bx, double* By, double* Bz,
-                       double tau, mhd25_report* rep);
+                       double tau, mhd25_report* rep, double* Uc);
 
 struct zero_args {
   int* fail;
@@ -169,9 +168,9 @@ static int strang_deferred(mhd25_ctx* c, double* U, double* Bx, double* By, doub
   const bool outer = c->opt.strang_order == 1;  // M(dt/2) H(dt) M(dt/2) instead of H(dt/2) M(dt) H(dt/2)
   auto magnetic = [&](double tau) -> int {
     BTRY(mag_to_primitive(c, U, c->rho, c->e, c->u));
-    BTRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, tau, nullptr));
+    BTRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, tau, nullptr, U));  // ends with the exchange to U
     if (c->opt.ar && c->opt.C_eta > 0.0) BTRY(extra_max_dev(c, c->eta, c->mp.K, eta_out));
-    return mag_to_conservative(c, c->rho, c->e, c->u, U);
+    return 0;
   };
   if (outer) BTRY(magnetic(0.5 * dt));
   BTRY(attempt_deferred(c, U, outer ? dt : 0.5 * dt, fail, acc));

@@ -26,7 +26,7 @@ int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, doub
                     const double* By, const double* Bz);
 int mag_velocity_prep(mhd25_ctx* c, const double* rho);
 int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
-                       const double* By, const double* Bz, bool stats_ready);
+                       const double* By, const double* Bz, bool stats_ready, double* Uc);
 int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,
                const double* Bz, double* eta);
 int mag_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u);
@@ -320,8 +320,10 @@ int mhd25_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, do
 }  // extern "C"
 
 // the magnetic substep without the entry check (the Strang step's own state is admissible)
+// With Uc (the conserved state whose density row holds rho) the substep ends with the exchange back
+// to Uc: formed inside the last velocity-OE projection, or by the exchange kernel without velocity OE.
 int step_magnetic_impl(mhd25_ctx* c, const double* rho, double* e, double* u, double* Bx, double* By, double* Bz,
-                       double tau, mhd25_report* rep) {
+                       double tau, mhd25_report* rep, double* Uc) {
   const long KN = c->mp.K * c->nn, G = c->G;
   const double* eta = nullptr;
   double eta_max = 0.0;
@@ -355,8 +357,9 @@ int step_magnetic_impl(mhd25_ctx* c, const double* rho, double* e, double* u, do
     io.ca = cas[s]; io.cb = cbs[s]; io.tau = tau;
     io.ustats = c->opt.oe_mag ? c->stats : nullptr;  // the update also forms the sensor's u statistics
     TRY(mag_update(c, io, 1));
-    if (c->opt.oe_mag) TRY(mag_velocity_apply(c, tau, rho, ou, oe, ox, oy, oz, true));
+    if (c->opt.oe_mag) TRY(mag_velocity_apply(c, tau, rho, ou, oe, ox, oy, oz, true, s == 2 ? Uc : nullptr));
   }
+  if (Uc && !c->opt.oe_mag) TRY(mag_to_conservative(c, rho, e, u, Uc));
   if (rep) {
     std::memset(rep, 0, sizeof(*rep));
     rep->eta_max = eta_max; rep->dt = tau;
@@ -378,7 +381,7 @@ int mhd25_step_magnetic(mhd25_ctx* c, const double* rho, double* e, double* u, d
     if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->dt = tau; rep->status = 2; }
     return fail(c, 2, "inadmissible input: a non-finite value or a non-positive nodal density or internal energy");
   }
-  return step_magnetic_impl(c, rho, e, u, Bx, By, Bz, tau, rep);
+  return step_magnetic_impl(c, rho, e, u, Bx, By, Bz, tau, rep, nullptr);
 }
 
 int mhd25_to_primitive(mhd25_ctx* c, const double* U, double* rho, double* e, double* u) {
@@ -417,18 +420,15 @@ int mhd25_strang_step(mhd25_ctx* c, double* U, double* Bx, double* By, double* B
   if (c->opt.strang_order == 0) {
     s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h1, true);  // also leaves (rho, e, u) of U
     if (s != 0) return restore(s);
-    TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, dt, &m));
-    TRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
+    TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, dt, &m, U));
     s = hydro_substep_rec(c, U, 0.5 * dt, 0, &h2);
   } else {
     // magnetic-outer composition (the entry word is read by the hydro attempt in the middle)
     TRY(mag_to_primitive(c, U, c->rho, c->e, c->u));
-    TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, 0.5 * dt, &m));
-    TRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
+    TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, 0.5 * dt, &m, U));
     s = hydro_substep_rec(c, U, dt, 0, &h1, true);  // also leaves (rho, e, u) of U
     if (s != 0) return restore(s);
-    TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, 0.5 * dt, &m));
-    TRY(mag_to_conservative(c, c->rho, c->e, c->u, U));
+    TRY(step_magnetic_impl(c, c->rho, c->e, c->u, Bx, By, Bz, 0.5 * dt, &m, U));
   }
   r.substeps_attempted = h1.substeps_attempted + h2.substeps_attempted;
   r.substeps_accepted = h1.substeps_accepted + h2.substeps_accepted;

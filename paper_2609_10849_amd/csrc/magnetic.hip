@@ -1168,7 +1168,7 @@ template <int P, int BS, bool R2>
 __device__ __forceinline__ void vel_proj_body(const double* __restrict__ rho, double* __restrict__ u,
                                                   double* __restrict__ en, const double* __restrict__ Psi,
                                                   const double* __restrict__ Dfac, const HydroTab* __restrict__ H,
-                                                  MeshP mp, long blk) {
+                                                  MeshP mp, double* __restrict__ Uc, long blk) {
   using C = VPJ<P, BS>;
   constexpr int NP = C::NP, NN = C::NN, EB = C::EB, NNP = C::NNP;
   constexpr long PS = C::PS, RS = C::RS;
@@ -1202,8 +1202,10 @@ __device__ __forceinline__ void vel_proj_body(const double* __restrict__ rho, do
       }
     }
   }
+  double rq = 0.0;
   if (act) {
-    const double wq = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
+    rq = rho[e * NN + q];
+    const double wq = mp.J * H->w[qi] * H->w[qj] * rq;
 #pragma unroll
     for (int d = 0; d < (R2 ? 2 : 3); ++d) sv[el][d][q] = wq * u[d * KN + e * NN + q];  // u_z = 0 in 2D2V
     if (q < NP) sD[el][q] = Dfac[e * NP + q];
@@ -1235,7 +1237,7 @@ __device__ __forceinline__ void vel_proj_body(const double* __restrict__ rho, do
     wl[1][shell_of(k)] += sc[el][1][k] * pk;
     if (!R2) wl[2][shell_of(k)] += sc[el][2][k] * pk;
   }
-  double heat = 0.0;
+  double heat = 0.0, un[3] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int d = 0; d < (R2 ? 2 : 3); ++d) {
     double v = wl[d][0];
@@ -1245,17 +1247,29 @@ __device__ __forceinline__ void vel_proj_body(const double* __restrict__ rho, do
       v += Dl * wl[d][l];
       heat += 0.5 * (1.0 - Dl * Dl) * wl[d][l] * wl[d][l];
     }
-    u[d * KN + e * NN + q] = v;
+    un[d] = v;
   }
-  en[e * NN + q] += heat;
+  const long n = e * NN + q;
+  if (!Uc) {
+#pragma unroll
+    for (int d = 0; d < (R2 ? 2 : 3); ++d) u[d * KN + n] = un[d];
+    en[n] += heat;
+  } else {
+    // last stage of a Strang step's magnetic substep: the exchange back to the conserved state
+    // (section "Local variable exchange") is formed here instead of by a separate pass; the density
+    // row of Uc already holds rho, and the primitive copies are not needed afterwards
+    const double ev = en[n] + heat;
+    Uc[KN + n] = rq * un[0]; Uc[2 * KN + n] = rq * un[1]; Uc[3 * KN + n] = rq * un[2];
+    Uc[4 * KN + n] = rq * ev + 0.5 * rq * (un[0] * un[0] + un[1] * un[1] + un[2] * un[2]);
+  }
 }
 
 template <int P, int BS, bool R2>
 __global__ __launch_bounds__(BS) void k_vel_proj(const double* __restrict__ rho, double* __restrict__ u,
                                                   double* __restrict__ en, const double* __restrict__ Psi,
                                                   const double* __restrict__ Dfac, const HydroTab* __restrict__ H,
-                                                  MeshP mp) {
-  vel_proj_body<P, BS, R2>(rho, u, en, Psi, Dfac, H, mp, (long)blockIdx.x);
+                                                  MeshP mp, double* __restrict__ Uc) {
+  vel_proj_body<P, BS, R2>(rho, u, en, Psi, Dfac, H, mp, Uc, (long)blockIdx.x);
 }
 
 struct vel_proj_args {
@@ -1266,13 +1280,14 @@ struct vel_proj_args {
   const double* Dfac;
   const HydroTab* H;
   MeshP mp;
+  double* Uc;
 };
 
 template <int P, int BS, bool R2>
 __global__ __launch_bounds__(BS) void k_vel_proj_rt(const vel_proj_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
   const vel_proj_args& a = A[r];
-  vel_proj_body<P, BS, R2>(gl(a.rho), gl(a.u), gl(a.en), gl(a.Psi), gl(a.Dfac), gl(a.H), a.mp, (long)blockIdx.x - boff[r]);
+  vel_proj_body<P, BS, R2>(gl(a.rho), gl(a.u), gl(a.en), gl(a.Psi), gl(a.Dfac), gl(a.H), a.mp, gl(a.Uc), (long)blockIdx.x - boff[r]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1866,7 +1881,7 @@ int mag_velocity_prep(mhd25_ctx* c, const double* rho) {
 }
 
 int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, double* e, const double* Bx,
-                       const double* By, const double* Bz, bool stats_ready) {
+                       const double* By, const double* Bz, bool stats_ready, double* Uc) {
   const long K = c->mp.K;
   const int nn = (c->p + 1) * (c->p + 1), eb = 256 / nn, eb2 = MHD_VP_BS / nn;
   const long nb = (K + eb - 1) / eb, nb2 = (K + eb2 - 1) / eb2;
@@ -1885,7 +1900,7 @@ int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, d
     if (!stats_ready) { c->err = "run-table plan: velocity statistics must come from the update"; return -2; }
     rt_record(c, RT_VEL_SENSOR, mkey(c->p, c->m, r2), nb,
               vel_sensor_args{rho, u, Bx, By, Bz, c->lines, c->glob, c->dfac, c->d_ht, c->d_mt, c->mp, tau, c->opt.s_M});
-    rt_record(c, RT_VEL_PROJ, mkey(c->p, c->m, r2), nb2, vel_proj_args{rho, u, e, c->psi, c->dfac, c->d_ht, c->mp});
+    rt_record(c, RT_VEL_PROJ, mkey(c->p, c->m, r2), nb2, vel_proj_args{rho, u, e, c->psi, c->dfac, c->d_ht, c->mp, Uc});
     return 0;
   }
 #define VSN(P, M)                                                                                                   \
@@ -1901,9 +1916,9 @@ int mag_velocity_apply(mhd25_ctx* c, double tau, const double* rho, double* u, d
 #undef VSN
 #define VPR(P)                                                                                                      \
   if (r2) hipLaunchKernelGGL((k_vel_proj<P, MHD_VP_BS, true>), dim3(nb2), dim3(MHD_VP_BS), 0, c->stream, rho, u, e, \
-                             c->psi, c->dfac, c->d_ht, c->mp);                                                        \
+                             c->psi, c->dfac, c->d_ht, c->mp, Uc);                                                    \
   else hipLaunchKernelGGL((k_vel_proj<P, MHD_VP_BS, false>), dim3(nb2), dim3(MHD_VP_BS), 0, c->stream, rho, u, e,   \
-                          c->psi, c->dfac, c->d_ht, c->mp)
+                          c->psi, c->dfac, c->d_ht, c->mp, Uc)
   {
     T_BEGIN(3);
     switch (c->p) { case 1: VPR(1); break; case 2: VPR(2); break; case 3: VPR(3); break; case 4: VPR(4); break;
@@ -1918,7 +1933,7 @@ int mag_velocity_oe(mhd25_ctx* c, double tau, const double* rho, double* u, doub
                     const double* By, const double* Bz) {
   int r = mag_velocity_prep(c, rho);
   if (r) return r;
-  return mag_velocity_apply(c, tau, rho, u, e, Bx, By, Bz, false);
+  return mag_velocity_apply(c, tau, rho, u, e, Bx, By, Bz, false, nullptr);
 }
 
 int mag_ar_eta(mhd25_ctx* c, const double* rho, const double* u, const double* Bx, const double* By,
