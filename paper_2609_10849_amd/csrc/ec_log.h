@@ -8,7 +8,8 @@
 // Natural logarithm of the EC flux variables: x = m 2^k with m in [sqrt(1/2), sqrt(2)), and
 // log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...) with s = (m - 1) / (m + 1), |s| < 0.1716; the
 // series is summed to s^21 (relative truncation below 3e-18) and k ln 2 is added in two parts (the
-// leading part holds 32 significant bits, so k times it is exact).  Within 2 ulp of the correctly
+// leading part holds 32 significant bits, so k times it is exact; the two constants are the public
+// ln2_hi / ln2_lo split of Sun's freely distributable fdlibm).  Within 2 ulp of the correctly
 // rounded logarithm over the whole double range, with about a third of the
 // library function's instructions.  Special arguments as the library: log 0 = -inf, log inf = inf,
 // NaN for negative and NaN arguments.
