@@ -47,6 +47,16 @@ typedef struct {
   int32_t p;                /* DGSEM degree, 1..6                                    */
   int32_t m;                /* magnetic degree, p-1 or p                             */
   double gamma;             /* ratio of specific heats (> 1)                         */
+  int32_t walls;            /* 0 (default): periodic Omega.  Bit 0 (bit 1): mirror walls normal to x
+                             * (to y), section "MHD rotor": Omega is the mirror-doubled image of the
+                             * box [x0, (x0+x1)/2] (resp. [y0, (y0+y1)/2]) in that direction, nx (ny)
+                             * even, and the caller supplies states with the mirror parities across
+                             * the box's walls (rho, p, tangential u even, normal u odd; B_x even and
+                             * B_y odd across both kinds of wall; B_z odd across x-normal and even
+                             * across y-normal walls).  Every operator is periodic on Omega, which
+                             * keeps those parities; the amplitudes of the stabilisers (OE, velocity
+                             * OE, A.R.) are taken over the box: the first nx/2 (ny/2) elements of
+                             * each row (column) and the box's DOFs, its wall nodes included.    */
 } mhd25_mesh_desc;
 
 typedef struct {
@@ -85,8 +95,8 @@ void mhd25_default_options(mhd25_options* opt);
 
 /* Create a context for one mesh.  `hip_stream` is a hipStream_t (NULL = default stream).
  * Allocates all device workspace (about 12 state-sized arrays).  Returns 0, or -1 for a null
- * pointer, nx or ny < 1, an empty domain, gamma <= 1, nx * ny * (m + 1) above 2^31 - 2^16 (far beyond
- * device memory) or invalid options; -4 for p outside 1..6 or m not in {p - 1, p}; -3 when host or device memory runs out. */
+ * pointer, nx or ny < 1, an empty domain, gamma <= 1, nx * ny * (m + 1) above 2^31 - 2^16 or
+ * nx * ny * (p + 1)^2 nodes at or above 2^29 (both far beyond device memory) or invalid options; -4 for p outside 1..6 or m not in {p - 1, p}; -3 when host or device memory runs out. */
 int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* hip_stream, mhd25_ctx** out);
 void mhd25_destroy(mhd25_ctx* ctx);
 /* Replace the options of an existing context (host-side only). */

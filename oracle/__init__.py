@@ -74,10 +74,13 @@ class Mesh:
     """Periodic Cartesian mesh: nx x ny elements on [x0,x1]x[y0,y1], Euler degree p,
     compatible magnetic degree m, ratio of specific heats gamma."""
 
-    def __init__(self, nx, ny, p, m, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=5.0 / 3.0):
+    def __init__(self, nx, ny, p, m, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=5.0 / 3.0, walls=0):
         self.nx, self.ny, self.p, self.m = int(nx), int(ny), int(p), int(m)
         self.x0, self.x1, self.y0, self.y1, self.gamma = map(float, (x0, x1, y0, y1, gamma))
-        self.im = np.array([self.nx, self.ny, self.p, self.m], dtype=np.int32)
+        self.walls = int(walls)  # bit 0 / bit 1: mirror-doubled in x / y, amplitudes over the box
+        if not 0 <= self.walls <= 3 or (self.walls & 1 and self.nx % 2) or (self.walls & 2 and self.ny % 2):
+            raise ValueError("walls is a 2-bit mask, and a mirror-doubled direction has an even element count")
+        self.im = np.array([self.nx, self.ny, self.p, self.m, self.walls], dtype=np.int32)
         self.dm = np.array([self.x0, self.x1, self.y0, self.y1, self.gamma], dtype=np.float64)
         self.K = self.nx * self.ny
         self.np1 = self.p + 1

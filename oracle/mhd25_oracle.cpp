@@ -18,6 +18,10 @@
 //   rho, e: [K][p+1][p+1]; u: [3][K][p+1][p+1];
 //   every magnetic array (B_x, B_y, B_z, E_*, J_*) is a periodic grid
 //   [ny*(m+1)][nx*(m+1)] of physical nodal values (see node_* helpers below).
+// Mirror walls (section "MHD rotor", reading R30): with bit 0 (bit 1) of walls set the mesh is the
+// mirror-doubled image, in x (y), of the box formed by the first nx/2 (ny/2) elements of each row
+// (column); every operator stays periodic on the doubled mesh and only the stabilisers' amplitudes
+// (line_stats, B_global_amp) are taken over the box.
 //
 // Build: g++ -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
 
@@ -156,6 +160,8 @@ static double dleg_end(int a, int r, int side /*+1 or -1*/) {
 // ---------------------------------------------------------------------------
 struct Mesh {
   int nx, ny, p, m;
+  int walls;   // bit 0 / bit 1: mirror-doubled in x / y (statistics over the box)
+  int bx, by;  // elements per row / column of the box the statistics cover
   double x0, x1, y0, y1, gamma, hx, hy, J;  // J = |J_K| = hx*hy/4
   int np;      // (p+1)
   int nn;      // (p+1)^2 nodes per element
@@ -176,7 +182,8 @@ struct Opts {
 
 static Mesh make_mesh(const int* im, const double* dm) {
   Mesh M;
-  M.nx = im[0]; M.ny = im[1]; M.p = im[2]; M.m = im[3];
+  M.nx = im[0]; M.ny = im[1]; M.p = im[2]; M.m = im[3]; M.walls = im[4];
+  M.bx = (M.walls & 1) ? M.nx / 2 : M.nx; M.by = (M.walls & 2) ? M.ny / 2 : M.ny;
   M.x0 = dm[0]; M.x1 = dm[1]; M.y0 = dm[2]; M.y1 = dm[3]; M.gamma = dm[4];
   M.hx = (M.x1 - M.x0) / M.nx; M.hy = (M.y1 - M.y0) / M.ny; M.J = M.hx * M.hy / 4.0;
   M.np = M.p + 1; M.nn = M.np * M.np; M.M1 = M.m + 1; M.K = (long)M.nx * M.ny;
@@ -427,20 +434,27 @@ static void jump_measure(const Mesh& M, long e, int dir, FieldFn field, double* 
 //   const_flag = 1 if the field is constant to roundoff (reading R11).
 struct LineStats { double dOm; std::vector<double> rowD, colD; int const_flag; };
 
+// With mirror walls every sum, mean and extremum runs over the box: its elements, and for a row
+// (column) the row's (column's) first bx (by) elements.
+static bool in_box(const Mesh& M, long e) { return e % M.nx < M.bx && e / M.nx < M.by; }
+
 static LineStats line_stats(const Mesh& M, const double* w /*[K][nn]*/) {
   LineStats S;
   double sum = 0.0, area = 0.0, amax = 0.0;
-  for (long e = 0; e < M.K; ++e)
+  for (long e = 0; e < M.K; ++e) {
+    if (!in_box(M, e)) continue;
     for (int j = 0; j < M.np; ++j)
       for (int i = 0; i < M.np; ++i) {
         double v = w[e * M.nn + j * M.np + i];
         sum += M.J * M.om[i] * M.om[j] * v;
         amax = std::max(amax, std::fabs(v));
       }
-  area = (double)M.K * M.hx * M.hy;
+  }
+  area = (double)M.bx * M.by * M.hx * M.hy;
   double mean = sum / area;
   double d = 0.0, vmin = w[0], vmax = w[0];
   for (long q = 0; q < M.K * M.nn; ++q) {
+    if (!in_box(M, q / M.nn)) continue;
     d = std::max(d, std::fabs(w[q] - mean));
     vmin = std::min(vmin, w[q]); vmax = std::max(vmax, w[q]);
   }
@@ -450,7 +464,7 @@ static LineStats line_stats(const Mesh& M, const double* w /*[K][nn]*/) {
   S.const_flag = vmax - vmin <= 1024.0 * 2.220446049250313e-16 * amax ? 1 : 0;
   S.rowD.assign(M.ny, 0.0); S.colD.assign(M.nx, 0.0);
   for (int pass = 0; pass < 2; ++pass) {
-    int nl = pass == 0 ? M.ny : M.nx, len = pass == 0 ? M.nx : M.ny;
+    int nl = pass == 0 ? M.ny : M.nx, len = pass == 0 ? M.bx : M.by;
     for (int l = 0; l < nl; ++l) {
       double s = 0.0, a = 0.0;
       for (int t = 0; t < len; ++t) {
@@ -1048,6 +1062,7 @@ static void B_global_amp(const Mesh& M, const double* Bx, const double* By, cons
   double integ = 0.0;
   const int nq = M.m + 2;
   for (long e = 0; e < M.K; ++e) {
+    if (!in_box(M, e)) continue;
     LocalB<double> L = local_B(M, e, Bx, By, Bz);
     for (int qy = 0; qy < nq; ++qy)
       for (int qx = 0; qx < nq; ++qx) {
@@ -1055,8 +1070,13 @@ static void B_global_amp(const Mesh& M, const double* Bx, const double* By, cons
         integ += M.J * M.oq[qx] * M.oq[qy] * BB[comp];
       }
   }
-  double mean = integ / ((double)M.K * M.hx * M.hy), d = 0.0, amax = 0.0, vmin = f[0], vmax = f[0];
+  double mean = integ / ((double)M.bx * M.by * M.hx * M.hy), d = 0.0, amax = 0.0, vmin = f[0], vmax = f[0];
+  // the box's DOFs: grid columns (rows) up to bx (by) (m+1) positions, and the wall position itself
+  // where the component's nodes in that direction are the shared GLL_{m+1} nodes (B_x in x, B_y in y)
+  const long NXg = (long)M.nx * M.M1, lim_x = (long)M.bx * M.M1 + ((M.walls & 1) && comp == 0 ? 1 : 0),
+             lim_y = (long)M.by * M.M1 + ((M.walls & 2) && comp == 1 ? 1 : 0);
   for (long g = 0; g < G; ++g) {
+    if (g % NXg >= lim_x || g / NXg >= lim_y) continue;
     d = std::max(d, std::fabs(f[g] - mean)); amax = std::max(amax, std::fabs(f[g]));
     vmin = std::min(vmin, f[g]); vmax = std::max(vmax, f[g]);
   }

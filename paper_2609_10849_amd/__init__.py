@@ -21,7 +21,7 @@ _dp = ctypes.c_void_p
 class MeshDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("x0", ctypes.c_double), ("x1", ctypes.c_double),
                 ("y0", ctypes.c_double), ("y1", ctypes.c_double), ("p", ctypes.c_int32), ("m", ctypes.c_int32),
-                ("gamma", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("walls", ctypes.c_int32)]
 
 
 class Options(ctypes.Structure):
@@ -139,11 +139,11 @@ class Solver:
     Layouts: U [5, K, p+1, p+1]; rho, e [K, p+1, p+1]; u [3, K, p+1, p+1]; magnetic grids
     [ny*(m+1), nx*(m+1)] (see include/mhd25.h).  All tensors float64 on the current device."""
 
-    def __init__(self, nx, ny, p, m, x0, x1, y0, y1, gamma=5.0 / 3.0, options=None, stream=None):
+    def __init__(self, nx, ny, p, m, x0, x1, y0, y1, gamma=5.0 / 3.0, options=None, stream=None, walls=0):
         if not torch.cuda.is_available():
             raise MHD25Error("no GPU visible: the HIP library has no CPU path")
         self.lib = load_library()
-        self.desc = MeshDesc(nx, ny, x0, x1, y0, y1, p, m, gamma)
+        self.desc = MeshDesc(nx, ny, x0, x1, y0, y1, p, m, gamma, walls)
         self.options = options if options is not None else Options.make()
         self.nx, self.ny, self.p, self.m = nx, ny, p, m
         self.K = nx * ny
@@ -160,7 +160,7 @@ class Solver:
 
     @classmethod
     def from_layout(cls, L, options=None):
-        return cls(L.nx, L.ny, L.p, L.m, L.x0, L.x1, L.y0, L.y1, L.gamma, options)
+        return cls(L.nx, L.ny, L.p, L.m, L.x0, L.x1, L.y0, L.y1, L.gamma, options, walls=getattr(L, "walls", 0))
 
     def close(self):
         if getattr(self, "h", None):
@@ -336,7 +336,8 @@ class Batch:
             raise MHD25Error("no GPU visible: the HIP library has no CPU path")
         self.lib = load_library()
         self.n = len(layouts)
-        arr = (MeshDesc * self.n)(*[MeshDesc(L.nx, L.ny, L.x0, L.x1, L.y0, L.y1, L.p, L.m, L.gamma) for L in layouts])
+        arr = (MeshDesc * self.n)(*[MeshDesc(L.nx, L.ny, L.x0, L.x1, L.y0, L.y1, L.p, L.m, L.gamma, getattr(L, "walls", 0))
+                                   for L in layouts])
         self.options = options if options is not None else Options.make()
         h = ctypes.c_void_p()
         r = self.lib.mhd25_batch_create(arr, self.n, ctypes.byref(self.options), _stream(), ctypes.byref(h))

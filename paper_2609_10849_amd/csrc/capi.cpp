@@ -133,6 +133,8 @@ int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stre
   if (d.p < 1 || d.p > MHD_MAXP) return -4;
   if (d.m != d.p && d.m != d.p - 1) return -4;
   if ((long)d.nx * d.ny * (d.m + 1) > MHD_MAX_ELEMENTS) return -1;
+  if ((long)d.nx * d.ny * (d.p + 1) * (d.p + 1) >= MHD_MAX_NODES) return -1;
+  if (d.walls < 0 || d.walls > 3 || ((d.walls & 1) && d.nx % 2) || ((d.walls & 2) && d.ny % 2)) return -1;
   mhd25_ctx* c = new (std::nothrow) mhd25_ctx();
   if (!c) return -3;
   c->mesh = d;
@@ -146,7 +148,11 @@ int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stre
   c->mp.J = c->mp.hx * c->mp.hy / 4.0; c->mp.gamma = d.gamma;
   c->mp.rhx = 1.0 / c->mp.hx; c->mp.rhy = 1.0 / c->mp.hy;
   c->mp.gk = 0.5 / (c->mp.gamma - 1.0);
-  c->mp.r4K = 1.0 / (4.0 * (double)c->mp.K); c->mp.r4nx = 1.0 / (4.0 * d.nx); c->mp.r4ny = 1.0 / (4.0 * d.ny);
+  c->mp.walls = d.walls;
+  c->mp.bx = (d.walls & 1) ? d.nx / 2 : d.nx; c->mp.by = (d.walls & 2) ? d.ny / 2 : d.ny;
+  c->mp.r4K = 1.0 / (4.0 * (double)c->mp.bx * c->mp.by);
+  c->mp.r4nx = 1.0 / (4.0 * c->mp.bx); c->mp.r4ny = 1.0 / (4.0 * c->mp.by);
+  c->mp.area = (double)((long)c->mp.bx * c->mp.by) * c->mp.hx * c->mp.hy;
   c->G = (long)d.nx * d.ny * c->M1 * c->M1;
   build_hydro_tables(c->p, &c->h_ht);
   build_mag_tables(c->p, c->m, &c->h_mt);

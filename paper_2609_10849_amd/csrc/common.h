@@ -55,7 +55,10 @@ struct MeshP {
   double hx, hy, J, gamma;
   double rhx, rhy;         // 1 / hx, 1 / hy
   double gk;               // 1 / (2 (gamma - 1)), the energy coefficient of the EC flux
-  double r4K, r4nx, r4ny;  // 1 / (4 K), 1 / (4 nx), 1 / (4 ny): element-average sums to means
+  int walls;               // bit 0 / bit 1: mirror walls normal to x / y, mesh doubled (see mhd25_mesh_desc)
+  int bx, by;              // elements per row / column of the box the statistics cover (nx, ny or nx/2, ny/2)
+  double r4K, r4nx, r4ny;  // 1 / (4 bx by), 1 / (4 bx), 1 / (4 by): element-average sums to means
+  double area;             // bx hx by hy, the box's area: integral sums over the box to means
   unsigned nx_mul;  // element row of e: (e * nx_mul) >> nx_sh, see elem_xy
   int nx_sh;
 };
@@ -86,6 +89,31 @@ __host__ __device__ __forceinline__ void elem_xy(const MeshP& mp, long e, long& 
   ey = row_of(mp, e);
   ex = e - ey * mp.nx;
 }
+
+// Node arrays: one component of a nodal field holds K (p+1)^2 doubles, fewer than 2^29 (mhd25_init
+// rejects larger meshes, whose state arrays alone would exceed the device memory), so the byte offset
+// of a node fits 32 bits.  A kernel addresses such an array through a buffer resource (its base in
+// scalar registers, its byte size as the range) and one 32-bit offset register per node, instead of
+// a 64-bit index product and sum per access; an access beyond the range returns 0 and is not made.
+constexpr long MHD_MAX_NODES = 1L << 29;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t node_rsrc(const double* base, long n) {
+  // word 3: 32-bit data format, the raw-buffer setting of the gfx9 family
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)(unsigned)(n * 8), 0x00020000);
+}
+__device__ __forceinline__ double bld(__amdgpu_buffer_rsrc_t r, unsigned boff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+}
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned boff, double v) {
+  using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0u, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, boff, 0, 0);
+}
+
+// 32-bit forms of the element split and of the periodic neighbour index (element indices < 2^31)
+__device__ __forceinline__ void elem_xy32(const MeshP& mp, int e, int& ex, int& ey) {
+  ey = (int)(((unsigned long long)(unsigned)e * mp.nx_mul) >> mp.nx_sh);
+  ex = e - ey * mp.nx;
+}
+__device__ __forceinline__ int wrap32(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
 // pointers of one magnetic residual / SSP-stage evaluation (magnetic.hip)
 struct MagIO {

@@ -41,17 +41,17 @@ __device__ __forceinline__ Prim make_prim(const double U[5], double g) {
 
 // Logarithmic mean (eq. euler-chandrashekar-flux) as a fraction num/den from the node values
 // a and their logarithms l.  Well separated (f^2 >= 1e-4 with f = (aR-aL)/(aR+aL)): (aR-aL)/(lR-lL).
-// Near-equal: (aL+aR) / (2 (1 + u/3 + u^2/5 + u^3/7)) with u = f^2 = tanh^2((lR-lL)/2) summed to the
-// x^8 term; the truncation of both series is below 1e-17 relative there.  The quotient is taken
-// by the caller, which folds the three divisions of the flux into one reciprocal.
+// Near-equal: with x = (lR-lL)/2 = atanh f, the mean is (aL+aR) tanh(x) / (2x) = (aL+aR) / (2 x coth x),
+// and 2 x coth x = 2 + y/6 - y^2/360 + y^3/15120 - ... in y = (lR-lL)^2 (the Laurent series of coth);
+// there y < 4.1e-4, so the first omitted term is below 1e-19 relative.  The quotient is taken by the
+// caller, which folds the three divisions of the flux into one reciprocal.
 struct Frac {
   double n, d;
 };
 __device__ __forceinline__ Frac lmean_frac(double aL, double aR, double lL, double lR) {
   const double d = aR - aL, s = aR + aL, dl = lR - lL;
-  const double x2 = 0.25 * dl * dl;
-  const double u = x2 * (1.0 - x2 * (2.0 / 3.0 - x2 * (17.0 / 45.0 - x2 * (62.0 / 315.0))));
-  const double pu = 2.0 * (1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0))));
+  const double y = dl * dl;
+  const double pu = 2.0 + y * (1.0 / 6.0 - y * (1.0 / 360.0 - y * (1.0 / 15120.0)));
   const bool near = d * d < 1e-4 * (s * s);
   return Frac{near ? s : d, near ? pu : dl};
 }
@@ -115,19 +115,17 @@ __device__ __forceinline__ void face_flux(const double uo[5], const double un[5]
   for (int c = 0; c < 5; ++c) F[c] = 0.5 * (Fo[c] + Fn[c]) - 0.5 * lam * (sgn * (un[c] - uo[c]));
 }
 
-__device__ __forceinline__ long wrap(long a, long n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
-
 // Face f = 2 D + side of element (ex, ey) (D 0: the x-normal faces, D 1: the y-normal faces; side 0
 // is the face at -1) and the face node `line` on it: the neighbour element en across the face, the
 // element's own face node qo and the neighbour's node qn at the same point (periodic mesh).
 template <int P>
-__device__ __forceinline__ void face_match(const MeshP& mp, long ex, long ey, int D, int side, int line, long& en,
+__device__ __forceinline__ void face_match(const MeshP& mp, int ex, int ey, int D, int side, int line, int& en,
                                            int& qo, int& qn) {
   constexpr int NP = P + 1;
   const int pos = side ? P : 0;
   qo = D == 0 ? line * NP + pos : pos * NP + line;
   qn = D == 0 ? line * NP + (P - pos) : (P - pos) * NP + line;
-  en = D == 0 ? ey * mp.nx + wrap(ex + (side ? 1 : -1), mp.nx) : wrap(ey + (side ? 1 : -1), mp.ny) * mp.nx + ex;
+  en = D == 0 ? ey * mp.nx + wrap32(ex + (side ? 1 : -1), mp.nx) : wrap32(ey + (side ? 1 : -1), mp.ny) * mp.nx + ex;
 }
 
 // One direction of the volume part of L_E for the thread's node: owned pairs, incoming halves.
@@ -193,16 +191,19 @@ __device__ __forceinline__ void surface_terms(double acc[5], bool act, int el, i
     // the volume accumulators wait in the (now free) primitive rows, to keep registers for the fluxes
 #pragma unroll
     for (int c = 0; c < 5; ++c) sp[c][tid] = acc[c];
-    long ex, ey;
-    elem_xy(mp, e, ex, ey);
+    int ex, ey;
+    elem_xy32(mp, (int)e, ex, ey);
     for (int f = q; f < 4 * NP; f += NN) {
       const int D = f / (2 * NP), side = (f / NP) & 1, line = f % NP;
-      long en;
-      int qo, qn;
+      int en, qo, qn;
       face_match<P>(mp, ex, ey, D, side, line, en, qo, qn);
+      const unsigned oo = ((unsigned)e * NN + qo) * 8u, on = ((unsigned)en * NN + qn) * 8u;
       double uo[5], un[5], F[5];
 #pragma unroll
-      for (int c = 0; c < 5; ++c) { uo[c] = Us[c * KN + e * NN + qo]; un[c] = Us[c * KN + en * NN + qn]; }
+      for (int c = 0; c < 5; ++c) {
+        const auto r = node_rsrc(Us + c * KN, KN);
+        uo[c] = bld(r, oo); un[c] = bld(r, on);
+      }
       face_flux(uo, un, side ? 1.0 : -1.0, mp.gamma, mp.gk, D, iface, F);
       const double sc = 2.0 * (D == 0 ? mp.rhx : mp.rhy);
       const double s = side ? -(sc * rcp_refined(T->w[P])) : sc * rcp_refined(T->w[0]);
@@ -310,15 +311,16 @@ __device__ __forceinline__ void hydro_stage_body(const double* __restrict__ Us, 
   const long e = blk * EB + el;
   const bool act = tid < C::NT && e < mp.K;
   const long KN = mp.K * NN;
+  const unsigned no = ((unsigned)e * NN + q) * 8u;  // the node's byte offset in a component array
   double U[5], UNo[5], acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   Prim me{};
   if (act) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) U[c] = Us[c * KN + e * NN + q];
+    for (int c = 0; c < 5; ++c) U[c] = bld(node_rsrc(Us + c * KN, KN), no);
     // U^n is issued early (it is only used at the end); the first stage (ca = 0) has no U^n term
     if (MODE == 1 && ca != 0.0) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) UNo[c] = Un[c * KN + e * NN + q];
+      for (int c = 0; c < 5; ++c) UNo[c] = bld(node_rsrc(Un + c * KN, KN), no);
     } else {
 #pragma unroll
       for (int c = 0; c < 5; ++c) UNo[c] = 0.0;
@@ -341,7 +343,7 @@ __device__ __forceinline__ void hydro_stage_body(const double* __restrict__ Us, 
   if (MODE == 0) {
     if (act) {
 #pragma unroll
-      for (int c = 0; c < 5; ++c) out[c * KN + e * NN + q] = acc[c];
+      for (int c = 0; c < 5; ++c) bst(node_rsrc(out + c * KN, KN), no, acc[c]);
     }
     return;
   }
@@ -350,7 +352,7 @@ __device__ __forceinline__ void hydro_stage_body(const double* __restrict__ Us, 
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
       Y[c] = U[c] + (cb * tau) * acc[c];
-      out[c * KN + e * NN + q] = Y[c];
+      bst(node_rsrc(out + c * KN, KN), no, Y[c]);
       sp[c][tid] = Y[c];
     }
   }
@@ -441,9 +443,10 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
   const long e = blk * EB + el;
   const bool act = tid < C::NT && e < mp.K;
   const long KN = mp.K * NN;
+  const unsigned no = ((unsigned)e * NN + q) * 8u;  // the node's byte offset in a component array
   const double g = mp.gamma;
-  long ex, ey;
-  elem_xy(mp, act ? e : 0, ex, ey);
+  int ex, ey;
+  elem_xy32(mp, act ? (int)e : 0, ex, ey);
   // grid line ln of direction D (D = 0: row, index along x; D = 1: column), position k on it
   auto nodeof = [](int D, int ln, int k) { return D == 0 ? ln * NP + k : k * NP + ln; };
   double U[5], a[5];
@@ -452,16 +455,18 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
   // go to LDS when their direction comes
   double nb[4][5];
   if (act && do_oe) {
-    const long nbe[4] = {ey * mp.nx + wrap(ex - 1, mp.nx), ey * mp.nx + wrap(ex + 1, mp.nx),
-                         wrap(ey - 1, mp.ny) * mp.nx + ex, wrap(ey + 1, mp.ny) * mp.nx + ex};
+    const int nbe[4] = {ey * mp.nx + wrap32(ex - 1, mp.nx), ey * mp.nx + wrap32(ex + 1, mp.nx),
+                        wrap32(ey - 1, mp.ny) * mp.nx + ex, wrap32(ey + 1, mp.ny) * mp.nx + ex};
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s) {
+      const unsigned on = ((unsigned)nbe[s] * NN + q) * 8u;
 #pragma unroll
-      for (int c = 0; c < 5; ++c) nb[s][c] = Ust[c * KN + nbe[s] * NN + q];
+      for (int c = 0; c < 5; ++c) nb[s][c] = bld(node_rsrc(Ust + c * KN, KN), on);
+    }
   }
   if (act) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) { U[c] = Ust[c * KN + e * NN + q]; su[c][tid] = U[c]; }
+    for (int c = 0; c < 5; ++c) { U[c] = bld(node_rsrc(Ust + c * KN, KN), no); su[c][tid] = U[c]; }
 #pragma unroll
     for (int c = 0; c < 5; ++c) a[c] = 0.25 * stats[(e * 5 + c) * 3];
   }
@@ -688,12 +693,12 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
   }
   if (act) {
 #pragma unroll
-    for (int c = 0; c < 5; ++c) Uout[c * KN + e * NN + q] = U[c];
+    for (int c = 0; c < 5; ++c) bst(node_rsrc(Uout + c * KN, KN), no, U[c]);
     if (rho_o) {  // primitive copy for the magnetic substep (the conversion's arithmetic)
-      const long n = e * NN + q;
       const double r = U[0], ux = U[1] / r, uy = U[2] / r, uz = U[3] / r;
-      rho_o[n] = r; u_o[n] = ux; u_o[KN + n] = uy; u_o[2 * KN + n] = uz;
-      e_o[n] = (U[4] - 0.5 * r * (ux * ux + uy * uy + uz * uz)) / r;
+      bst(node_rsrc(rho_o, KN), no, r);
+      bst(node_rsrc(u_o, KN), no, ux); bst(node_rsrc(u_o + KN, KN), no, uy); bst(node_rsrc(u_o + 2 * KN, KN), no, uz);
+      bst(node_rsrc(e_o, KN), no, (U[4] - 0.5 * r * (ux * ux + uy * uy + uz * uz)) / r);
     }
     if (q == 0) {
       if (flags) flags[e] = f;
@@ -755,15 +760,15 @@ __global__ __launch_bounds__(256) void k_face_map(int32_t* __restrict__ nbr, int
   if (t >= 4 * mp.K) return;
   const long e = t >> 2;
   const int f = (int)(t & 3), D = f >> 1, side = f & 1;
-  long ex, ey;
-  elem_xy(mp, e, ex, ey);
-  long en = 0;
+  int ex, ey;
+  elem_xy32(mp, (int)e, ex, ey);
+  int en = 0;
   for (int line = 0; line < NP; ++line) {
     int qo, qn;
     face_match<P>(mp, ex, ey, D, side, line, en, qo, qn);
-    if (fmap) fmap[t * NP + line] = (int32_t)(en * NN + qn);
+    if (fmap) fmap[t * NP + line] = en * NN + qn;
   }
-  nbr[t] = (int32_t)en;
+  nbr[t] = en;
 }
 
 // Entry copy of a conservative state with the admissibility test of every node: all five values
@@ -809,9 +814,13 @@ __global__ __launch_bounds__(256) void k_copy_check(const double* __restrict__ a
 // by a fixed tree.
 constexpr int LRC = 8, LRP = 256 / LRC;
 
+// A row reduces its first rx elements and a column its first ry (the whole mesh on a periodic
+// domain; the box of a mirror-walled mesh, whose other elements are mirror images: every row's and
+// column's statistics are then those of the box's own, up to the sign of an odd field).
 template <int NC>
 __device__ __forceinline__ void line_reduce_body(const double* __restrict__ stats, double* __restrict__ lines,
-                                                     int nx, int ny, const int* __restrict__ flag, long blk) {
+                                                     int nx, int ny, int rx, int ry, const int* __restrict__ flag,
+                                                     long blk) {
   constexpr int nc = NC;  // components per element record (compile-time, so that no load waits on a branch)
   __shared__ double red[15][256];
   if (flag && *flag) return;
@@ -834,12 +843,12 @@ __device__ __forceinline__ void line_reduce_body(const double* __restrict__ stat
   // every result bit, is that of the plain loop)
   if (b < ny) {
 #pragma unroll 4
-    for (int k = t; k < nx; k += 256) take((long)b * nx + k);
+    for (int k = t; k < rx; k += 256) take((long)b * nx + k);
   } else {
     const int col = (b - ny) * LRC + t % LRC, ph = t / LRC;
     if (col < nx)
 #pragma unroll 4
-      for (int r = ph; r < ny; r += LRP) take((long)r * nx + col);
+      for (int r = ph; r < ry; r += LRP) take((long)r * nx + col);
   }
 #pragma unroll
   for (int k = 0; k < 15; ++k) red[k][t] = v[k];
@@ -865,8 +874,8 @@ __device__ __forceinline__ void line_reduce_body(const double* __restrict__ stat
 
 template <int NC>
 __global__ __launch_bounds__(256) void k_line_reduce(const double* __restrict__ stats, double* __restrict__ lines,
-                                                     int nx, int ny, const int* __restrict__ flag) {
-  line_reduce_body<NC>(stats, lines, nx, ny, flag, (long)blockIdx.x);
+                                                     int nx, int ny, int rx, int ry, const int* __restrict__ flag) {
+  line_reduce_body<NC>(stats, lines, nx, ny, rx, ry, flag, (long)blockIdx.x);
 }
 
 struct line_reduce_args {
@@ -874,6 +883,8 @@ struct line_reduce_args {
   double* lines;
   int nx;
   int ny;
+  int rx;
+  int ry;
   const int* flag;
 };
 
@@ -881,10 +892,10 @@ template <int NC>
 __global__ __launch_bounds__(256) void k_line_reduce_rt(const line_reduce_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
   const line_reduce_args& a = A[r];
-  line_reduce_body<NC>(gl(a.stats), gl(a.lines), a.nx, a.ny, gl(a.flag), (long)blockIdx.x - boff[r]);
+  line_reduce_body<NC>(gl(a.stats), gl(a.lines), a.nx, a.ny, a.rx, a.ry, gl(a.flag), (long)blockIdx.x - boff[r]);
 }
 
-// Global reduction of the first `n` line results (the rows) into glob[nc][3]: all NC components in
+// Global reduction of the first `n` line results (the rows of the periodic mesh or of the box) into glob[nc][3]: all NC components in
 // one tree (each component's accumulation order is that of its own tree), so the block passes
 // eight barriers instead of eight per component.
 template <int NC>
@@ -1003,14 +1014,15 @@ static int check(mhd25_ctx* c, hipError_t e, const char* what) {
 static int launch_reductions(mhd25_ctx* c, const double* stats, int nc, const int* flag) {
   const dim3 grid(c->mp.ny + (c->mp.nx + LRC - 1) / LRC);
   if (c->rec) {
-    rt_record(c, RT_LINE_REDUCE, nc, grid.x, line_reduce_args{stats, c->lines, c->mp.nx, c->mp.ny, flag});
-    rt_record(c, RT_GLOBAL_REDUCE, nc, 1, global_reduce_args{c->lines, c->glob, c->mp.ny, flag});
+    rt_record(c, RT_LINE_REDUCE, nc, grid.x,
+              line_reduce_args{stats, c->lines, c->mp.nx, c->mp.ny, c->mp.bx, c->mp.by, flag});
+    rt_record(c, RT_GLOBAL_REDUCE, nc, 1, global_reduce_args{c->lines, c->glob, c->mp.by, flag});
     return 0;
   }
 #define LR(NC)                                                                                                    \
   hipLaunchKernelGGL((k_line_reduce<NC>), grid, dim3(256), 0, c->stream, stats, c->lines, c->mp.nx, c->mp.ny,    \
-                     flag);                                                                                       \
-  hipLaunchKernelGGL((k_global_reduce<NC>), dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.ny, flag)
+                     c->mp.bx, c->mp.by, flag);                                                                   \
+  hipLaunchKernelGGL((k_global_reduce<NC>), dim3(1), dim3(256), 0, c->stream, c->lines, c->glob, c->mp.by, flag)
   switch (nc) { case 1: LR(1); break; case 2: LR(2); break; case 3: LR(3); break; case 4: LR(4); break;
                 case 5: LR(5); break; default: c->err = "line reduction: unsupported component count"; return -2; }
 #undef LR

@@ -1424,10 +1424,9 @@ __device__ __forceinline__ void ar_eta_body(const double* __restrict__ tr, const
   elem_xy(mp, e, ex, ey);
   double dOm[3];
   bool cf[3];
-  const double area = (double)mp.K * mp.hx * mp.hy;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    const double mean = bglob[c * 3] / area, mn = bglob[c * 3 + 1], mx = bglob[c * 3 + 2];
+    const double mean = bglob[c * 3] / mp.area, mn = bglob[c * 3 + 1], mx = bglob[c * 3 + 2];
     dOm[c] = fmax(mx - mean, mean - mn);
     cf[c] = mx - mn <= 1024.0 * EPSM * fmax(fabs(mx), fabs(mn));  // roundoff-level variation (exact test)
   }
@@ -1499,17 +1498,20 @@ __device__ __forceinline__ void B_stats_body(const double* __restrict__ Bx, cons
   long ex, ey;
   elem_xy(mp, e, ex, ey);
   double s[3] = {0, 0, 0}, mn[3] = {DBL_MAX, DBL_MAX, DBL_MAX}, mx[3] = {-DBL_MAX, -DBL_MAX, -DBL_MAX};
+  // extrema over the element's own DOFs (its upper shared nodes belong to the next element); on a
+  // mirror-walled mesh the box's last column / row of elements also takes the box's wall DOFs
+  const bool wx = (mp.walls & 1) && ex == mp.bx - 1, wy = (mp.walls & 2) && ey == mp.by - 1;
   for (int j = 0; j < B; ++j)
     for (int i = 0; i < A; ++i) {
       const double v = Bx[gix(mp, B, ex, ey, i, j)];
       s[0] += T->ww[i] * T->wg[j] * v;
-      if (i < B) { mn[0] = fmin(mn[0], v); mx[0] = fmax(mx[0], v); }
+      if (i < B || wx) { mn[0] = fmin(mn[0], v); mx[0] = fmax(mx[0], v); }
     }
   for (int j = 0; j < A; ++j)
     for (int i = 0; i < B; ++i) {
       const double v = By[gix(mp, B, ex, ey, i, j)];
       s[1] += T->wg[i] * T->ww[j] * v;
-      if (j < B) { mn[1] = fmin(mn[1], v); mx[1] = fmax(mx[1], v); }
+      if (j < B || wy) { mn[1] = fmin(mn[1], v); mx[1] = fmax(mx[1], v); }
     }
   for (int j = 0; j < B; ++j)
     for (int i = 0; i < B; ++i) {

@@ -39,8 +39,9 @@ def gauss_nodes(k):
 class Layout:
     """Node coordinates of every field on an nx x ny periodic mesh."""
 
-    def __init__(self, nx, ny, p, m, x0, x1, y0, y1, gamma=GAMMA):
+    def __init__(self, nx, ny, p, m, x0, x1, y0, y1, gamma=GAMMA, walls=0):
         self.nx, self.ny, self.p, self.m = nx, ny, p, m
+        self.walls = walls  # bit 0 / bit 1: mirror-doubled in x / y (MIRROR_PARITY), statistics over the box
         self.x0, self.x1, self.y0, self.y1 = x0, x1, y0, y1
         self.gamma = gamma
         self.hx = (x1 - x0) / nx
@@ -50,7 +51,7 @@ class Layout:
 
     def desc(self):
         return dict(nx=self.nx, ny=self.ny, p=self.p, m=self.m, x0=self.x0, x1=self.x1,
-                    y0=self.y0, y1=self.y1, gamma=self.gamma)
+                    y0=self.y0, y1=self.y1, gamma=self.gamma, walls=self.walls)
 
     # physical coordinate of reference point s in element index e along x / y
     def _px(self, ex, s):
@@ -275,6 +276,71 @@ def balsara_vortex(nx=64, ny=64, p=2, m=2, t=0.0, gamma=GAMMA):
     Bx, By = L.curl_of_potential(-gw / (2.0 * math.pi))
     Bz = np.zeros_like(Bx)
     return L, U, Bx, By, Bz
+
+
+# Mirror walls (section "MHD rotor" states mirror boundary conditions without their discretisation).
+# Reading: a mirror wall is a plane of reflection symmetry of the flow.  Reflection across a wall
+# whose normal is x (resp. y) maps a state to its mirror image with these field parities; ideal MHD
+# and every operator of the scheme (fluxes, stabilisers, sensors) are invariant under each of these
+# maps, the B signs being the axial-vector law for an x-normal wall and the polar-vector law (the
+# axial law composed with the symmetry B -> -B) for a y-normal wall, which together keep a uniform
+# B_x, as the rotor starts with, smooth across every wall.  The wall then has zero normal velocity
+# and zero B_y, and zero normal derivative of the even fields.  A box with mirror walls on all four
+# sides is solved as its mirror-doubled periodic domain: the box, its images across x = x1 and
+# y = y1 and across both, on a periodic mesh of twice the element count per direction whose element
+# faces include the walls (mesh flag walls = 3; 1 or 2 for walls normal to x or to y only).  The periodic operators keep the doubled state
+# mirror-symmetric (to rounding), which imposes the wall conditions, and the stabilisers' global and
+# line amplitudes are taken over the box itself (an odd field's mean over the doubled domain would be
+# zero); restricting to the first quadrant returns the box.
+MIRROR_PARITY = {
+    "x": {"rho": 1, "ux": -1, "uy": 1, "uz": 1, "p": 1, "Bx": 1, "By": -1, "Bz": -1},
+    "y": {"rho": 1, "ux": 1, "uy": -1, "uz": 1, "p": 1, "Bx": 1, "By": -1, "Bz": 1},
+}
+
+
+def _fold(X, a, b):
+    """Position in [a, b] of the point X of the doubled interval [a, 2b - a], and +1 / -1 for the
+    box itself / its mirror image across b."""
+    inside = X <= b
+    return np.where(inside, X, 2.0 * b - X), np.where(inside, 1.0, -1.0)
+
+
+def _mirror_sign(field, sx, sy):
+    """Sign of `field` at a point of the box (+1, +1), of its x image (-1, +1), y image or both."""
+    return (np.where(sx < 0, MIRROR_PARITY["x"][field], 1.0) *
+            np.where(sy < 0, MIRROR_PARITY["y"][field], 1.0))
+
+
+def rotor_mirror(n=256, p=2, m=2, gamma=GAMMA):
+    """MHD rotor of section "MHD rotor" on [0,1]^2 with mirror walls, returned as the mirror-doubled
+    periodic problem on [0,2]^2 with 2n x 2n elements (the box is the quadrant ex, ey < n):
+    rho = 10 and rigid rotation with unit speed at r = 0.1 inside r < 0.1 about (1/2, 1/2); over
+    0.1 <= r < 0.115 the density and the tangential speed fall linearly to the ambient rho = 1,
+    u = 0; p = 0.5; uniform B = (2.5/sqrt(4 pi), 0, 0).  Point values at the nodes; the images
+    carry the parities of MIRROR_PARITY."""
+    L = Layout(2 * n, 2 * n, p, m, 0.0, 2.0, 0.0, 2.0, gamma=gamma, walls=3)
+    X, Y = L.u_nodes()
+    Xf, sx = _fold(X, 0.0, 1.0)
+    Yf, sy = _fold(Y, 0.0, 1.0)
+    dx, dy = Xf - 0.5, Yf - 0.5
+    r = np.sqrt(dx * dx + dy * dy)
+    f = np.clip((0.115 - r) / 0.015, 0.0, 1.0)
+    rho = np.where(r < 0.1, 10.0, 1.0 + 9.0 * f)
+    speed = np.where(r < 0.1, r / 0.1, f)  # tangential speed
+    rs = np.where(r > 0.0, r, 1.0)
+    ux = _mirror_sign("ux", sx, sy) * (-speed * dy / rs)
+    uy = _mirror_sign("uy", sx, sy) * (speed * dx / rs)
+    U = conservative(rho, ux, uy, np.zeros_like(X), np.full_like(X, 0.5), gamma)
+    Bx = np.full((2 * n * L.M1, 2 * n * L.M1), 2.5 / math.sqrt(4.0 * math.pi))
+    return L, U, Bx, np.zeros_like(Bx), np.zeros_like(Bx)
+
+
+def mirror_quadrant(L, U):
+    """The box (first quadrant) of a mirror-doubled state U[5][K][p+1][p+1]: elements ex, ey < nx/2,
+    ny/2, in the box's own element order."""
+    nx, ny = L.nx // 2, L.ny // 2
+    V = U.reshape(5, L.ny, L.nx, L.p + 1, L.p + 1)[:, :ny, :nx]
+    return np.ascontiguousarray(V.reshape(5, nx * ny, L.p + 1, L.p + 1))
 
 
 def ensemble_draws(nruns=64, seed=0):

@@ -11,6 +11,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
@@ -29,6 +30,32 @@
 #define __builtin_amdgcn_rcp(x) (1.0 / (x))  // hardware 1/x estimate
 #define __builtin_amdgcn_readfirstlane(x) (x)  // callers pass wave-uniform values
 #define MHD_GLOBAL_AS  // one address space on the host
+
+// Raw buffer resources: a base and a range in bytes.  An access outside the range is a kernel
+// indexing error here (on the GPU a load there would return 0), so it aborts the test process.
+struct EmuBufferRsrc {
+  char* base;
+  unsigned long long n;
+};
+typedef unsigned EmuU32x2 __attribute__((vector_size(8)));
+inline EmuBufferRsrc emu_make_buffer_rsrc(void* p, short, int n, int) { return {(char*)p, (unsigned)n}; }
+inline char* emu_buffer_at(const EmuBufferRsrc& r, unsigned off, unsigned soff) {
+  const unsigned long long a = (unsigned long long)off + soff;
+  if (a + 8 > r.n) { std::fprintf(stderr, "hipemu: buffer access at byte %llu of %llu\n", a, r.n); std::abort(); }
+  return r.base + a;
+}
+inline EmuU32x2 emu_raw_buffer_load_b64(EmuBufferRsrc r, unsigned off, unsigned soff, int) {
+  EmuU32x2 v;
+  std::memcpy(&v, emu_buffer_at(r, off, soff), 8);
+  return v;
+}
+inline void emu_raw_buffer_store_b64(EmuU32x2 v, EmuBufferRsrc r, unsigned off, unsigned soff, int) {
+  std::memcpy(emu_buffer_at(r, off, soff), &v, 8);
+}
+#define __amdgpu_buffer_rsrc_t EmuBufferRsrc
+#define __builtin_amdgcn_make_buffer_rsrc emu_make_buffer_rsrc
+#define __builtin_amdgcn_raw_buffer_load_b64 emu_raw_buffer_load_b64
+#define __builtin_amdgcn_raw_buffer_store_b64 emu_raw_buffer_store_b64
 
 struct dim3 {
   unsigned x, y, z;

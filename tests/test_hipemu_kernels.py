@@ -163,7 +163,11 @@ def test_emulated_invalid_arguments(emu):
                       (pk.MeshDesc(4, 4, 0.0, 1.0, 0.0, 1.0, 2, 2, 1.0), -1),
                       (pk.MeshDesc(4, 4, 0.0, 1.0, 0.0, 1.0, 7, 7, 5.0 / 3.0), -4),
                       (pk.MeshDesc(4, 4, 0.0, 1.0, 0.0, 1.0, 3, 1, 5.0 / 3.0), -4),
-                      (pk.MeshDesc(46341, 46341, 0.0, 1.0, 0.0, 1.0, 2, 2, 5.0 / 3.0), -1)):
+                      (pk.MeshDesc(46341, 46341, 0.0, 1.0, 0.0, 1.0, 2, 2, 5.0 / 3.0), -1),
+                      (pk.MeshDesc(9000, 9000, 0.0, 1.0, 0.0, 1.0, 2, 1, 5.0 / 3.0), -1),  # 2^29 nodes
+                      (pk.MeshDesc(5, 4, 0.0, 1.0, 0.0, 1.0, 2, 2, 5.0 / 3.0, 1), -1),     # walls, odd nx
+                      (pk.MeshDesc(4, 5, 0.0, 1.0, 0.0, 1.0, 2, 2, 5.0 / 3.0, 2), -1),     # walls, odd ny
+                      (pk.MeshDesc(4, 4, 0.0, 1.0, 0.0, 1.0, 2, 2, 5.0 / 3.0, 4), -1)):
         assert lib.mhd25_init(ctypes.byref(bad), None, None, ctypes.byref(h)) == code
     opts = pk.Options.make(iface_flux=2)
     assert lib.mhd25_init(ctypes.byref(ok), ctypes.byref(opts), None, ctypes.byref(h)) == -1
