@@ -521,7 +521,9 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
           double ja = 0.0, jd = 0.0, jb = 0.0, jc = 0.0;
 #pragma unroll
           for (int k = 0; k < NP; ++k) {
-            const double d0 = T->Dr0[r][k], dp = T->Drp[r][k];
+            // the +1 row from the -1 row: on the symmetric GLL nodes d^r l_k (+1) = (-1)^r d^r l_{p-k} (-1),
+            // which the tables hold bit for bit, so one table stays in scalar registers instead of two
+            const double d0 = T->Dr0[r][k], dp = (r & 1) ? -T->Dr0[r][P - k] : T->Dr0[r][P - k];
             ja += d0 * own[k];
             jd += dp * own[k];
             jb += dp * mn[k];
@@ -557,7 +559,15 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
       __syncthreads();
     }
     // modal damping with line tasks: x transform of each row, then per column the y transform,
-    // the shell factors and the inverse y transform, then the inverse x transform of each row
+    // the shell factors and the inverse y transform, then the inverse x transform of each row.
+    // On the symmetric GLL nodes Tf[a][k] = (-1)^a Tf[a][p-k] and V[k][a] = (-1)^a V[p-k][a], bit for
+    // bit in the tables, so only the entries with k <= p/2 are read (fewer scalar registers).
+    auto tf = [&](int a, int k) {
+      return k <= P / 2 ? T->Tf[a][k] : ((a & 1) ? -T->Tf[a][P - k] : T->Tf[a][P - k]);
+    };
+    auto vt = [&](int k, int a) {
+      return k <= P / 2 ? T->V[k][a] : ((a & 1) ? -T->V[P - k][a] : T->V[P - k][a]);
+    };
     for (int t = q; act && t < NL; t += NN) {
       const int c = t / NP, ln = t - c * NP;
       double v[NP];
@@ -567,7 +577,7 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
       for (int aa = 0; aa < NP; ++aa) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) s += T->Tf[aa][k] * v[k];
+        for (int k = 0; k < NP; ++k) s += tf(aa, k) * v[k];
         st[c][el * NN + ln * NP + aa] = s;  // [row][x mode]
       }
     }
@@ -604,14 +614,14 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
       for (int b = 0; b < NP; ++b) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) s += T->Tf[b][k] * v[k];
+        for (int k = 0; k < NP; ++k) s += tf(b, k) * v[k];
         cb[b] = sD[el][aa > b ? aa : b] * s;  // coefficient (x mode aa, y mode b), damped
       }
 #pragma unroll
       for (int jj = 0; jj < NP; ++jj) {
         double s = 0.0;
 #pragma unroll
-        for (int b = 0; b < NP; ++b) s += T->V[jj][b] * cb[b];
+        for (int b = 0; b < NP; ++b) s += vt(jj, b) * cb[b];
         st[c][el * NN + jj * NP + aa] = s;  // [row][x mode]
       }
     }
@@ -626,7 +636,7 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
       for (int ii = 0; ii < NP; ++ii) {
         double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < NP; ++k) s += T->V[ii][k] * v[k];
+        for (int k = 0; k < NP; ++k) s += vt(ii, k) * v[k];
         su[c][el * NN + ln * NP + ii] = s;
         mn = fmin(mn, s);
       }
