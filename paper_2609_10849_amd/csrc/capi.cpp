@@ -156,6 +156,19 @@ int mhd25_init(const mhd25_mesh_desc* mesh, const mhd25_options* opt, void* stre
   c->G = (long)d.nx * d.ny * c->M1 * c->M1;
   build_hydro_tables(c->p, &c->h_ht);
   build_mag_tables(c->p, c->m, &c->h_mt);
+  {  // reciprocal lumped weights of the gathered nodes (a shared node adds its neighbours' weights)
+    const int A = c->m + 2, B = c->m + 1;
+    const MagTab& t = c->h_mt;
+    for (int j = 0; j < B; ++j)
+      for (int i = 0; i < B; ++i) {
+        const long double wx = (long double)t.ww[i] + (i == 0 ? t.ww[A - 1] : 0.0L);
+        const long double wy = (long double)t.ww[j] + (j == 0 ? t.ww[A - 1] : 0.0L);
+        const long double J = c->mp.J;
+        c->h_mt.rjw[0][j][i] = (double)(1.0L / (J * wx * wy));               // W: GLL in x and y
+        c->h_mt.rjw[1][j][i] = (double)(1.0L / (J * (long double)t.wg[i] * wy));  // N_x: Gauss in x
+        c->h_mt.rjw[2][j][i] = (double)(1.0L / (J * wx * (long double)t.wg[j]));  // N_y: Gauss in y
+      }
+  }
   const long K = c->mp.K, KN = K * c->nn, n5 = 5 * KN, G = c->G;
   const int a = c->m + 2, b = c->m + 1;
   const long ny_ = d.ny, nx_ = d.nx;

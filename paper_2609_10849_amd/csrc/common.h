@@ -42,6 +42,10 @@ struct MagTab {
   double D_W_V[MHD_MAXN][MHD_MAXN], I_G_V[MHD_MAXN][MHD_MAXN];
   double I_G_E[2][MHD_MAXN], I_V_E[2][MHD_MAXN];   // basis values at -1 and +1
   double I_V_Q[MHD_MAXN][MHD_MAXN];
+  // 1 / (|J_K| w) of a gathered node, per local position [j][i] < m+1 of its owning element: the
+  // lumped weight w sums the contributions of every element sharing the node (W, N_x, N_y nodes).
+  // Mesh dependent: set by mhd25_init.
+  double rjw[3][MHD_MAXN][MHD_MAXN];
 };
 
 // velocity-OE basis table per element: nn rows (one per node) of nn values, each row padded to

@@ -26,13 +26,14 @@ struct MC {
 
 __device__ __forceinline__ long wrapl(long a, long n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
 
-// global index of local node (i, j) of element (ex, ey) on a magnetic grid
+// global index of local node (i, j) of element (ex, ey) on a magnetic grid (32-bit arithmetic: a
+// grid holds fewer than 2^29 nodes, which mhd25_init guarantees)
 __device__ __forceinline__ long gix(const MeshP& mp, int B, long ex, long ey, int i, int j) {
-  const long NX = (long)mp.nx * B, NY = (long)mp.ny * B;
-  long gx = ex * B + i, gy = ey * B + j;
+  const int NX = mp.nx * B, NY = mp.ny * B;
+  int gx = (int)ex * B + i, gy = (int)ey * B + j;
   if (gx >= NX) gx -= NX;
   if (gy >= NY) gy -= NY;
-  return gy * NX + gx;
+  return (long)(gy * NX + gx);
 }
 
 // R2: the 2D2V reduced system (u_z = B_z = 0, in-plane E and J identically zero); B_z is not read
@@ -1501,18 +1502,23 @@ __device__ __forceinline__ void B_stats_body(const double* __restrict__ Bx, cons
   // extrema over the element's own DOFs (its upper shared nodes belong to the next element); on a
   // mirror-walled mesh the box's last column / row of elements also takes the box's wall DOFs
   const bool wx = (mp.walls & 1) && ex == mp.bx - 1, wy = (mp.walls & 2) && ey == mp.by - 1;
+  // outer loops rolled: fully unrolled, the three loops keep every load in flight at once (about
+  // 190 VGPRs, 2 waves per SIMD instead of 6)
+#pragma unroll 1
   for (int j = 0; j < B; ++j)
     for (int i = 0; i < A; ++i) {
       const double v = Bx[gix(mp, B, ex, ey, i, j)];
       s[0] += T->ww[i] * T->wg[j] * v;
       if (i < B || wx) { mn[0] = fmin(mn[0], v); mx[0] = fmax(mx[0], v); }
     }
+#pragma unroll 1
   for (int j = 0; j < A; ++j)
     for (int i = 0; i < B; ++i) {
       const double v = By[gix(mp, B, ex, ey, i, j)];
       s[1] += T->wg[i] * T->ww[j] * v;
       if (j < B || wy) { mn[1] = fmin(mn[1], v); mx[1] = fmax(mx[1], v); }
     }
+#pragma unroll 1
   for (int j = 0; j < B; ++j)
     for (int i = 0; i < B; ++i) {
       const double v = Bz[gix(mp, B, ex, ey, i, j)];
@@ -1558,32 +1564,33 @@ __device__ __forceinline__ void gather_body(const double* __restrict__ Lx, const
                                                 double* __restrict__ Oy, double* __restrict__ Oz,
                                                 const MagTab* __restrict__ T, MeshP mp, long blk) {
   constexpr int A = M + 2, B = M + 1, AA = A * A, AB = A * B;
-  const long NX = (long)mp.nx * B, G = NX * mp.ny * B;
+  const int NX = mp.nx * B;
+  const long G = (long)NX * mp.ny * B;  // below 2^29 (mhd25_init)
   const long g = blk * blockDim.x + threadIdx.x;
   if (g >= G) return;
-  const long gy = row_of(mp, g / B), gx = g - gy * NX;  // g / (nx B) = (g / B) / nx
-  const long ex = gx / B, ey = gy / B;
+  const int gy = (int)row_of(mp, g / B), gx = (int)g - gy * NX;  // g / (nx B) = (g / B) / nx
+  const int ex = gx / B, ey = gy / B;
   const int i = gx - ex * B, j = gy - ey * B;
-  const long e = ey * mp.nx + ex;
-  const long eL = ey * mp.nx + wrapl(ex - 1, mp.nx), eD = wrapl(ey - 1, mp.ny) * mp.nx + ex;
-  const long eLD = wrapl(ey - 1, mp.ny) * mp.nx + wrapl(ex - 1, mp.nx);
+  const long e = (long)ey * mp.nx + ex;
+  const long eL = (long)ey * mp.nx + wrap32(ex - 1, mp.nx), eD = (long)wrap32(ey - 1, mp.ny) * mp.nx + ex;
+  const long eLD = (long)wrap32(ey - 1, mp.ny) * mp.nx + wrap32(ex - 1, mp.nx);
   {  // W node
-    double s = Lz[e * AA + j * A + i], w = T->ww[i] * T->ww[j];
-    if (i == 0) { s += Lz[eL * AA + j * A + (A - 1)]; w += T->ww[A - 1] * T->ww[j]; }
-    if (j == 0) { s += Lz[eD * AA + (A - 1) * A + i]; w += T->ww[i] * T->ww[A - 1]; }
-    if (i == 0 && j == 0) { s += Lz[eLD * AA + (A - 1) * A + (A - 1)]; w += T->ww[A - 1] * T->ww[A - 1]; }
-    Oz[g] = s / (mp.J * w);
+    double s = Lz[e * AA + j * A + i];
+    if (i == 0) s += Lz[eL * AA + j * A + (A - 1)];
+    if (j == 0) s += Lz[eD * AA + (A - 1) * A + i];
+    if (i == 0 && j == 0) s += Lz[eLD * AA + (A - 1) * A + (A - 1)];
+    Oz[g] = s * T->rjw[0][j][i];
   }
   if (R2) return;  // the 2D2V system has no in-plane J or E
   {  // N_x node: Gauss in x (i), GLL in y (j); local index j*B + i
-    double s = Lx[e * AB + j * B + i], w = T->wg[i] * T->ww[j];
-    if (j == 0) { s += Lx[eD * AB + (A - 1) * B + i]; w += T->wg[i] * T->ww[A - 1]; }
-    Ox[g] = s / (mp.J * w);
+    double s = Lx[e * AB + j * B + i];
+    if (j == 0) s += Lx[eD * AB + (A - 1) * B + i];
+    Ox[g] = s * T->rjw[1][j][i];
   }
   {  // N_y node: GLL in x (i), Gauss in y (j); local index j*A + i
-    double s = Ly[e * AB + j * A + i], w = T->ww[i] * T->wg[j];
-    if (i == 0) { s += Ly[eL * AB + j * A + (A - 1)]; w += T->ww[A - 1] * T->wg[j]; }
-    Oy[g] = s / (mp.J * w);
+    double s = Ly[e * AB + j * A + i];
+    if (i == 0) s += Ly[eL * AB + j * A + (A - 1)];
+    Oy[g] = s * T->rjw[2][j][i];
   }
 }
 
