@@ -191,7 +191,9 @@ int mhd25_cfl_dt(mhd25_ctx* ctx, const double* U, const double* Bx, const double
 int mhd25_B_from_potential(mhd25_ctx* ctx, const double* A, double* Bx, double* By);
 
 /* Diagnostics (host out[6]): mass = sum M rho, mechanical energy sum M E_mech,
- * magnetic energy (B,B)_B / 2, ||div B||_{L2}, min nodal rho, min nodal p. */
+ * magnetic energy (B,B)_B / 2, ||div B||_{L2}, min nodal rho, min nodal p.  Over the whole mesh:
+ * on a mirror-walled mesh the sums are those of the box times the number of images (2 or 4), the
+ * L2 norm the box's times the square root of that number. */
 int mhd25_diagnostics(mhd25_ctx* ctx, const double* U, const double* Bx, const double* By,
                       const double* Bz, double* out6);
 
