@@ -831,7 +831,7 @@ __device__ __forceinline__ void vel_prep_body(const double* __restrict__ rho, do
     for (int k2 = 0; k2 < NN; ++k2) {
       double s = 0.0;
 #pragma unroll
-      for (int jj = 0; jj < NP; ++jj) s += sV[jj][mode_b(k2)] * w[jj][mode_a(k2)];
+      for (int jj = 0; jj < NP; ++jj) s += H->V[jj][mode_b(k2)] * w[jj][mode_a(k2)];  // uniform: scalar loads
       *((act0 && k2 <= q) ? &sL[el][rq + k2] : &sdum[tid & 7]) = s;
     }
   }
