@@ -52,14 +52,14 @@ def ptr(a):
 
 
 def context(lib, pk, L, opts):
-    d = pk.MeshDesc(L.nx, L.ny, L.x0, L.x1, L.y0, L.y1, L.p, L.m, L.gamma)
+    d = pk.MeshDesc(L.nx, L.ny, L.x0, L.x1, L.y0, L.y1, L.p, L.m, L.gamma, getattr(L, "walls", 0))
     h = ctypes.c_void_p()
     assert lib.mhd25_init(ctypes.byref(d), ctypes.byref(opts), None, ctypes.byref(h)) == 0
     return h
 
 
 def omesh(L):
-    return O.Mesh(L.nx, L.ny, L.p, L.m, L.x0, L.x1, L.y0, L.y1, L.gamma)
+    return O.Mesh(L.nx, L.ny, L.p, L.m, L.x0, L.x1, L.y0, L.y1, L.gamma, walls=getattr(L, "walls", 0))
 
 
 @pytest.mark.parametrize("p,oe", [(1, 1), (2, 1), (3, 1), (4, 0), (4, 1), (6, 1)])
@@ -501,3 +501,26 @@ def test_emulated_magnetic_vjp_with_eta(emu, pm):
         for g, r, a in zip(got, grads, ins):
             r = r.reshape(a.shape)
             assert np.abs(g - r).max() <= 1e-12 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("walls", [3, 1])
+def test_emulated_strang_step_mirror_walls(emu, walls):
+    """Mirror walls (box statistics in the line, global and B reductions): one fully stabilised
+    Strang step of a mirror-symmetric state on a doubled 8 x 8 mesh equals the oracle's to 1e-12,
+    limiter decisions bit for bit."""
+    lib, pk = emu
+    from tests._mirror import mirror_state
+    L, U, Bx, By, Bz = mirror_state(4, 2, 2)
+    L.walls = walls
+    h = context(lib, pk, L, pk.Options.full())
+    st = [np.ascontiguousarray(a.copy()) for a in (U, Bx, By, Bz)]
+    rep = pk.Report()
+    assert lib.mhd25_strang_step(h, *[ptr(a) for a in st], 2e-3, ctypes.byref(rep)) == 0
+    flags = np.zeros(L.K, np.uint8)
+    assert lib.mhd25_decisions(h, ctypes.c_void_p(flags.ctypes.data), L.K) == 0
+    lib.mhd25_destroy(h)
+    ref = O.strang_step(omesh(L), O.Options.full(), U, Bx, By, Bz, 2e-3)
+    assert (flags == ref[5]).all()
+    for a, r in zip(st, ref[:4]):
+        if np.abs(r).max() > 0:
+            assert np.abs(a - r).max() <= 1e-12 * np.abs(r).max()
