@@ -65,12 +65,6 @@ struct EmuIdx { unsigned x, y, z; };
 struct alignas(16) double2 { double x, y; };
 inline thread_local EmuIdx threadIdx{0, 0, 0}, blockIdx{0, 0, 0};
 inline thread_local dim3 blockDim, gridDim;
-// direct global-to-LDS load: lane l of the wave writes `size` bytes at lds + l * size
-inline void emu_global_load_lds(const void* g, void* lds, unsigned size, int, int) {
-  std::memcpy(static_cast<char*>(lds) + (threadIdx.x % 64) * size, g, size);
-}
-#define __builtin_amdgcn_global_load_lds emu_global_load_lds
-#define __builtin_amdgcn_s_waitcnt(x) ((void)0)  // host loads complete at once
 
 inline thread_local std::barrier<>* emu_bar = nullptr;
 inline void __syncthreads() { emu_bar->arrive_and_wait(); }
