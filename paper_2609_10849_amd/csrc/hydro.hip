@@ -508,7 +508,7 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
       // derivatives at both faces of the element and of its neighbours.  The squared, weighted
       // jumps of derivative order r overwrite the task's own staged slots (position r on the line)
       for (int t = q; act && t < NL; t += NN) {
-        const int c = t / NP, ln = t - c * NP;
+        const int ln = t / 5, c = t - ln * 5;  // component fastest (fewer LDS bank conflicts)
         double own[NP], mn[NP], pl[NP];
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
@@ -542,7 +542,7 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
 #pragma unroll
         for (int c = 0; c < 5; ++c) Dsh = act ? fmax(Dsh, samp[el][D][c]) : 0.0;
         for (int t = q; act && t < 5 * NP; t += NN) {
-          const int rr = t % NP, c = t / NP;
+          const int rr = t / 5, c = t - rr * 5;
           double v = 0.0;
           if (Dsh > 0.0 && !scst[el][c]) {
             double sm = 0.0, spp = 0.0;
@@ -569,7 +569,7 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
       return k <= P / 2 ? T->V[k][a] : ((a & 1) ? -T->V[P - k][a] : T->V[P - k][a]);
     };
     for (int t = q; act && t < NL; t += NN) {
-      const int c = t / NP, ln = t - c * NP;
+      const int ln = t / 5, c = t - ln * 5;  // component fastest (fewer LDS bank conflicts)
       double v[NP];
 #pragma unroll
       for (int k = 0; k < NP; ++k) v[k] = su[c][el * NN + ln * NP + k];
@@ -606,7 +606,7 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
     }
     __syncthreads();
     for (int t = q; act && t < NL; t += NN) {
-      const int c = t / NP, aa = t - c * NP;
+      const int aa = t / 5, c = t - aa * 5;
       double v[NP], cb[NP];
 #pragma unroll
       for (int k = 0; k < NP; ++k) v[k] = st[c][el * NN + k * NP + aa];
@@ -627,7 +627,7 @@ __device__ __forceinline__ void hydro_oe_pp_body(const double* __restrict__ Ust,
     }
     __syncthreads();
     for (int t = q; act && t < NL; t += NN) {
-      const int c = t / NP, ln = t - c * NP;
+      const int ln = t / 5, c = t - ln * 5;  // component fastest (fewer LDS bank conflicts)
       double v[NP];
 #pragma unroll
       for (int k = 0; k < NP; ++k) v[k] = st[c][el * NN + ln * NP + k];
