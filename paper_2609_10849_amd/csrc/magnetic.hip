@@ -946,9 +946,12 @@ __device__ __forceinline__ void vel_sensor_body(const double* __restrict__ rho, 
   const int qi = q % NP, qj = q / NP;
   const long e = blk * EB + el;
   const bool act = el < EB && e < mp.K;
-  long ex, ey;
-  elem_xy(mp, act ? e : 0, ex, ey);
+  int ex, ey;
+  elem_xy32(mp, act ? (int)e : 0, ex, ey);
   const long KN = mp.K * NN;
+  // node arrays through buffer resources and 32-bit byte offsets (arrays below 2^29 nodes)
+  auto uoff = [&](int el_) { return ((unsigned)el_ * NN + q) * 8u; };
+  const __amdgpu_buffer_rsrc_t ur[3] = {node_rsrc(u, KN), node_rsrc(u + KN, KN), node_rsrc(u + 2 * KN, KN)};
   for (int t = tid; t < NP * NP; t += 256) {
     tD0[t / NP][t % NP] = H->Dr0[t / NP][t % NP];
     tDp[t / NP][t % NP] = H->Drp[t / NP][t % NP];
@@ -962,8 +965,8 @@ __device__ __forceinline__ void vel_sensor_body(const double* __restrict__ rho, 
   double uu[3] = {0.0, 0.0, 0.0}, rq = 1.0;
   if (act) {
 #pragma unroll
-    for (int d = 0; d < NU; ++d) { uu[d] = u[d * KN + e * NN + q]; su[el][d][q] = uu[d]; }
-    rq = rho[e * NN + q];
+    for (int d = 0; d < NU; ++d) { uu[d] = bld(ur[d], uoff((int)e)); su[el][d][q] = uu[d]; }
+    rq = bld(node_rsrc(rho, KN), uoff((int)e));
     for (int k = q; k < AB; k += NN) {
       sbb[el][k] = Bx[gix(mp, B, ex, ey, k % A, k / A)];
       sbb[el][AB + k] = By[gix(mp, B, ex, ey, k % B, k / B)];
@@ -1018,11 +1021,11 @@ __device__ __forceinline__ void vel_sensor_body(const double* __restrict__ rho, 
   // the x-direction phases (they go to LDS once those are done)
   double uy_nb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (act) {
-    const long em = wrapl(ey - 1, mp.ny) * mp.nx + ex, ep = wrapl(ey + 1, mp.ny) * mp.nx + ex;
+    const unsigned om = uoff(wrap32(ey - 1, mp.ny) * mp.nx + ex), op = uoff(wrap32(ey + 1, mp.ny) * mp.nx + ex);
 #pragma unroll
     for (int c = 0; c < NU; ++c) {
-      uy_nb[c] = u[c * KN + em * NN + q];
-      uy_nb[3 + c] = u[c * KN + ep * NN + q];
+      uy_nb[c] = bld(ur[c], om);
+      uy_nb[3 + c] = bld(ur[c], op);
     }
   }
 #pragma unroll
@@ -1030,11 +1033,11 @@ __device__ __forceinline__ void vel_sensor_body(const double* __restrict__ rho, 
     // neighbours across the faces normal to D: sx rows 0..2 minus side, 3..5 plus side
     if (act) {
       if (D == 0) {
-        const long em = ey * mp.nx + wrapl(ex - 1, mp.nx), ep = ey * mp.nx + wrapl(ex + 1, mp.nx);
+        const unsigned om = uoff(ey * mp.nx + wrap32(ex - 1, mp.nx)), op = uoff(ey * mp.nx + wrap32(ex + 1, mp.nx));
 #pragma unroll
         for (int c = 0; c < NU; ++c) {
-          sx[el][c][q] = u[c * KN + em * NN + q];
-          sx[el][3 + c][q] = u[c * KN + ep * NN + q];
+          sx[el][c][q] = bld(ur[c], om);
+          sx[el][3 + c][q] = bld(ur[c], op);
         }
       } else {
 #pragma unroll
