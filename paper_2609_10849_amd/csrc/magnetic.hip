@@ -849,15 +849,21 @@ __device__ __forceinline__ void vel_prep_body(const double* __restrict__ rho, do
     *((act0 && q == 0) ? &srd[el][0] : &sdum[tid & 7]) = rk;
   }
   __syncthreads();
+  // Only the rows q > k read row k: the LDS returns data to active lanes only, and LDS bandwidth
+  // bounds this kernel, so the lanes at or above the diagonal stay masked (their Lr[k] = 0 is
+  // never used).
 #pragma unroll
   for (int k = 0; k + 1 < NN; ++k) {
-    double s0 = sL[el][rq + k], s1 = 0.0;  // G[q][k] (used only for q > k)
+    Lr[k] = 0.0;
+    if (q > k) {
+      double s0 = sL[el][rq + k], s1 = 0.0;  // G[q][k]
 #pragma unroll
-    for (int m = 0; m < k; ++m) {
-      if (m & 1) s1 -= Lr[m] * sL[el][k * (k + 1) / 2 + m];
-      else s0 -= Lr[m] * sL[el][k * (k + 1) / 2 + m];
+      for (int m = 0; m < k; ++m) {
+        if (m & 1) s1 -= Lr[m] * sL[el][k * (k + 1) / 2 + m];
+        else s0 -= Lr[m] * sL[el][k * (k + 1) / 2 + m];
+      }
+      Lr[k] = (s0 + s1) * srd[el][k];  // L[q][k]
     }
-    Lr[k] = (s0 + s1) * srd[el][k];  // L[q][k] on the rows q > k; never read on the others
     *((act0 && q > k) ? &sL[el][rq + k] : &sdum[tid & 7]) = Lr[k];
     piv -= Lr[k] * Lr[k];
     const double rk = rsqrt_refined(piv);  // pivot of row k + 1 (used by that row only)
