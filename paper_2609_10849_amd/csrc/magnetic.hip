@@ -849,9 +849,8 @@ __device__ __forceinline__ void vel_prep_body(const double* __restrict__ rho, do
     *((act0 && q == 0) ? &srd[el][0] : &sdum[tid & 7]) = rk;
   }
   __syncthreads();
-  // Only the rows q > k read row k: the LDS returns data to active lanes only, and LDS bandwidth
-  // bounds this kernel, so the lanes at or above the diagonal stay masked (their Lr[k] = 0 is
-  // never used).
+  // Only the rows q > k read row k; the lanes at or above the diagonal stay masked (measured
+  // faster than letting them read and discard; their Lr[k] = 0 is never used).
 #pragma unroll
   for (int k = 0; k + 1 < NN; ++k) {
     Lr[k] = 0.0;
