@@ -54,7 +54,7 @@ def kernel_table(N, k):
         (3, "velocity-OE projection", "k_vel_proj<", "magnetic.hip",
          psi + 3 * nn * 8 + 2 * nn * 8 + NP * 8 + 4 * nn * 8, None, blk(128, nn)),
         (4, "velocity-OE preparation (Gram, Cholesky, basis)", "k_vel_prep<", "magnetic.hip",
-         nn * 8 + psi, None, blk(64, nn)),
+         nn * 8 + psi, None, blk(128, nn)),
         (5, "E loads", "k_E_loads<", "magnetic.hip", 3 * nn * 8 + 2 * grid3 + 8 + loads, None, blk(128, nt)),
         (6, "velocity-OE sensor", "k_vel_sensor<", "magnetic.hip", 4 * nn * 8 + grid3 + NP * 8, None, blk(256, nn)),
         (7, "J loads", "k_J_loads<", "magnetic.hip", grid3 + loads, None, blk(256, nt)),

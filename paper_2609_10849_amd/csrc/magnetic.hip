@@ -739,8 +739,7 @@ __global__ __launch_bounds__(256) void k_field_stats(const double* __restrict__ 
 // Velocity OE (eq. magnetic-oe-sensor .. eq. magnetic-oe-map).  The rho-weighted projections use
 // the shell-ordered tensor Legendre basis orthonormalised in the rho-weighted product,
 // psi = phi L^{-T} with G = L L^T the Gram matrix.  rho is frozen during a magnetic substep, so
-// Psi[q][k] = psi_k(x_q) is computed once per substep (k_vel_prep, one wave per block so the
-// Cholesky barriers are cheap) and reused by the three stages: per stage k_vel_sensor forms the
+// Psi[q][k] = psi_k(x_q) is computed once per substep (k_vel_prep) and reused by the three stages: per stage k_vel_sensor forms the
 // damping factors and k_vel_proj applies the map.
 // ---------------------------------------------------------------------------------------------
 // shell index of mode k in the shell ordering (shell l holds modes l^2 .. (l+1)^2 - 1)
@@ -761,12 +760,19 @@ __host__ __device__ constexpr int mode_b(int k) {
   return r < l ? l : r - l;
 }
 
+// threads per block of the velocity-OE preparation (EB = MHD_PREP_BS / (N+1)^2 elements a block).
+// Measured on the 1024^2, N = 4 workload: 128 threads (5 elements, 98 % of the lanes busy) take
+// 2.67 ms against 3.16 ms for one-wave blocks (2 elements, 78 %), although the Cholesky barriers
+// then span two waves; 256 threads measure the same as 128.
+#ifndef MHD_PREP_BS
+#define MHD_PREP_BS 128
+#endif
 template <int P>
 struct VP {
-  static constexpr int NP = P + 1, NN = NP * NP, EB = 64 / NN > 0 ? 64 / NN : 1;
+  static constexpr int NP = P + 1, NN = NP * NP, EB = MHD_PREP_BS / NN > 0 ? MHD_PREP_BS / NN : 1;
 };
 
-// One wave per block (EB elements).  The Gram matrix is formed by sum factorisation and packed in
+// EB elements per block, one thread per node.  The Gram matrix is formed by sum factorisation and packed in
 // LDS; a left-looking Cholesky (thread q owns row q, one barrier per column) overwrites it with L,
 // and row q of Psi = Phi L^{-T} follows by forward substitution with L read from LDS.  Mode indices
 // are compile-time constants in the unrolled loops, and masked arithmetic replaces branches, so
@@ -777,7 +783,7 @@ __device__ __forceinline__ void vel_prep_body(const double* __restrict__ rho, do
                                                  const HydroTab* __restrict__ H, MeshP mp, long blk) {
   constexpr int NP = P + 1, NN = NP * NP, EB = VP<P>::EB, NL = NN * (NN + 1) / 2;
   constexpr int NPS = NP * (NP + 1) / 2;  // pairs a <= a'
-  // LDS, sized so that 24 one-wave blocks fit on a CU at N = 4 (6 waves per SIMD):
+  // LDS (16 KB per 128-thread block at N = 4, so LDS is not what limits the blocks per CU):
   // - sL holds the packed Gram matrix and then L.  Until the Gram rows are written, its first
   //   EB NN entries hold the node weights sw, whose last reads come before the barrier that
   //   precedes the Gram rows.
@@ -792,7 +798,7 @@ __device__ __forceinline__ void vel_prep_body(const double* __restrict__ rho, do
   const int el = act0 ? el0 : 0, q = act0 ? tid - el0 * NN : 0;  // idle lanes shadow lane 0
   const int qi = q % NP, qj = q / NP;
   const long e = blk * EB + el;
-  for (int t = tid; t < NP * NP; t += 64) sV[t / NP][t % NP] = H->V[t / NP][t % NP];
+  for (int t = tid; t < NP * NP; t += MHD_PREP_BS) sV[t / NP][t % NP] = H->V[t / NP][t % NP];
   if (act0) sw[el][q] = mp.J * H->w[qi] * H->w[qj] * rho[e * NN + q];
   __syncthreads();
   // sum factorisation: Hm[qj][a][a'] = sum_qi W[qj][qi] V[qi][a] V[qi][a'], symmetric in (a, a'),
@@ -898,7 +904,7 @@ __device__ __forceinline__ void vel_prep_body(const double* __restrict__ rho, do
 }
 
 template <int P>
-__global__ __launch_bounds__(64) void k_vel_prep(const double* __restrict__ rho, double* __restrict__ Psi,
+__global__ __launch_bounds__(MHD_PREP_BS) void k_vel_prep(const double* __restrict__ rho, double* __restrict__ Psi,
                                                  const HydroTab* __restrict__ H, MeshP mp) {
   vel_prep_body<P>(rho, Psi, H, mp, (long)blockIdx.x);
 }
@@ -911,7 +917,7 @@ struct vel_prep_args {
 };
 
 template <int P>
-__global__ __launch_bounds__(64) void k_vel_prep_rt(const vel_prep_args* __restrict__ A, const int* __restrict__ boff, int nr) {
+__global__ __launch_bounds__(MHD_PREP_BS) void k_vel_prep_rt(const vel_prep_args* __restrict__ A, const int* __restrict__ boff, int nr) {
   const int r = rt_run(boff, nr);
   const vel_prep_args& a = A[r];
   vel_prep_body<P>(gl(a.rho), gl(a.Psi), gl(a.H), a.mp, (long)blockIdx.x - boff[r]);
@@ -1887,7 +1893,7 @@ int mag_velocity_prep(mhd25_ctx* c, const double* rho) {
               vel_prep_args{rho, c->psi, c->d_ht, c->mp});
     return 0;
   }
-#define VPR(P) hipLaunchKernelGGL((k_vel_prep<P>), dim3((K + VP<P>::EB - 1) / VP<P>::EB), dim3(64), 0, c->stream, rho, \
+#define VPR(P) hipLaunchKernelGGL((k_vel_prep<P>), dim3((K + VP<P>::EB - 1) / VP<P>::EB), dim3(MHD_PREP_BS), 0, c->stream, rho, \
                                   c->psi, c->d_ht, c->mp)
   T_BEGIN(4);
   switch (c->p) { case 1: VPR(1); break; case 2: VPR(2); break; case 3: VPR(3); break; case 4: VPR(4); break;
@@ -2103,7 +2109,7 @@ int magnetic_rt_launch(const RtRecord& h, const void* dargs, const int* dboff, i
     }
     case RT_VEL_PREP: {
       const vel_prep_args* A = (const vel_prep_args*)dargs;
-#define F(P) hipLaunchKernelGGL((k_vel_prep_rt<P>), g, dim3(64), 0, s, A, dboff, nr)
+#define F(P) hipLaunchKernelGGL((k_vel_prep_rt<P>), g, dim3(MHD_PREP_BS), 0, s, A, dboff, nr)
       switch (h.key) { case 1: F(1); break; case 2: F(2); break; case 3: F(3); break; case 4: F(4); break;
                        case 5: F(5); break; case 6: F(6); break; default: return -4; }
 #undef F
